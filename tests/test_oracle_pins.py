@@ -1,0 +1,392 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a library
+routine (numpy's Gauss-Legendre rule, scipy's spherical harmonics), a closed
+form (areas, volumes, eigen-relations of the layer potentials on the sphere,
+the exterior sphere formulas), or an identity that holds on any closed
+surface (Gauss, the Stokes double-layer rigid-motion identity).
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import sph_harm_y
+
+from paper_1811_10270_amd import workloads as W
+
+
+def tri(n, m):
+    return n * (n + 1) // 2 + m
+
+
+def field(p, entries):
+    c = np.zeros((p + 1) * (p + 2))
+    for (n, m), v in entries.items():
+        v = complex(v)
+        c[2 * tri(n, m)] += v.real
+        c[2 * tri(n, m) + 1] += v.imag
+    return c
+
+
+def real_y(n, m, theta, phi):
+    """Real field 2 Re(0.5 Y_nm) (m > 0) or Y_n0, from scipy."""
+    return np.real(sph_harm_y(n, m, theta, phi))
+
+
+def y_entry(n, m):
+    return {(n, m): (1.0 if m == 0 else 0.5)}
+
+
+def sphere_x(p, R=1.0, centre=(0.0, 0.0, 0.0), axes=(1.0, 1.0, 1.0)):
+    blk = np.zeros(3 * (p + 1) * (p + 2))
+    nc2 = (p + 1) * (p + 2)
+    for (c, n, m), v in W.SPHERE_TABLE.items():
+        k = c * nc2 + 2 * tri(n, m)
+        blk[k] += (v * R * axes[c]).real
+        blk[k + 1] += (v * R * axes[c]).imag
+    for c in range(3):
+        blk[c * nc2] += math.sqrt(4 * math.pi) * centre[c]
+    return blk
+
+
+def make_susp(p, xcoef, f=None, sig=None, u=None, q_self=None, q_far=None, grid_mode=0):
+    nc2 = (p + 1) * (p + 2)
+    f = np.zeros(3 * nc2) if f is None else f
+    sig = np.zeros(nc2) if sig is None else sig
+    pa = np.array([p], np.int32)
+    return W.Suspension("pin", pa, np.array([q_self or 2 * p], np.int32),
+                        np.array([q_far or 2 * p], np.int32), grid_mode, xcoef, f, sig, u,
+                        np.zeros((1, 3)), np.ones(1))
+
+
+def grid_angles(p, grid_mode, ora):
+    t, _ = ora.gauss_legendre(p + 1)
+    nlon = ora.nlon_of(p, grid_mode)
+    th = np.repeat(np.arccos(t), nlon)
+    ph = np.tile(2 * np.pi * np.arange(nlon) / nlon, p + 1)
+    return th, ph
+
+
+# ---------------------------------------------------------------------------
+# Grid and spherical harmonics (Sec. 2, eq. normalized_spharm, eq. pneg)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 2, 5, 17, 33, 65, 97])
+def test_gauss_legendre_matches_numpy(ora, n):
+    t, w = ora.gauss_legendre(n)
+    tn, wn = np.polynomial.legendre.leggauss(n)
+    assert np.all(np.diff(t) < 0), "nodes must be ordered with theta increasing"
+    np.testing.assert_allclose(t, tn[::-1], atol=2e-15, rtol=0)
+    np.testing.assert_allclose(w, wn[::-1], atol=2e-14, rtol=0)
+    # exact for Legendre polynomials of degree < 2n (numpy's own rule is
+    # the less accurate of the two at large n, hence this sharper check)
+    for k in range(2 * n):
+        c = np.zeros(k + 1)
+        c[k] = 1.0
+        val = w @ np.polynomial.legendre.legval(t, c)
+        assert abs(val - (2.0 if k == 0 else 0.0)) < 2e-15
+
+
+@pytest.mark.parametrize("theta", [1e-3, 0.3, 1.1, 1.9, math.pi - 2e-3])
+def test_pbar_and_derivatives_match_scipy(ora, theta):
+    p = 14
+    phi = 0.77
+    P, dP, Ps = ora.pbar(p, theta)
+    s = math.sin(theta)
+    for n in range(p + 1):
+        for m in range(n + 1):
+            y, (dth, dph) = sph_harm_y(n, m, theta, phi, diff_n=1)
+            e = np.exp(1j * m * phi)
+            assert abs(P[tri(n, m)] * e - y) < 1e-13
+            assert abs(dP[tri(n, m)] * e - dth) < 2e-12
+            if m > 0:
+                # (1/sin) d/dphi Y_nm = i m Pbar/sin e^{im phi}
+                assert abs(1j * m * Ps[tri(n, m)] * e - dph / s) < 1e-12 * max(1.0, abs(dph / s))
+
+
+def test_sh_point_real_field_and_derivatives(ora):
+    p = 9
+    rng = np.random.default_rng(0)
+    c = rng.standard_normal((p + 1) * (p + 2))
+    for n in range(p + 1):
+        c[2 * tri(n, 0) + 1] = 0.0
+    for theta, phi in [(0.4, 2.0), (2.5, -1.0), (1e-4, 0.3)]:
+        v, dt, dph = ora.sh_point(p, c, theta, phi)
+        ref = 0.0
+        rdt = 0.0
+        rdp = 0.0
+        for n in range(p + 1):
+            for m in range(-n, n + 1):
+                if m >= 0:
+                    cnm = complex(c[2 * tri(n, m)], c[2 * tri(n, m) + 1])
+                else:
+                    cc = complex(c[2 * tri(n, -m)], c[2 * tri(n, -m) + 1])
+                    cnm = (-1) ** (-m) * cc.conjugate()
+                y, (dy, dyp) = sph_harm_y(n, m, theta, phi, diff_n=1)
+                ref += cnm * y
+                rdt += cnm * dy
+                rdp += cnm * dyp
+        assert abs(v[0] - ref.real) < 1e-12 and abs(ref.imag) < 1e-12
+        assert abs(dt[0] - rdt.real) < 1e-11
+        assert abs(dph[0] - rdp.real / math.sin(theta)) < 1e-9 * max(1, abs(dph[0]))
+
+
+@pytest.mark.parametrize("p,Q", [(8, 8), (10, 10), (10, 21), (16, 32)])
+def test_synthesis_analysis_round_trip(ora, p, Q):
+    rng = np.random.default_rng(p * 100 + Q)
+    c = rng.standard_normal((p + 1) * (p + 2))
+    for n in range(p + 1):
+        c[2 * tri(n, 0) + 1] = 0.0
+    g = ora.synth_grid(p, c, Q, 0)
+    c2 = ora.analyze_grid(p, g, Q, 0)
+    np.testing.assert_allclose(c2, c, atol=1e-13, rtol=0)
+    # the values themselves against scipy at a few nodes
+    th, ph = grid_angles(Q, 0, ora)
+    for idx in [0, 7, len(th) // 2, len(th) - 1]:
+        ref = 0.0
+        for n in range(p + 1):
+            for m in range(n + 1):
+                y = sph_harm_y(n, m, th[idx], ph[idx])
+                cc = complex(c[2 * tri(n, m)], c[2 * tri(n, m) + 1])
+                ref += (cc * y).real * (1 if m == 0 else 2)
+        assert abs(g.ravel()[idx] - ref) < 1e-12
+
+
+def test_grid_mode_1_round_trip_below_nyquist(ora):
+    # with 2Q longitudes the analysis is exact for degree p < Q
+    p, Q = 7, 9
+    rng = np.random.default_rng(5)
+    c = rng.standard_normal((p + 1) * (p + 2))
+    for n in range(p + 1):
+        c[2 * tri(n, 0) + 1] = 0.0
+    g = ora.synth_grid(p, c, Q, 1)
+    np.testing.assert_allclose(ora.analyze_grid(p, g, Q, 1), c, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Geometry and the regular quadrature (eq. reg_quadrature)
+# ---------------------------------------------------------------------------
+def test_unit_sphere_area_volume_normal(ora):
+    p = 4
+    x = sphere_x(p)
+    a, v, _ = ora.surface_integrals(p, x, 8)
+    assert abs(a - 4 * math.pi) < 1e-13 and abs(v - 4 * math.pi / 3) < 1e-13
+    for th, ph in [(0.3, 0.2), (2.0, 4.0), (1e-6, 1.0)]:
+        xx, n, J = ora.geom_point(p, x, th, ph)
+        s = np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+        np.testing.assert_allclose(xx, s, atol=1e-15)
+        np.testing.assert_allclose(n, s, atol=1e-13)
+        assert abs(J - 1.0) < 1e-13
+
+
+def test_ellipsoid_volume_area_element(ora):
+    a_, b_, c_ = 1.3, 0.8, 1.1
+    p = 3
+    x = sphere_x(p, axes=(a_, b_, c_), centre=(0.5, -2.0, 1.0))
+    area, vol, _ = ora.surface_integrals(p, x, 40)
+    assert abs(vol - 4 * math.pi * a_ * b_ * c_ / 3) < 1e-12
+    # Knud Thomsen's formula is approximate; check the area against a brute
+    # 2D Gauss rule on the parametrisation instead (independent integrand).
+    tg, wg = np.polynomial.legendre.leggauss(200)
+    th = (tg + 1) * math.pi / 2
+    ph = (tg + 1) * math.pi
+    TH, PH = np.meshgrid(th, ph, indexing="ij")
+    xt = np.stack([a_ * np.cos(TH) * np.cos(PH), b_ * np.cos(TH) * np.sin(PH), -c_ * np.sin(TH)])
+    xp = np.stack([-a_ * np.sin(TH) * np.sin(PH), b_ * np.sin(TH) * np.cos(PH), 0 * TH])
+    cr = np.cross(xt, xp, axis=0)
+    dA = np.linalg.norm(cr, axis=0)
+    ref = (math.pi / 2) * math.pi * np.einsum("i,j,ij->", wg, wg, dA)
+    assert abs(area - ref) < 1e-10
+
+
+def test_taylor_shape_radius_and_volume(ora):
+    # r = 1 + eps' Y_20 (normalised) = 1 + eps P_2 with eps = eps' sqrt(5/4pi):
+    # V = (4pi/3)(1 + 3 eps^2/5 + 2 eps^3/35)
+    epsn = 0.1
+    s = W.single_drop(16, seed=1, eps_y20=epsn, amp=0.0)
+    eps = epsn * math.sqrt(5 / (4 * math.pi))
+    _, vol, _ = ora.surface_integrals(16, s.xcoef, 16)
+    assert abs(vol - 4 * math.pi / 3 * (1 + 3 * eps ** 2 / 5 + 2 * eps ** 3 / 35)) < 1e-13
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        th, ph = rng.uniform(0, math.pi), rng.uniform(0, 2 * math.pi)
+        xx, _, _ = ora.geom_point(16, s.xcoef, th, ph)
+        r = 1 + eps * 0.5 * (3 * math.cos(th) ** 2 - 1)
+        s_hat = np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+        np.testing.assert_allclose(xx, r * s_hat, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Singular rule (eq. mod_weights + rotation) on the unit sphere
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("nm", [(0, 0), (1, 0), (2, 1), (3, 3), (5, 2), (8, 4)])
+def test_unit_sphere_laplace_eigenrelations(ora, nm):
+    n, m = nm
+    p = 8
+    s = make_susp(p, sphere_x(p), sig=field(p, y_entry(n, m)))
+    td, tn = ora.all_targets(s)
+    sel = np.arange(0, len(td), 5)
+    out = ora.self_(s, td[sel], tn[sel])
+    th, ph = grid_angles(p, 0, ora)
+    y = real_y(n, m, th[sel], ph[sel])
+    np.testing.assert_allclose(out[6], y / (2 * n + 1), atol=2e-14)        # S_L
+    np.testing.assert_allclose(out[7], -y / (2 * (2 * n + 1)), atol=2e-14)  # L
+    np.testing.assert_allclose(out[8], y / (2 * (2 * n + 1)), atol=2e-14)   # K*
+
+
+def test_unit_sphere_stokes_identities(ora):
+    p = 8
+    x = sphere_x(p)
+    nc2 = (p + 1) * (p + 2)
+    e = np.array([0.3, -1.2, 0.7])
+    const = np.zeros(3 * nc2)
+    for c in range(3):
+        const[c * nc2] = e[c] * math.sqrt(4 * math.pi)
+    td, tn = ora.all_targets(make_susp(p, x))
+    sel = np.arange(0, len(td), 3)
+    th, ph = grid_angles(p, 0, ora)
+    s_hat = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)])[:, sel]
+    # S[e] = (4/3) e ; D[e] = e
+    out = ora.self_(make_susp(p, x, f=const, u=const), td[sel], tn[sel])
+    np.testing.assert_allclose(out[0:3], (4 / 3) * e[:, None] * np.ones_like(s_hat), atol=1e-13)
+    np.testing.assert_allclose(out[3:6], e[:, None] * np.ones_like(s_hat), atol=1e-13)
+    # S[n] = 0 (n = x on the unit sphere); D[w x x] = w x x0
+    w = np.array([0.4, 0.9, -0.5])
+    rot = np.zeros(3 * nc2)
+    xs = x.reshape(3, nc2)
+    rv = np.stack([w[1] * xs[2] - w[2] * xs[1], w[2] * xs[0] - w[0] * xs[2],
+                   w[0] * xs[1] - w[1] * xs[0]])
+    rot[:] = rv.ravel()
+    out = ora.self_(make_susp(p, x, f=x.copy(), u=rot), td[sel], tn[sel])
+    np.testing.assert_allclose(out[0:3], 0.0, atol=1e-13)
+    np.testing.assert_allclose(out[3:6], np.cross(w, s_hat.T).T, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Singular rule on deformed drops: identities valid on any closed surface
+# ---------------------------------------------------------------------------
+def _identity_errors(ora, s, q, sel_stride=11):
+    p = int(s.p[0])
+    nc2 = (p + 1) * (p + 2)
+    U = np.array([0.2, -0.5, 0.9])
+    w = np.array([-0.3, 0.6, 0.25])
+    xs = s.xcoef.reshape(3, nc2)
+    u = np.stack([w[1] * xs[2] - w[2] * xs[1], w[2] * xs[0] - w[0] * xs[2],
+                  w[0] * xs[1] - w[1] * xs[0]])
+    for c in range(3):
+        u[c, 0] += U[c] * math.sqrt(4 * math.pi)
+    sig = np.zeros(nc2)
+    sig[0] = math.sqrt(4 * math.pi)            # sigma = 1
+    ss = make_susp(p, s.xcoef, f=np.zeros(3 * nc2), sig=sig, u=u.ravel(), q_self=q, q_far=q)
+    td, tn = ora.all_targets(ss)
+    sel = np.arange(0, len(td), sel_stride)
+    out = ora.self_(ss, td[sel], tn[sel])
+    x0, _ = ora.targets(ss, td[sel], tn[sel])
+    gauss = np.abs(out[7] + 0.5).max()
+    rigid = (U[:, None] + np.cross(w, x0.T).T)
+    dl = np.abs(out[3:6] - rigid).max()
+    return gauss, dl
+
+
+def test_deformed_drop_gauss_and_rigid_motion(ora):
+    s = W.single_drop(16, seed=1)
+    g32, d32 = _identity_errors(ora, s, 32)
+    g48, d48 = _identity_errors(ora, s, 48)
+    # spectral convergence of the singular rule in the upsampling degree
+    assert g32 < 1e-7 and d32 < 1e-6, (g32, d32)
+    assert g48 < 1e-9 and d48 < 1e-8, (g48, d48)
+
+
+def test_ellipsoid_gauss_identity(ora):
+    p = 6
+    x = sphere_x(p, axes=(1.25, 0.85, 1.0))
+    s = make_susp(p, x)
+    g, d = _identity_errors(ora, s, 24, sel_stride=3)
+    assert g < 1e-6 and d < 1e-5, (g, d)
+
+
+# ---------------------------------------------------------------------------
+# Far field (eq. reg_quadrature): exterior of the unit sphere
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("nm", [(0, 0), (1, 1), (2, 0), (4, 3)])
+def test_exterior_sphere_laplace(ora, nm):
+    n, m = nm
+    p = 8
+    s = make_susp(p, sphere_x(p), sig=field(p, y_entry(n, m)), q_far=24)
+    rng = np.random.default_rng(11)
+    for d in (2.5, 4.0):
+        dirs = rng.standard_normal((3, 6))
+        dirs /= np.linalg.norm(dirs, axis=0)
+        x0 = d * dirs
+        out = ora.far_points(s, x0, dirs)
+        th = np.arccos(dirs[2])
+        ph = np.arctan2(dirs[1], dirs[0])
+        y = real_y(n, m, th, ph)
+        np.testing.assert_allclose(out[6], y / ((2 * n + 1) * d ** (n + 1)), atol=1e-13)
+        np.testing.assert_allclose(out[7], n * y / ((2 * n + 1) * d ** (n + 1)), atol=1e-13)
+
+
+def test_exterior_sphere_stokeslet_translating_sphere(ora):
+    p = 6
+    nc2 = (p + 1) * (p + 2)
+    e = np.array([0.5, 1.0, -0.25])
+    f = np.zeros(3 * nc2)
+    for c in range(3):
+        f[c * nc2] = e[c] * math.sqrt(4 * math.pi)
+    s = make_susp(p, sphere_x(p), f=f, q_far=24)
+    rng = np.random.default_rng(4)
+    x0 = rng.standard_normal((3, 5))
+    x0 *= 3.0 / np.linalg.norm(x0, axis=0)
+    out = ora.far_points(s, x0, x0 / 3.0)
+    for i in range(5):
+        d = x0[:, i]
+        dn = np.linalg.norm(d)
+        G = np.eye(3) / dn + np.outer(d, d) / dn ** 3
+        quad = (np.eye(3) / dn ** 3 - 3 * np.outer(d, d) / dn ** 5) / 3.0
+        ref = (G + quad) @ e          # (1/4pi) * 4pi a^2 [G + a^2/3 (...)] e, a = 1
+        np.testing.assert_allclose(out[0:3, i], ref, atol=1e-13)
+
+
+def test_exterior_zero_identities_deformed(ora):
+    s0 = W.single_drop(16, seed=1)
+    p = 16
+    nc2 = (p + 1) * (p + 2)
+    U = np.array([0.1, 0.2, -0.3])
+    u = np.zeros(3 * nc2)
+    for c in range(3):
+        u[c * nc2] = U[c] * math.sqrt(4 * math.pi)
+    sig = np.zeros(nc2)
+    sig[0] = math.sqrt(4 * math.pi)
+    s = make_susp(p, s0.xcoef, sig=sig, u=u, q_far=48)
+    rng = np.random.default_rng(8)
+    x0 = rng.standard_normal((3, 8))
+    x0 *= 2.2 / np.linalg.norm(x0, axis=0)
+    out = ora.far_points(s, x0, x0 / 2.2)
+    assert np.abs(out[7]).max() < 1e-12          # L[1] = 0 outside
+    assert np.abs(out[3:6]).max() < 1e-12        # D[U] = 0 outside
+
+
+def test_far_at_nodes_consistent_with_points(ora):
+    s = W.two_drops(6, seed=2, gap=0.5)
+    td, tn = ora.all_targets(s)
+    sel = np.arange(0, len(td), 9)
+    a = ora.far(s, td[sel], tn[sel])
+    x0, n0 = ora.targets(s, td[sel], tn[sel])
+    # the far sum at a node of drop 0 equals the full sum over drop 1 only
+    b = ora.far_points(s, x0, n0, exclude=td[sel])
+    np.testing.assert_array_equal(a, b)
+    # two unit spheres: S_L of sigma on the other sphere equals the
+    # exterior formula about that sphere's centre
+    assert np.all(np.isfinite(a))
+
+
+def test_generator_draws_are_seeded():
+    a = W.batched_suspension(seed=3)
+    b = W.batched_suspension(seed=3)
+    np.testing.assert_array_equal(a.xcoef, b.xcoef)
+    np.testing.assert_array_equal(a.p, b.p)
+    assert sorted(np.bincount(a.p)[[16, 24, 32, 48]].tolist()) == [16, 16, 16, 16]
+    # clearance between drops is at least the requested gap (bound radii)
+    d = np.linalg.norm(a.centres[:, None] - a.centres[None], axis=2)
+    rr = a.radius_bound[:, None] + a.radius_bound[None] + 0.2
+    np.fill_diagonal(d, np.inf)
+    assert np.all(d >= rr)
