@@ -1,0 +1,161 @@
+/*
+ * ehdbim.h -- C ABI of the MI355X layer-potential library for drops
+ * represented by spherical harmonics (Sorgentone, Tornberg & Vlahovska,
+ * "A 3D boundary integral method for the electrohydrodynamics of
+ * surfactant-covered drops", arXiv 1811.10270).
+ *
+ * What the library computes (one call of ehd_layer_potentials):
+ * at every node of every drop's own Gaussian grid (the target nodes), the
+ *   Stokes single layer   S[f](x0) = 1/(4 pi) int f . G(x0,x) dS      (3 comp.)
+ *   Stokes double layer   D[u](x0) = 1/(4 pi) int u . T(x0,x) . n dS  (3 comp.)
+ *   Laplace single layer  S_L[s](x0) = 1/(4 pi) int s / r dS          (1)
+ *   Laplace double layer  L[s](x0) = 1/(4 pi) int s (xh . n) / r^3 dS (1)
+ *   adjoint double layer  K*[s](x0) = 1/(4 pi) int s (xh . n0) / r^3 dS (1)
+ * with xh = x0 - x, r = |xh|, G = I/r + xh xh / r^3, T = -6 xh xh xh / r^5,
+ * n the outward normal at x and n0 the one at x0 (paper: Sec. 1, eq. GandT;
+ * Sec. 2, eq. op_stokes and eq. dl_op_laplace; K* is the kernel of eq. E_n).
+ * Each sum runs over all drops: the target's own drop by the singular rule
+ * (Sec. 2.1, eq. mod_weights: the expansion is rotated so that the target is
+ * the north pole of an upsampled Gaussian grid of degree q_self), every other
+ * drop by the regular rule (eq. reg_quadrature) on its upsampled degree-q_far
+ * grid (direct summation).
+ *
+ * Data layout (all FP64 unless stated):
+ *   SH coefficients: orthonormal complex spherical harmonics with the
+ *   Condon-Shortley phase (Sec. 2, eq. normalized_spharm, eq. pneg).  A real
+ *   field of degree p is stored by its m >= 0 coefficients, (re, im)
+ *   interleaved, at complex index n(n+1)/2 + m: (p+1)(p+2) doubles.  A
+ *   K-field array holds the drops one after another; drop d's block starts
+ *   at K * off[d] doubles, off[d] = sum_{e<d} (p_e+1)(p_e+2), and inside it
+ *   the K fields follow one another.  x: K = 3 (Cartesian components of the
+ *   surface, Sec. 2 after eq. spharm_ex); f, u: K = 3; sigma: K = 1.
+ *   Imaginary parts of m = 0 coefficients are ignored (taken as zero).
+ *   Grids: degree P has P+1 Gauss-Legendre latitudes, theta increasing, and
+ *   nlon longitudes phi_k = 2 pi k / nlon, with nlon = 2P+2 (EHD_GRID_PAPER,
+ *   the paper's grid) or 2P (EHD_GRID_2P); node index j*nlon + k.
+ *   Targets: global index = (sum of earlier drops' node counts) + j*nlon + k.
+ *   Outputs: [row][global target], rows = the components of the requested
+ *   kinds in the order S_x S_y S_z D_x D_y D_z S_L L K* (unrequested kinds
+ *   take no row).
+ *
+ * Ownership: pointers named *_d are caller-owned device memory on the
+ * context's device, *_h host memory; both are read (or written) during the
+ * call only and never retained.  Calls are asynchronous on the context's
+ * stream, except where stated; a later call or ehd_sync reports
+ * asynchronous HIP failures.
+ *
+ * Errors: every call returns EHD_OK or an error code; on an argument error
+ * nothing is enqueued and no output is written.  ehd_last_error gives a
+ * message.  A context is used by one host thread at a time.
+ */
+#ifndef EHDBIM_H
+#define EHDBIM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ehd_ctx ehd_ctx;
+
+enum {
+    EHD_OK = 0,
+    EHD_E_ARG = 1,         /* invalid argument (null, range, alignment)   */
+    EHD_E_SHAPE = 2,       /* degrees / sizes not supported                */
+    EHD_E_STATE = 3,       /* call order (e.g. no drops set)               */
+    EHD_E_NOMEM = 4,       /* device allocation failed                     */
+    EHD_E_HIP = 5          /* a HIP runtime call failed                    */
+};
+
+enum {
+    EHD_STOKES_SL = 1,     /* S[f]  : 3 rows */
+    EHD_STOKES_DL = 2,     /* D[u]  : 3 rows */
+    EHD_LAP_SL = 4,        /* S_L[sigma] : 1 row */
+    EHD_LAP_DL = 8,        /* L[sigma]   : 1 row */
+    EHD_LAP_DLADJ = 16,    /* K*[sigma]  : 1 row */
+    EHD_ALL_KINDS = 31
+};
+
+enum {
+    EHD_FAR_FP64 = 0,      /* far-field sums in FP64                         */
+    EHD_FAR_FP32C = 1      /* FP32 arithmetic on drop-centred coordinates,
+                              FP32 accumulation per source tile, compensated
+                              (Kahan) accumulation of the tile sums          */
+};
+
+enum { EHD_GRID_PAPER = 0, EHD_GRID_2P = 1 };
+
+/* Largest drop degree p the singular self-interaction supports (its rotated
+ * expansion of all fields is kept in the 160 KiB of LDS of one CU). */
+#define EHD_MAX_P 48
+/* Largest upsampled grid degree. */
+#define EHD_MAX_Q 160
+
+/* Create a context on HIP device `device`; `stream` is a hipStream_t (NULL:
+ * the null stream), e.g. torch.cuda.current_stream().cuda_stream.
+ * *out receives the context.  Returns EHD_E_HIP if the device is unusable. */
+int ehd_create(ehd_ctx** out, int device, void* stream);
+
+/* Release the context and all its device memory.  NULL is accepted. */
+void ehd_destroy(ehd_ctx* ctx);
+
+/* Message describing the last failed call on ctx (never NULL).  With
+ * ctx == NULL, the message of the last failed ehd_create. */
+const char* ehd_last_error(const ehd_ctx* ctx);
+
+/* Host-only: (nlat, nlon) of the degree-P grid in grid_mode. */
+int ehd_grid_dims(int P, int grid_mode, int* nlat, int* nlon);
+
+/* Define the drops: ndrops >= 1; p_h[d] in [1, EHD_MAX_P]; q_self_h[d] and
+ * q_far_h[d] in [p_h[d], EHD_MAX_Q] (upsampled quadrature degrees of the
+ * singular and of the regular rule, Sec. 2.1); grid_mode as above;
+ * xcoef_d: 3-field packed surface coefficients (copied; the caller may free
+ * them after the call).  Builds the quadrature tables, rotation tables and
+ * the geometry of targets and far-field sources.  Synchronous: returns when
+ * the set-up work on the stream is done. */
+int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
+                  const int* q_far_h, int grid_mode, const double* xcoef_d);
+
+/* Number of target nodes (sum over drops of nlat*nlon) of the current drops. */
+int ehd_num_targets(const ehd_ctx* ctx, long long* ntargets);
+
+/* Evaluate the layer potentials of the requested `kinds` (EHD_* bit mask)
+ * for densities fcoef_d (3 fields; needed for EHD_STOKES_SL), ucoef_d (3
+ * fields, NULL: u = f; needed for EHD_STOKES_DL) and sigcoef_d (1 field;
+ * needed for the Laplace kinds), all in the packed layout of the current
+ * drops.  far_prec: EHD_FAR_FP64 or EHD_FAR_FP32C (the singular
+ * self-interaction is always FP64).
+ * self_out_d: [rows][ntargets] FP64; receives self + far if far_out_d is
+ * NULL, else the self part only, and far_out_d [rows][ntargets] the far
+ * part.  Buffers must not overlap the inputs. */
+int ehd_layer_potentials(ehd_ctx* ctx, const double* fcoef_d, const double* ucoef_d,
+                         const double* sigcoef_d, unsigned kinds, int far_prec,
+                         double* self_out_d, double* far_out_d);
+
+/* Synthesis: values of nfields packed fields (degree p of each drop) at the
+ * drops' own grid nodes, grid_d[field][global target]. */
+int ehd_synthesize(ehd_ctx* ctx, int nfields, const double* coef_d, double* grid_d);
+
+/* Galerkin analysis (Sec. 2, the inner product before eq. BIM_galerkin):
+ * coef_d receives (y, Y_nm) = int_{S^2} y conj(Y_nm) ds for n <= p, m >= 0,
+ * computed with the Gaussian grid quadrature from grid_d[field][global target]. */
+int ehd_analyze(ehd_ctx* ctx, int nfields, const double* grid_d, double* coef_d);
+
+/* Positions x0 and outward unit normals n0 at the target nodes,
+ * x_d[3][ntargets], n_d[3][ntargets]. */
+int ehd_target_geometry(ehd_ctx* ctx, double* x_d, double* n_d);
+
+/* Wait for the context's stream; reports asynchronous HIP failures. */
+int ehd_sync(ehd_ctx* ctx);
+
+/* Host-only: Wigner small-d matrix d^n_{m m'}(beta), m, m' = -n..n, written
+ * row-major to out[(m+n)*(2n+1) + (m'+n)], with
+ * Y_nm(Ry(beta) v) = sum_m' d^n_{m m'}(beta) Y_nm'(v)
+ * (the convention of the rotation that takes a target to the pole,
+ * Sec. 2.1 after eq. mod_weights).  n in [0, 200]. */
+int ehd_wigner_d(int n, double beta, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EHDBIM_H */

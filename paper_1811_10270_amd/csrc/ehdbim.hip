@@ -1,0 +1,1173 @@
+// MI355X (gfx950) layer-potential library: HIP kernels and the C ABI declared
+// in include/ehdbim.h.  Paper: Sorgentone, Tornberg & Vlahovska,
+// arXiv 1811.10270, Sec. 2 (spectral representation, Galerkin form, layer
+// operators) and Sec. 2.1 (regular, singular quadrature).
+//
+// Pipeline of one evaluation (all on the context's stream):
+//   k_synth (densities on the far grids) -> k_src_dens (weighted source
+//   records, FP64 and FP32) -> k_self (rotation + rotated-grid synthesis +
+//   singular reduction, FP64) -> k_far64 / k_far32 (direct sums over the
+//   other drops) -> k_combine (scaling, component selection).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "ehdbim.h"
+#include "tables.h"
+
+using ehd::ncoef;
+using ehd::nlon_of;
+using ehd::tri;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kInv4Pi = 0.25 / kPi;
+constexpr int kThreads = 256;
+constexpr int kTile = 256;        // far-field sources per LDS tile
+constexpr int kRec64 = 14;        // x(3) n(3) w(1) wf(3) wu(3) wsig(1)
+constexpr int kRec32 = 13;        // x-c(3) n(3) wf(3) wu(3) wsig(1)
+
+// ---------------------------------------------------------------------------
+// Device-side descriptors
+// ---------------------------------------------------------------------------
+struct LegTab {                // degree-p expansions on a degree-Q grid
+    const double* P;           // [Q+1][ncoef(p)]   Pbar_n^m(cos theta_i)
+    const double* dP;          // [Q+1][ncoef(p)]   dPbar_n^m/dtheta
+    const double* wq;          // [Q+1] (2 pi / nlon) * w_i^G
+    const double* wsing;       // [Q+1] (2 pi / nlon) * w_i^G * 2 sin(theta_i/2) sum_{n<=Q} P_n
+    const double* rsin;        // [Q+1] 1 / sin theta_i
+    const double* trig;        // [nlon][p+1][2] cos(m phi_l), sin(m phi_l)
+    int p, Q, nlon, pad;
+};
+
+struct WigTab {                // rotation blocks for each latitude of the p-grid
+    const double* A;           // [p+1][wig_block(p)]
+    const double* B;
+    int p, pad;
+};
+
+struct DropInfo {
+    int p, qs, qf, nlon_p, nlon_s, nlon_f;
+    int leg_pp, leg_ps, leg_pf, wig;
+    long long coff;            // per-field coefficient offset (doubles)
+    long long toff;            // first target node
+    long long soff;            // first far-field source slot (tile aligned)
+    long long ns;              // real far-field source nodes
+    double c[3];               // reference centre (mean position)
+};
+
+__device__ __forceinline__ int tri_n(int idx)
+{
+    int n = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+    while ((n + 1) * (n + 2) / 2 <= idx) ++n;
+    while (n * (n + 1) / 2 > idx) --n;
+    return n;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Synthesis of K packed fields on a grid (own p-grid or far q-grid), one
+// block per (drop, latitude).  Legendre sums per m into LDS, then the
+// longitude sums per node.  Optional theta derivative and (1/sin) phi
+// derivative (paper Sec. 2: derivatives from the SH coefficients).
+// out[v * vstride + node], v = f (value), K+f (d/dtheta), 2K+f ((1/s) d/dphi).
+// ---------------------------------------------------------------------------
+template <int K, bool DERIV>
+__global__ __launch_bounds__(kThreads) void k_synth(const DropInfo* __restrict__ drops,
+                                                    const LegTab* __restrict__ legs, int far_grid,
+                                                    const int2* __restrict__ rows,
+                                                    const double* __restrict__ coef,
+                                                    double* __restrict__ out, long long vstride)
+{
+    __shared__ double2 G[K][EHD_MAX_P + 1];
+    __shared__ double2 Gd[DERIV ? K : 1][EHD_MAX_P + 1];
+    const int2 r = rows[blockIdx.x];
+    const DropInfo D = drops[r.x];
+    const LegTab L = legs[far_grid ? D.leg_pf : D.leg_pp];
+    const int p = L.p, i = r.y;
+    const long nc = ncoef(p);
+    const double* cf = coef + (long long)K * D.coff;
+    const double* Prow = L.P + (long long)i * nc;
+    const double* dProw = L.dP + (long long)i * nc;
+    for (int it = threadIdx.x; it < K * (p + 1); it += blockDim.x) {
+        const int f = it / (p + 1), m = it % (p + 1);
+        double ar = 0.0, ai = 0.0, dr = 0.0, di = 0.0;
+        for (int n = m; n <= p; ++n) {
+            const long k = tri(n, m);
+            const double cr = cf[2 * (f * nc + k)], ci = (m == 0) ? 0.0 : cf[2 * (f * nc + k) + 1];
+            const double pv = Prow[k];
+            ar += pv * cr;
+            ai += pv * ci;
+            if (DERIV) {
+                const double dv = dProw[k];
+                dr += dv * cr;
+                di += dv * ci;
+            }
+        }
+        G[f][m] = make_double2(ar, ai);
+        if (DERIV) Gd[f][m] = make_double2(dr, di);
+    }
+    __syncthreads();
+    const long long node0 = (far_grid ? D.soff : D.toff) + (long long)i * L.nlon;
+    const double rs = L.rsin[i];
+    for (int l = threadIdx.x; l < L.nlon; l += blockDim.x) {
+        const double* tr = L.trig + (long long)l * (p + 1) * 2;
+        double v[K], vt[K], vp[K];
+        for (int f = 0; f < K; ++f) {
+            v[f] = G[f][0].x;
+            vt[f] = DERIV ? Gd[f][0].x : 0.0;
+            vp[f] = 0.0;
+        }
+        for (int m = 1; m <= p; ++m) {
+            const double c = tr[2 * m], s = tr[2 * m + 1];
+            for (int f = 0; f < K; ++f) {
+                const double2 g = G[f][m];
+                v[f] += 2.0 * (g.x * c - g.y * s);
+                if (DERIV) {
+                    const double2 gd = Gd[f][m];
+                    vt[f] += 2.0 * (gd.x * c - gd.y * s);
+                    vp[f] -= 2.0 * m * (g.x * s + g.y * c);
+                }
+            }
+        }
+        for (int f = 0; f < K; ++f) {
+            out[f * vstride + node0 + l] = v[f];
+            if (DERIV) {
+                out[(K + f) * vstride + node0 + l] = vt[f];
+                out[(2 * K + f) * vstride + node0 + l] = vp[f] * rs;
+            }
+        }
+    }
+}
+
+// Geometry from synthesized x, x_theta, x_phi/sin: n = x_t x x_ps / |.|,
+// J = |x_t x x_ps|.  For targets: x0[3][T], n0[3][T].  For far sources:
+// FP64 records x, n, w = (2 pi/nlon) w_i J, and the FP32 drop-centred copy.
+__global__ void k_geom_targets(const double* __restrict__ syn, long long vstride, long long T,
+                               double* __restrict__ x0, double* __restrict__ n0)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    double xt[3], xp[3];
+    for (int c = 0; c < 3; ++c) {
+        x0[c * T + t] = syn[c * vstride + t];
+        xt[c] = syn[(3 + c) * vstride + t];
+        xp[c] = syn[(6 + c) * vstride + t];
+    }
+    const double cx = xt[1] * xp[2] - xt[2] * xp[1];
+    const double cy = xt[2] * xp[0] - xt[0] * xp[2];
+    const double cz = xt[0] * xp[1] - xt[1] * xp[0];
+    const double ij = 1.0 / sqrt(cx * cx + cy * cy + cz * cz);
+    n0[t] = cx * ij;
+    n0[T + t] = cy * ij;
+    n0[2 * T + t] = cz * ij;
+}
+
+__global__ void k_geom_sources(const DropInfo* __restrict__ drops, const LegTab* __restrict__ legs,
+                               const int* __restrict__ slot_drop, const double* __restrict__ syn,
+                               long long vstride, long long Spad, double* __restrict__ src64,
+                               float* __restrict__ src32)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= Spad) return;
+    const int d = slot_drop[s];
+    const DropInfo D = drops[d];
+    const long long local = s - D.soff;
+    if (local >= D.ns) {  // padding slot: zero weight at the drop centre
+        for (int c = 0; c < 3; ++c) {
+            src64[c * Spad + s] = D.c[c];
+            src64[(3 + c) * Spad + s] = 0.0;
+            src32[c * Spad + s] = 0.0f;
+            src32[(3 + c) * Spad + s] = 0.0f;
+        }
+        src64[6 * Spad + s] = 0.0;
+        return;
+    }
+    const LegTab L = legs[D.leg_pf];
+    const int i = (int)(local / L.nlon);
+    double x[3], xt[3], xp[3];
+    for (int c = 0; c < 3; ++c) {
+        x[c] = syn[c * vstride + s];
+        xt[c] = syn[(3 + c) * vstride + s];
+        xp[c] = syn[(6 + c) * vstride + s];
+    }
+    const double cx = xt[1] * xp[2] - xt[2] * xp[1];
+    const double cy = xt[2] * xp[0] - xt[0] * xp[2];
+    const double cz = xt[0] * xp[1] - xt[1] * xp[0];
+    const double J = sqrt(cx * cx + cy * cy + cz * cz);
+    const double n[3] = {cx / J, cy / J, cz / J};
+    for (int c = 0; c < 3; ++c) {
+        src64[c * Spad + s] = x[c];
+        src64[(3 + c) * Spad + s] = n[c];
+        src32[c * Spad + s] = (float)(x[c] - D.c[c]);
+        src32[(3 + c) * Spad + s] = (float)n[c];
+    }
+    src64[6 * Spad + s] = L.wq[i] * J;
+}
+
+// Weighted densities of the far-field sources (both precisions).
+__global__ void k_src_dens(const double* __restrict__ synf, const double* __restrict__ synu,
+                           const double* __restrict__ syns, long long vstride, long long Spad,
+                           double* __restrict__ src64, float* __restrict__ src32)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= Spad) return;
+    const double w = src64[6 * Spad + s];
+    for (int c = 0; c < 3; ++c) {
+        const double f = synf ? w * synf[c * vstride + s] : 0.0;
+        const double u = synu ? w * synu[c * vstride + s] : f;
+        src64[(7 + c) * Spad + s] = f;
+        src64[(10 + c) * Spad + s] = u;
+        src32[(6 + c) * Spad + s] = (float)f;
+        src32[(9 + c) * Spad + s] = (float)u;
+    }
+    const double sg = syns ? w * syns[s] : 0.0;
+    src64[13 * Spad + s] = sg;
+    src32[12 * Spad + s] = (float)sg;
+}
+
+// ---------------------------------------------------------------------------
+// Singular self-interaction, one block per target (paper Sec. 2.1,
+// eq. mod_weights and the rotation of the target to the north pole).
+//   1. rotated coefficients c'_{nm'} = sum_m d^n_{m m'}(theta_t) e^{i m phi_t} c_nm
+//      of every field, in the real form of tables.h, into LDS;
+//   2. for each latitude of the rotated degree-q grid: Legendre sums
+//      (values for all fields, theta derivative for x) into LDS, then per
+//      node the longitude sums, n, J, and the kernels with the modified
+//      weights;
+//   3. block reduction.
+// Fields in LDS: x(3) [f(3)] [u(3)] [sigma(1)]; D uses u when present, f
+// otherwise.  Output: raw[comp][T] (already scaled by 1/(4 pi)).
+// ---------------------------------------------------------------------------
+template <bool HF, bool HU, bool HS>
+__global__ __launch_bounds__(kThreads) void k_self(
+    const DropInfo* __restrict__ drops, const LegTab* __restrict__ legs,
+    const WigTab* __restrict__ wigs, const int* __restrict__ order, const int* __restrict__ tdrop,
+    const double* __restrict__ xcoef, const double* __restrict__ fcoef,
+    const double* __restrict__ ucoef, const double* __restrict__ scoef,
+    const double* __restrict__ tx, const double* __restrict__ tnrm, long long T, unsigned kinds,
+    double* __restrict__ raw)
+{
+    constexpr int NF = 3 + (HF ? 3 : 0) + (HU ? 3 : 0) + (HS ? 1 : 0);
+    constexpr int FOFF = 3, UOFF = 3 + (HF ? 3 : 0), SOFF = 3 + (HF ? 3 : 0) + (HU ? 3 : 0);
+    constexpr int NV = NF + 3;  // + theta derivatives of x
+    extern __shared__ double2 lds[];
+    __shared__ double red[kThreads / 64][9];
+
+    const long long tg = order[blockIdx.x];
+    const int d = tdrop[tg];
+    const DropInfo D = drops[d];
+    const int p = D.p;
+    const long nc = ncoef(p);
+    const int node = (int)(tg - D.toff), j = node / D.nlon_p, k = node % D.nlon_p;
+    const LegTab Lq = legs[D.leg_ps];
+    const LegTab Lp = legs[D.leg_pp];
+    const WigTab W = wigs[D.wig];
+    double2* cr = lds;                 // [NF][nc]
+    double2* G = lds + NF * nc;        // [NV][p+1]
+
+    const double* fld[NF];
+    for (int c = 0; c < 3; ++c) fld[c] = xcoef + 3 * D.coff + c * 2 * nc;
+    if (HF) for (int c = 0; c < 3; ++c) fld[FOFF + c] = fcoef + 3 * D.coff + c * 2 * nc;
+    if (HU) for (int c = 0; c < 3; ++c) fld[UOFF + c] = ucoef + 3 * D.coff + c * 2 * nc;
+    if (HS) fld[SOFF] = scoef + D.coff;
+
+    // 1. rotation
+    {
+        const long wb = ehd::wig_block(p);
+        const double* A = W.A + (long long)j * wb;
+        const double* B = W.B + (long long)j * wb;
+        const double* ph = Lp.trig + (long long)k * (p + 1) * 2;
+        for (int it = threadIdx.x; it < nc; it += blockDim.x) {
+            const int n = tri_n(it), mp = it - n * (n + 1) / 2;
+            double are[NF], aim[NF];
+            for (int f = 0; f < NF; ++f) { are[f] = 0.0; aim[f] = 0.0; }
+            const double* An = A + ehd::wig_off(n);
+            const double* Bn = B + ehd::wig_off(n);
+            for (int m = 0; m <= n; ++m) {
+                const double a = An[m * (n + 1) + mp], b = Bn[m * (n + 1) + mp];
+                const double cm = ph[2 * m], sm = ph[2 * m + 1];
+                const long kk = 2 * tri(n, m);
+                for (int f = 0; f < NF; ++f) {
+                    const double c0 = fld[f][kk], c1 = (m == 0) ? 0.0 : fld[f][kk + 1];
+                    are[f] += a * (c0 * cm - c1 * sm);
+                    aim[f] += b * (c0 * sm + c1 * cm);
+                }
+            }
+            for (int f = 0; f < NF; ++f) cr[f * nc + it] = make_double2(are[f], aim[f]);
+        }
+    }
+    __syncthreads();
+
+    double x0[3], n0[3];
+    for (int c = 0; c < 3; ++c) { x0[c] = tx[c * T + tg]; n0[c] = tnrm[c * T + tg]; }
+    double acc[9];
+    for (int c = 0; c < 9; ++c) acc[c] = 0.0;
+    const bool wS = (kinds & EHD_STOKES_SL) && HF;
+    const bool wD = (kinds & EHD_STOKES_DL) && (HF || HU);
+    const bool wSL = (kinds & EHD_LAP_SL) && HS, wL = (kinds & EHD_LAP_DL) && HS;
+    const bool wK = (kinds & EHD_LAP_DLADJ) && HS;
+
+    for (int i = 0; i <= Lq.Q; ++i) {
+        const double* Prow = Lq.P + (long long)i * nc;
+        const double* dProw = Lq.dP + (long long)i * nc;
+        for (int it = threadIdx.x; it < (NF + 3) * (p + 1); it += blockDim.x) {
+            const int v = it / (p + 1), m = it % (p + 1);
+            const bool der = v >= NF;
+            const int f = der ? v - NF : v;
+            const double* tab = der ? dProw : Prow;
+            double ar = 0.0, ai = 0.0;
+            for (int n = m; n <= p; ++n) {
+                const long kk = tri(n, m);
+                const double2 c = cr[f * nc + kk];
+                ar += tab[kk] * c.x;
+                ai += tab[kk] * c.y;
+            }
+            G[v * (p + 1) + m] = make_double2(ar, ai);
+        }
+        __syncthreads();
+        const double wi = Lq.wsing[i], rs = Lq.rsin[i];
+        for (int l = threadIdx.x; l < Lq.nlon; l += blockDim.x) {
+            const double* tr = Lq.trig + (long long)l * (p + 1) * 2;
+            double val[NF], xt[3], xp[3];
+            for (int f = 0; f < NF; ++f) val[f] = G[f * (p + 1)].x;
+            for (int c = 0; c < 3; ++c) { xt[c] = G[(NF + c) * (p + 1)].x; xp[c] = 0.0; }
+            for (int m = 1; m <= p; ++m) {
+                const double cm = 2.0 * tr[2 * m], sm = 2.0 * tr[2 * m + 1];
+                for (int f = 0; f < NF; ++f) {
+                    const double2 g = G[f * (p + 1) + m];
+                    val[f] += g.x * cm - g.y * sm;
+                    if (f < 3) xp[f] -= m * (g.x * sm + g.y * cm);
+                }
+                for (int c = 0; c < 3; ++c) {
+                    const double2 g = G[(NF + c) * (p + 1) + m];
+                    xt[c] += g.x * cm - g.y * sm;
+                }
+            }
+            for (int c = 0; c < 3; ++c) xp[c] *= rs;
+            const double cx = xt[1] * xp[2] - xt[2] * xp[1];
+            const double cy = xt[2] * xp[0] - xt[0] * xp[2];
+            const double cz = xt[0] * xp[1] - xt[1] * xp[0];
+            const double J = sqrt(cx * cx + cy * cy + cz * cz);
+            const double w = wi * J, iJ = 1.0 / J;
+            const double nx = cx * iJ, ny = cy * iJ, nz = cz * iJ;
+            const double hx = x0[0] - val[0], hy = x0[1] - val[1], hz = x0[2] - val[2];
+            const double r2 = hx * hx + hy * hy + hz * hz;
+            const double ir = 1.0 / sqrt(r2), ir2 = ir * ir, ir3 = ir * ir2;
+            const double hn = hx * nx + hy * ny + hz * nz;
+            if constexpr (HF) {
+                if (wS) {
+                    const double f0 = val[FOFF], f1 = val[FOFF + 1], f2 = val[FOFF + 2];
+                    const double hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
+                    acc[0] += w * (f0 * ir + hx * hf);
+                    acc[1] += w * (f1 * ir + hy * hf);
+                    acc[2] += w * (f2 * ir + hz * hf);
+                }
+            }
+            if constexpr (HF || HU) {
+                if (wD) {
+                    constexpr int uo = HU ? UOFF : FOFF;
+                    const double hu = hx * val[uo] + hy * val[uo + 1] + hz * val[uo + 2];
+                    const double t = -6.0 * w * hu * hn * ir3 * ir2;
+                    acc[3] += t * hx;
+                    acc[4] += t * hy;
+                    acc[5] += t * hz;
+                }
+            }
+            if constexpr (HS) {
+                const double sg = w * val[SOFF];
+                if (wSL) acc[6] += sg * ir;
+                if (wL) acc[7] += sg * hn * ir3;
+                if (wK) acc[8] += sg * (hx * n0[0] + hy * n0[1] + hz * n0[2]) * ir3;
+            }
+        }
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int c = 0; c < 9; ++c) {
+        const double s = wave_sum(acc[c]);
+        if (lane == 0) red[wv][c] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        double s = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) s += red[w][threadIdx.x];
+        const unsigned bit = threadIdx.x < 3 ? EHD_STOKES_SL : threadIdx.x < 6 ? EHD_STOKES_DL
+                             : threadIdx.x == 6 ? EHD_LAP_SL : threadIdx.x == 7 ? EHD_LAP_DL
+                                                                                : EHD_LAP_DLADJ;
+        const bool mine = (threadIdx.x < 3 && HF) || (threadIdx.x >= 3 && threadIdx.x < 6 && (HF || HU)) ||
+                          (threadIdx.x >= 6 && HS);
+        if ((kinds & bit) && mine) raw[threadIdx.x * T + tg] = s * kInv4Pi;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Far field, FP64: each thread one target, sources streamed through LDS in
+// tiles of one drop each (drop-aligned padding), tiles split over blockIdx.y.
+// partial[chunk][comp][T] (unscaled).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_far64(const double* __restrict__ tx,
+                                                    const double* __restrict__ tnrm,
+                                                    const int* __restrict__ tdrop, long long T,
+                                                    const double* __restrict__ src, long long Spad,
+                                                    const int* __restrict__ tile_drop, int ntiles,
+                                                    int tiles_per_chunk, unsigned kinds,
+                                                    double* __restrict__ partial)
+{
+    __shared__ double sm[kRec64][kTile];
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = t < T;
+    const long long tt = valid ? t : 0;
+    const double x0 = tx[tt], y0 = tx[T + tt], z0 = tx[2 * T + tt];
+    const double n0x = tnrm[tt], n0y = tnrm[T + tt], n0z = tnrm[2 * T + tt];
+    const int myd = valid ? tdrop[tt] : -1;
+    double acc[9];
+    for (int c = 0; c < 9; ++c) acc[c] = 0.0;
+    const bool wS = kinds & EHD_STOKES_SL, wD = kinds & EHD_STOKES_DL;
+    const bool wSL = kinds & EHD_LAP_SL, wL = kinds & EHD_LAP_DL, wK = kinds & EHD_LAP_DLADJ;
+    const int t0 = blockIdx.y * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
+    for (int tile = t0; tile < t1; ++tile) {
+        const long long s = (long long)tile * kTile + threadIdx.x;
+        for (int r = 0; r < kRec64; ++r) sm[r][threadIdx.x] = src[r * Spad + s];
+        __syncthreads();
+        if (tile_drop[tile] != myd) {
+            for (int q = 0; q < kTile; ++q) {
+                const double hx = x0 - sm[0][q], hy = y0 - sm[1][q], hz = z0 - sm[2][q];
+                const double r2 = hx * hx + hy * hy + hz * hz;
+                const double ir = 1.0 / sqrt(r2), ir2 = ir * ir, ir3 = ir * ir2;
+                const double hn = hx * sm[3][q] + hy * sm[4][q] + hz * sm[5][q];
+                if (wS) {
+                    const double f0 = sm[7][q], f1 = sm[8][q], f2 = sm[9][q];
+                    const double hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
+                    acc[0] += f0 * ir + hx * hf;
+                    acc[1] += f1 * ir + hy * hf;
+                    acc[2] += f2 * ir + hz * hf;
+                }
+                if (wD) {
+                    const double hu = hx * sm[10][q] + hy * sm[11][q] + hz * sm[12][q];
+                    const double tq = -6.0 * hu * hn * ir3 * ir2;
+                    acc[3] += tq * hx;
+                    acc[4] += tq * hy;
+                    acc[5] += tq * hz;
+                }
+                const double sg = sm[13][q];
+                if (wSL) acc[6] += sg * ir;
+                if (wL) acc[7] += sg * hn * ir3;
+                if (wK) acc[8] += sg * (hx * n0x + hy * n0y + hz * n0z) * ir3;
+            }
+        }
+        __syncthreads();
+    }
+    if (valid)
+        for (int c = 0; c < 9; ++c) partial[((long long)blockIdx.y * 9 + c) * T + t] = acc[c];
+}
+
+// Far field, FP32 with drop-centred coordinates: per tile, the target's
+// position relative to the source drop's centre is formed in FP64 and split
+// into an FP32 head and tail; sources are stored relative to the same centre.
+// The tile sum is accumulated in FP32 and added to a compensated (Kahan)
+// FP32 running sum.
+__global__ __launch_bounds__(kThreads) void k_far32(const double* __restrict__ tx,
+                                                    const double* __restrict__ tnrm,
+                                                    const int* __restrict__ tdrop, long long T,
+                                                    const float* __restrict__ src, long long Spad,
+                                                    const int* __restrict__ tile_drop,
+                                                    const double* __restrict__ dcentre, int ntiles,
+                                                    int tiles_per_chunk, unsigned kinds,
+                                                    double* __restrict__ partial)
+{
+    __shared__ float sm[kRec32][kTile];
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = t < T;
+    const long long tt = valid ? t : 0;
+    const double X0 = tx[tt], Y0 = tx[T + tt], Z0 = tx[2 * T + tt];
+    const float n0x = (float)tnrm[tt], n0y = (float)tnrm[T + tt], n0z = (float)tnrm[2 * T + tt];
+    const int myd = valid ? tdrop[tt] : -1;
+    float sum[9], cmp[9];
+    for (int c = 0; c < 9; ++c) { sum[c] = 0.0f; cmp[c] = 0.0f; }
+    const bool wS = kinds & EHD_STOKES_SL, wD = kinds & EHD_STOKES_DL;
+    const bool wSL = kinds & EHD_LAP_SL, wL = kinds & EHD_LAP_DL, wK = kinds & EHD_LAP_DLADJ;
+    const int t0 = blockIdx.y * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
+    for (int tile = t0; tile < t1; ++tile) {
+        const long long s = (long long)tile * kTile + threadIdx.x;
+        for (int r = 0; r < kRec32; ++r) sm[r][threadIdx.x] = src[r * Spad + s];
+        __syncthreads();
+        const int sd = tile_drop[tile];
+        if (sd != myd) {
+            const double dx = X0 - dcentre[3 * sd], dy = Y0 - dcentre[3 * sd + 1],
+                         dz = Z0 - dcentre[3 * sd + 2];
+            const float ax = (float)dx, ay = (float)dy, az = (float)dz;
+            const float bx = (float)(dx - ax), by = (float)(dy - ay), bz = (float)(dz - az);
+            float a[9];
+            for (int c = 0; c < 9; ++c) a[c] = 0.0f;
+            for (int q = 0; q < kTile; ++q) {
+                const float hx = (ax - sm[0][q]) + bx, hy = (ay - sm[1][q]) + by,
+                            hz = (az - sm[2][q]) + bz;
+                const float r2 = hx * hx + hy * hy + hz * hz;
+                const float ir = __frsqrt_rn(r2), ir2 = ir * ir, ir3 = ir * ir2;
+                const float hn = hx * sm[3][q] + hy * sm[4][q] + hz * sm[5][q];
+                if (wS) {
+                    const float f0 = sm[6][q], f1 = sm[7][q], f2 = sm[8][q];
+                    const float hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
+                    a[0] += f0 * ir + hx * hf;
+                    a[1] += f1 * ir + hy * hf;
+                    a[2] += f2 * ir + hz * hf;
+                }
+                if (wD) {
+                    const float hu = hx * sm[9][q] + hy * sm[10][q] + hz * sm[11][q];
+                    const float tq = -6.0f * hu * hn * ir3 * ir2;
+                    a[3] += tq * hx;
+                    a[4] += tq * hy;
+                    a[5] += tq * hz;
+                }
+                const float sg = sm[12][q];
+                if (wSL) a[6] += sg * ir;
+                if (wL) a[7] += sg * hn * ir3;
+                if (wK) a[8] += sg * (hx * n0x + hy * n0y + hz * n0z) * ir3;
+            }
+            for (int c = 0; c < 9; ++c) {  // Kahan
+                const float y = a[c] - cmp[c];
+                const float tsum = sum[c] + y;
+                cmp[c] = (tsum - sum[c]) - y;
+                sum[c] = tsum;
+            }
+        }
+        __syncthreads();
+    }
+    if (valid)
+        for (int c = 0; c < 9; ++c)
+            partial[((long long)blockIdx.y * 9 + c) * T + t] = (double)sum[c] - (double)cmp[c];
+}
+
+// Outputs: rows of the requested kinds, scaled far sums added to (or written
+// beside) the self part.
+struct RowMap {
+    int n;
+    int comp[9];
+};
+
+__global__ void k_combine(const double* __restrict__ raw_self, const double* __restrict__ partial,
+                          int nchunk, long long T, RowMap rows, double* __restrict__ self_out,
+                          double* __restrict__ far_out)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    for (int r = 0; r < rows.n; ++r) {
+        const int c = rows.comp[r];
+        double f = 0.0;
+        for (int ch = 0; ch < nchunk; ++ch) f += partial[((long long)ch * 9 + c) * T + t];
+        f *= kInv4Pi;
+        const double s = raw_self[(long long)c * T + t];
+        if (far_out) {
+            self_out[(long long)r * T + t] = s;
+            far_out[(long long)r * T + t] = f;
+        } else {
+            self_out[(long long)r * T + t] = s + f;
+        }
+    }
+}
+
+// Galerkin analysis: one block per (drop, n(n+1)/2+m) coefficient group,
+// (y, Y_nm) = sum_j sum_k (2pi/nlon) w_j y_jk Pbar_n^m(t_j) e^{-i m phi_k}.
+__global__ void k_analyze(const DropInfo* __restrict__ drops, const LegTab* __restrict__ legs,
+                          const int2* __restrict__ items, int nf, const double* __restrict__ grid,
+                          long long T, double* __restrict__ coef)
+{
+    const int2 it = items[blockIdx.x];
+    const DropInfo D = drops[it.x];
+    const LegTab L = legs[D.leg_pp];
+    const int p = L.p, kk = it.y;
+    const int n = tri_n(kk), m = kk - n * (n + 1) / 2;
+    const long nc = ncoef(p);
+    const int npts = (L.Q + 1) * L.nlon;
+    __shared__ double rr[kThreads / 64][2];
+    for (int f = 0; f < nf; ++f) {
+        double ar = 0.0, ai = 0.0;
+        for (int q = threadIdx.x; q < npts; q += blockDim.x) {
+            const int j = q / L.nlon, l = q % L.nlon;
+            const double y = grid[(long long)f * T + D.toff + q] * L.wq[j] * L.P[(long long)j * nc + kk];
+            const double* tr = L.trig + ((long long)l * (p + 1) + m) * 2;
+            ar += y * tr[0];
+            ai -= y * tr[1];
+        }
+        ar = wave_sum(ar);
+        ai = wave_sum(ai);
+        if ((threadIdx.x & 63) == 0) { rr[threadIdx.x >> 6][0] = ar; rr[threadIdx.x >> 6][1] = ai; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double sr = 0.0, si = 0.0;
+            for (int w = 0; w < (int)(blockDim.x / 64); ++w) { sr += rr[w][0]; si += rr[w][1]; }
+            double* cb = coef + (long long)nf * D.coff + (long long)f * 2 * nc;
+            cb[2 * kk] = sr;
+            cb[2 * kk + 1] = (m == 0) ? 0.0 : si;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+struct ehd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int max_lds = 65536;
+
+    // drops
+    int nd = 0, grid_mode = 0;
+    std::vector<int> p, qs, qf;
+    std::vector<DropInfo> info;
+    long long T = 0, Spad = 0, ncoef_total = 0;  // ncoef_total: doubles per field
+    int ntiles = 0;
+    std::vector<int> self_order_h;
+
+    // device buffers
+    std::vector<void*> allocs;
+    DropInfo* d_info = nullptr;
+    LegTab* d_legs = nullptr;
+    WigTab* d_wigs = nullptr;
+    double* d_x = nullptr;           // own copy of x coefficients
+    double* d_tx = nullptr;          // [3][T]
+    double* d_tn = nullptr;          // [3][T]
+    int* d_tdrop = nullptr;          // [T]
+    int* d_order = nullptr;          // [T] self work order
+    int* d_slot_drop = nullptr;      // [Spad]
+    int* d_tile_drop = nullptr;      // [ntiles]
+    double* d_centre = nullptr;      // [3*nd]
+    double* d_src64 = nullptr;       // [kRec64][Spad]
+    float* d_src32 = nullptr;        // [kRec32][Spad]
+    double* d_syn = nullptr;         // synthesis scratch [9][max(T,Spad)]
+    long long syn_stride = 0;
+    double* d_raw = nullptr;         // [9][T]
+    double* d_partial = nullptr;     // [nchunk][9][T]
+    int nchunk = 1;
+    int2* d_rows_p = nullptr;        // rows of own grids
+    int2* d_rows_f = nullptr;        // rows of far grids
+    int nrows_p = 0, nrows_f = 0;
+    int2* d_an_items = nullptr;
+    int n_an_items = 0;
+    DropInfo* d_info_tmp = nullptr;  // per-field views for ehd_synthesize
+
+    void free_all()
+    {
+        for (void* a : allocs) (void)hipFree(a);
+        allocs.clear();
+        d_info = nullptr;
+        d_legs = nullptr;
+        d_wigs = nullptr;
+        nd = 0;
+    }
+};
+
+static std::string g_create_err = "no error";
+
+#define EHD_FAIL(ctx, code, ...)                                              \
+    do {                                                                      \
+        char _b[512];                                                         \
+        snprintf(_b, sizeof(_b), __VA_ARGS__);                                \
+        (ctx)->err = _b;                                                      \
+        return (code);                                                        \
+    } while (0)
+
+#define EHD_HIP(ctx, call)                                                                   \
+    do {                                                                                     \
+        hipError_t _e = (call);                                                              \
+        if (_e != hipSuccess)                                                                \
+            EHD_FAIL(ctx, EHD_E_HIP, "%s failed: %s", #call, hipGetErrorString(_e));         \
+    } while (0)
+
+template <typename T>
+static int dev_alloc(ehd_ctx* ctx, T** out, size_t count)
+{
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&p, sizeof(T) * count);
+    if (e != hipSuccess) {
+        ctx->err = std::string("hipMalloc failed: ") + hipGetErrorString(e);
+        return EHD_E_NOMEM;
+    }
+    ctx->allocs.push_back(p);
+    *out = (T*)p;
+    return EHD_OK;
+}
+
+template <typename T>
+static int upload(ehd_ctx* ctx, T** out, const std::vector<T>& h)
+{
+    int rc = dev_alloc(ctx, out, h.size());
+    if (rc) return rc;
+    if (!h.empty()) {
+        hipError_t e = hipMemcpyAsync(*out, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice,
+                                      ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) {
+            ctx->err = std::string("upload failed: ") + hipGetErrorString(e);
+            return EHD_E_HIP;
+        }
+    }
+    return EHD_OK;
+}
+
+static size_t self_lds_bytes(int p, int nf) { return (size_t)(nf * ncoef(p) + (nf + 3) * (p + 1)) * 16; }
+
+template <bool HF, bool HU, bool HS>
+static int launch_self(ehd_ctx* ctx, const double* f, const double* u, const double* s, unsigned kinds)
+{
+    constexpr int NF = 3 + (HF ? 3 : 0) + (HU ? 3 : 0) + (HS ? 1 : 0);
+    int pmax = 1;
+    for (int pp : ctx->p) pmax = std::max(pmax, pp);
+    const size_t lds = self_lds_bytes(pmax, NF);
+    if (lds > (size_t)ctx->max_lds)
+        EHD_FAIL(ctx, EHD_E_SHAPE, "self-interaction needs %zu bytes of LDS (limit %d)", lds, ctx->max_lds);
+    if (lds > 65536)
+        EHD_HIP(ctx, hipFuncSetAttribute((const void*)k_self<HF, HU, HS>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((k_self<HF, HU, HS>), dim3((unsigned)ctx->T), dim3(kThreads), lds, ctx->stream,
+                       ctx->d_info, ctx->d_legs, ctx->d_wigs, ctx->d_order, ctx->d_tdrop, ctx->d_x, f,
+                       u, s, ctx->d_tx, ctx->d_tn, ctx->T, kinds, ctx->d_raw);
+    EHD_HIP(ctx, hipGetLastError());
+    return EHD_OK;
+}
+
+extern "C" {
+
+int ehd_create(ehd_ctx** out, int device, void* stream)
+{
+    if (!out) { g_create_err = "out is NULL"; return EHD_E_ARG; }
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        g_create_err = "no HIP device";
+        return EHD_E_HIP;
+    }
+    if (device < 0 || device >= ndev) { g_create_err = "device index out of range"; return EHD_E_ARG; }
+    if (hipSetDevice(device) != hipSuccess) { g_create_err = "hipSetDevice failed"; return EHD_E_HIP; }
+    ehd_ctx* c = new ehd_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess &&
+        lds > 0)
+        c->max_lds = lds;
+    *out = c;
+    return EHD_OK;
+}
+
+void ehd_destroy(ehd_ctx* ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    ctx->free_all();
+    delete ctx;
+}
+
+const char* ehd_last_error(const ehd_ctx* ctx)
+{
+    return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+int ehd_grid_dims(int P, int grid_mode, int* nlat, int* nlon)
+{
+    if (P < 1 || P > EHD_MAX_Q || (grid_mode != 0 && grid_mode != 1) || !nlat || !nlon) return EHD_E_ARG;
+    *nlat = P + 1;
+    *nlon = nlon_of(P, grid_mode);
+    return EHD_OK;
+}
+
+int ehd_wigner_d(int n, double beta, double* out)
+{
+    if (n < 0 || n > 200 || !out) return EHD_E_ARG;
+    std::vector<double> d;
+    ehd::wigner_d(n, beta, d);
+    std::memcpy(out, d.data(), sizeof(double) * d.size());
+    return EHD_OK;
+}
+
+int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h, const int* q_far_h,
+                  int grid_mode, const double* xcoef_d)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (ndrops < 1 || !p_h || !q_self_h || !q_far_h || !xcoef_d)
+        EHD_FAIL(ctx, EHD_E_ARG, "ndrops must be >= 1 and all pointers non-NULL");
+    if (grid_mode != 0 && grid_mode != 1) EHD_FAIL(ctx, EHD_E_ARG, "grid_mode must be 0 or 1");
+    if (((uintptr_t)xcoef_d) % 8) EHD_FAIL(ctx, EHD_E_ARG, "xcoef_d must be 8-byte aligned");
+    for (int d = 0; d < ndrops; ++d) {
+        if (p_h[d] < 1 || p_h[d] > EHD_MAX_P)
+            EHD_FAIL(ctx, EHD_E_SHAPE, "drop %d: p = %d outside [1, %d]", d, p_h[d], EHD_MAX_P);
+        if (q_self_h[d] < p_h[d] || q_self_h[d] > EHD_MAX_Q || q_far_h[d] < p_h[d] || q_far_h[d] > EHD_MAX_Q)
+            EHD_FAIL(ctx, EHD_E_SHAPE, "drop %d: q_self = %d, q_far = %d must lie in [p, %d]", d,
+                     q_self_h[d], q_far_h[d], EHD_MAX_Q);
+        if (grid_mode == 1 && p_h[d] < 2)
+            EHD_FAIL(ctx, EHD_E_SHAPE, "grid_mode 1 needs p >= 2");
+    }
+    EHD_HIP(ctx, hipSetDevice(ctx->device));
+    if (ctx->stream) EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->free_all();
+    int rc;
+    ctx->nd = ndrops;
+    ctx->grid_mode = grid_mode;
+    ctx->p.assign(p_h, p_h + ndrops);
+    ctx->qs.assign(q_self_h, q_self_h + ndrops);
+    ctx->qf.assign(q_far_h, q_far_h + ndrops);
+
+    // --- quadrature tables per distinct (p, Q) pair, rotation tables per p
+    std::map<std::pair<int, int>, int> legid;
+    std::map<int, int> wigid;
+    std::vector<LegTab> legs;
+    std::vector<WigTab> wigs;
+    auto want_leg = [&](int pp, int Q, bool singular) -> int {
+        auto key = std::make_pair(pp, Q * 2 + (singular ? 1 : 0));
+        auto it = legid.find(key);
+        if (it != legid.end()) return it->second;
+        std::vector<double> t, w, P, dP, msum;
+        ehd::gauss_legendre(Q + 1, t, w);
+        ehd::legendre_tables(pp, t, P, dP);
+        const int nl = nlon_of(Q, grid_mode);
+        std::vector<double> wq(Q + 1), ws(Q + 1), rs(Q + 1), trig((size_t)nl * (pp + 1) * 2);
+        ehd::singular_factor(Q, t, msum);
+        for (int i = 0; i <= Q; ++i) {
+            wq[i] = 2.0 * kPi / nl * w[i];
+            ws[i] = wq[i] * msum[i];
+            rs[i] = 1.0 / std::sqrt((1.0 - t[i]) * (1.0 + t[i]));
+        }
+        for (int l = 0; l < nl; ++l)
+            for (int m = 0; m <= pp; ++m) {
+                const double a = 2.0 * kPi * (double)((long)m * l % nl) / nl;
+                trig[((size_t)l * (pp + 1) + m) * 2] = std::cos(a);
+                trig[((size_t)l * (pp + 1) + m) * 2 + 1] = std::sin(a);
+            }
+        LegTab L{};
+        double* dptr;
+        if (upload(ctx, &dptr, P)) return -1;
+        L.P = dptr;
+        if (upload(ctx, &dptr, dP)) return -1;
+        L.dP = dptr;
+        if (upload(ctx, &dptr, wq)) return -1;
+        L.wq = dptr;
+        if (upload(ctx, &dptr, ws)) return -1;
+        L.wsing = dptr;
+        if (upload(ctx, &dptr, rs)) return -1;
+        L.rsin = dptr;
+        if (upload(ctx, &dptr, trig)) return -1;
+        L.trig = dptr;
+        L.p = pp;
+        L.Q = Q;
+        L.nlon = nl;
+        legs.push_back(L);
+        legid[key] = (int)legs.size() - 1;
+        return (int)legs.size() - 1;
+    };
+    auto want_wig = [&](int pp) -> int {
+        auto it = wigid.find(pp);
+        if (it != wigid.end()) return it->second;
+        std::vector<double> t, w;
+        ehd::gauss_legendre(pp + 1, t, w);
+        const long wb = ehd::wig_block(pp);
+        std::vector<double> A((size_t)(pp + 1) * wb), B((size_t)(pp + 1) * wb);
+        for (int j = 0; j <= pp; ++j) {
+            const double beta = std::atan2(std::sqrt((1.0 - t[j]) * (1.0 + t[j])), t[j]);
+            ehd::rotation_blocks(pp, beta, A.data() + (size_t)j * wb, B.data() + (size_t)j * wb);
+        }
+        WigTab Wt{};
+        double* dptr;
+        if (upload(ctx, &dptr, A)) return -1;
+        Wt.A = dptr;
+        if (upload(ctx, &dptr, B)) return -1;
+        Wt.B = dptr;
+        Wt.p = pp;
+        wigs.push_back(Wt);
+        wigid[pp] = (int)wigs.size() - 1;
+        return (int)wigs.size() - 1;
+    };
+
+    // --- per-drop layout
+    ctx->info.assign(ndrops, DropInfo{});
+    long long coff = 0, toff = 0, soff = 0;
+    for (int d = 0; d < ndrops; ++d) {
+        DropInfo& D = ctx->info[d];
+        D.p = p_h[d];
+        D.qs = q_self_h[d];
+        D.qf = q_far_h[d];
+        D.nlon_p = nlon_of(D.p, grid_mode);
+        D.nlon_s = nlon_of(D.qs, grid_mode);
+        D.nlon_f = nlon_of(D.qf, grid_mode);
+        D.leg_pp = want_leg(D.p, D.p, false);
+        D.leg_ps = want_leg(D.p, D.qs, true);
+        D.leg_pf = want_leg(D.p, D.qf, false);
+        D.wig = want_wig(D.p);
+        if (D.leg_pp < 0 || D.leg_ps < 0 || D.leg_pf < 0 || D.wig < 0) return EHD_E_NOMEM;
+        D.coff = coff;
+        D.toff = toff;
+        D.soff = soff;
+        D.ns = (long long)(D.qf + 1) * D.nlon_f;
+        coff += (long long)(D.p + 1) * (D.p + 2);
+        toff += (long long)(D.p + 1) * D.nlon_p;
+        soff += (D.ns + kTile - 1) / kTile * kTile;
+    }
+    ctx->ncoef_total = coff;
+    ctx->T = toff;
+    ctx->Spad = soff;
+    ctx->ntiles = (int)(soff / kTile);
+    if ((rc = upload(ctx, &ctx->d_legs, legs))) return rc;
+    if ((rc = upload(ctx, &ctx->d_wigs, wigs))) return rc;
+
+    // own copy of x, centres from the degree-0 coefficients
+    if ((rc = dev_alloc(ctx, &ctx->d_x, 3 * coff))) return rc;
+    EHD_HIP(ctx, hipMemcpyAsync(ctx->d_x, xcoef_d, sizeof(double) * 3 * coff, hipMemcpyDeviceToDevice,
+                                ctx->stream));
+    {
+        std::vector<double> c00(3 * ndrops);
+        for (int d = 0; d < ndrops; ++d)
+            for (int c = 0; c < 3; ++c)
+                EHD_HIP(ctx, hipMemcpyAsync(&c00[3 * d + c],
+                                            xcoef_d + 3 * ctx->info[d].coff +
+                                                (long long)c * (ctx->info[d].p + 1) * (ctx->info[d].p + 2),
+                                            sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        for (int d = 0; d < ndrops; ++d)
+            for (int c = 0; c < 3; ++c) ctx->info[d].c[c] = c00[3 * d + c] / std::sqrt(4.0 * kPi);
+        std::vector<double> cen(3 * ndrops);
+        for (int d = 0; d < ndrops; ++d)
+            for (int c = 0; c < 3; ++c) cen[3 * d + c] = ctx->info[d].c[c];
+        if ((rc = upload(ctx, &ctx->d_centre, cen))) return rc;
+    }
+    if ((rc = upload(ctx, &ctx->d_info, ctx->info))) return rc;
+
+    // index tables
+    std::vector<int> tdrop(ctx->T), slot_drop(ctx->Spad), tile_drop(ctx->ntiles);
+    std::vector<int2> rows_p, rows_f, an_items;
+    for (int d = 0; d < ndrops; ++d) {
+        const DropInfo& D = ctx->info[d];
+        for (long long t = 0; t < (long long)(D.p + 1) * D.nlon_p; ++t) tdrop[D.toff + t] = d;
+        const long long padded = (D.ns + kTile - 1) / kTile * kTile;
+        for (long long s = 0; s < padded; ++s) slot_drop[D.soff + s] = d;
+        for (long long tl = 0; tl < padded / kTile; ++tl) tile_drop[D.soff / kTile + tl] = d;
+        for (int i = 0; i <= D.p; ++i) rows_p.push_back(make_int2(d, i));
+        for (int i = 0; i <= D.qf; ++i) rows_f.push_back(make_int2(d, i));
+        for (int k = 0; k < ncoef(D.p); ++k) an_items.push_back(make_int2(d, k));
+    }
+    // self work order: most expensive targets first
+    std::vector<int> dorder(ndrops);
+    for (int d = 0; d < ndrops; ++d) dorder[d] = d;
+    std::stable_sort(dorder.begin(), dorder.end(), [&](int a, int b) {
+        const DropInfo &A = ctx->info[a], &B = ctx->info[b];
+        const double ca = (double)(A.qs + 1) * A.nlon_s * (A.p + 1), cb = (double)(B.qs + 1) * B.nlon_s * (B.p + 1);
+        return ca > cb;
+    });
+    ctx->self_order_h.clear();
+    for (int d : dorder) {
+        const DropInfo& D = ctx->info[d];
+        for (long long t = 0; t < (long long)(D.p + 1) * D.nlon_p; ++t) ctx->self_order_h.push_back((int)(D.toff + t));
+    }
+    if ((rc = upload(ctx, &ctx->d_tdrop, tdrop))) return rc;
+    if ((rc = upload(ctx, &ctx->d_slot_drop, slot_drop))) return rc;
+    if ((rc = upload(ctx, &ctx->d_tile_drop, tile_drop))) return rc;
+    if ((rc = upload(ctx, &ctx->d_rows_p, rows_p))) return rc;
+    if ((rc = upload(ctx, &ctx->d_rows_f, rows_f))) return rc;
+    if ((rc = upload(ctx, &ctx->d_an_items, an_items))) return rc;
+    if ((rc = upload(ctx, &ctx->d_order, ctx->self_order_h))) return rc;
+    ctx->nrows_p = (int)rows_p.size();
+    ctx->nrows_f = (int)rows_f.size();
+    ctx->n_an_items = (int)an_items.size();
+
+    // work buffers
+    const long long T = ctx->T, S = ctx->Spad;
+    ctx->syn_stride = std::max(T, S);
+    if ((rc = dev_alloc(ctx, &ctx->d_syn, 16 * ctx->syn_stride))) return rc;
+    if ((rc = dev_alloc(ctx, &ctx->d_tx, 3 * T))) return rc;
+    if ((rc = dev_alloc(ctx, &ctx->d_tn, 3 * T))) return rc;
+    if ((rc = dev_alloc(ctx, &ctx->d_src64, (size_t)kRec64 * S))) return rc;
+    if ((rc = dev_alloc(ctx, &ctx->d_src32, (size_t)kRec32 * S))) return rc;
+    if ((rc = dev_alloc(ctx, &ctx->d_raw, 9 * T))) return rc;
+    const long long tblocks = (T + kThreads - 1) / kThreads;
+    ctx->nchunk = (int)std::min<long long>(std::max<long long>(1, (2048 + tblocks - 1) / tblocks), ctx->ntiles);
+    if ((rc = dev_alloc(ctx, &ctx->d_partial, (size_t)ctx->nchunk * 9 * T))) return rc;
+    if ((rc = dev_alloc(ctx, &ctx->d_info_tmp, ndrops))) return rc;
+
+    // --- target geometry (own grids) and far-source geometry
+    const long long vs = ctx->syn_stride;
+    hipLaunchKernelGGL((k_synth<3, true>), dim3(ctx->nrows_p), dim3(kThreads), 0, ctx->stream,
+                       ctx->d_info, ctx->d_legs, 0, ctx->d_rows_p, ctx->d_x, ctx->d_syn, vs);
+    hipLaunchKernelGGL(k_geom_targets, dim3((T + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_syn, vs, T,
+                       ctx->d_tx, ctx->d_tn);
+    hipLaunchKernelGGL((k_synth<3, true>), dim3(ctx->nrows_f), dim3(kThreads), 0, ctx->stream,
+                       ctx->d_info, ctx->d_legs, 1, ctx->d_rows_f, ctx->d_x, ctx->d_syn, vs);
+    hipLaunchKernelGGL(k_geom_sources, dim3((S + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_info,
+                       ctx->d_legs, ctx->d_slot_drop, ctx->d_syn, vs, S, ctx->d_src64, ctx->d_src32);
+    EHD_HIP(ctx, hipGetLastError());
+    EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return EHD_OK;
+}
+
+int ehd_num_targets(const ehd_ctx* ctx, long long* ntargets)
+{
+    if (!ctx || !ntargets) return EHD_E_ARG;
+    *ntargets = ctx->T;
+    return ctx->nd ? EHD_OK : EHD_E_STATE;
+}
+
+int ehd_layer_potentials(ehd_ctx* ctx, const double* fcoef_d, const double* ucoef_d,
+                         const double* sigcoef_d, unsigned kinds, int far_prec, double* self_out_d,
+                         double* far_out_d)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ctx->nd) EHD_FAIL(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if (kinds == 0 || (kinds & ~(unsigned)EHD_ALL_KINDS)) EHD_FAIL(ctx, EHD_E_ARG, "invalid kinds mask 0x%x", kinds);
+    if (far_prec != EHD_FAR_FP64 && far_prec != EHD_FAR_FP32C) EHD_FAIL(ctx, EHD_E_ARG, "invalid far_prec %d", far_prec);
+    if (!self_out_d) EHD_FAIL(ctx, EHD_E_ARG, "self_out_d is NULL");
+    const bool needS = kinds & EHD_STOKES_SL, needD = kinds & EHD_STOKES_DL;
+    const bool needLap = kinds & (EHD_LAP_SL | EHD_LAP_DL | EHD_LAP_DLADJ);
+    const bool needF = needS || (needD && !ucoef_d);
+    const bool needU = needD && ucoef_d;
+    if (needF && !fcoef_d) EHD_FAIL(ctx, EHD_E_ARG, "fcoef_d is needed for the requested kinds");
+    if (needLap && !sigcoef_d) EHD_FAIL(ctx, EHD_E_ARG, "sigcoef_d is needed for the Laplace kinds");
+    for (const void* q : {(const void*)fcoef_d, (const void*)ucoef_d, (const void*)sigcoef_d,
+                          (const void*)self_out_d, (const void*)far_out_d})
+        if (((uintptr_t)q) % 8) EHD_FAIL(ctx, EHD_E_ARG, "device pointers must be 8-byte aligned");
+    EHD_HIP(ctx, hipSetDevice(ctx->device));
+
+    RowMap rows{};
+    for (int c = 0; c < 9; ++c) {
+        const unsigned bit = c < 3 ? EHD_STOKES_SL : c < 6 ? EHD_STOKES_DL : c == 6 ? EHD_LAP_SL
+                             : c == 7 ? EHD_LAP_DL : EHD_LAP_DLADJ;
+        if (kinds & bit) rows.comp[rows.n++] = c;
+    }
+
+    const long long T = ctx->T, S = ctx->Spad, vs = ctx->syn_stride;
+    // 1. densities on the far grids -> weighted source records
+    double* synf = needF ? ctx->d_syn : nullptr;
+    double* synu = needU ? ctx->d_syn + 3 * vs : nullptr;
+    double* syns = needLap ? ctx->d_syn + 6 * vs : nullptr;
+    if (needF)
+        hipLaunchKernelGGL((k_synth<3, false>), dim3(ctx->nrows_f), dim3(kThreads), 0, ctx->stream, ctx->d_info,
+                           ctx->d_legs, 1, ctx->d_rows_f, fcoef_d, synf, vs);
+    if (needU)
+        hipLaunchKernelGGL((k_synth<3, false>), dim3(ctx->nrows_f), dim3(kThreads), 0, ctx->stream, ctx->d_info,
+                           ctx->d_legs, 1, ctx->d_rows_f, ucoef_d, synu, vs);
+    if (needLap)
+        hipLaunchKernelGGL((k_synth<1, false>), dim3(ctx->nrows_f), dim3(kThreads), 0, ctx->stream, ctx->d_info,
+                           ctx->d_legs, 1, ctx->d_rows_f, sigcoef_d, syns, vs);
+    hipLaunchKernelGGL(k_src_dens, dim3((S + 255) / 256), dim3(256), 0, ctx->stream, synf, synu, syns, vs, S,
+                       ctx->d_src64, ctx->d_src32);
+    EHD_HIP(ctx, hipGetLastError());
+
+    // 2. singular self-interaction (one or two passes depending on LDS)
+    int pmax = 1;
+    for (int pp : ctx->p) pmax = std::max(pmax, pp);
+    const int nf_all = 3 + (needF ? 3 : 0) + (needU ? 3 : 0) + (needLap ? 1 : 0);
+    int rc = EHD_OK;
+    if (self_lds_bytes(pmax, nf_all) <= (size_t)ctx->max_lds || !needU || !(needF || needLap)) {
+        if (needF && needU && needLap) rc = launch_self<true, true, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
+        else if (needF && needU) rc = launch_self<true, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
+        else if (needF && needLap) rc = launch_self<true, false, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
+        else if (needU && needLap) rc = launch_self<false, true, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
+        else if (needF) rc = launch_self<true, false, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
+        else if (needU) rc = launch_self<false, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
+        else rc = launch_self<false, false, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
+    } else {
+        // u separate and everything does not fit: D in its own pass
+        const unsigned k1 = kinds & ~(unsigned)EHD_STOKES_DL;
+        if (needF && needLap) rc = launch_self<true, false, true>(ctx, fcoef_d, nullptr, sigcoef_d, k1);
+        else if (needF) rc = launch_self<true, false, false>(ctx, fcoef_d, nullptr, sigcoef_d, k1);
+        else rc = launch_self<false, false, true>(ctx, fcoef_d, nullptr, sigcoef_d, k1);
+        if (rc == EHD_OK) rc = launch_self<false, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, EHD_STOKES_DL);
+    }
+    if (rc) return rc;
+
+    // 3. far field
+    const long long tblocks = (T + kThreads - 1) / kThreads;
+    const int tpc = (ctx->ntiles + ctx->nchunk - 1) / ctx->nchunk;
+    dim3 grid((unsigned)tblocks, (unsigned)ctx->nchunk);
+    if (far_prec == EHD_FAR_FP64)
+        hipLaunchKernelGGL(k_far64, grid, dim3(kThreads), 0, ctx->stream, ctx->d_tx, ctx->d_tn, ctx->d_tdrop, T,
+                           ctx->d_src64, S, ctx->d_tile_drop, ctx->ntiles, tpc, kinds, ctx->d_partial);
+    else
+        hipLaunchKernelGGL(k_far32, grid, dim3(kThreads), 0, ctx->stream, ctx->d_tx, ctx->d_tn, ctx->d_tdrop, T,
+                           ctx->d_src32, S, ctx->d_tile_drop, ctx->d_centre, ctx->ntiles, tpc, kinds,
+                           ctx->d_partial);
+    EHD_HIP(ctx, hipGetLastError());
+
+    // 4. outputs
+    hipLaunchKernelGGL(k_combine, dim3((T + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_raw, ctx->d_partial,
+                       ctx->nchunk, T, rows, self_out_d, far_out_d);
+    EHD_HIP(ctx, hipGetLastError());
+    return EHD_OK;
+}
+
+int ehd_synthesize(ehd_ctx* ctx, int nfields, const double* coef_d, double* grid_d)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ctx->nd) EHD_FAIL(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if (nfields < 1 || !coef_d || !grid_d) EHD_FAIL(ctx, EHD_E_ARG, "nfields >= 1 and non-NULL pointers required");
+    EHD_HIP(ctx, hipSetDevice(ctx->device));
+    // One field at a time through the K = 1 kernel on per-field views: field
+    // f of drop d starts at nfields*coff[d] + f*(p+1)(p+2) doubles, so each
+    // launch reads a descriptor copy whose offsets point there.  Synchronous
+    // (the host descriptor copy is reused per field).
+    std::vector<DropInfo> shifted(ctx->info);
+    DropInfo* d_sh = ctx->d_info_tmp;
+    for (int f = 0; f < nfields; ++f) {
+        for (int d = 0; d < ctx->nd; ++d)
+            shifted[d].coff = (long long)nfields * ctx->info[d].coff + (long long)f * (ctx->info[d].p + 1) * (ctx->info[d].p + 2);
+        EHD_HIP(ctx, hipMemcpyAsync(d_sh, shifted.data(), sizeof(DropInfo) * shifted.size(),
+                                    hipMemcpyHostToDevice, ctx->stream));
+        hipLaunchKernelGGL((k_synth<1, false>), dim3(ctx->nrows_p), dim3(kThreads), 0, ctx->stream, d_sh,
+                           ctx->d_legs, 0, ctx->d_rows_p, coef_d, grid_d + (long long)f * ctx->T, ctx->T);
+        EHD_HIP(ctx, hipGetLastError());
+        EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return EHD_OK;
+}
+
+int ehd_analyze(ehd_ctx* ctx, int nfields, const double* grid_d, double* coef_d)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ctx->nd) EHD_FAIL(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if (nfields < 1 || !coef_d || !grid_d) EHD_FAIL(ctx, EHD_E_ARG, "nfields >= 1 and non-NULL pointers required");
+    EHD_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_analyze, dim3(ctx->n_an_items), dim3(kThreads), 0, ctx->stream, ctx->d_info, ctx->d_legs,
+                       ctx->d_an_items, nfields, grid_d, ctx->T, coef_d);
+    EHD_HIP(ctx, hipGetLastError());
+    return EHD_OK;
+}
+
+int ehd_target_geometry(ehd_ctx* ctx, double* x_d, double* n_d)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ctx->nd) EHD_FAIL(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if (!x_d || !n_d) EHD_FAIL(ctx, EHD_E_ARG, "x_d and n_d must be non-NULL");
+    EHD_HIP(ctx, hipSetDevice(ctx->device));
+    EHD_HIP(ctx, hipMemcpyAsync(x_d, ctx->d_tx, sizeof(double) * 3 * ctx->T, hipMemcpyDeviceToDevice, ctx->stream));
+    EHD_HIP(ctx, hipMemcpyAsync(n_d, ctx->d_tn, sizeof(double) * 3 * ctx->T, hipMemcpyDeviceToDevice, ctx->stream));
+    return EHD_OK;
+}
+
+int ehd_sync(ehd_ctx* ctx)
+{
+    if (!ctx) return EHD_E_ARG;
+    EHD_HIP(ctx, hipSetDevice(ctx->device));
+    if (ctx->stream) EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    else EHD_HIP(ctx, hipDeviceSynchronize());
+    EHD_HIP(ctx, hipGetLastError());
+    return EHD_OK;
+}
+
+}  // extern "C"

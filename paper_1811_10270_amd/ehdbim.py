@@ -1,0 +1,186 @@
+"""Thin ctypes binding of ``libehdbim.so`` (declared in include/ehdbim.h).
+
+Argument marshalling only: device tensors are passed by pointer, every step
+of the computation runs in the library's HIP kernels.  There is no fallback:
+if the library is missing or fails to load, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libehdbim.so")
+
+EHD_OK, EHD_E_ARG, EHD_E_SHAPE, EHD_E_STATE, EHD_E_NOMEM, EHD_E_HIP = range(6)
+STOKES_SL, STOKES_DL, LAP_SL, LAP_DL, LAP_DLADJ = 1, 2, 4, 8, 16
+ALL_KINDS = 31
+METRIC_KINDS = STOKES_SL | STOKES_DL | LAP_SL | LAP_DL
+FAR_FP64, FAR_FP32C = 0, 1
+GRID_PAPER, GRID_2P = 0, 1
+MAX_P = 48
+MAX_Q = 160
+
+COMPONENTS = ("Sx", "Sy", "Sz", "Dx", "Dy", "Dz", "SL", "L", "Kstar")
+_KIND_OF_COMP = (STOKES_SL,) * 3 + (STOKES_DL,) * 3 + (LAP_SL, LAP_DL, LAP_DLADJ)
+
+EXPORTED = ("ehd_create", "ehd_destroy", "ehd_last_error", "ehd_grid_dims", "ehd_set_drops",
+            "ehd_num_targets", "ehd_layer_potentials", "ehd_synthesize", "ehd_analyze",
+            "ehd_target_geometry", "ehd_sync", "ehd_wigner_d")
+
+_lib = None
+
+
+class EhdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ehdbim error {code}: {msg}")
+        self.code = code
+
+
+def load(path: str = LIB_PATH):
+    """Load the shared library (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(there is no non-HIP fallback)")
+    lib = C.CDLL(path)
+    vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)
+    lib.ehd_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, vp]
+    lib.ehd_destroy.argtypes = [vp]
+    lib.ehd_destroy.restype = None
+    lib.ehd_last_error.argtypes = [vp]
+    lib.ehd_last_error.restype = C.c_char_p
+    lib.ehd_grid_dims.argtypes = [C.c_int, C.c_int, ip, ip]
+    lib.ehd_set_drops.argtypes = [vp, C.c_int, ip, ip, ip, C.c_int, vp]
+    lib.ehd_num_targets.argtypes = [vp, C.POINTER(C.c_longlong)]
+    lib.ehd_layer_potentials.argtypes = [vp, vp, vp, vp, C.c_uint, C.c_int, vp, vp]
+    lib.ehd_synthesize.argtypes = [vp, C.c_int, vp, vp]
+    lib.ehd_analyze.argtypes = [vp, C.c_int, vp, vp]
+    lib.ehd_target_geometry.argtypes = [vp, vp, vp]
+    lib.ehd_sync.argtypes = [vp]
+    lib.ehd_wigner_d.argtypes = [C.c_int, C.c_double, dp]
+    _lib = lib
+    return lib
+
+
+def rows_for_kinds(kinds: int) -> list[int]:
+    """Component indices (into COMPONENTS) of the output rows for `kinds`."""
+    return [c for c in range(9) if kinds & _KIND_OF_COMP[c]]
+
+
+def grid_dims(P: int, grid_mode: int = GRID_PAPER) -> tuple[int, int]:
+    lib = load()
+    a, b = C.c_int(), C.c_int()
+    rc = lib.ehd_grid_dims(P, grid_mode, C.byref(a), C.byref(b))
+    if rc:
+        raise EhdError(rc, "invalid grid")
+    return a.value, b.value
+
+
+def wigner_d(n: int, beta: float):
+    import numpy as np
+    out = np.zeros((2 * n + 1) ** 2)
+    rc = load().ehd_wigner_d(n, float(beta), out.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc:
+        raise EhdError(rc, "invalid Wigner request")
+    return out.reshape(2 * n + 1, 2 * n + 1)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("device tensors (torch, on the GPU) are required")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("contiguous float64 tensors are required")
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One library context bound to a device and a HIP stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        lib = load()
+        self._lib = lib
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        rc = lib.ehd_create(C.byref(h), device, C.c_void_p(stream.cuda_stream))
+        if rc:
+            raise EhdError(rc, lib.ehd_last_error(None).decode())
+        self._h = h
+        self.device = device
+        self.ntargets = 0
+
+    def _check(self, rc: int):
+        if rc:
+            raise EhdError(rc, self._lib.ehd_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ehd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_drops(self, p, q_self, q_far, grid_mode: int, xcoef: torch.Tensor):
+        import numpy as np
+        p = np.ascontiguousarray(p, np.int32)
+        qs = np.ascontiguousarray(q_self, np.int32)
+        qf = np.ascontiguousarray(q_far, np.int32)
+        ip = C.POINTER(C.c_int)
+        self._check(self._lib.ehd_set_drops(self._h, len(p), p.ctypes.data_as(ip),
+                                            qs.ctypes.data_as(ip), qf.ctypes.data_as(ip),
+                                            grid_mode, _ptr(xcoef)))
+        n = C.c_longlong()
+        self._check(self._lib.ehd_num_targets(self._h, C.byref(n)))
+        self.ntargets = n.value
+        self.p = p
+
+    def layer_potentials(self, fcoef, ucoef, sigcoef, kinds: int, far_prec: int,
+                         self_out: torch.Tensor, far_out: torch.Tensor | None = None):
+        self._check(self._lib.ehd_layer_potentials(self._h, _ptr(fcoef), _ptr(ucoef),
+                                                   _ptr(sigcoef), kinds, far_prec,
+                                                   _ptr(self_out), _ptr(far_out)))
+
+    def synthesize(self, nfields: int, coef: torch.Tensor, grid: torch.Tensor):
+        self._check(self._lib.ehd_synthesize(self._h, nfields, _ptr(coef), _ptr(grid)))
+
+    def analyze(self, nfields: int, grid: torch.Tensor, coef: torch.Tensor):
+        self._check(self._lib.ehd_analyze(self._h, nfields, _ptr(grid), _ptr(coef)))
+
+    def target_geometry(self, x: torch.Tensor, n: torch.Tensor):
+        self._check(self._lib.ehd_target_geometry(self._h, _ptr(x), _ptr(n)))
+
+    def sync(self):
+        self._check(self._lib.ehd_sync(self._h))
+
+
+def evaluate(susp, kinds: int = ALL_KINDS, far_prec: int = FAR_FP64, split: bool = True,
+             device: int = 0):
+    """Convenience: one evaluation of a workloads.Suspension on `device`.
+    Returns (self_out, far_out) as CPU float64 tensors [rows][ntargets]."""
+    dev = torch.device("cuda", device)
+    ctx = Context(device)
+    x = torch.from_numpy(susp.xcoef).to(dev)
+    ctx.set_drops(susp.p, susp.q_self, susp.q_far, susp.grid_mode, x)
+    f = torch.from_numpy(susp.fcoef).to(dev)
+    s = torch.from_numpy(susp.sigcoef).to(dev)
+    u = torch.from_numpy(susp.ucoef).to(dev) if susp.ucoef is not None else None
+    rows = len(rows_for_kinds(kinds))
+    so = torch.zeros(rows, ctx.ntargets, dtype=torch.float64, device=dev)
+    fo = torch.zeros_like(so) if split else None
+    ctx.layer_potentials(f, u, s, kinds, far_prec, so, fo)
+    ctx.sync()
+    out = (so.cpu(), fo.cpu() if fo is not None else None)
+    ctx.close()
+    return out

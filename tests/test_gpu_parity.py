@@ -1,0 +1,240 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Bar: FP64 results within 1e-10 relative (normwise per output component:
+max |gpu - oracle| / max |oracle| over the targets compared).  The FP32 far
+field is held to its measured bound (see FP32_FAR_BOUND).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1811_10270_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+FP32_FAR_BOUND = 2e-6
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1811_10270_amd import ehdbim
+    ehdbim.load()
+    return ehdbim
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def normwise(got, ref):
+    den = np.abs(ref).max(axis=-1)
+    den = np.where(den == 0, 1.0, den)
+    return np.abs(got - ref).max(axis=-1) / den
+
+
+def run(E, s, kinds=31, far_prec=0, split=True):
+    say(f"[gpu] {s.name}: ndrops={s.ndrops} p={sorted(set(s.p.tolist()))} kinds={kinds} "
+        f"far_prec={far_prec} grid_mode={s.grid_mode}")
+    return E.evaluate(s, kinds=kinds, far_prec=far_prec, split=split)
+
+
+def sample(s, per_drop, seed=0):
+    rng = np.random.default_rng(seed)
+    td, tn = oracle.all_targets(s)
+    off = s.target_offsets()
+    idx = []
+    for d in range(s.ndrops):
+        n = off[d + 1] - off[d]
+        k = min(per_drop, n)
+        pick = rng.choice(n, size=k, replace=False)
+        # always include the first and last node (poles' neighbourhoods)
+        pick = np.unique(np.concatenate([pick, [0, n - 1]]))
+        idx.append(off[d] + pick)
+    idx = np.concatenate(idx)
+    return idx, td[idx], tn[idx]
+
+
+# ---------------------------------------------------------------------------
+def test_target_geometry_and_synthesis(E):
+    import torch
+    s = W.batched_suspension(seed=3)
+    s = W.subset(s, [0, 1, 2, 3, 4, 5])
+    ctx = E.Context(0)
+    dev = torch.device("cuda", 0)
+    ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+    T = ctx.ntargets
+    x = torch.zeros(3, T, dtype=torch.float64, device=dev)
+    n = torch.zeros_like(x)
+    ctx.target_geometry(x, n)
+    g = torch.zeros(1, T, dtype=torch.float64, device=dev)
+    ctx.synthesize(1, torch.from_numpy(s.sigcoef).to(dev), g)
+    c = torch.zeros(s.sigcoef.shape[0], dtype=torch.float64, device=dev)
+    ctx.analyze(1, g, c)
+    ctx.sync()
+    td, tn = oracle.all_targets(s)
+    xr, nr = oracle.targets(s, td, tn)
+    assert np.abs(x.cpu().numpy() - xr).max() < 1e-12
+    assert np.abs(n.cpu().numpy() - nr).max() < 1e-12
+    # synthesis against the oracle, drop by drop
+    off = s.target_offsets()
+    coff = W.drop_offsets(s.p.astype(np.int64))
+    gg = g.cpu().numpy()[0]
+    for d in range(s.ndrops):
+        p = int(s.p[d])
+        ref = oracle.synth_grid(p, s.sigcoef[coff[d]:coff[d + 1]], p, s.grid_mode).ravel()
+        assert np.abs(gg[off[d]:off[d + 1]] - ref).max() < 1e-12
+    # exact round trip on the paper's grid
+    cc = c.cpu().numpy()
+    for d in range(s.ndrops):
+        blk = s.sigcoef[coff[d]:coff[d + 1]].copy()
+        p = int(s.p[d])
+        for nn in range(p + 1):
+            blk[2 * (nn * (nn + 1) // 2) + 1] = 0.0
+        assert np.abs(cc[coff[d]:coff[d + 1]] - blk).max() < 1e-12
+    ctx.close()
+
+
+def test_self_single_drop_full(E):
+    """Single drop p=16 (shape 1 + 0.1 Y20 + random), q=32, every target."""
+    s = W.single_drop(16, seed=1)
+    so, fo = run(E, s)
+    td, tn = oracle.all_targets(s)
+    ref = oracle.self_(s, td, tn)
+    err = normwise(so.numpy(), ref)
+    say("self p16 normwise err", err)
+    assert np.all(err < FP64_TOL), err
+    assert np.abs(fo.numpy()).max() == 0.0      # one drop: no far field
+
+
+def test_self_grid_mode_2p_and_separate_u(E):
+    s = W.with_separate_u(W.single_drop(12, seed=4, grid_mode=1))
+    s.q_self[:] = 30
+    so, _ = run(E, s)
+    td, tn = oracle.all_targets(s)
+    ref = oracle.self_(s, td, tn)
+    err = normwise(so.numpy(), ref)
+    say("self p12 mode-2p separate-u err", err)
+    assert np.all(err < FP64_TOL), err
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_self_tiny_degrees(E, p):
+    s = W.single_drop(p, seed=7, eps_y20=0.0, amp=0.02)
+    s.q_self[:] = 4 * p + 1
+    s.q_far[:] = p
+    so, _ = run(E, s)
+    td, tn = oracle.all_targets(s)
+    ref = oracle.self_(s, td, tn)
+    err = normwise(so.numpy(), ref)
+    assert np.all(err < FP64_TOL), err
+
+
+def test_far_fp64_two_drops(E):
+    """Two p=12 spheres at gap 0.1, far grid q = 3p (near-contact pair)."""
+    s = W.two_drops(12, seed=2, q_far_mult=3)
+    so, fo = run(E, s)
+    td, tn = oracle.all_targets(s)
+    ref = oracle.far(s, td, tn)
+    err = normwise(fo.numpy(), ref)
+    say("far fp64 two drops err", err)
+    assert np.all(err < FP64_TOL), err
+
+
+def test_far_fp32_two_drops_bound(E):
+    s = W.two_drops(12, seed=2, q_far_mult=3)
+    _, fo = run(E, s, far_prec=1)
+    td, tn = oracle.all_targets(s)
+    ref = oracle.far(s, td, tn)
+    err = normwise(fo.numpy(), ref)
+    say("far fp32 two drops err", err)
+    assert np.all(err < FP32_FAR_BOUND), err
+
+
+def test_mixed_degrees_subset_all_kinds(E):
+    """Six drops of the batched suspension (p in {16,24,32,48}), sampled
+    targets, self and far separately, FP64."""
+    s0 = W.batched_suspension(seed=3)
+    pick = [int(np.where(s0.p == pp)[0][0]) for pp in (16, 24, 32, 48)]
+    s = W.subset(s0, pick + [int(np.where(s0.p == 16)[0][1]), int(np.where(s0.p == 48)[0][1])])
+    so, fo = run(E, s)
+    idx, td, tn = sample(s, 12, seed=1)
+    rs = oracle.self_(s, td, tn)
+    rf = oracle.far(s, td, tn)
+    es = normwise(so.numpy()[:, idx], rs)
+    ef = normwise(fo.numpy()[:, idx], rf)
+    say("subset self err", es, "far err", ef)
+    assert np.all(es < FP64_TOL) and np.all(ef < FP64_TOL), (es, ef)
+
+
+def test_kinds_rows_and_summed_output(E):
+    s = W.two_drops(8, seed=5)
+    so_all, fo_all = run(E, s, kinds=31)
+    kinds = E.STOKES_DL | E.LAP_SL
+    rows = E.rows_for_kinds(kinds)
+    so, fo = run(E, s, kinds=kinds)
+    assert so.shape[0] == len(rows) == 4
+    np.testing.assert_array_equal(so.numpy(), so_all.numpy()[rows])
+    np.testing.assert_array_equal(fo.numpy(), fo_all.numpy()[rows])
+    tot, none = run(E, s, kinds=31, split=False)
+    assert none is None
+    np.testing.assert_allclose(tot.numpy(), so_all.numpy() + fo_all.numpy(), rtol=0, atol=1e-14)
+
+
+def test_argument_errors(E):
+    import torch
+    ctx = E.Context(0)
+    dev = torch.device("cuda", 0)
+    x = torch.zeros(3 * 20, dtype=torch.float64, device=dev)
+    with pytest.raises(E.EhdError) as ei:
+        ctx.set_drops([0], [4], [4], 0, x)
+    assert ei.value.code == E.EHD_E_SHAPE
+    with pytest.raises(E.EhdError) as ei:
+        ctx.set_drops([60], [120], [120], 0, torch.zeros(3 * 61 * 62, dtype=torch.float64, device=dev))
+    assert ei.value.code == E.EHD_E_SHAPE
+    out = torch.zeros(9, 10, dtype=torch.float64, device=dev)
+    with pytest.raises(E.EhdError) as ei:
+        ctx.layer_potentials(x, None, x, 31, 0, out)
+    assert ei.value.code == E.EHD_E_STATE
+    s = W.single_drop(3, seed=1)
+    ctx.set_drops(s.p, s.q_self, s.q_far, 0, torch.from_numpy(s.xcoef).to(dev))
+    f = torch.from_numpy(s.fcoef).to(dev)
+    sg = torch.from_numpy(s.sigcoef).to(dev)
+    for bad_kinds in (0, 32, 64):
+        with pytest.raises(E.EhdError):
+            ctx.layer_potentials(f, None, sg, bad_kinds, 0, out)
+    with pytest.raises(E.EhdError):
+        ctx.layer_potentials(f, None, sg, 31, 7, out)
+    with pytest.raises(E.EhdError):
+        ctx.layer_potentials(f, None, None, E.LAP_SL, 0, out)
+    ctx.close()
+
+
+def test_full_batched_suspension_sampled(E):
+    """The full 64-drop batched suspension, FP64 and FP32 far field, sampled
+    targets against the oracle (self and far separately)."""
+    s = W.batched_suspension(seed=3)
+    so, fo = run(E, s, kinds=31, far_prec=0)
+    _, fo32 = run(E, s, kinds=31, far_prec=1)
+    rng = np.random.default_rng(2)
+    td_all, tn_all = oracle.all_targets(s)
+    idx = np.sort(rng.choice(len(td_all), size=48, replace=False))
+    rf = oracle.far(s, td_all[idx], tn_all[idx])
+    ef = normwise(fo.numpy()[:, idx], rf)
+    ef32 = normwise(fo32.numpy()[:, idx], rf)
+    say("batched far fp64 err", ef)
+    say("batched far fp32 err", ef32)
+    assert np.all(ef < FP64_TOL), ef
+    assert np.all(ef32 < FP32_FAR_BOUND), ef32
+    sidx = idx[::6]
+    rs = oracle.self_(s, td_all[sidx], tn_all[sidx])
+    es = normwise(so.numpy()[:, sidx], rs)
+    say("batched self err", es)
+    assert np.all(es < FP64_TOL), es
