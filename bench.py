@@ -1,0 +1,193 @@
+"""Benchmark: layer-potential target evaluations per second on one MI355X.
+
+One step = one call of ehd_layer_potentials over the whole workload: the
+singular self-interaction of every target (FP64, rotated-pole rule) plus the
+far-field direct sums over every other drop (FP32 with compensated
+accumulation by default), the four potentials of the metric (S, D, S_L, L:
+8 values per target).  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_FP64_TFLOPS = 78.6        # vector and matrix
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+# FP32 without packed instructions: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+PEAK_FP32_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+FAR_FLOPS_PER_INTERACTION = 53   # S 18, D 19, S_L 2, L 3, xh/r^2/powers 11 (K* would add 5)
+SELF_KERNEL_FLOPS_PER_NODE = 75
+
+
+def self_flops_per_drop(p: int, q: int, grid_mode: int) -> float:
+    """Algorithmic FP64 work of the singular self-interaction of one drop:
+    rotation of 7 fields, Legendre sums (7 fields + 3 theta derivatives),
+    longitude sums of 13 grid quantities, kernel evaluation per rotated node."""
+    nlon_p = 2 * p + 2 if grid_mode == 0 else 2 * p
+    nlon_q = 2 * q + 2 if grid_mode == 0 else 2 * q
+    T = (p + 1) * nlon_p
+    rot = 4 * 7 * T * sum((n + 1) * (2 * n + 1) for n in range(p + 1))
+    leg = 4 * (q + 1) * ((p + 1) * (p + 2) // 2) * 10 * T
+    dft = 2 * nlon_q * (2 * p + 1) * (q + 1) * 13 * T
+    ker = SELF_KERNEL_FLOPS_PER_NODE * T * (q + 1) * nlon_q
+    return float(rot + leg + dft + ker)
+
+
+def far_interactions(s) -> float:
+    tot = 0.0
+    nt = []
+    ns = []
+    for d in range(s.ndrops):
+        p, qf = int(s.p[d]), int(s.q_far[d])
+        nlp = 2 * p + 2 if s.grid_mode == 0 else 2 * p
+        nlq = 2 * qf + 2 if s.grid_mode == 0 else 2 * qf
+        nt.append((p + 1) * nlp)
+        ns.append((qf + 1) * nlq)
+    S = sum(ns)
+    for d in range(s.ndrops):
+        tot += nt[d] * (S - ns[d])
+    return tot
+
+
+def cpu_baseline(s, nsample: int, seed: int = 0):
+    """The oracle timed on a bounded random sample of the workload's targets:
+    self (singular rule) + far (all other drops) for each sampled target."""
+    import numpy as np
+    import oracle
+    td, tn = oracle.all_targets(s)
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(len(td), size=min(nsample, len(td)), replace=False))
+    t0 = time.perf_counter()
+    oracle.self_(s, td[idx], tn[idx])
+    t1 = time.perf_counter()
+    oracle.far(s, td[idx], tn[idx])
+    t2 = time.perf_counter()
+    return {
+        "value": len(idx) / (t2 - t0),
+        "unit": "target-evals/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{len(idx)} random targets of {len(td)} (seed {seed}), self + far over all "
+                  f"{s.ndrops} drops, FP64; self {t1 - t0:.1f} s, far {t2 - t1:.1f} s",
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="batched_64_mixed_p",
+                    choices=["batched_64_mixed_p", "large_256_p32", "two_drops_p32",
+                             "single_drop_p16"])
+    ap.add_argument("--far-prec", default="fp32c", choices=["fp32c", "fp64"])
+    ap.add_argument("--grid-mode", type=int, default=0)
+    ap.add_argument("--cpu-sample", type=int, default=96)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(the multi-GPU sharding is described, not built)"}))
+        return 2
+
+    import torch
+    from paper_1811_10270_amd import ehdbim as E
+    from paper_1811_10270_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU available"}))
+        return 1
+    dev = torch.device("cuda", 0)
+    s = W.WORKLOADS[args.workload](args.grid_mode)
+    far_prec = E.FAR_FP32C if args.far_prec == "fp32c" else E.FAR_FP64
+    kinds = E.METRIC_KINDS
+
+    ctx = E.Context(0)
+    ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+    T = ctx.ntargets
+    f = torch.from_numpy(s.fcoef).to(dev)
+    sig = torch.from_numpy(s.sigcoef).to(dev)
+    out = torch.empty(len(E.rows_for_kinds(kinds)), T, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        ctx.layer_potentials(f, None, sig, kinds, far_prec, out)
+    ctx.sync()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ctx.set_timing(K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        ctx.layer_potentials(f, None, sig, kinds, far_prec, out)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dt = t1 - t0
+    stages = [ctx.stage_times(i) for i in range(K)]
+    avg = [sum(st[k] for st in stages) / K for k in range(4)]
+
+    # roofline of the dominant kernel
+    self_flops = sum(self_flops_per_drop(int(s.p[d]), int(s.q_self[d]), s.grid_mode)
+                     for d in range(s.ndrops))
+    far_flops = far_interactions(s) * FAR_FLOPS_PER_INTERACTION
+    if avg[1] >= avg[2]:
+        achieved = self_flops / (avg[1] * 1e-3) / 1e12
+        roof = {"kernel": "k_self (rotation + rotated-grid synthesis + singular reduction, FP64)",
+                "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "algorithmic_flops": self_flops, "avg_ms": avg[1]}
+    else:
+        peak = PEAK_FP32_UNPACKED_TFLOPS if far_prec == E.FAR_FP32C else PEAK_FP64_TFLOPS
+        achieved = far_flops / (avg[2] * 1e-3) / 1e12
+        roof = {"kernel": "k_far32 (far-field direct sums)" if far_prec == E.FAR_FP32C
+                else "k_far64 (far-field direct sums)",
+                "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None, "algorithmic_flops": far_flops,
+                "avg_ms": avg[2]}
+
+    res = {
+        "metric": "layer-potential target evals/sec (singular+far) FP64 self + "
+                  + ("FP32 far" if far_prec == E.FAR_FP32C else "FP64 far"),
+        "value": T * K / dt,
+        "unit": "target-evals/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": dt / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32" if far_prec == E.FAR_FP32C else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "ndrops": s.ndrops,
+                   "p": sorted(set(int(x) for x in s.p)), "targets": T,
+                   "q_self": "2p", "q_far": "2p", "grid": "paper (2p+2 longitudes)"
+                   if s.grid_mode == 0 else "2p longitudes",
+                   "kinds": "S,D,S_L,L", "far_prec": args.far_prec,
+                   "far_interactions": far_interactions(s)},
+        "stage_ms": dict(zip(E.STAGES, avg)),
+        "self_tflops": self_flops / (avg[1] * 1e-3) / 1e12,
+        "far_tflops": far_flops / (avg[2] * 1e-3) / 1e12,
+        "roofline": roof,
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(s, args.cpu_sample)
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

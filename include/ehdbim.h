@@ -147,6 +147,18 @@ int ehd_target_geometry(ehd_ctx* ctx, double* x_d, double* n_d);
 /* Wait for the context's stream; reports asynchronous HIP failures. */
 int ehd_sync(ehd_ctx* ctx);
 
+/* Stage timing with HIP events recorded on the context's stream (no host
+ * synchronisation during the calls).  nslots > 0 enables it: the i-th
+ * following ehd_layer_potentials call records into slot i % nslots;
+ * nslots == 0 disables it and frees the events. */
+int ehd_set_timing(ehd_ctx* ctx, int nslots);
+
+/* Elapsed milliseconds of the stages of the call recorded in `slot`:
+ * ms[0] source densities (synthesis on the far grids + records),
+ * ms[1] singular self-interaction, ms[2] far field, ms[3] combination.
+ * Waits for the recorded events.  EHD_E_STATE if the slot holds no call. */
+int ehd_stage_times(ehd_ctx* ctx, int slot, double* ms);
+
 /* Host-only: Wigner small-d matrix d^n_{m m'}(beta), m, m' = -n..n, written
  * row-major to out[(m+n)*(2n+1) + (m'+n)], with
  * Y_nm(Ry(beta) v) = sum_m' d^n_{m m'}(beta) Y_nm'(v)

@@ -662,6 +662,25 @@ struct ehd_ctx {
     int nrows_p = 0, nrows_f = 0;
     int2* d_an_items = nullptr;
     int n_an_items = 0;
+
+    // stage timing
+    static constexpr int kStages = 4;
+    std::vector<hipEvent_t> events;  // [nslots][kStages + 1]
+    std::vector<int> slot_used;
+    int nslots = 0;
+    long long ncalls = 0;
+
+    void free_events()
+    {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        events.clear();
+        slot_used.clear();
+        nslots = 0;
+    }
+    void mark(int stage)
+    {
+        if (nslots) (void)hipEventRecord(events[(ncalls % nslots) * (kStages + 1) + stage], stream);
+    }
     DropInfo* d_info_tmp = nullptr;  // per-field views for ehd_synthesize
 
     void free_all()
@@ -776,6 +795,7 @@ void ehd_destroy(ehd_ctx* ctx)
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
     ctx->free_all();
+    ctx->free_events();
     delete ctx;
 }
 
@@ -1052,6 +1072,7 @@ int ehd_layer_potentials(ehd_ctx* ctx, const double* fcoef_d, const double* ucoe
     }
 
     const long long T = ctx->T, S = ctx->Spad, vs = ctx->syn_stride;
+    ctx->mark(0);
     // 1. densities on the far grids -> weighted source records
     double* synf = needF ? ctx->d_syn : nullptr;
     double* synu = needU ? ctx->d_syn + 3 * vs : nullptr;
@@ -1069,6 +1090,7 @@ int ehd_layer_potentials(ehd_ctx* ctx, const double* fcoef_d, const double* ucoe
                        ctx->d_src64, ctx->d_src32);
     EHD_HIP(ctx, hipGetLastError());
 
+    ctx->mark(1);
     // 2. singular self-interaction (one or two passes depending on LDS)
     int pmax = 1;
     for (int pp : ctx->p) pmax = std::max(pmax, pp);
@@ -1091,6 +1113,7 @@ int ehd_layer_potentials(ehd_ctx* ctx, const double* fcoef_d, const double* ucoe
         if (rc == EHD_OK) rc = launch_self<false, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, EHD_STOKES_DL);
     }
     if (rc) return rc;
+    ctx->mark(2);
 
     // 3. far field
     const long long tblocks = (T + kThreads - 1) / kThreads;
@@ -1105,10 +1128,14 @@ int ehd_layer_potentials(ehd_ctx* ctx, const double* fcoef_d, const double* ucoe
                            ctx->d_partial);
     EHD_HIP(ctx, hipGetLastError());
 
+    ctx->mark(3);
     // 4. outputs
     hipLaunchKernelGGL(k_combine, dim3((T + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_raw, ctx->d_partial,
                        ctx->nchunk, T, rows, self_out_d, far_out_d);
     EHD_HIP(ctx, hipGetLastError());
+    ctx->mark(4);
+    if (ctx->nslots) ctx->slot_used[ctx->ncalls % ctx->nslots] = 1;
+    ++ctx->ncalls;
     return EHD_OK;
 }
 
@@ -1157,6 +1184,37 @@ int ehd_target_geometry(ehd_ctx* ctx, double* x_d, double* n_d)
     EHD_HIP(ctx, hipSetDevice(ctx->device));
     EHD_HIP(ctx, hipMemcpyAsync(x_d, ctx->d_tx, sizeof(double) * 3 * ctx->T, hipMemcpyDeviceToDevice, ctx->stream));
     EHD_HIP(ctx, hipMemcpyAsync(n_d, ctx->d_tn, sizeof(double) * 3 * ctx->T, hipMemcpyDeviceToDevice, ctx->stream));
+    return EHD_OK;
+}
+
+int ehd_set_timing(ehd_ctx* ctx, int nslots)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (nslots < 0 || nslots > 100000) EHD_FAIL(ctx, EHD_E_ARG, "nslots must be in [0, 100000]");
+    EHD_HIP(ctx, hipSetDevice(ctx->device));
+    if (ctx->stream) EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->free_events();
+    if (nslots == 0) return EHD_OK;
+    ctx->events.resize((size_t)nslots * (ehd_ctx::kStages + 1));
+    for (auto& e : ctx->events) EHD_HIP(ctx, hipEventCreate(&e));
+    ctx->slot_used.assign(nslots, 0);
+    ctx->nslots = nslots;
+    ctx->ncalls = 0;
+    return EHD_OK;
+}
+
+int ehd_stage_times(ehd_ctx* ctx, int slot, double* ms)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ms || slot < 0 || slot >= ctx->nslots) EHD_FAIL(ctx, EHD_E_ARG, "invalid slot or ms pointer");
+    if (!ctx->slot_used[slot]) EHD_FAIL(ctx, EHD_E_STATE, "slot %d holds no recorded call", slot);
+    hipEvent_t* ev = &ctx->events[(size_t)slot * (ehd_ctx::kStages + 1)];
+    EHD_HIP(ctx, hipEventSynchronize(ev[ehd_ctx::kStages]));
+    for (int k = 0; k < ehd_ctx::kStages; ++k) {
+        float t = 0.0f;
+        EHD_HIP(ctx, hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+        ms[k] = t;
+    }
     return EHD_OK;
 }
 

@@ -28,7 +28,9 @@ _KIND_OF_COMP = (STOKES_SL,) * 3 + (STOKES_DL,) * 3 + (LAP_SL, LAP_DL, LAP_DLADJ
 
 EXPORTED = ("ehd_create", "ehd_destroy", "ehd_last_error", "ehd_grid_dims", "ehd_set_drops",
             "ehd_num_targets", "ehd_layer_potentials", "ehd_synthesize", "ehd_analyze",
-            "ehd_target_geometry", "ehd_sync", "ehd_wigner_d")
+            "ehd_target_geometry", "ehd_sync", "ehd_wigner_d", "ehd_set_timing",
+            "ehd_stage_times")
+STAGES = ("densities", "self", "far", "combine")
 
 _lib = None
 
@@ -63,6 +65,8 @@ def load(path: str = LIB_PATH):
     lib.ehd_target_geometry.argtypes = [vp, vp, vp]
     lib.ehd_sync.argtypes = [vp]
     lib.ehd_wigner_d.argtypes = [C.c_int, C.c_double, dp]
+    lib.ehd_set_timing.argtypes = [vp, C.c_int]
+    lib.ehd_stage_times.argtypes = [vp, C.c_int, dp]
     _lib = lib
     return lib
 
@@ -163,6 +167,15 @@ class Context:
 
     def sync(self):
         self._check(self._lib.ehd_sync(self._h))
+
+    def set_timing(self, nslots: int):
+        self._check(self._lib.ehd_set_timing(self._h, nslots))
+
+    def stage_times(self, slot: int):
+        """Milliseconds of (densities, self, far, combine) of a recorded call."""
+        ms = (C.c_double * 4)()
+        self._check(self._lib.ehd_stage_times(self._h, slot, ms))
+        return list(ms)
 
 
 def evaluate(susp, kinds: int = ALL_KINDS, far_prec: int = FAR_FP64, split: bool = True,
