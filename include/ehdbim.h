@@ -107,7 +107,9 @@ int ehd_grid_dims(int P, int grid_mode, int* nlat, int* nlon);
 
 /* Define the drops: ndrops >= 1; p_h[d] in [1, EHD_MAX_P]; q_self_h[d] and
  * q_far_h[d] in [p_h[d], EHD_MAX_Q] (upsampled quadrature degrees of the
- * singular and of the regular rule, Sec. 2.1); grid_mode as above;
+ * singular and of the regular rule, Sec. 2.1), and the rotated grid of the
+ * singular rule has at most 256 longitudes (q_self <= 127 on the paper's
+ * grid, <= 128 with EHD_GRID_2P); grid_mode as above;
  * xcoef_d: 3-field packed surface coefficients (copied; the caller may free
  * them after the call).  Builds the quadrature tables, rotation tables and
  * the geometry of targets and far-field sources.  Synchronous: returns when

@@ -44,6 +44,8 @@ struct LegTab {                // degree-p expansions on a degree-Q grid
     const double* wsing;       // [Q+1] (2 pi / nlon) * w_i^G * 2 sin(theta_i/2) sum_{n<=Q} P_n
     const double* rsin;        // [Q+1] 1 / sin theta_i
     const double* trig;        // [nlon][p+1][2] cos(m phi_l), sin(m phi_l)
+    const double* afrag;       // MFMA A fragments of the half-period cos/sin
+                               // tables: [row tile][k-step (even, odd)][lane]
     int p, Q, nlon, pad;
 };
 
@@ -244,15 +246,52 @@ __global__ void k_src_dens(const double* __restrict__ synf, const double* __rest
 // eq. mod_weights and the rotation of the target to the north pole).
 //   1. rotated coefficients c'_{nm'} = sum_m d^n_{m m'}(theta_t) e^{i m phi_t} c_nm
 //      of every field, in the real form of tables.h, into LDS;
-//   2. for each latitude of the rotated degree-q grid: Legendre sums
-//      (values for all fields, theta derivative for x) into LDS, then per
-//      node the longitude sums, n, J, and the kernels with the modified
-//      weights;
+//   2. for each latitude i of the rotated degree-q grid:
+//      a. Legendre sums G_f(m) = sum_n Pbar_n^m(t_i) c'_f(n,m) (and the theta
+//         derivative table for x) on the vector ALU, written as real
+//         Fourier coefficients (cos / sin of m phi) of every grid quantity
+//         (x, x_theta, x_phi / sin theta, densities) into LDS;
+//      b. longitude sums as FP64 MFMA products: the nodes phi_l and
+//         phi_l + pi share the even-m and odd-m partial sums E, O
+//         (values E + O and E - O), so two GEMMs of half the rows, with the
+//         cos/sin table as the register-resident A operand, the Fourier
+//         coefficients as B (columns = grid quantities);
+//      c. per node: normal, area factor, the kernels with the modified
+//         weights, accumulated per thread;
 //   3. block reduction.
 // Fields in LDS: x(3) [f(3)] [u(3)] [sigma(1)]; D uses u when present, f
 // otherwise.  Output: raw[comp][T] (already scaled by 1/(4 pi)).
 // ---------------------------------------------------------------------------
-template <bool HF, bool HU, bool HS>
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Longitude-sum geometry of the (p, q) rotated grid:
+//   H = nlon_q / 2 rows per half period, nLT = ceil(H/16) row tiles,
+//   KE = 2*floor(p/2)+1 even-m terms, KO = 2*ceil(p/2) odd-m terms,
+//   nKE = ceil(KE/4), nKO = ceil(KO/4) MFMA k-steps.
+struct HalfGrid {
+    int H, nLT, KE, KO, nKE, nKO;
+};
+__host__ __device__ inline HalfGrid half_grid(int p, int nlonq)
+{
+    HalfGrid h;
+    h.H = nlonq / 2;
+    h.nLT = (h.H + 15) / 16;
+    h.KE = 2 * (p / 2) + 1;
+    h.KO = 2 * ((p + 1) / 2);
+    h.nKE = (h.KE + 3) / 4;
+    h.nKO = (h.KO + 3) / 4;
+    return h;
+}
+
+// Compile-time bounds of one degree class (all p <= PMAX, q <= 2 PMAX + pad).
+template <int PMAX>
+struct SelfClass {
+    static constexpr int KSE = (2 * (PMAX / 2) + 1 + 3) / 4;   // max even k-steps
+    static constexpr int KSO = (2 * ((PMAX + 1) / 2) + 3) / 4; // max odd k-steps
+    static constexpr int TPW = 2;                              // row tiles per wave (max)
+};
+
+template <int PMAX, bool HF, bool HU, bool HS>
 __global__ __launch_bounds__(kThreads) void k_self(
     const DropInfo* __restrict__ drops, const LegTab* __restrict__ legs,
     const WigTab* __restrict__ wigs, const int* __restrict__ order, const int* __restrict__ tdrop,
@@ -263,7 +302,10 @@ __global__ __launch_bounds__(kThreads) void k_self(
 {
     constexpr int NF = 3 + (HF ? 3 : 0) + (HU ? 3 : 0) + (HS ? 1 : 0);
     constexpr int FOFF = 3, UOFF = 3 + (HF ? 3 : 0), SOFF = 3 + (HF ? 3 : 0) + (HU ? 3 : 0);
-    constexpr int NV = NF + 3;  // + theta derivatives of x
+    constexpr int NV = NF + 6;           // + x_theta(3), x_phi/sin(3)
+    constexpr int VD = 9;                // first density variant
+    using SC = SelfClass<PMAX>;
+    static_assert(NV <= 16, "at most 16 grid quantities per MFMA column tile");
     extern __shared__ double2 lds[];
     __shared__ double red[kThreads / 64][9];
 
@@ -276,14 +318,34 @@ __global__ __launch_bounds__(kThreads) void k_self(
     const LegTab Lq = legs[D.leg_ps];
     const LegTab Lp = legs[D.leg_pp];
     const WigTab W = wigs[D.wig];
-    double2* cr = lds;                 // [NF][nc]
-    double2* G = lds + NF * nc;        // [NV][p+1]
+    const HalfGrid hg = half_grid(p, Lq.nlon);
+    double2* cr = lds;                               // [NF][nc]
+    double* R = reinterpret_cast<double*>(lds + NF * nc);  // Fourier coefs / node values
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
     const double* fld[NF];
     for (int c = 0; c < 3; ++c) fld[c] = xcoef + 3 * D.coff + c * 2 * nc;
     if (HF) for (int c = 0; c < 3; ++c) fld[FOFF + c] = fcoef + 3 * D.coff + c * 2 * nc;
     if (HU) for (int c = 0; c < 3; ++c) fld[UOFF + c] = ucoef + 3 * D.coff + c * 2 * nc;
     if (HS) fld[SOFF] = scoef + D.coff;
+
+    // register-resident A operand: cos/sin(m phi_l) fragments of this wave's
+    // row tiles, even-m and odd-m blocks
+    double afE[SC::TPW][SC::KSE], afO[SC::TPW][SC::KSO];
+    {
+        const int nks = hg.nKE + hg.nKO;
+#pragma unroll
+        for (int tt = 0; tt < SC::TPW; ++tt) {
+            const int t = wv + 4 * tt;
+            const double* src = Lq.afrag + (long long)t * nks * 64 + lane;
+#pragma unroll
+            for (int ks = 0; ks < SC::KSE; ++ks)
+                afE[tt][ks] = (t < hg.nLT && ks < hg.nKE) ? src[(long long)ks * 64] : 0.0;
+#pragma unroll
+            for (int ks = 0; ks < SC::KSO; ++ks)
+                afO[tt][ks] = (t < hg.nLT && ks < hg.nKO) ? src[(long long)(hg.nKE + ks) * 64] : 0.0;
+        }
+    }
 
     // 1. rotation
     {
@@ -310,7 +372,6 @@ __global__ __launch_bounds__(kThreads) void k_self(
             for (int f = 0; f < NF; ++f) cr[f * nc + it] = make_double2(are[f], aim[f]);
         }
     }
-    __syncthreads();
 
     double x0[3], n0[3];
     for (int c = 0; c < 3; ++c) { x0[c] = tx[c * T + tg]; n0[c] = tnrm[c * T + tg]; }
@@ -320,47 +381,103 @@ __global__ __launch_bounds__(kThreads) void k_self(
     const bool wD = (kinds & EHD_STOKES_DL) && (HF || HU);
     const bool wSL = (kinds & EHD_LAP_SL) && HS, wL = (kinds & EHD_LAP_DL) && HS;
     const bool wK = (kinds & EHD_LAP_DLADJ) && HS;
+    const int keRows = 4 * hg.nKE, koRows = 4 * hg.nKO;
+    double* GE = R;                     // [4 nKE][16]
+    double* GO = R + keRows * 16;       // [4 nKO][16]
 
     for (int i = 0; i <= Lq.Q; ++i) {
+        __syncthreads();  // previous node values consumed, c' complete
+        // a. Legendre sums -> real Fourier coefficients
         const double* Prow = Lq.P + (long long)i * nc;
         const double* dProw = Lq.dP + (long long)i * nc;
-        for (int it = threadIdx.x; it < (NF + 3) * (p + 1); it += blockDim.x) {
-            const int v = it / (p + 1), m = it % (p + 1);
-            const bool der = v >= NF;
-            const int f = der ? v - NF : v;
-            const double* tab = der ? dProw : Prow;
-            double ar = 0.0, ai = 0.0;
+        const double rs = Lq.rsin[i];
+        for (int it = threadIdx.x; it < NF * (p + 1); it += blockDim.x) {
+            const int f = it / (p + 1), m = it % (p + 1);
+            double ar = 0.0, ai = 0.0, dr = 0.0, di = 0.0;
             for (int n = m; n <= p; ++n) {
                 const long kk = tri(n, m);
                 const double2 c = cr[f * nc + kk];
-                ar += tab[kk] * c.x;
-                ai += tab[kk] * c.y;
+                const double pv = Prow[kk];
+                ar += pv * c.x;
+                ai += pv * c.y;
+                if (f < 3) {
+                    const double dv = dProw[kk];
+                    dr += dv * c.x;
+                    di += dv * c.y;
+                }
             }
-            G[v * (p + 1) + m] = make_double2(ar, ai);
+            // row (k) of the cos and sin terms of degree m in the E / O blocks
+            double* Gb = (m & 1) ? GO : GE;
+            const int kc = (m == 0) ? 0 : m - 1, ks = m;
+            const double sc = (m == 0) ? 1.0 : 2.0;
+            const int v = (f < 3) ? f : VD + (f - 3);
+            Gb[kc * 16 + v] = sc * ar;
+            if (m > 0) Gb[ks * 16 + v] = -sc * ai;
+            if (f < 3) {
+                Gb[kc * 16 + 3 + f] = sc * dr;
+                if (m > 0) Gb[ks * 16 + 3 + f] = -sc * di;
+                // x_phi / sin theta: cos coef m b_m / s, sin coef -m a_m / s
+                Gb[kc * 16 + 6 + f] = (m == 0) ? 0.0 : -sc * m * ai * rs;
+                if (m > 0) Gb[ks * 16 + 6 + f] = -sc * m * ar * rs;
+            }
+        }
+        // zero the padding rows of both blocks (their A entries are zero too)
+        for (int z = threadIdx.x; z < (keRows - hg.KE) * 16; z += blockDim.x) GE[hg.KE * 16 + z] = 0.0;
+        for (int z = threadIdx.x; z < (koRows - hg.KO) * 16; z += blockDim.x) GO[hg.KO * 16 + z] = 0.0;
+        __syncthreads();
+
+        // b. longitude sums on MFMA
+        dbl4 accE[SC::TPW], accO[SC::TPW];
+        for (int tt = 0; tt < SC::TPW; ++tt) { accE[tt] = dbl4{0, 0, 0, 0}; accO[tt] = dbl4{0, 0, 0, 0}; }
+#pragma unroll
+        for (int ks = 0; ks < SC::KSE; ++ks) {
+            if (ks < hg.nKE) {
+                const double b = GE[(4 * ks + (lane >> 4)) * 16 + (lane & 15)];
+#pragma unroll
+                for (int tt = 0; tt < SC::TPW; ++tt)
+                    if (wv + 4 * tt < hg.nLT)
+                        accE[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(afE[tt][ks], b, accE[tt], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int ks = 0; ks < SC::KSO; ++ks) {
+            if (ks < hg.nKO) {
+                const double b = GO[(4 * ks + (lane >> 4)) * 16 + (lane & 15)];
+#pragma unroll
+                for (int tt = 0; tt < SC::TPW; ++tt)
+                    if (wv + 4 * tt < hg.nLT)
+                        accO[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(afO[tt][ks], b, accO[tt], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // all B reads done before the node values overwrite R
+        {
+            const int v = lane & 15;
+            for (int tt = 0; tt < SC::TPW; ++tt) {
+                const int t = wv + 4 * tt;
+                if (t >= hg.nLT || v >= NV) continue;
+                // MFMA f64 16x16x4 result layout: element r of lane holds
+                // row (lane / 16) + 4 r, column lane % 16
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int l = 16 * t + (lane >> 4) + 4 * r;
+                    if (l < hg.H) {
+                        R[l * NV + v] = accE[tt][r] + accO[tt][r];
+                        R[(l + hg.H) * NV + v] = accE[tt][r] - accO[tt][r];
+                    }
+                }
+            }
         }
         __syncthreads();
-        const double wi = Lq.wsing[i], rs = Lq.rsin[i];
+
+        // c. kernels at the nodes of this latitude
+        const double wi = Lq.wsing[i];
         for (int l = threadIdx.x; l < Lq.nlon; l += blockDim.x) {
-            const double* tr = Lq.trig + (long long)l * (p + 1) * 2;
-            double val[NF], xt[3], xp[3];
-            for (int f = 0; f < NF; ++f) val[f] = G[f * (p + 1)].x;
-            for (int c = 0; c < 3; ++c) { xt[c] = G[(NF + c) * (p + 1)].x; xp[c] = 0.0; }
-            for (int m = 1; m <= p; ++m) {
-                const double cm = 2.0 * tr[2 * m], sm = 2.0 * tr[2 * m + 1];
-                for (int f = 0; f < NF; ++f) {
-                    const double2 g = G[f * (p + 1) + m];
-                    val[f] += g.x * cm - g.y * sm;
-                    if (f < 3) xp[f] -= m * (g.x * sm + g.y * cm);
-                }
-                for (int c = 0; c < 3; ++c) {
-                    const double2 g = G[(NF + c) * (p + 1) + m];
-                    xt[c] += g.x * cm - g.y * sm;
-                }
-            }
-            for (int c = 0; c < 3; ++c) xp[c] *= rs;
-            const double cx = xt[1] * xp[2] - xt[2] * xp[1];
-            const double cy = xt[2] * xp[0] - xt[0] * xp[2];
-            const double cz = xt[0] * xp[1] - xt[1] * xp[0];
+            const double* val = R + l * NV;
+            const double xt0 = val[3], xt1 = val[4], xt2 = val[5];
+            const double xp0 = val[6], xp1 = val[7], xp2 = val[8];
+            const double cx = xt1 * xp2 - xt2 * xp1;
+            const double cy = xt2 * xp0 - xt0 * xp2;
+            const double cz = xt0 * xp1 - xt1 * xp0;
             const double J = sqrt(cx * cx + cy * cy + cz * cz);
             const double w = wi * J, iJ = 1.0 / J;
             const double nx = cx * iJ, ny = cy * iJ, nz = cz * iJ;
@@ -370,7 +487,7 @@ __global__ __launch_bounds__(kThreads) void k_self(
             const double hn = hx * nx + hy * ny + hz * nz;
             if constexpr (HF) {
                 if (wS) {
-                    const double f0 = val[FOFF], f1 = val[FOFF + 1], f2 = val[FOFF + 2];
+                    const double f0 = val[VD], f1 = val[VD + 1], f2 = val[VD + 2];
                     const double hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
                     acc[0] += w * (f0 * ir + hx * hf);
                     acc[1] += w * (f1 * ir + hy * hf);
@@ -379,7 +496,7 @@ __global__ __launch_bounds__(kThreads) void k_self(
             }
             if constexpr (HF || HU) {
                 if (wD) {
-                    constexpr int uo = HU ? UOFF : FOFF;
+                    constexpr int uo = VD + (HU ? UOFF : FOFF) - 3;
                     const double hu = hx * val[uo] + hy * val[uo + 1] + hz * val[uo + 2];
                     const double t = -6.0 * w * hu * hn * ir3 * ir2;
                     acc[3] += t * hx;
@@ -388,15 +505,13 @@ __global__ __launch_bounds__(kThreads) void k_self(
                 }
             }
             if constexpr (HS) {
-                const double sg = w * val[SOFF];
+                const double sg = w * val[VD + SOFF - 3];
                 if (wSL) acc[6] += sg * ir;
                 if (wL) acc[7] += sg * hn * ir3;
                 if (wK) acc[8] += sg * (hx * n0[0] + hy * n0[1] + hz * n0[2]) * ir3;
             }
         }
-        __syncthreads();
     }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int c = 0; c < 9; ++c) {
         const double s = wave_sum(acc[c]);
         if (lane == 0) red[wv][c] = s;
@@ -635,7 +750,11 @@ struct ehd_ctx {
     std::vector<DropInfo> info;
     long long T = 0, Spad = 0, ncoef_total = 0;  // ncoef_total: doubles per field
     int ntiles = 0;
+    // singular self-interaction work, by degree class (PMAX 16, 24, 32, 48):
+    // targets of the class's drops, most expensive drops first
     std::vector<int> self_order_h;
+    int cls_off[5] = {0, 0, 0, 0, 0};
+    std::vector<int> cls_drops[4];
 
     // device buffers
     std::vector<void*> allocs;
@@ -743,25 +862,57 @@ static int upload(ehd_ctx* ctx, T** out, const std::vector<T>& h)
     return EHD_OK;
 }
 
-static size_t self_lds_bytes(int p, int nf) { return (size_t)(nf * ncoef(p) + (nf + 3) * (p + 1)) * 16; }
+static const int kClassP[4] = {16, 24, 32, 48};
+static int degree_class(int p)
+{
+    for (int c = 0; c < 4; ++c)
+        if (p <= kClassP[c]) return c;
+    return -1;
+}
+
+// Dynamic LDS of k_self for a set of drops: rotated coefficients of nf
+// fields plus the larger of the Fourier-coefficient block and the node block.
+static size_t self_lds_bytes(const ehd_ctx* ctx, const std::vector<int>& drops, int nf)
+{
+    size_t best = 0;
+    for (int d : drops) {
+        const DropInfo& D = ctx->info[d];
+        const HalfGrid h = half_grid(D.p, D.nlon_s);
+        const size_t g = (size_t)(4 * h.nKE + 4 * h.nKO) * 16 * 8;
+        const size_t nodes = (size_t)D.nlon_s * (nf + 6) * 8;
+        best = std::max(best, (size_t)nf * ncoef(D.p) * 16 + std::max(g, nodes));
+    }
+    return best;
+}
+
+template <int PMAX, bool HF, bool HU, bool HS>
+static int launch_self_class(ehd_ctx* ctx, int cls, const double* f, const double* u, const double* s,
+                             unsigned kinds)
+{
+    constexpr int NF = 3 + (HF ? 3 : 0) + (HU ? 3 : 0) + (HS ? 1 : 0);
+    const int count = ctx->cls_off[cls + 1] - ctx->cls_off[cls];
+    if (count == 0) return EHD_OK;
+    const size_t lds = self_lds_bytes(ctx, ctx->cls_drops[cls], NF);
+    if (lds > (size_t)ctx->max_lds)
+        EHD_FAIL(ctx, EHD_E_SHAPE, "self-interaction needs %zu bytes of LDS (limit %d)", lds, ctx->max_lds);
+    if (lds > 65536)
+        EHD_HIP(ctx, hipFuncSetAttribute((const void*)k_self<PMAX, HF, HU, HS>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((k_self<PMAX, HF, HU, HS>), dim3((unsigned)count), dim3(kThreads), lds, ctx->stream,
+                       ctx->d_info, ctx->d_legs, ctx->d_wigs, ctx->d_order + ctx->cls_off[cls], ctx->d_tdrop,
+                       ctx->d_x, f, u, s, ctx->d_tx, ctx->d_tn, ctx->T, kinds, ctx->d_raw);
+    EHD_HIP(ctx, hipGetLastError());
+    return EHD_OK;
+}
 
 template <bool HF, bool HU, bool HS>
 static int launch_self(ehd_ctx* ctx, const double* f, const double* u, const double* s, unsigned kinds)
 {
-    constexpr int NF = 3 + (HF ? 3 : 0) + (HU ? 3 : 0) + (HS ? 1 : 0);
-    int pmax = 1;
-    for (int pp : ctx->p) pmax = std::max(pmax, pp);
-    const size_t lds = self_lds_bytes(pmax, NF);
-    if (lds > (size_t)ctx->max_lds)
-        EHD_FAIL(ctx, EHD_E_SHAPE, "self-interaction needs %zu bytes of LDS (limit %d)", lds, ctx->max_lds);
-    if (lds > 65536)
-        EHD_HIP(ctx, hipFuncSetAttribute((const void*)k_self<HF, HU, HS>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((k_self<HF, HU, HS>), dim3((unsigned)ctx->T), dim3(kThreads), lds, ctx->stream,
-                       ctx->d_info, ctx->d_legs, ctx->d_wigs, ctx->d_order, ctx->d_tdrop, ctx->d_x, f,
-                       u, s, ctx->d_tx, ctx->d_tn, ctx->T, kinds, ctx->d_raw);
-    EHD_HIP(ctx, hipGetLastError());
-    return EHD_OK;
+    int rc = launch_self_class<48, HF, HU, HS>(ctx, 3, f, u, s, kinds);
+    if (!rc) rc = launch_self_class<32, HF, HU, HS>(ctx, 2, f, u, s, kinds);
+    if (!rc) rc = launch_self_class<24, HF, HU, HS>(ctx, 1, f, u, s, kinds);
+    if (!rc) rc = launch_self_class<16, HF, HU, HS>(ctx, 0, f, u, s, kinds);
+    return rc;
 }
 
 extern "C" {
@@ -837,6 +988,9 @@ int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
                      q_self_h[d], q_far_h[d], EHD_MAX_Q);
         if (grid_mode == 1 && p_h[d] < 2)
             EHD_FAIL(ctx, EHD_E_SHAPE, "grid_mode 1 needs p >= 2");
+        if (nlon_of(q_self_h[d], grid_mode) > 256)
+            EHD_FAIL(ctx, EHD_E_SHAPE, "drop %d: q_self = %d gives more than 256 longitudes on the rotated grid",
+                     d, q_self_h[d]);
     }
     EHD_HIP(ctx, hipSetDevice(ctx->device));
     if (ctx->stream) EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -874,8 +1028,42 @@ int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
                 trig[((size_t)l * (pp + 1) + m) * 2] = std::cos(a);
                 trig[((size_t)l * (pp + 1) + m) * 2 + 1] = std::sin(a);
             }
+        // MFMA A fragments of the half-period cos/sin tables (singular grids):
+        // lane holds A[row 16t + lane%16][term 4ks + lane/16]; even-m terms
+        // (cos 0, then cos m, sin m for m = 2, 4, ...) for ks < nKE, odd-m
+        // terms (cos m, sin m for m = 1, 3, ...) after them.
+        std::vector<double> afrag;
+        if (singular) {
+            const HalfGrid h = half_grid(pp, nl);
+            const int nks = h.nKE + h.nKO;
+            afrag.assign((size_t)h.nLT * nks * 64, 0.0);
+            for (int t = 0; t < h.nLT; ++t)
+                for (int ks = 0; ks < nks; ++ks)
+                    for (int lane = 0; lane < 64; ++lane) {
+                        const int l = 16 * t + (lane & 15);
+                        const bool odd = ks >= h.nKE;
+                        const int term = 4 * (odd ? ks - h.nKE : ks) + (lane >> 4);
+                        if (l >= h.H || term >= (odd ? h.KO : h.KE)) continue;
+                        int m;
+                        bool is_cos;
+                        if (!odd) {
+                            if (term == 0) { m = 0; is_cos = true; }
+                            else if (term & 1) { m = term + 1; is_cos = true; }
+                            else { m = term; is_cos = false; }
+                        } else {
+                            if ((term & 1) == 0) { m = term + 1; is_cos = true; }
+                            else { m = term; is_cos = false; }
+                        }
+                        const double a = 2.0 * kPi * (double)((long)m * l % nl) / nl;
+                        afrag[((size_t)t * nks + ks) * 64 + lane] = is_cos ? std::cos(a) : std::sin(a);
+                    }
+        }
         LegTab L{};
         double* dptr;
+        if (singular) {
+            if (upload(ctx, &dptr, afrag)) return -1;
+            L.afrag = dptr;
+        }
         if (upload(ctx, &dptr, P)) return -1;
         L.P = dptr;
         if (upload(ctx, &dptr, dP)) return -1;
@@ -984,7 +1172,8 @@ int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
         for (int i = 0; i <= D.qf; ++i) rows_f.push_back(make_int2(d, i));
         for (int k = 0; k < ncoef(D.p); ++k) an_items.push_back(make_int2(d, k));
     }
-    // self work order: most expensive targets first
+    // self work order: by degree class (largest first), inside a class the
+    // most expensive drops first
     std::vector<int> dorder(ndrops);
     for (int d = 0; d < ndrops; ++d) dorder[d] = d;
     std::stable_sort(dorder.begin(), dorder.end(), [&](int a, int b) {
@@ -993,10 +1182,18 @@ int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
         return ca > cb;
     });
     ctx->self_order_h.clear();
-    for (int d : dorder) {
-        const DropInfo& D = ctx->info[d];
-        for (long long t = 0; t < (long long)(D.p + 1) * D.nlon_p; ++t) ctx->self_order_h.push_back((int)(D.toff + t));
+    for (int c = 0; c < 4; ++c) ctx->cls_drops[c].clear();
+    for (int cls = 0; cls < 4; ++cls) {
+        ctx->cls_off[cls] = (int)ctx->self_order_h.size();
+        for (int d : dorder) {
+            const DropInfo& D = ctx->info[d];
+            if (degree_class(D.p) != cls) continue;
+            ctx->cls_drops[cls].push_back(d);
+            for (long long t = 0; t < (long long)(D.p + 1) * D.nlon_p; ++t)
+                ctx->self_order_h.push_back((int)(D.toff + t));
+        }
     }
+    ctx->cls_off[4] = (int)ctx->self_order_h.size();
     if ((rc = upload(ctx, &ctx->d_tdrop, tdrop))) return rc;
     if ((rc = upload(ctx, &ctx->d_slot_drop, slot_drop))) return rc;
     if ((rc = upload(ctx, &ctx->d_tile_drop, tile_drop))) return rc;
@@ -1092,11 +1289,12 @@ int ehd_layer_potentials(ehd_ctx* ctx, const double* fcoef_d, const double* ucoe
 
     ctx->mark(1);
     // 2. singular self-interaction (one or two passes depending on LDS)
-    int pmax = 1;
-    for (int pp : ctx->p) pmax = std::max(pmax, pp);
     const int nf_all = 3 + (needF ? 3 : 0) + (needU ? 3 : 0) + (needLap ? 1 : 0);
+    bool fits = true;
+    for (int c = 0; c < 4; ++c)
+        fits = fits && self_lds_bytes(ctx, ctx->cls_drops[c], nf_all) <= (size_t)ctx->max_lds;
     int rc = EHD_OK;
-    if (self_lds_bytes(pmax, nf_all) <= (size_t)ctx->max_lds || !needU || !(needF || needLap)) {
+    if (fits || !needU || !(needF || needLap)) {
         if (needF && needU && needLap) rc = launch_self<true, true, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
         else if (needF && needU) rc = launch_self<true, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
         else if (needF && needLap) rc = launch_self<true, false, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
