@@ -46,6 +46,9 @@ struct LegTab {                // degree-p expansions on a degree-Q grid
     const double* trig;        // [nlon][p+1][2] cos(m phi_l), sin(m phi_l)
     const double* afrag;       // MFMA A fragments of the half-period cos/sin
                                // tables: [row tile][k-step (even, odd)][lane]
+    const double* cs;          // [Q+1][2] cos theta_i, sin theta_i
+    const double* rec;         // [ncoef(p)][2] (a_nm, b_nm) of the recurrence
+                               // Pbar_n^m = a_nm (t Pbar_{n-1}^m - b_nm Pbar_{n-2}^m)
     int p, Q, nlon, pad;
 };
 
@@ -71,6 +74,25 @@ __device__ __forceinline__ int tri_n(int idx)
     while ((n + 1) * (n + 2) / 2 <= idx) ++n;
     while (n * (n + 1) / 2 > idx) --n;
     return n;
+}
+
+// Pointers read from descriptor structs are generic to the compiler; the
+// tables and coefficients live in device global memory, so say so and get
+// global (not flat) loads, which do not hold up LDS traffic.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const T* p)
+{
+    return (const __attribute__((address_space(1))) T*)p;
+}
+
+// 1/sqrt(x) in FP64: hardware estimate refined by two Newton steps
+// (y <- y (3 - x y^2) / 2), relative error at the level of a few ulp.
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * (1.5 - 0.5 * x * y * y);
+    y = y * (1.5 - 0.5 * x * y * y);
+    return y;
 }
 
 template <typename T>
@@ -283,16 +305,19 @@ __host__ __device__ inline HalfGrid half_grid(int p, int nlonq)
     return h;
 }
 
-// Compile-time bounds of one degree class (all p <= PMAX, q <= 2 PMAX + pad).
+// Compile-time bounds of one degree class (all p <= PMAX; the rotated grid
+// has at most 8 row tiles of 16 half-period longitudes).
 template <int PMAX>
 struct SelfClass {
     static constexpr int KSE = (2 * (PMAX / 2) + 1 + 3) / 4;   // max even k-steps
     static constexpr int KSO = (2 * ((PMAX + 1) / 2) + 3) / 4; // max odd k-steps
-    static constexpr int TPW = 2;                              // row tiles per wave (max)
+    static constexpr int NT = PMAX >= 32 ? 512 : 256;          // threads per block
+    static constexpr int NW = NT / 64;                         // waves per block
+    static constexpr int TPW = (8 + NW - 1) / NW;              // row tiles per wave (max)
 };
 
 template <int PMAX, bool HF, bool HU, bool HS>
-__global__ __launch_bounds__(kThreads) void k_self(
+__global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     const DropInfo* __restrict__ drops, const LegTab* __restrict__ legs,
     const WigTab* __restrict__ wigs, const int* __restrict__ order, const int* __restrict__ tdrop,
     const double* __restrict__ xcoef, const double* __restrict__ fcoef,
@@ -306,8 +331,9 @@ __global__ __launch_bounds__(kThreads) void k_self(
     constexpr int VD = 9;                // first density variant
     using SC = SelfClass<PMAX>;
     static_assert(NV <= 16, "at most 16 grid quantities per MFMA column tile");
+    constexpr int NT = SC::NT, NW = SC::NW;
     extern __shared__ double2 lds[];
-    __shared__ double red[kThreads / 64][9];
+    __shared__ double red[NW][9];
 
     const long long tg = order[blockIdx.x];
     const int d = tdrop[tg];
@@ -323,11 +349,11 @@ __global__ __launch_bounds__(kThreads) void k_self(
     double* R = reinterpret_cast<double*>(lds + NF * nc);  // Fourier coefs / node values
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
-    const double* fld[NF];
-    for (int c = 0; c < 3; ++c) fld[c] = xcoef + 3 * D.coff + c * 2 * nc;
-    if (HF) for (int c = 0; c < 3; ++c) fld[FOFF + c] = fcoef + 3 * D.coff + c * 2 * nc;
-    if (HU) for (int c = 0; c < 3; ++c) fld[UOFF + c] = ucoef + 3 * D.coff + c * 2 * nc;
-    if (HS) fld[SOFF] = scoef + D.coff;
+    const __attribute__((address_space(1))) double* fld[NF];
+    for (int c = 0; c < 3; ++c) fld[c] = gmem(xcoef + 3 * D.coff + c * 2 * nc);
+    if (HF) for (int c = 0; c < 3; ++c) fld[FOFF + c] = gmem(fcoef + 3 * D.coff + c * 2 * nc);
+    if (HU) for (int c = 0; c < 3; ++c) fld[UOFF + c] = gmem(ucoef + 3 * D.coff + c * 2 * nc);
+    if (HS) fld[SOFF] = gmem(scoef + D.coff);
 
     // register-resident A operand: cos/sin(m phi_l) fragments of this wave's
     // row tiles, even-m and odd-m blocks
@@ -336,8 +362,8 @@ __global__ __launch_bounds__(kThreads) void k_self(
         const int nks = hg.nKE + hg.nKO;
 #pragma unroll
         for (int tt = 0; tt < SC::TPW; ++tt) {
-            const int t = wv + 4 * tt;
-            const double* src = Lq.afrag + (long long)t * nks * 64 + lane;
+            const int t = wv + NW * tt;
+            const auto src = gmem(Lq.afrag + (long long)t * nks * 64 + lane);
 #pragma unroll
             for (int ks = 0; ks < SC::KSE; ++ks)
                 afE[tt][ks] = (t < hg.nLT && ks < hg.nKE) ? src[(long long)ks * 64] : 0.0;
@@ -350,15 +376,15 @@ __global__ __launch_bounds__(kThreads) void k_self(
     // 1. rotation
     {
         const long wb = ehd::wig_block(p);
-        const double* A = W.A + (long long)j * wb;
-        const double* B = W.B + (long long)j * wb;
-        const double* ph = Lp.trig + (long long)k * (p + 1) * 2;
+        const auto A = gmem(W.A + (long long)j * wb);
+        const auto B = gmem(W.B + (long long)j * wb);
+        const auto ph = gmem(Lp.trig + (long long)k * (p + 1) * 2);
         for (int it = threadIdx.x; it < nc; it += blockDim.x) {
             const int n = tri_n(it), mp = it - n * (n + 1) / 2;
             double are[NF], aim[NF];
             for (int f = 0; f < NF; ++f) { are[f] = 0.0; aim[f] = 0.0; }
-            const double* An = A + ehd::wig_off(n);
-            const double* Bn = B + ehd::wig_off(n);
+            const auto An = A + ehd::wig_off(n);
+            const auto Bn = B + ehd::wig_off(n);
             for (int m = 0; m <= n; ++m) {
                 const double a = An[m * (n + 1) + mp], b = Bn[m * (n + 1) + mp];
                 const double cm = ph[2 * m], sm = ph[2 * m + 1];
@@ -384,76 +410,179 @@ __global__ __launch_bounds__(kThreads) void k_self(
     const int keRows = 4 * hg.nKE, koRows = 4 * hg.nKO;
     double* GE = R;                     // [4 nKE][16]
     double* GO = R + keRows * 16;       // [4 nKO][16]
+    // The Fourier block shares its memory with the node values; rows and
+    // columns it does not rewrite hold finite node values later, which meet
+    // zero A entries (padding terms) or feed unused output columns.  Start
+    // from zeros so that no uninitialised pattern reaches the MFMA.
+    {
+        const int nR = max((keRows + koRows) * 16, Lq.nlon * NV);
+        for (int z = threadIdx.x; z < nR; z += blockDim.x) R[z] = 0.0;
+    }
+
+    // Legendre work item of this thread: (field f, degree pair {mp, p-mp},
+    // part of the concatenated n range of column m0 = mp (n = m0..p) followed
+    // by column m1 = p-mp (n = m1..p; empty when m1 == m0)).  This part covers
+    // local entries [e0, e1); the first one is degree n_s of column m_s.
+    const int npair = p / 2 + 1, nitem = npair * NF;
+    int split = 1;
+    while (split < 8 && nitem * split * 2 <= NT) split *= 2;
+    const int item = threadIdx.x / split, part = threadIdx.x % split;
+    const bool live = item < nitem;
+    const int f = item % NF, mp = item / NF;
+    const int m0 = mp, m1 = p - mp;
+    const int len0 = p + 1 - m0, len1 = (m1 == m0) ? 0 : p + 1 - m1;
+    int e0, e1;
+    {
+        const int len = len0 + len1;
+        const int chunk = (len + split - 1) / split;
+        e0 = live ? min(len, part * chunk) : 0;
+        e1 = live ? min(len, e0 + chunk) : 0;
+    }
+    const bool in0 = e0 < len0;                       // starts in column m0
+    const bool crosses = in0 && e1 > len0;            // continues into column m1
+    const int ms = in0 ? m0 : m1, ns = in0 ? m0 + e0 : m1 + (e0 - len0);
+    const long ks0 = tri(ns, ms), kb0 = tri(m1, m1);
+    const auto cst = gmem(Lq.cs);
+    const auto recg = gmem(Lq.rec);
+    // seeds: Pbar and dPbar/dtheta at (ns, ms), at (ns - 1, ms), and at the
+    // start (m1, m1) of the second column
+    double sP0, sP1, sD0, sD1, sPb, sDb;
+    auto load_seeds = [&](int lat) {
+        const auto Pr = gmem(Lq.P + (long long)lat * nc);
+        const auto Dr = gmem(Lq.dP + (long long)lat * nc);
+        const bool any = e1 > e0, prev = any && ns > ms;
+        sP0 = any ? Pr[ks0] : 0.0;
+        sD0 = any ? Dr[ks0] : 0.0;
+        sP1 = prev ? Pr[ks0 - ns] : 0.0;
+        sD1 = prev ? Dr[ks0 - ns] : 0.0;
+        sPb = crosses ? Pr[kb0] : 0.0;
+        sDb = crosses ? Dr[kb0] : 0.0;
+    };
+    load_seeds(0);
 
     for (int i = 0; i <= Lq.Q; ++i) {
         __syncthreads();  // previous node values consumed, c' complete
-        // a. Legendre sums -> real Fourier coefficients
-        const double* Prow = Lq.P + (long long)i * nc;
-        const double* dProw = Lq.dP + (long long)i * nc;
-        const double rs = Lq.rsin[i];
-        for (int it = threadIdx.x; it < NF * (p + 1); it += blockDim.x) {
-            const int f = it / (p + 1), m = it % (p + 1);
-            double ar = 0.0, ai = 0.0, dr = 0.0, di = 0.0;
-            for (int n = m; n <= p; ++n) {
-                const long kk = tri(n, m);
-                const double2 c = cr[f * nc + kk];
-                const double pv = Prow[kk];
-                ar += pv * c.x;
-                ai += pv * c.y;
-                if (f < 3) {
-                    const double dv = dProw[kk];
-                    dr += dv * c.x;
-                    di += dv * c.y;
+        // a. Legendre sums -> real Fourier coefficients.  Each thread walks
+        //    its n range in order, generating Pbar_n^m(t_i) and its theta
+        //    derivative by the three-term recurrence in n (and the recurrence
+        //    differentiated in theta) from two seeds per range, loaded a
+        //    latitude ahead; the parts of one item are combined by shuffles.
+        const double ti = cst[2 * i], si = cst[2 * i + 1];
+        const double rs = 1.0 / si;
+        {
+            double s[2][4];
+            for (int h = 0; h < 2; ++h)
+                for (int q = 0; q < 4; ++q) s[h][q] = 0.0;
+            {
+                const double2* cf = cr + f * nc;
+                int n = ns;
+                long kk = ks0;
+                double P0 = sP0, P1 = sP1, D0 = sD0, D1 = sD1;
+                double sr = 0.0, sii = 0.0, tr = 0.0, tii = 0.0;
+                double zr = 0.0, zi = 0.0, yr = 0.0, yi = 0.0;   // sums of column m0
+                {
+                    const double2 c = cf[kk];
+                    sr = P0 * c.x;
+                    sii = P0 * c.y;
+                    tr = D0 * c.x;
+                    tii = D0 * c.y;
+                }
+#pragma unroll 4
+                for (int e = e0 + 1; e < e1; ++e) {
+                    const bool sw = (e == len0);              // first entry of column m1
+                    n = sw ? m1 : n + 1;
+                    kk = sw ? kb0 : kk + n;
+                    // at a column start the recurrence coefficients are zero
+                    // (table entries for n = m) and the seed is taken instead
+                    const double ra_ = recg[2 * kk], rb_ = recg[2 * kk + 1];
+                    const double Pn = sw ? sPb : ra_ * (ti * P0 - rb_ * P1);
+                    const double Dn = sw ? sDb : ra_ * (ti * D0 - si * P0 - rb_ * D1);
+                    P1 = P0;
+                    P0 = Pn;
+                    D1 = D0;
+                    D0 = Dn;
+                    zr = sw ? sr : zr;
+                    zi = sw ? sii : zi;
+                    yr = sw ? tr : yr;
+                    yi = sw ? tii : yi;
+                    sr = sw ? 0.0 : sr;
+                    sii = sw ? 0.0 : sii;
+                    tr = sw ? 0.0 : tr;
+                    tii = sw ? 0.0 : tii;
+                    const double2 c = cf[kk];
+                    sr += P0 * c.x;
+                    sii += P0 * c.y;
+                    tr += D0 * c.x;
+                    tii += D0 * c.y;
+                }
+                if (e1 > e0) {
+                    if (crosses) {
+                        s[0][0] = zr; s[0][1] = zi; s[0][2] = yr; s[0][3] = yi;
+                        s[1][0] = sr; s[1][1] = sii; s[1][2] = tr; s[1][3] = tii;
+                    } else {
+                        const int h = in0 ? 0 : 1;
+                        s[h][0] = sr; s[h][1] = sii; s[h][2] = tr; s[h][3] = tii;
+                    }
                 }
             }
-            // row (k) of the cos and sin terms of degree m in the E / O blocks
-            double* Gb = (m & 1) ? GO : GE;
-            const int kc = (m == 0) ? 0 : m - 1, ks = m;
-            const double sc = (m == 0) ? 1.0 : 2.0;
-            const int v = (f < 3) ? f : VD + (f - 3);
-            Gb[kc * 16 + v] = sc * ar;
-            if (m > 0) Gb[ks * 16 + v] = -sc * ai;
-            if (f < 3) {
-                Gb[kc * 16 + 3 + f] = sc * dr;
-                if (m > 0) Gb[ks * 16 + 3 + f] = -sc * di;
-                // x_phi / sin theta: cos coef m b_m / s, sin coef -m a_m / s
-                Gb[kc * 16 + 6 + f] = (m == 0) ? 0.0 : -sc * m * ai * rs;
-                if (m > 0) Gb[ks * 16 + 6 + f] = -sc * m * ar * rs;
+            for (int off = 1; off < split; off <<= 1)
+                for (int h = 0; h < 2; ++h)
+                    for (int q = 0; q < 4; ++q) s[h][q] += __shfl_xor(s[h][q], off, 64);
+            if (live && part == 0) {
+                for (int h = 0; h < 2; ++h) {
+                    const int m = h ? p - mp : mp;
+                    if (h == 1 && m == mp) break;
+                    const double ar = s[h][0], ai = s[h][1], dr = s[h][2], di = s[h][3];
+                    // rows of the cos and sin terms of degree m in the E / O blocks
+                    double* Gb = (m & 1) ? GO : GE;
+                    const int kc = (m == 0) ? 0 : m - 1, ks = m;
+                    const double sc = (m == 0) ? 1.0 : 2.0;
+                    const int v = (f < 3) ? f : VD + (f - 3);
+                    Gb[kc * 16 + v] = sc * ar;
+                    if (m > 0) Gb[ks * 16 + v] = -sc * ai;
+                    if (f < 3) {
+                        Gb[kc * 16 + 3 + f] = sc * dr;
+                        if (m > 0) Gb[ks * 16 + 3 + f] = -sc * di;
+                        // x_phi / sin theta: cos coef m b_m / s, sin coef -m a_m / s
+                        Gb[kc * 16 + 6 + f] = (m == 0) ? 0.0 : -sc * m * ai * rs;
+                        if (m > 0) Gb[ks * 16 + 6 + f] = -sc * m * ar * rs;
+                    }
+                }
             }
         }
-        // zero the padding rows of both blocks (their A entries are zero too)
-        for (int z = threadIdx.x; z < (keRows - hg.KE) * 16; z += blockDim.x) GE[hg.KE * 16 + z] = 0.0;
-        for (int z = threadIdx.x; z < (koRows - hg.KO) * 16; z += blockDim.x) GO[hg.KO * 16 + z] = 0.0;
+        // seeds of latitude i + 1, loaded now so that they arrive during the
+        // MFMA and kernel phases (no other global loads are pending then)
+        if (i < Lq.Q) load_seeds(i + 1);
         __syncthreads();
 
-        // b. longitude sums on MFMA
+        // b. longitude sums on MFMA (even and odd chains interleaved)
         dbl4 accE[SC::TPW], accO[SC::TPW];
         for (int tt = 0; tt < SC::TPW; ++tt) { accE[tt] = dbl4{0, 0, 0, 0}; accO[tt] = dbl4{0, 0, 0, 0}; }
+        constexpr int KSM = SC::KSE > SC::KSO ? SC::KSE : SC::KSO;
 #pragma unroll
-        for (int ks = 0; ks < SC::KSE; ++ks) {
-            if (ks < hg.nKE) {
+        for (int ks = 0; ks < KSM; ++ks) {
+            if (ks < SC::KSE && ks < hg.nKE) {
                 const double b = GE[(4 * ks + (lane >> 4)) * 16 + (lane & 15)];
 #pragma unroll
                 for (int tt = 0; tt < SC::TPW; ++tt)
-                    if (wv + 4 * tt < hg.nLT)
-                        accE[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(afE[tt][ks], b, accE[tt], 0, 0, 0);
+                    if (wv + NW * tt < hg.nLT)
+                        accE[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(afE[tt][ks < SC::KSE ? ks : 0], b,
+                                                                        accE[tt], 0, 0, 0);
             }
-        }
-#pragma unroll
-        for (int ks = 0; ks < SC::KSO; ++ks) {
-            if (ks < hg.nKO) {
+            if (ks < SC::KSO && ks < hg.nKO) {
                 const double b = GO[(4 * ks + (lane >> 4)) * 16 + (lane & 15)];
 #pragma unroll
                 for (int tt = 0; tt < SC::TPW; ++tt)
-                    if (wv + 4 * tt < hg.nLT)
-                        accO[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(afO[tt][ks], b, accO[tt], 0, 0, 0);
+                    if (wv + NW * tt < hg.nLT)
+                        accO[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(afO[tt][ks < SC::KSO ? ks : 0], b,
+                                                                        accO[tt], 0, 0, 0);
             }
         }
         __syncthreads();  // all B reads done before the node values overwrite R
         {
             const int v = lane & 15;
             for (int tt = 0; tt < SC::TPW; ++tt) {
-                const int t = wv + 4 * tt;
+                const int t = wv + NW * tt;
                 if (t >= hg.nLT || v >= NV) continue;
                 // MFMA f64 16x16x4 result layout: element r of lane holds
                 // row (lane / 16) + 4 r, column lane % 16
@@ -470,7 +599,7 @@ __global__ __launch_bounds__(kThreads) void k_self(
         __syncthreads();
 
         // c. kernels at the nodes of this latitude
-        const double wi = Lq.wsing[i];
+        const double wi = gmem(Lq.wsing)[i];
         for (int l = threadIdx.x; l < Lq.nlon; l += blockDim.x) {
             const double* val = R + l * NV;
             const double xt0 = val[3], xt1 = val[4], xt2 = val[5];
@@ -478,12 +607,13 @@ __global__ __launch_bounds__(kThreads) void k_self(
             const double cx = xt1 * xp2 - xt2 * xp1;
             const double cy = xt2 * xp0 - xt0 * xp2;
             const double cz = xt0 * xp1 - xt1 * xp0;
-            const double J = sqrt(cx * cx + cy * cy + cz * cz);
-            const double w = wi * J, iJ = 1.0 / J;
+            const double J2 = cx * cx + cy * cy + cz * cz;
+            const double iJ = rsqrt_nr(J2);
+            const double w = wi * J2 * iJ;
             const double nx = cx * iJ, ny = cy * iJ, nz = cz * iJ;
             const double hx = x0[0] - val[0], hy = x0[1] - val[1], hz = x0[2] - val[2];
             const double r2 = hx * hx + hy * hy + hz * hz;
-            const double ir = 1.0 / sqrt(r2), ir2 = ir * ir, ir3 = ir * ir2;
+            const double ir = rsqrt_nr(r2), ir2 = ir * ir, ir3 = ir * ir2;
             const double hn = hx * nx + hy * ny + hz * nz;
             if constexpr (HF) {
                 if (wS) {
@@ -519,7 +649,7 @@ __global__ __launch_bounds__(kThreads) void k_self(
     __syncthreads();
     if (threadIdx.x < 9) {
         double s = 0.0;
-        for (int w = 0; w < kThreads / 64; ++w) s += red[w][threadIdx.x];
+        for (int w = 0; w < NW; ++w) s += red[w][threadIdx.x];
         const unsigned bit = threadIdx.x < 3 ? EHD_STOKES_SL : threadIdx.x < 6 ? EHD_STOKES_DL
                              : threadIdx.x == 6 ? EHD_LAP_SL : threadIdx.x == 7 ? EHD_LAP_DL
                                                                                 : EHD_LAP_DLADJ;
@@ -898,7 +1028,8 @@ static int launch_self_class(ehd_ctx* ctx, int cls, const double* f, const doubl
     if (lds > 65536)
         EHD_HIP(ctx, hipFuncSetAttribute((const void*)k_self<PMAX, HF, HU, HS>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((k_self<PMAX, HF, HU, HS>), dim3((unsigned)count), dim3(kThreads), lds, ctx->stream,
+    hipLaunchKernelGGL((k_self<PMAX, HF, HU, HS>), dim3((unsigned)count), dim3(SelfClass<PMAX>::NT), lds,
+                       ctx->stream,
                        ctx->d_info, ctx->d_legs, ctx->d_wigs, ctx->d_order + ctx->cls_off[cls], ctx->d_tdrop,
                        ctx->d_x, f, u, s, ctx->d_tx, ctx->d_tn, ctx->T, kinds, ctx->d_raw);
     EHD_HIP(ctx, hipGetLastError());
@@ -1076,6 +1207,24 @@ int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
         L.rsin = dptr;
         if (upload(ctx, &dptr, trig)) return -1;
         L.trig = dptr;
+        {
+            std::vector<double> cs(2 * (Q + 1)), rec(2 * ncoef(pp), 0.0);
+            for (int i = 0; i <= Q; ++i) {
+                cs[2 * i] = t[i];
+                cs[2 * i + 1] = std::sqrt((1.0 - t[i]) * (1.0 + t[i]));
+            }
+            for (int m = 0; m <= pp; ++m)
+                for (int n = m + 1; n <= pp; ++n) {
+                    const double nn = n, mm = m;
+                    rec[2 * tri(n, m)] = std::sqrt((4.0 * nn * nn - 1.0) / (nn * nn - mm * mm));
+                    rec[2 * tri(n, m) + 1] =
+                        std::sqrt(((nn - 1.0) * (nn - 1.0) - mm * mm) / (4.0 * (nn - 1.0) * (nn - 1.0) - 1.0));
+                }
+            if (upload(ctx, &dptr, cs)) return -1;
+            L.cs = dptr;
+            if (upload(ctx, &dptr, rec)) return -1;
+            L.rec = dptr;
+        }
         L.p = pp;
         L.Q = Q;
         L.nlon = nl;
