@@ -46,9 +46,8 @@ struct LegTab {                // degree-p expansions on a degree-Q grid
     const double* trig;        // [nlon][p+1][2] cos(m phi_l), sin(m phi_l)
     const double* afrag;       // MFMA A fragments of the half-period cos/sin
                                // tables: [row tile][k-step (even, odd)][lane]
-    const double* cs;          // [Q+1][2] cos theta_i, sin theta_i
-    const double* rec;         // [ncoef(p)][2] (a_nm, b_nm) of the recurrence
-                               // Pbar_n^m = a_nm (t Pbar_{n-1}^m - b_nm Pbar_{n-2}^m)
+    const double* Pc;          // singular grids: [Q+1][cm(m) + n - m] Pbar_n^m, columns
+    const double* dPc;         // of fixed m stored contiguously (cm: column_start)
     int p, Q, nlon, pad;
 };
 
@@ -67,6 +66,10 @@ struct DropInfo {
     long long ns;              // real far-field source nodes
     double c[3];               // reference centre (mean position)
 };
+
+// Column-major index of the (n, m) triangle, n = m..p: column m starts at
+// column_start(p, m) = m (p + 1) - m (m - 1) / 2.
+__host__ __device__ inline int column_start(int p, int m) { return m * (p + 1) - m * (m - 1) / 2; }
 
 __device__ __forceinline__ int tri_n(int idx)
 {
@@ -395,7 +398,8 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
                     aim[f] += b * (c0 * sm + c1 * cm);
                 }
             }
-            for (int f = 0; f < NF; ++f) cr[f * nc + it] = make_double2(are[f], aim[f]);
+            const int cpos = column_start(p, mp) + n - mp;   // column-major position
+            for (int f = 0; f < NF; ++f) cr[f * nc + cpos] = make_double2(are[f], aim[f]);
         }
     }
 
@@ -408,136 +412,74 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     const bool wSL = (kinds & EHD_LAP_SL) && HS, wL = (kinds & EHD_LAP_DL) && HS;
     const bool wK = (kinds & EHD_LAP_DLADJ) && HS;
     const int keRows = 4 * hg.nKE, koRows = 4 * hg.nKO;
-    double* GE = R;                     // [4 nKE][16]
-    double* GO = R + keRows * 16;       // [4 nKO][16]
-    // The Fourier block shares its memory with the node values; rows and
-    // columns it does not rewrite hold finite node values later, which meet
-    // zero A entries (padding terms) or feed unused output columns.  Start
-    // from zeros so that no uninitialised pattern reaches the MFMA.
+    const int gsz = (keRows + koRows) * 16;            // one latitude's Fourier block
+    // Two latitudes per pass: Fourier blocks G[0], G[1] (even rows, then odd
+    // rows, 16 columns each); afterwards the same memory holds the node values
+    // of one latitude at a time.  Rows and columns a block does not rewrite
+    // hold finite node values later, which meet zero A entries (padding
+    // terms) or feed unused output columns; start from zeros so that no
+    // uninitialised pattern reaches the MFMA.
     {
-        const int nR = max((keRows + koRows) * 16, Lq.nlon * NV);
+        const int nR = max(2 * gsz, Lq.nlon * NV);
         for (int z = threadIdx.x; z < nR; z += blockDim.x) R[z] = 0.0;
     }
 
-    // Legendre work item of this thread: (field f, degree pair {mp, p-mp},
-    // part of the concatenated n range of column m0 = mp (n = m0..p) followed
-    // by column m1 = p-mp (n = m1..p; empty when m1 == m0)).  This part covers
-    // local entries [e0, e1); the first one is degree n_s of column m_s.
-    const int npair = p / 2 + 1, nitem = npair * NF;
-    int split = 1;
-    while (split < 8 && nitem * split * 2 <= NT) split *= 2;
-    const int item = threadIdx.x / split, part = threadIdx.x % split;
-    const bool live = item < nitem;
-    const int f = item % NF, mp = item / NF;
-    const int m0 = mp, m1 = p - mp;
-    const int len0 = p + 1 - m0, len1 = (m1 == m0) ? 0 : p + 1 - m1;
-    int e0, e1;
-    {
-        const int len = len0 + len1;
-        const int chunk = (len + split - 1) / split;
-        e0 = live ? min(len, part * chunk) : 0;
-        e1 = live ? min(len, e0 + chunk) : 0;
-    }
-    const bool in0 = e0 < len0;                       // starts in column m0
-    const bool crosses = in0 && e1 > len0;            // continues into column m1
-    const int ms = in0 ? m0 : m1, ns = in0 ? m0 + e0 : m1 + (e0 - len0);
-    const long ks0 = tri(ns, ms), kb0 = tri(m1, m1);
-    const auto cst = gmem(Lq.cs);
-    const auto recg = gmem(Lq.rec);
-    // seeds: Pbar and dPbar/dtheta at (ns, ms), at (ns - 1, ms), and at the
-    // start (m1, m1) of the second column
-    double sP0, sP1, sD0, sD1, sPb, sDb;
-    auto load_seeds = [&](int lat) {
-        const auto Pr = gmem(Lq.P + (long long)lat * nc);
-        const auto Dr = gmem(Lq.dP + (long long)lat * nc);
-        const bool any = e1 > e0, prev = any && ns > ms;
-        sP0 = any ? Pr[ks0] : 0.0;
-        sD0 = any ? Dr[ks0] : 0.0;
-        sP1 = prev ? Pr[ks0 - ns] : 0.0;
-        sD1 = prev ? Dr[ks0 - ns] : 0.0;
-        sPb = crosses ? Pr[kb0] : 0.0;
-        sDb = crosses ? Dr[kb0] : 0.0;
-    };
-    load_seeds(0);
+    // Legendre work item of this thread: field f (fastest) and degree
+    // column m; it walks n = m..p through contiguous column-major storage.
+    const int f = threadIdx.x % NF, mcol = threadIdx.x / NF;
+    const bool live = mcol <= p;
+    const int cstart = live ? column_start(p, mcol) : 0, clen = live ? p + 1 - mcol : 0;
 
-    for (int i = 0; i <= Lq.Q; ++i) {
+    for (int i = 0; i <= Lq.Q; i += 2) {
+        const bool two = i + 1 <= Lq.Q;
         __syncthreads();  // previous node values consumed, c' complete
-        // a. Legendre sums -> real Fourier coefficients.  Each thread walks
-        //    its n range in order, generating Pbar_n^m(t_i) and its theta
-        //    derivative by the three-term recurrence in n (and the recurrence
-        //    differentiated in theta) from two seeds per range, loaded a
-        //    latitude ahead; the parts of one item are combined by shuffles.
-        const double ti = cst[2 * i], si = cst[2 * i + 1];
-        const double rs = 1.0 / si;
+        // a. Legendre sums -> real Fourier coefficients of latitudes i, i+1
         {
-            double s[2][4];
-            for (int h = 0; h < 2; ++h)
-                for (int q = 0; q < 4; ++q) s[h][q] = 0.0;
-            {
-                const double2* cf = cr + f * nc;
-                int n = ns;
-                long kk = ks0;
-                double P0 = sP0, P1 = sP1, D0 = sD0, D1 = sD1;
-                double sr = 0.0, sii = 0.0, tr = 0.0, tii = 0.0;
-                double zr = 0.0, zi = 0.0, yr = 0.0, yi = 0.0;   // sums of column m0
-                {
-                    const double2 c = cf[kk];
-                    sr = P0 * c.x;
-                    sii = P0 * c.y;
-                    tr = D0 * c.x;
-                    tii = D0 * c.y;
-                }
+            const int i1 = two ? i + 1 : i;
+            const auto P0 = gmem(Lq.Pc + (long long)i * nc + cstart);
+            const auto D0 = gmem(Lq.dPc + (long long)i * nc + cstart);
+            const auto P1 = gmem(Lq.Pc + (long long)i1 * nc + cstart);
+            const auto D1 = gmem(Lq.dPc + (long long)i1 * nc + cstart);
+            const double2* cf = cr + f * nc + cstart;
+            double ar0 = 0.0, ai0 = 0.0, dr0 = 0.0, di0 = 0.0;
+            double ar1 = 0.0, ai1 = 0.0, dr1 = 0.0, di1 = 0.0;
+            if (f < 3) {
 #pragma unroll 4
-                for (int e = e0 + 1; e < e1; ++e) {
-                    const bool sw = (e == len0);              // first entry of column m1
-                    n = sw ? m1 : n + 1;
-                    kk = sw ? kb0 : kk + n;
-                    // at a column start the recurrence coefficients are zero
-                    // (table entries for n = m) and the seed is taken instead
-                    const double ra_ = recg[2 * kk], rb_ = recg[2 * kk + 1];
-                    const double Pn = sw ? sPb : ra_ * (ti * P0 - rb_ * P1);
-                    const double Dn = sw ? sDb : ra_ * (ti * D0 - si * P0 - rb_ * D1);
-                    P1 = P0;
-                    P0 = Pn;
-                    D1 = D0;
-                    D0 = Dn;
-                    zr = sw ? sr : zr;
-                    zi = sw ? sii : zi;
-                    yr = sw ? tr : yr;
-                    yi = sw ? tii : yi;
-                    sr = sw ? 0.0 : sr;
-                    sii = sw ? 0.0 : sii;
-                    tr = sw ? 0.0 : tr;
-                    tii = sw ? 0.0 : tii;
-                    const double2 c = cf[kk];
-                    sr += P0 * c.x;
-                    sii += P0 * c.y;
-                    tr += D0 * c.x;
-                    tii += D0 * c.y;
+                for (int j = 0; j < clen; ++j) {
+                    const double2 c = cf[j];
+                    const double p0 = P0[j], d0 = D0[j], p1 = P1[j], d1 = D1[j];
+                    ar0 += p0 * c.x;
+                    ai0 += p0 * c.y;
+                    dr0 += d0 * c.x;
+                    di0 += d0 * c.y;
+                    ar1 += p1 * c.x;
+                    ai1 += p1 * c.y;
+                    dr1 += d1 * c.x;
+                    di1 += d1 * c.y;
                 }
-                if (e1 > e0) {
-                    if (crosses) {
-                        s[0][0] = zr; s[0][1] = zi; s[0][2] = yr; s[0][3] = yi;
-                        s[1][0] = sr; s[1][1] = sii; s[1][2] = tr; s[1][3] = tii;
-                    } else {
-                        const int h = in0 ? 0 : 1;
-                        s[h][0] = sr; s[h][1] = sii; s[h][2] = tr; s[h][3] = tii;
-                    }
+            } else {
+#pragma unroll 4
+                for (int j = 0; j < clen; ++j) {
+                    const double2 c = cf[j];
+                    const double p0 = P0[j], p1 = P1[j];
+                    ar0 += p0 * c.x;
+                    ai0 += p0 * c.y;
+                    ar1 += p1 * c.x;
+                    ai1 += p1 * c.y;
                 }
             }
-            for (int off = 1; off < split; off <<= 1)
-                for (int h = 0; h < 2; ++h)
-                    for (int q = 0; q < 4; ++q) s[h][q] += __shfl_xor(s[h][q], off, 64);
-            if (live && part == 0) {
-                for (int h = 0; h < 2; ++h) {
-                    const int m = h ? p - mp : mp;
-                    if (h == 1 && m == mp) break;
-                    const double ar = s[h][0], ai = s[h][1], dr = s[h][2], di = s[h][3];
+            if (live) {
+                const int m = mcol;
+                const int kc = (m == 0) ? 0 : m - 1, ks = m;
+                const double sc = (m == 0) ? 1.0 : 2.0;
+                const int v = (f < 3) ? f : VD + (f - 3);
+                for (int sl = 0; sl < 2; ++sl) {
+                    if (sl == 1 && !two) break;
+                    const double ar = sl ? ar1 : ar0, ai = sl ? ai1 : ai0;
+                    const double dr = sl ? dr1 : dr0, di = sl ? di1 : di0;
+                    const double rs = gmem(Lq.rsin)[i + sl];
                     // rows of the cos and sin terms of degree m in the E / O blocks
-                    double* Gb = (m & 1) ? GO : GE;
-                    const int kc = (m == 0) ? 0 : m - 1, ks = m;
-                    const double sc = (m == 0) ? 1.0 : 2.0;
-                    const int v = (f < 3) ? f : VD + (f - 3);
+                    double* Gb = R + sl * gsz + ((m & 1) ? keRows * 16 : 0);
                     Gb[kc * 16 + v] = sc * ar;
                     if (m > 0) Gb[ks * 16 + v] = -sc * ai;
                     if (f < 3) {
@@ -550,95 +492,108 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
                 }
             }
         }
-        // seeds of latitude i + 1, loaded now so that they arrive during the
-        // MFMA and kernel phases (no other global loads are pending then)
-        if (i < Lq.Q) load_seeds(i + 1);
         __syncthreads();
 
-        // b. longitude sums on MFMA (even and odd chains interleaved)
-        dbl4 accE[SC::TPW], accO[SC::TPW];
-        for (int tt = 0; tt < SC::TPW; ++tt) { accE[tt] = dbl4{0, 0, 0, 0}; accO[tt] = dbl4{0, 0, 0, 0}; }
+        // b. longitude sums on MFMA (even and odd chains of both latitudes
+        //    interleaved)
+        dbl4 accE[2][SC::TPW], accO[2][SC::TPW];
+        for (int sl = 0; sl < 2; ++sl)
+            for (int tt = 0; tt < SC::TPW; ++tt) {
+                accE[sl][tt] = dbl4{0, 0, 0, 0};
+                accO[sl][tt] = dbl4{0, 0, 0, 0};
+            }
         constexpr int KSM = SC::KSE > SC::KSO ? SC::KSE : SC::KSO;
+        const int boff = (4 * 0 + (lane >> 4)) * 16 + (lane & 15);
 #pragma unroll
         for (int ks = 0; ks < KSM; ++ks) {
             if (ks < SC::KSE && ks < hg.nKE) {
-                const double b = GE[(4 * ks + (lane >> 4)) * 16 + (lane & 15)];
+                const double b0 = R[ks * 64 + boff], b1 = R[gsz + ks * 64 + boff];
 #pragma unroll
                 for (int tt = 0; tt < SC::TPW; ++tt)
-                    if (wv + NW * tt < hg.nLT)
-                        accE[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(afE[tt][ks < SC::KSE ? ks : 0], b,
-                                                                        accE[tt], 0, 0, 0);
+                    if (wv + NW * tt < hg.nLT) {
+                        const double a = afE[tt][ks < SC::KSE ? ks : 0];
+                        accE[0][tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, accE[0][tt], 0, 0, 0);
+                        accE[1][tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, accE[1][tt], 0, 0, 0);
+                    }
             }
             if (ks < SC::KSO && ks < hg.nKO) {
-                const double b = GO[(4 * ks + (lane >> 4)) * 16 + (lane & 15)];
+                const double b0 = R[keRows * 16 + ks * 64 + boff], b1 = R[gsz + keRows * 16 + ks * 64 + boff];
 #pragma unroll
                 for (int tt = 0; tt < SC::TPW; ++tt)
-                    if (wv + NW * tt < hg.nLT)
-                        accO[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(afO[tt][ks < SC::KSO ? ks : 0], b,
-                                                                        accO[tt], 0, 0, 0);
+                    if (wv + NW * tt < hg.nLT) {
+                        const double a = afO[tt][ks < SC::KSO ? ks : 0];
+                        accO[0][tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, accO[0][tt], 0, 0, 0);
+                        accO[1][tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, accO[1][tt], 0, 0, 0);
+                    }
             }
         }
-        __syncthreads();  // all B reads done before the node values overwrite R
-        {
-            const int v = lane & 15;
-            for (int tt = 0; tt < SC::TPW; ++tt) {
-                const int t = wv + NW * tt;
-                if (t >= hg.nLT || v >= NV) continue;
-                // MFMA f64 16x16x4 result layout: element r of lane holds
-                // row (lane / 16) + 4 r, column lane % 16
+
+        for (int sl = 0; sl < 2; ++sl) {
+            if (sl == 1 && !two) break;
+            __syncthreads();  // B reads (sl = 0) or node reads (sl = 1) done before R is rewritten
+            {
+                const int v = lane & 15;
+                for (int tt = 0; tt < SC::TPW; ++tt) {
+                    const int t = wv + NW * tt;
+                    if (t >= hg.nLT || v >= NV) continue;
+                    // MFMA f64 16x16x4 result layout: element r of lane holds
+                    // row (lane / 16) + 4 r, column lane % 16
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int l = 16 * t + (lane >> 4) + 4 * r;
-                    if (l < hg.H) {
-                        R[l * NV + v] = accE[tt][r] + accO[tt][r];
-                        R[(l + hg.H) * NV + v] = accE[tt][r] - accO[tt][r];
+                    for (int r = 0; r < 4; ++r) {
+                        const int l = 16 * t + (lane >> 4) + 4 * r;
+                        if (l < hg.H) {
+                            const double e = sl ? accE[1][tt][r] : accE[0][tt][r];
+                            const double o = sl ? accO[1][tt][r] : accO[0][tt][r];
+                            R[l * NV + v] = e + o;
+                            R[(l + hg.H) * NV + v] = e - o;
+                        }
                     }
                 }
             }
-        }
-        __syncthreads();
+            __syncthreads();
 
-        // c. kernels at the nodes of this latitude
-        const double wi = gmem(Lq.wsing)[i];
-        for (int l = threadIdx.x; l < Lq.nlon; l += blockDim.x) {
-            const double* val = R + l * NV;
-            const double xt0 = val[3], xt1 = val[4], xt2 = val[5];
-            const double xp0 = val[6], xp1 = val[7], xp2 = val[8];
-            const double cx = xt1 * xp2 - xt2 * xp1;
-            const double cy = xt2 * xp0 - xt0 * xp2;
-            const double cz = xt0 * xp1 - xt1 * xp0;
-            const double J2 = cx * cx + cy * cy + cz * cz;
-            const double iJ = rsqrt_nr(J2);
-            const double w = wi * J2 * iJ;
-            const double nx = cx * iJ, ny = cy * iJ, nz = cz * iJ;
-            const double hx = x0[0] - val[0], hy = x0[1] - val[1], hz = x0[2] - val[2];
-            const double r2 = hx * hx + hy * hy + hz * hz;
-            const double ir = rsqrt_nr(r2), ir2 = ir * ir, ir3 = ir * ir2;
-            const double hn = hx * nx + hy * ny + hz * nz;
-            if constexpr (HF) {
-                if (wS) {
-                    const double f0 = val[VD], f1 = val[VD + 1], f2 = val[VD + 2];
-                    const double hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
-                    acc[0] += w * (f0 * ir + hx * hf);
-                    acc[1] += w * (f1 * ir + hy * hf);
-                    acc[2] += w * (f2 * ir + hz * hf);
+            // c. kernels at the nodes of latitude i + sl
+            const double wi = gmem(Lq.wsing)[i + sl];
+            for (int l = threadIdx.x; l < Lq.nlon; l += blockDim.x) {
+                const double* val = R + l * NV;
+                const double xt0 = val[3], xt1 = val[4], xt2 = val[5];
+                const double xp0 = val[6], xp1 = val[7], xp2 = val[8];
+                const double cx = xt1 * xp2 - xt2 * xp1;
+                const double cy = xt2 * xp0 - xt0 * xp2;
+                const double cz = xt0 * xp1 - xt1 * xp0;
+                const double J2 = cx * cx + cy * cy + cz * cz;
+                const double iJ = rsqrt_nr(J2);
+                const double w = wi * J2 * iJ;
+                const double nx = cx * iJ, ny = cy * iJ, nz = cz * iJ;
+                const double hx = x0[0] - val[0], hy = x0[1] - val[1], hz = x0[2] - val[2];
+                const double r2 = hx * hx + hy * hy + hz * hz;
+                const double ir = rsqrt_nr(r2), ir2 = ir * ir, ir3 = ir * ir2;
+                const double hn = hx * nx + hy * ny + hz * nz;
+                if constexpr (HF) {
+                    if (wS) {
+                        const double f0 = val[VD], f1 = val[VD + 1], f2 = val[VD + 2];
+                        const double hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
+                        acc[0] += w * (f0 * ir + hx * hf);
+                        acc[1] += w * (f1 * ir + hy * hf);
+                        acc[2] += w * (f2 * ir + hz * hf);
+                    }
                 }
-            }
-            if constexpr (HF || HU) {
-                if (wD) {
-                    constexpr int uo = VD + (HU ? UOFF : FOFF) - 3;
-                    const double hu = hx * val[uo] + hy * val[uo + 1] + hz * val[uo + 2];
-                    const double t = -6.0 * w * hu * hn * ir3 * ir2;
-                    acc[3] += t * hx;
-                    acc[4] += t * hy;
-                    acc[5] += t * hz;
+                if constexpr (HF || HU) {
+                    if (wD) {
+                        constexpr int uo = VD + (HU ? UOFF : FOFF) - 3;
+                        const double hu = hx * val[uo] + hy * val[uo + 1] + hz * val[uo + 2];
+                        const double t = -6.0 * w * hu * hn * ir3 * ir2;
+                        acc[3] += t * hx;
+                        acc[4] += t * hy;
+                        acc[5] += t * hz;
+                    }
                 }
-            }
-            if constexpr (HS) {
-                const double sg = w * val[VD + SOFF - 3];
-                if (wSL) acc[6] += sg * ir;
-                if (wL) acc[7] += sg * hn * ir3;
-                if (wK) acc[8] += sg * (hx * n0[0] + hy * n0[1] + hz * n0[2]) * ir3;
+                if constexpr (HS) {
+                    const double sg = w * val[VD + SOFF - 3];
+                    if (wSL) acc[6] += sg * ir;
+                    if (wL) acc[7] += sg * hn * ir3;
+                    if (wK) acc[8] += sg * (hx * n0[0] + hy * n0[1] + hz * n0[2]) * ir3;
+                }
             }
         }
     }
@@ -1001,14 +956,15 @@ static int degree_class(int p)
 }
 
 // Dynamic LDS of k_self for a set of drops: rotated coefficients of nf
-// fields plus the larger of the Fourier-coefficient block and the node block.
+// fields plus the larger of two latitudes' Fourier blocks and one latitude's
+// node values.
 static size_t self_lds_bytes(const ehd_ctx* ctx, const std::vector<int>& drops, int nf)
 {
     size_t best = 0;
     for (int d : drops) {
         const DropInfo& D = ctx->info[d];
         const HalfGrid h = half_grid(D.p, D.nlon_s);
-        const size_t g = (size_t)(4 * h.nKE + 4 * h.nKO) * 16 * 8;
+        const size_t g = (size_t)2 * (4 * h.nKE + 4 * h.nKO) * 16 * 8;  // two latitudes
         const size_t nodes = (size_t)D.nlon_s * (nf + 6) * 8;
         best = std::max(best, (size_t)nf * ncoef(D.p) * 16 + std::max(g, nodes));
     }
@@ -1023,7 +979,8 @@ static int launch_self_class(ehd_ctx* ctx, int cls, const double* f, const doubl
     const int count = ctx->cls_off[cls + 1] - ctx->cls_off[cls];
     if (count == 0) return EHD_OK;
     const size_t lds = self_lds_bytes(ctx, ctx->cls_drops[cls], NF);
-    if (lds > (size_t)ctx->max_lds)
+    const size_t lds_static = (size_t)SelfClass<PMAX>::NW * 9 * 8;   // reduction scratch
+    if (lds + lds_static > (size_t)ctx->max_lds)
         EHD_FAIL(ctx, EHD_E_SHAPE, "self-interaction needs %zu bytes of LDS (limit %d)", lds, ctx->max_lds);
     if (lds > 65536)
         EHD_HIP(ctx, hipFuncSetAttribute((const void*)k_self<PMAX, HF, HU, HS>,
@@ -1207,23 +1164,19 @@ int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
         L.rsin = dptr;
         if (upload(ctx, &dptr, trig)) return -1;
         L.trig = dptr;
-        {
-            std::vector<double> cs(2 * (Q + 1)), rec(2 * ncoef(pp), 0.0);
-            for (int i = 0; i <= Q; ++i) {
-                cs[2 * i] = t[i];
-                cs[2 * i + 1] = std::sqrt((1.0 - t[i]) * (1.0 + t[i]));
-            }
-            for (int m = 0; m <= pp; ++m)
-                for (int n = m + 1; n <= pp; ++n) {
-                    const double nn = n, mm = m;
-                    rec[2 * tri(n, m)] = std::sqrt((4.0 * nn * nn - 1.0) / (nn * nn - mm * mm));
-                    rec[2 * tri(n, m) + 1] =
-                        std::sqrt(((nn - 1.0) * (nn - 1.0) - mm * mm) / (4.0 * (nn - 1.0) * (nn - 1.0) - 1.0));
-                }
-            if (upload(ctx, &dptr, cs)) return -1;
-            L.cs = dptr;
-            if (upload(ctx, &dptr, rec)) return -1;
-            L.rec = dptr;
+        if (singular) {
+            const long ncp = ncoef(pp);
+            std::vector<double> Pc((size_t)(Q + 1) * ncp), dPc((size_t)(Q + 1) * ncp);
+            for (int i = 0; i <= Q; ++i)
+                for (int m = 0; m <= pp; ++m)
+                    for (int n = m; n <= pp; ++n) {
+                        Pc[(size_t)i * ncp + column_start(pp, m) + n - m] = P[(size_t)i * ncp + tri(n, m)];
+                        dPc[(size_t)i * ncp + column_start(pp, m) + n - m] = dP[(size_t)i * ncp + tri(n, m)];
+                    }
+            if (upload(ctx, &dptr, Pc)) return -1;
+            L.Pc = dptr;
+            if (upload(ctx, &dptr, dPc)) return -1;
+            L.dPc = dptr;
         }
         L.p = pp;
         L.Q = Q;
@@ -1441,7 +1394,7 @@ int ehd_layer_potentials(ehd_ctx* ctx, const double* fcoef_d, const double* ucoe
     const int nf_all = 3 + (needF ? 3 : 0) + (needU ? 3 : 0) + (needLap ? 1 : 0);
     bool fits = true;
     for (int c = 0; c < 4; ++c)
-        fits = fits && self_lds_bytes(ctx, ctx->cls_drops[c], nf_all) <= (size_t)ctx->max_lds;
+        fits = fits && self_lds_bytes(ctx, ctx->cls_drops[c], nf_all) + 8 * 9 * 8 <= (size_t)ctx->max_lds;
     int rc = EHD_OK;
     if (fits || !needU || !(needF || needLap)) {
         if (needF && needU && needLap) rc = launch_self<true, true, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
