@@ -95,6 +95,10 @@ def main(argv=None):
     ap.add_argument("--grid-mode", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the evaluation as a recorded HIP graph (stage times then hold "
+                         "the whole evaluation in the first stage)")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -117,6 +121,15 @@ def main(argv=None):
     ctx = E.Context(0)
     ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
     T = ctx.ntargets
+    tile = {"targets_per_thread": ctx.far_config()[0], "source_chunks": ctx.far_config()[1],
+            "autotuned": False}
+    if not args.no_autotune:
+        from paper_1811_10270_amd import autotune
+        tpt, nch, timings, cached = autotune.autotune_far(ctx, s.p, s.q_far, s.grid_mode, far_prec)
+        tile = {"targets_per_thread": tpt, "source_chunks": nch, "autotuned": True,
+                "from_cache": cached}
+    if args.graph:
+        ctx.set_graph(True)
     f = torch.from_numpy(s.fcoef).to(dev)
     sig = torch.from_numpy(s.sigcoef).to(dev)
     out = torch.empty(len(E.rows_for_kinds(kinds)), T, dtype=torch.float64, device=dev)
@@ -142,7 +155,9 @@ def main(argv=None):
     self_flops = sum(self_flops_per_drop(int(s.p[d]), int(s.q_self[d]), s.grid_mode)
                      for d in range(s.ndrops))
     far_flops = far_interactions(s) * FAR_FLOPS_PER_INTERACTION
-    if avg[1] >= avg[2]:
+    if args.graph:
+        roof = None
+    elif avg[1] >= avg[2]:
         achieved = self_flops / (avg[1] * 1e-3) / 1e12
         roof = {"kernel": "k_self (rotation + rotated-grid synthesis + singular reduction, FP64)",
                 "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
@@ -176,7 +191,8 @@ def main(argv=None):
                    "q_self": "2p", "q_far": "2p", "grid": "paper (2p+2 longitudes)"
                    if s.grid_mode == 0 else "2p longitudes",
                    "kinds": "S,D,S_L,L", "far_prec": args.far_prec,
-                   "far_interactions": far_interactions(s)},
+                   "far_interactions": far_interactions(s), "far_tile": tile,
+                   "graph": bool(args.graph)},
         "stage_ms": dict(zip(E.STAGES, avg)),
         "self_tflops": self_flops / (avg[1] * 1e-3) / 1e12,
         "far_tflops": far_flops / (avg[2] * 1e-3) / 1e12,

@@ -161,6 +161,29 @@ int ehd_set_timing(ehd_ctx* ctx, int nslots);
  * Waits for the recorded events.  EHD_E_STATE if the slot holds no call. */
 int ehd_stage_times(ehd_ctx* ctx, int slot, double* ms);
 
+/* Graph mode (enable != 0): ehd_layer_potentials records its launch
+ * sequence as a HIP graph the first time it is called with a given argument
+ * set (pointers, kinds, far_prec, far-field tile shape) and replays the graph
+ * on later calls with the same arguments; any change of arguments, of the
+ * tile shape or of the drops records a new graph.  Device buffers may be
+ * rewritten between calls (the graph reads them at replay).  With stage
+ * timing on, ms[0] of a replayed call holds the whole evaluation.
+ * Synchronises the stream. */
+int ehd_set_graph(ehd_ctx* ctx, int enable);
+
+/* Far-field tile shape: targets per thread (1 or 2) and number of source
+ * chunks (1..16, at most the number of source tiles) the targets' sums are
+ * split into.  ehd_set_drops sets a default; the autotuner (ehd_time_far over
+ * candidates, paper_1811_10270_amd/autotune.py) picks the fastest. */
+int ehd_set_far_config(ehd_ctx* ctx, int targets_per_thread, int nchunk);
+int ehd_get_far_config(const ehd_ctx* ctx, int* targets_per_thread, int* nchunk);
+
+/* Autotuner support: mean milliseconds of `reps` launches of the far-field
+ * kernel of precision far_prec with the given tile shape, on the current
+ * source records, timed with HIP events (all kinds).  Overwrites the far
+ * field's partial sums (not the caller's outputs).  Synchronous. */
+int ehd_time_far(ehd_ctx* ctx, int far_prec, int targets_per_thread, int nchunk, int reps, double* ms);
+
 /* Host-only: Wigner small-d matrix d^n_{m m'}(beta), m, m' = -n..n, written
  * row-major to out[(m+n)*(2n+1) + (m'+n)], with
  * Y_nm(Ry(beta) v) = sum_m' d^n_{m m'}(beta) Y_nm'(v)

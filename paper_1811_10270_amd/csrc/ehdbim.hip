@@ -33,6 +33,7 @@ constexpr int kThreads = 256;
 constexpr int kTile = 256;        // far-field sources per LDS tile
 constexpr int kRec64 = 14;        // x(3) n(3) w(1) wf(3) wu(3) wsig(1)
 constexpr int kRec32 = 13;        // x-c(3) n(3) wf(3) wu(3) wsig(1)
+constexpr int kMaxChunks = 16;    // far field: largest number of source chunks
 
 // ---------------------------------------------------------------------------
 // Device-side descriptors
@@ -615,10 +616,12 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
 }
 
 // ---------------------------------------------------------------------------
-// Far field, FP64: each thread one target, sources streamed through LDS in
-// tiles of one drop each (drop-aligned padding), tiles split over blockIdx.y.
-// partial[chunk][comp][T] (unscaled).
+// Far field: each thread TPT targets (rows t, t + 256, ...), sources streamed
+// through LDS in tiles of one drop each (drop-aligned padding), tiles split
+// over blockIdx.y.  partial[chunk][comp][T] (unscaled).  TPT and the number
+// of chunks are the tile-shape parameters the autotuner picks.
 // ---------------------------------------------------------------------------
+template <int TPT>
 __global__ __launch_bounds__(kThreads) void k_far64(const double* __restrict__ tx,
                                                     const double* __restrict__ tnrm,
                                                     const int* __restrict__ tdrop, long long T,
@@ -628,14 +631,18 @@ __global__ __launch_bounds__(kThreads) void k_far64(const double* __restrict__ t
                                                     double* __restrict__ partial)
 {
     __shared__ double sm[kRec64][kTile];
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = t < T;
-    const long long tt = valid ? t : 0;
-    const double x0 = tx[tt], y0 = tx[T + tt], z0 = tx[2 * T + tt];
-    const double n0x = tnrm[tt], n0y = tnrm[T + tt], n0z = tnrm[2 * T + tt];
-    const int myd = valid ? tdrop[tt] : -1;
-    double acc[9];
-    for (int c = 0; c < 9; ++c) acc[c] = 0.0;
+    double x0[TPT], y0[TPT], z0[TPT], n0x[TPT], n0y[TPT], n0z[TPT], acc[TPT][9];
+    int myd[TPT];
+    long long tt[TPT];
+    for (int q = 0; q < TPT; ++q) {
+        tt[q] = (long long)blockIdx.x * blockDim.x * TPT + q * blockDim.x + threadIdx.x;
+        const bool valid = tt[q] < T;
+        const long long u = valid ? tt[q] : 0;
+        x0[q] = tx[u]; y0[q] = tx[T + u]; z0[q] = tx[2 * T + u];
+        n0x[q] = tnrm[u]; n0y[q] = tnrm[T + u]; n0z[q] = tnrm[2 * T + u];
+        myd[q] = valid ? tdrop[u] : -1;
+        for (int c = 0; c < 9; ++c) acc[q][c] = 0.0;
+    }
     const bool wS = kinds & EHD_STOKES_SL, wD = kinds & EHD_STOKES_DL;
     const bool wSL = kinds & EHD_LAP_SL, wL = kinds & EHD_LAP_DL, wK = kinds & EHD_LAP_DLADJ;
     const int t0 = blockIdx.y * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
@@ -643,43 +650,48 @@ __global__ __launch_bounds__(kThreads) void k_far64(const double* __restrict__ t
         const long long s = (long long)tile * kTile + threadIdx.x;
         for (int r = 0; r < kRec64; ++r) sm[r][threadIdx.x] = src[r * Spad + s];
         __syncthreads();
-        if (tile_drop[tile] != myd) {
-            for (int q = 0; q < kTile; ++q) {
-                const double hx = x0 - sm[0][q], hy = y0 - sm[1][q], hz = z0 - sm[2][q];
+        const int sd = tile_drop[tile];
+        for (int q = 0; q < kTile; ++q) {
+#pragma unroll
+            for (int k = 0; k < TPT; ++k) {
+                if (sd == myd[k]) continue;
+                const double hx = x0[k] - sm[0][q], hy = y0[k] - sm[1][q], hz = z0[k] - sm[2][q];
                 const double r2 = hx * hx + hy * hy + hz * hz;
-                const double ir = 1.0 / sqrt(r2), ir2 = ir * ir, ir3 = ir * ir2;
+                const double ir = rsqrt_nr(r2), ir2 = ir * ir, ir3 = ir * ir2;
                 const double hn = hx * sm[3][q] + hy * sm[4][q] + hz * sm[5][q];
                 if (wS) {
                     const double f0 = sm[7][q], f1 = sm[8][q], f2 = sm[9][q];
                     const double hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
-                    acc[0] += f0 * ir + hx * hf;
-                    acc[1] += f1 * ir + hy * hf;
-                    acc[2] += f2 * ir + hz * hf;
+                    acc[k][0] += f0 * ir + hx * hf;
+                    acc[k][1] += f1 * ir + hy * hf;
+                    acc[k][2] += f2 * ir + hz * hf;
                 }
                 if (wD) {
                     const double hu = hx * sm[10][q] + hy * sm[11][q] + hz * sm[12][q];
                     const double tq = -6.0 * hu * hn * ir3 * ir2;
-                    acc[3] += tq * hx;
-                    acc[4] += tq * hy;
-                    acc[5] += tq * hz;
+                    acc[k][3] += tq * hx;
+                    acc[k][4] += tq * hy;
+                    acc[k][5] += tq * hz;
                 }
                 const double sg = sm[13][q];
-                if (wSL) acc[6] += sg * ir;
-                if (wL) acc[7] += sg * hn * ir3;
-                if (wK) acc[8] += sg * (hx * n0x + hy * n0y + hz * n0z) * ir3;
+                if (wSL) acc[k][6] += sg * ir;
+                if (wL) acc[k][7] += sg * hn * ir3;
+                if (wK) acc[k][8] += sg * (hx * n0x[k] + hy * n0y[k] + hz * n0z[k]) * ir3;
             }
         }
         __syncthreads();
     }
-    if (valid)
-        for (int c = 0; c < 9; ++c) partial[((long long)blockIdx.y * 9 + c) * T + t] = acc[c];
+    for (int k = 0; k < TPT; ++k)
+        if (tt[k] < T)
+            for (int c = 0; c < 9; ++c) partial[((long long)blockIdx.y * 9 + c) * T + tt[k]] = acc[k][c];
 }
 
-// Far field, FP32 with drop-centred coordinates: per tile, the target's
+// Far field, FP32 with drop-centred coordinates: per tile, each target's
 // position relative to the source drop's centre is formed in FP64 and split
 // into an FP32 head and tail; sources are stored relative to the same centre.
 // The tile sum is accumulated in FP32 and added to a compensated (Kahan)
 // FP32 running sum.
+template <int TPT>
 __global__ __launch_bounds__(kThreads) void k_far32(const double* __restrict__ tx,
                                                     const double* __restrict__ tnrm,
                                                     const int* __restrict__ tdrop, long long T,
@@ -690,14 +702,19 @@ __global__ __launch_bounds__(kThreads) void k_far32(const double* __restrict__ t
                                                     double* __restrict__ partial)
 {
     __shared__ float sm[kRec32][kTile];
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = t < T;
-    const long long tt = valid ? t : 0;
-    const double X0 = tx[tt], Y0 = tx[T + tt], Z0 = tx[2 * T + tt];
-    const float n0x = (float)tnrm[tt], n0y = (float)tnrm[T + tt], n0z = (float)tnrm[2 * T + tt];
-    const int myd = valid ? tdrop[tt] : -1;
-    float sum[9], cmp[9];
-    for (int c = 0; c < 9; ++c) { sum[c] = 0.0f; cmp[c] = 0.0f; }
+    double X0[TPT], Y0[TPT], Z0[TPT];
+    float n0x[TPT], n0y[TPT], n0z[TPT], sum[TPT][9], cmp[TPT][9];
+    int myd[TPT];
+    long long tt[TPT];
+    for (int q = 0; q < TPT; ++q) {
+        tt[q] = (long long)blockIdx.x * blockDim.x * TPT + q * blockDim.x + threadIdx.x;
+        const bool valid = tt[q] < T;
+        const long long u = valid ? tt[q] : 0;
+        X0[q] = tx[u]; Y0[q] = tx[T + u]; Z0[q] = tx[2 * T + u];
+        n0x[q] = (float)tnrm[u]; n0y[q] = (float)tnrm[T + u]; n0z[q] = (float)tnrm[2 * T + u];
+        myd[q] = valid ? tdrop[u] : -1;
+        for (int c = 0; c < 9; ++c) { sum[q][c] = 0.0f; cmp[q][c] = 0.0f; }
+    }
     const bool wS = kinds & EHD_STOKES_SL, wD = kinds & EHD_STOKES_DL;
     const bool wSL = kinds & EHD_LAP_SL, wL = kinds & EHD_LAP_DL, wK = kinds & EHD_LAP_DLADJ;
     const int t0 = blockIdx.y * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
@@ -706,50 +723,59 @@ __global__ __launch_bounds__(kThreads) void k_far32(const double* __restrict__ t
         for (int r = 0; r < kRec32; ++r) sm[r][threadIdx.x] = src[r * Spad + s];
         __syncthreads();
         const int sd = tile_drop[tile];
-        if (sd != myd) {
-            const double dx = X0 - dcentre[3 * sd], dy = Y0 - dcentre[3 * sd + 1],
-                         dz = Z0 - dcentre[3 * sd + 2];
-            const float ax = (float)dx, ay = (float)dy, az = (float)dz;
-            const float bx = (float)(dx - ax), by = (float)(dy - ay), bz = (float)(dz - az);
-            float a[9];
-            for (int c = 0; c < 9; ++c) a[c] = 0.0f;
-            for (int q = 0; q < kTile; ++q) {
-                const float hx = (ax - sm[0][q]) + bx, hy = (ay - sm[1][q]) + by,
-                            hz = (az - sm[2][q]) + bz;
+        bool other = false;   // some target of this thread is not on the tile's drop
+        for (int k = 0; k < TPT; ++k) other = other || (sd != myd[k]);
+        float ax[TPT], ay[TPT], az[TPT], bx[TPT], by[TPT], bz[TPT], a[TPT][9];
+        for (int k = 0; k < TPT; ++k) {
+            const double dx = X0[k] - dcentre[3 * sd], dy = Y0[k] - dcentre[3 * sd + 1],
+                         dz = Z0[k] - dcentre[3 * sd + 2];
+            ax[k] = (float)dx; ay[k] = (float)dy; az[k] = (float)dz;
+            bx[k] = (float)(dx - ax[k]); by[k] = (float)(dy - ay[k]); bz[k] = (float)(dz - az[k]);
+            for (int c = 0; c < 9; ++c) a[k][c] = 0.0f;
+        }
+        for (int q = 0; q < (other ? kTile : 0); ++q) {
+#pragma unroll
+            for (int k = 0; k < TPT; ++k) {
+                const float hx = (ax[k] - sm[0][q]) + bx[k], hy = (ay[k] - sm[1][q]) + by[k],
+                            hz = (az[k] - sm[2][q]) + bz[k];
                 const float r2 = hx * hx + hy * hy + hz * hz;
                 const float ir = __frsqrt_rn(r2), ir2 = ir * ir, ir3 = ir * ir2;
                 const float hn = hx * sm[3][q] + hy * sm[4][q] + hz * sm[5][q];
                 if (wS) {
                     const float f0 = sm[6][q], f1 = sm[7][q], f2 = sm[8][q];
                     const float hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
-                    a[0] += f0 * ir + hx * hf;
-                    a[1] += f1 * ir + hy * hf;
-                    a[2] += f2 * ir + hz * hf;
+                    a[k][0] += f0 * ir + hx * hf;
+                    a[k][1] += f1 * ir + hy * hf;
+                    a[k][2] += f2 * ir + hz * hf;
                 }
                 if (wD) {
                     const float hu = hx * sm[9][q] + hy * sm[10][q] + hz * sm[11][q];
                     const float tq = -6.0f * hu * hn * ir3 * ir2;
-                    a[3] += tq * hx;
-                    a[4] += tq * hy;
-                    a[5] += tq * hz;
+                    a[k][3] += tq * hx;
+                    a[k][4] += tq * hy;
+                    a[k][5] += tq * hz;
                 }
                 const float sg = sm[12][q];
-                if (wSL) a[6] += sg * ir;
-                if (wL) a[7] += sg * hn * ir3;
-                if (wK) a[8] += sg * (hx * n0x + hy * n0y + hz * n0z) * ir3;
+                if (wSL) a[k][6] += sg * ir;
+                if (wL) a[k][7] += sg * hn * ir3;
+                if (wK) a[k][8] += sg * (hx * n0x[k] + hy * n0y[k] + hz * n0z[k]) * ir3;
             }
-            for (int c = 0; c < 9; ++c) {  // Kahan
-                const float y = a[c] - cmp[c];
-                const float tsum = sum[c] + y;
-                cmp[c] = (tsum - sum[c]) - y;
-                sum[c] = tsum;
+        }
+        for (int k = 0; k < TPT; ++k) {
+            if (sd == myd[k]) continue;      // own drop: tile not counted
+            for (int c = 0; c < 9; ++c) {    // Kahan
+                const float y = a[k][c] - cmp[k][c];
+                const float tsum = sum[k][c] + y;
+                cmp[k][c] = (tsum - sum[k][c]) - y;
+                sum[k][c] = tsum;
             }
         }
         __syncthreads();
     }
-    if (valid)
-        for (int c = 0; c < 9; ++c)
-            partial[((long long)blockIdx.y * 9 + c) * T + t] = (double)sum[c] - (double)cmp[c];
+    for (int k = 0; k < TPT; ++k)
+        if (tt[k] < T)
+            for (int c = 0; c < 9; ++c)
+                partial[((long long)blockIdx.y * 9 + c) * T + tt[k]] = (double)sum[k][c] - (double)cmp[k][c];
 }
 
 // Outputs: rows of the requested kinds, scaled far sums added to (or written
@@ -859,8 +885,34 @@ struct ehd_ctx {
     double* d_syn = nullptr;         // synthesis scratch [9][max(T,Spad)]
     long long syn_stride = 0;
     double* d_raw = nullptr;         // [9][T]
-    double* d_partial = nullptr;     // [nchunk][9][T]
-    int nchunk = 1;
+    double* d_partial = nullptr;     // [kMaxChunks][9][T]
+    int nchunk = 1;                  // far field: source chunks (grid y)
+    int far_tpt = 1;                 // far field: targets per thread
+
+    // graph mode: the launch sequence of ehd_layer_potentials recorded once
+    // per argument set and replayed
+    bool graph_on = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    struct GraphKey {
+        const void *f, *u, *s;
+        void *so, *fo;
+        unsigned kinds;
+        int prec, tpt, nchunk;
+        bool operator==(const GraphKey& o) const
+        {
+            return f == o.f && u == o.u && s == o.s && so == o.so && fo == o.fo && kinds == o.kinds &&
+                   prec == o.prec && tpt == o.tpt && nchunk == o.nchunk;
+        }
+    } gkey{};
+    hipStream_t ls = nullptr;        // stream the current evaluation launches on
+    bool capturing = false;
+
+    void drop_graph()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        gexec = nullptr;
+    }
     int2* d_rows_p = nullptr;        // rows of own grids
     int2* d_rows_f = nullptr;        // rows of far grids
     int nrows_p = 0, nrows_f = 0;
@@ -883,7 +935,7 @@ struct ehd_ctx {
     }
     void mark(int stage)
     {
-        if (nslots) (void)hipEventRecord(events[(ncalls % nslots) * (kStages + 1) + stage], stream);
+        if (nslots && !capturing) (void)hipEventRecord(events[(ncalls % nslots) * (kStages + 1) + stage], stream);
     }
     DropInfo* d_info_tmp = nullptr;  // per-field views for ehd_synthesize
 
@@ -986,7 +1038,7 @@ static int launch_self_class(ehd_ctx* ctx, int cls, const double* f, const doubl
         EHD_HIP(ctx, hipFuncSetAttribute((const void*)k_self<PMAX, HF, HU, HS>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL((k_self<PMAX, HF, HU, HS>), dim3((unsigned)count), dim3(SelfClass<PMAX>::NT), lds,
-                       ctx->stream,
+                       ctx->ls,
                        ctx->d_info, ctx->d_legs, ctx->d_wigs, ctx->d_order + ctx->cls_off[cls], ctx->d_tdrop,
                        ctx->d_x, f, u, s, ctx->d_tx, ctx->d_tn, ctx->T, kinds, ctx->d_raw);
     EHD_HIP(ctx, hipGetLastError());
@@ -1033,6 +1085,8 @@ void ehd_destroy(ehd_ctx* ctx)
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
+    ctx->drop_graph();
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     ctx->free_all();
     ctx->free_events();
     delete ctx;
@@ -1082,6 +1136,7 @@ int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
     }
     EHD_HIP(ctx, hipSetDevice(ctx->device));
     if (ctx->stream) EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->drop_graph();
     ctx->free_all();
     int rc;
     ctx->nd = ndrops;
@@ -1317,8 +1372,10 @@ int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
     if ((rc = dev_alloc(ctx, &ctx->d_src32, (size_t)kRec32 * S))) return rc;
     if ((rc = dev_alloc(ctx, &ctx->d_raw, 9 * T))) return rc;
     const long long tblocks = (T + kThreads - 1) / kThreads;
-    ctx->nchunk = (int)std::min<long long>(std::max<long long>(1, (2048 + tblocks - 1) / tblocks), ctx->ntiles);
-    if ((rc = dev_alloc(ctx, &ctx->d_partial, (size_t)ctx->nchunk * 9 * T))) return rc;
+    ctx->far_tpt = 1;
+    ctx->nchunk = (int)std::min<long long>(std::min<long long>(std::max<long long>(1, (2048 + tblocks - 1) / tblocks),
+                                                               ctx->ntiles), kMaxChunks);
+    if ((rc = dev_alloc(ctx, &ctx->d_partial, (size_t)kMaxChunks * 9 * T))) return rc;
     if ((rc = dev_alloc(ctx, &ctx->d_info_tmp, ndrops))) return rc;
 
     // --- target geometry (own grids) and far-source geometry
@@ -1343,26 +1400,44 @@ int ehd_num_targets(const ehd_ctx* ctx, long long* ntargets)
     return ctx->nd ? EHD_OK : EHD_E_STATE;
 }
 
-int ehd_layer_potentials(ehd_ctx* ctx, const double* fcoef_d, const double* ucoef_d,
-                         const double* sigcoef_d, unsigned kinds, int far_prec, double* self_out_d,
-                         double* far_out_d)
+// Far-field launch with the context's tile shape (targets per thread, source
+// chunks) on the context's launch stream.
+static int launch_far(ehd_ctx* ctx, int far_prec, unsigned kinds, int tpt, int nchunk)
 {
-    if (!ctx) return EHD_E_ARG;
-    if (!ctx->nd) EHD_FAIL(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
-    if (kinds == 0 || (kinds & ~(unsigned)EHD_ALL_KINDS)) EHD_FAIL(ctx, EHD_E_ARG, "invalid kinds mask 0x%x", kinds);
-    if (far_prec != EHD_FAR_FP64 && far_prec != EHD_FAR_FP32C) EHD_FAIL(ctx, EHD_E_ARG, "invalid far_prec %d", far_prec);
-    if (!self_out_d) EHD_FAIL(ctx, EHD_E_ARG, "self_out_d is NULL");
+    const long long T = ctx->T, S = ctx->Spad;
+    const long long tblocks = (T + (long long)kThreads * tpt - 1) / ((long long)kThreads * tpt);
+    const int tpc = (ctx->ntiles + nchunk - 1) / nchunk;
+    dim3 grid((unsigned)tblocks, (unsigned)nchunk);
+    if (far_prec == EHD_FAR_FP64) {
+        if (tpt == 2)
+            hipLaunchKernelGGL(k_far64<2>, grid, dim3(kThreads), 0, ctx->ls, ctx->d_tx, ctx->d_tn, ctx->d_tdrop,
+                               T, ctx->d_src64, S, ctx->d_tile_drop, ctx->ntiles, tpc, kinds, ctx->d_partial);
+        else
+            hipLaunchKernelGGL(k_far64<1>, grid, dim3(kThreads), 0, ctx->ls, ctx->d_tx, ctx->d_tn, ctx->d_tdrop,
+                               T, ctx->d_src64, S, ctx->d_tile_drop, ctx->ntiles, tpc, kinds, ctx->d_partial);
+    } else {
+        if (tpt == 2)
+            hipLaunchKernelGGL(k_far32<2>, grid, dim3(kThreads), 0, ctx->ls, ctx->d_tx, ctx->d_tn, ctx->d_tdrop,
+                               T, ctx->d_src32, S, ctx->d_tile_drop, ctx->d_centre, ctx->ntiles, tpc, kinds,
+                               ctx->d_partial);
+        else
+            hipLaunchKernelGGL(k_far32<1>, grid, dim3(kThreads), 0, ctx->ls, ctx->d_tx, ctx->d_tn, ctx->d_tdrop,
+                               T, ctx->d_src32, S, ctx->d_tile_drop, ctx->d_centre, ctx->ntiles, tpc, kinds,
+                               ctx->d_partial);
+    }
+    EHD_HIP(ctx, hipGetLastError());
+    return EHD_OK;
+}
+
+// The launch sequence of one evaluation, on ctx->ls.
+static int enqueue_evaluation(ehd_ctx* ctx, const double* fcoef_d, const double* ucoef_d,
+                              const double* sigcoef_d, unsigned kinds, int far_prec, double* self_out_d,
+                              double* far_out_d)
+{
     const bool needS = kinds & EHD_STOKES_SL, needD = kinds & EHD_STOKES_DL;
     const bool needLap = kinds & (EHD_LAP_SL | EHD_LAP_DL | EHD_LAP_DLADJ);
     const bool needF = needS || (needD && !ucoef_d);
     const bool needU = needD && ucoef_d;
-    if (needF && !fcoef_d) EHD_FAIL(ctx, EHD_E_ARG, "fcoef_d is needed for the requested kinds");
-    if (needLap && !sigcoef_d) EHD_FAIL(ctx, EHD_E_ARG, "sigcoef_d is needed for the Laplace kinds");
-    for (const void* q : {(const void*)fcoef_d, (const void*)ucoef_d, (const void*)sigcoef_d,
-                          (const void*)self_out_d, (const void*)far_out_d})
-        if (((uintptr_t)q) % 8) EHD_FAIL(ctx, EHD_E_ARG, "device pointers must be 8-byte aligned");
-    EHD_HIP(ctx, hipSetDevice(ctx->device));
-
     RowMap rows{};
     for (int c = 0; c < 9; ++c) {
         const unsigned bit = c < 3 ? EHD_STOKES_SL : c < 6 ? EHD_STOKES_DL : c == 6 ? EHD_LAP_SL
@@ -1377,15 +1452,15 @@ int ehd_layer_potentials(ehd_ctx* ctx, const double* fcoef_d, const double* ucoe
     double* synu = needU ? ctx->d_syn + 3 * vs : nullptr;
     double* syns = needLap ? ctx->d_syn + 6 * vs : nullptr;
     if (needF)
-        hipLaunchKernelGGL((k_synth<3, false>), dim3(ctx->nrows_f), dim3(kThreads), 0, ctx->stream, ctx->d_info,
+        hipLaunchKernelGGL((k_synth<3, false>), dim3(ctx->nrows_f), dim3(kThreads), 0, ctx->ls, ctx->d_info,
                            ctx->d_legs, 1, ctx->d_rows_f, fcoef_d, synf, vs);
     if (needU)
-        hipLaunchKernelGGL((k_synth<3, false>), dim3(ctx->nrows_f), dim3(kThreads), 0, ctx->stream, ctx->d_info,
+        hipLaunchKernelGGL((k_synth<3, false>), dim3(ctx->nrows_f), dim3(kThreads), 0, ctx->ls, ctx->d_info,
                            ctx->d_legs, 1, ctx->d_rows_f, ucoef_d, synu, vs);
     if (needLap)
-        hipLaunchKernelGGL((k_synth<1, false>), dim3(ctx->nrows_f), dim3(kThreads), 0, ctx->stream, ctx->d_info,
+        hipLaunchKernelGGL((k_synth<1, false>), dim3(ctx->nrows_f), dim3(kThreads), 0, ctx->ls, ctx->d_info,
                            ctx->d_legs, 1, ctx->d_rows_f, sigcoef_d, syns, vs);
-    hipLaunchKernelGGL(k_src_dens, dim3((S + 255) / 256), dim3(256), 0, ctx->stream, synf, synu, syns, vs, S,
+    hipLaunchKernelGGL(k_src_dens, dim3((S + 255) / 256), dim3(256), 0, ctx->ls, synf, synu, syns, vs, S,
                        ctx->d_src64, ctx->d_src32);
     EHD_HIP(ctx, hipGetLastError());
 
@@ -1416,27 +1491,141 @@ int ehd_layer_potentials(ehd_ctx* ctx, const double* fcoef_d, const double* ucoe
     ctx->mark(2);
 
     // 3. far field
-    const long long tblocks = (T + kThreads - 1) / kThreads;
-    const int tpc = (ctx->ntiles + ctx->nchunk - 1) / ctx->nchunk;
-    dim3 grid((unsigned)tblocks, (unsigned)ctx->nchunk);
-    if (far_prec == EHD_FAR_FP64)
-        hipLaunchKernelGGL(k_far64, grid, dim3(kThreads), 0, ctx->stream, ctx->d_tx, ctx->d_tn, ctx->d_tdrop, T,
-                           ctx->d_src64, S, ctx->d_tile_drop, ctx->ntiles, tpc, kinds, ctx->d_partial);
-    else
-        hipLaunchKernelGGL(k_far32, grid, dim3(kThreads), 0, ctx->stream, ctx->d_tx, ctx->d_tn, ctx->d_tdrop, T,
-                           ctx->d_src32, S, ctx->d_tile_drop, ctx->d_centre, ctx->ntiles, tpc, kinds,
-                           ctx->d_partial);
-    EHD_HIP(ctx, hipGetLastError());
+    if ((rc = launch_far(ctx, far_prec, kinds, ctx->far_tpt, ctx->nchunk))) return rc;
 
     ctx->mark(3);
     // 4. outputs
-    hipLaunchKernelGGL(k_combine, dim3((T + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_raw, ctx->d_partial,
+    hipLaunchKernelGGL(k_combine, dim3((T + 255) / 256), dim3(256), 0, ctx->ls, ctx->d_raw, ctx->d_partial,
                        ctx->nchunk, T, rows, self_out_d, far_out_d);
     EHD_HIP(ctx, hipGetLastError());
     ctx->mark(4);
+    return EHD_OK;
+}
+
+int ehd_layer_potentials(ehd_ctx* ctx, const double* fcoef_d, const double* ucoef_d,
+                         const double* sigcoef_d, unsigned kinds, int far_prec, double* self_out_d,
+                         double* far_out_d)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ctx->nd) EHD_FAIL(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if (kinds == 0 || (kinds & ~(unsigned)EHD_ALL_KINDS)) EHD_FAIL(ctx, EHD_E_ARG, "invalid kinds mask 0x%x", kinds);
+    if (far_prec != EHD_FAR_FP64 && far_prec != EHD_FAR_FP32C) EHD_FAIL(ctx, EHD_E_ARG, "invalid far_prec %d", far_prec);
+    if (!self_out_d) EHD_FAIL(ctx, EHD_E_ARG, "self_out_d is NULL");
+    const bool needS = kinds & EHD_STOKES_SL, needD = kinds & EHD_STOKES_DL;
+    const bool needLap = kinds & (EHD_LAP_SL | EHD_LAP_DL | EHD_LAP_DLADJ);
+    const bool needF = needS || (needD && !ucoef_d);
+    if (needF && !fcoef_d) EHD_FAIL(ctx, EHD_E_ARG, "fcoef_d is needed for the requested kinds");
+    if (needLap && !sigcoef_d) EHD_FAIL(ctx, EHD_E_ARG, "sigcoef_d is needed for the Laplace kinds");
+    for (const void* q : {(const void*)fcoef_d, (const void*)ucoef_d, (const void*)sigcoef_d,
+                          (const void*)self_out_d, (const void*)far_out_d})
+        if (((uintptr_t)q) % 8) EHD_FAIL(ctx, EHD_E_ARG, "device pointers must be 8-byte aligned");
+    EHD_HIP(ctx, hipSetDevice(ctx->device));
+
+    int rc;
+    if (!ctx->graph_on) {
+        ctx->ls = ctx->stream;
+        rc = enqueue_evaluation(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds, far_prec, self_out_d, far_out_d);
+    } else {
+        const ehd_ctx::GraphKey key{fcoef_d, ucoef_d, sigcoef_d, self_out_d, far_out_d, kinds, far_prec,
+                                    ctx->far_tpt, ctx->nchunk};
+        if (!ctx->gexec || !(key == ctx->gkey)) {
+            ctx->drop_graph();
+            // record the sequence on the private stream, then instantiate
+            ctx->ls = ctx->cap_stream;
+            ctx->capturing = true;
+            hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) {
+                ctx->capturing = false;
+                EHD_FAIL(ctx, EHD_E_HIP, "hipStreamBeginCapture failed: %s", hipGetErrorString(e));
+            }
+            rc = enqueue_evaluation(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds, far_prec, self_out_d, far_out_d);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(ctx->cap_stream, &g);
+            ctx->capturing = false;
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) EHD_FAIL(ctx, EHD_E_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                ctx->gexec = nullptr;
+                EHD_FAIL(ctx, EHD_E_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+            }
+            ctx->gkey = key;
+        }
+        ctx->mark(0);
+        EHD_HIP(ctx, hipGraphLaunch(ctx->gexec, ctx->stream));
+        for (int k = 1; k <= ehd_ctx::kStages; ++k) ctx->mark(k);
+        rc = EHD_OK;
+    }
+    if (rc) return rc;
     if (ctx->nslots) ctx->slot_used[ctx->ncalls % ctx->nslots] = 1;
     ++ctx->ncalls;
     return EHD_OK;
+}
+
+int ehd_set_graph(ehd_ctx* ctx, int enable)
+{
+    if (!ctx) return EHD_E_ARG;
+    EHD_HIP(ctx, hipSetDevice(ctx->device));
+    if (ctx->stream) EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->drop_graph();
+    if (enable && !ctx->cap_stream)
+        EHD_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    ctx->graph_on = enable != 0;
+    return EHD_OK;
+}
+
+int ehd_set_far_config(ehd_ctx* ctx, int targets_per_thread, int nchunk)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ctx->nd) EHD_FAIL(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if ((targets_per_thread != 1 && targets_per_thread != 2) || nchunk < 1 || nchunk > kMaxChunks ||
+        nchunk > ctx->ntiles)
+        EHD_FAIL(ctx, EHD_E_ARG, "targets_per_thread must be 1 or 2 and nchunk in [1, %d] (and <= %d tiles)",
+                 kMaxChunks, ctx->ntiles);
+    ctx->far_tpt = targets_per_thread;
+    ctx->nchunk = nchunk;
+    return EHD_OK;
+}
+
+int ehd_get_far_config(const ehd_ctx* ctx, int* targets_per_thread, int* nchunk)
+{
+    if (!ctx || !targets_per_thread || !nchunk) return EHD_E_ARG;
+    *targets_per_thread = ctx->far_tpt;
+    *nchunk = ctx->nchunk;
+    return ctx->nd ? EHD_OK : EHD_E_STATE;
+}
+
+int ehd_time_far(ehd_ctx* ctx, int far_prec, int targets_per_thread, int nchunk, int reps, double* ms)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ctx->nd) EHD_FAIL(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if (!ms || reps < 1 || reps > 1000 || (far_prec != EHD_FAR_FP64 && far_prec != EHD_FAR_FP32C))
+        EHD_FAIL(ctx, EHD_E_ARG, "invalid arguments");
+    if ((targets_per_thread != 1 && targets_per_thread != 2) || nchunk < 1 || nchunk > kMaxChunks ||
+        nchunk > ctx->ntiles)
+        EHD_FAIL(ctx, EHD_E_ARG, "invalid tile shape");
+    EHD_HIP(ctx, hipSetDevice(ctx->device));
+    hipEvent_t e0, e1;
+    EHD_HIP(ctx, hipEventCreate(&e0));
+    EHD_HIP(ctx, hipEventCreate(&e1));
+    ctx->ls = ctx->stream;
+    int rc = launch_far(ctx, far_prec, EHD_ALL_KINDS, targets_per_thread, nchunk);  // warm-up
+    if (!rc) {
+        (void)hipEventRecord(e0, ctx->stream);
+        for (int r = 0; r < reps && !rc; ++r) rc = launch_far(ctx, far_prec, EHD_ALL_KINDS, targets_per_thread, nchunk);
+        (void)hipEventRecord(e1, ctx->stream);
+        (void)hipEventSynchronize(e1);
+        float t = 0.0f;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        *ms = t / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
 
 int ehd_synthesize(ehd_ctx* ctx, int nfields, const double* coef_d, double* grid_d)

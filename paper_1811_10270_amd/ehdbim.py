@@ -29,7 +29,8 @@ _KIND_OF_COMP = (STOKES_SL,) * 3 + (STOKES_DL,) * 3 + (LAP_SL, LAP_DL, LAP_DLADJ
 EXPORTED = ("ehd_create", "ehd_destroy", "ehd_last_error", "ehd_grid_dims", "ehd_set_drops",
             "ehd_num_targets", "ehd_layer_potentials", "ehd_synthesize", "ehd_analyze",
             "ehd_target_geometry", "ehd_sync", "ehd_wigner_d", "ehd_set_timing",
-            "ehd_stage_times")
+            "ehd_stage_times", "ehd_set_graph", "ehd_set_far_config", "ehd_get_far_config",
+            "ehd_time_far")
 STAGES = ("densities", "self", "far", "combine")
 
 _lib = None
@@ -67,6 +68,10 @@ def load(path: str = LIB_PATH):
     lib.ehd_wigner_d.argtypes = [C.c_int, C.c_double, dp]
     lib.ehd_set_timing.argtypes = [vp, C.c_int]
     lib.ehd_stage_times.argtypes = [vp, C.c_int, dp]
+    lib.ehd_set_graph.argtypes = [vp, C.c_int]
+    lib.ehd_set_far_config.argtypes = [vp, C.c_int, C.c_int]
+    lib.ehd_get_far_config.argtypes = [vp, ip, ip]
+    lib.ehd_time_far.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, dp]
     _lib = lib
     return lib
 
@@ -170,6 +175,23 @@ class Context:
 
     def set_timing(self, nslots: int):
         self._check(self._lib.ehd_set_timing(self._h, nslots))
+
+    def set_graph(self, enable: bool):
+        self._check(self._lib.ehd_set_graph(self._h, 1 if enable else 0))
+
+    def set_far_config(self, targets_per_thread: int, nchunk: int):
+        self._check(self._lib.ehd_set_far_config(self._h, targets_per_thread, nchunk))
+
+    def far_config(self):
+        a, b = C.c_int(), C.c_int()
+        self._check(self._lib.ehd_get_far_config(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def time_far(self, far_prec: int, targets_per_thread: int, nchunk: int, reps: int = 3) -> float:
+        ms = C.c_double()
+        self._check(self._lib.ehd_time_far(self._h, far_prec, targets_per_thread, nchunk, reps,
+                                           C.byref(ms)))
+        return ms.value
 
     def stage_times(self, slot: int):
         """Milliseconds of (densities, self, far, combine) of a recorded call."""

@@ -1,0 +1,108 @@
+"""GPU: graph-mode replays and far-field tile shapes (batching row).
+
+Graph replays must equal eager evaluations bit for bit (every kernel is
+deterministic: fixed reduction orders, no atomics), also when the device
+buffers are rewritten between replays and eager work runs in between; every
+far-field tile shape must give the FP64 far field to rounding."""
+import numpy as np
+import pytest
+
+from paper_1811_10270_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1811_10270_amd import ehdbim
+    ehdbim.load()
+    return ehdbim
+
+
+def _setup(E, s):
+    import torch
+    dev = torch.device("cuda", 0)
+    ctx = E.Context(0)
+    ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+    f = torch.from_numpy(s.fcoef).to(dev)
+    sg = torch.from_numpy(s.sigcoef).to(dev)
+    return ctx, f, sg, dev
+
+
+def test_graph_replays_match_eager(E):
+    import torch
+    s = W.subset(W.batched_suspension(seed=3), list(range(10)))
+    ctx, f, sg, dev = _setup(E, s)
+    T = ctx.ntargets
+    so = torch.zeros(9, T, dtype=torch.float64, device=dev)
+    fo = torch.zeros_like(so)
+    ref_s, ref_f = [], []
+    for scale in (1.0, -0.5, 2.0):
+        f.mul_(scale)
+        sg.mul_(scale)
+        ctx.layer_potentials(f, None, sg, E.ALL_KINDS, E.FAR_FP32C, so, fo)
+        ctx.sync()
+        ref_s.append(so.clone())
+        ref_f.append(fo.clone())
+        f.div_(scale)
+        sg.div_(scale)
+    ctx.set_graph(True)
+    for rep in range(2):
+        for k, scale in enumerate((1.0, -0.5, 2.0)):
+            f.mul_(scale)
+            sg.mul_(scale)
+            so.zero_()
+            fo.zero_()
+            ctx.layer_potentials(f, None, sg, E.ALL_KINDS, E.FAR_FP32C, so, fo)
+            ctx.sync()
+            assert torch.equal(so, ref_s[k]) and torch.equal(fo, ref_f[k]), (rep, k)
+            f.div_(scale)
+            sg.div_(scale)
+            # eager work of the program between replays
+            torch.cuda.synchronize()
+            _ = (so * 2.0).sum().item()
+    # changing arguments records a new graph
+    ctx.layer_potentials(f, None, sg, E.METRIC_KINDS, E.FAR_FP32C, so[:8], fo[:8])
+    ctx.sync()
+    assert torch.equal(so[:8], ref_s[0][:8])
+    ctx.set_graph(False)
+    ctx.close()
+
+
+def test_far_tile_shapes_agree_and_autotune(E, tmp_path):
+    import torch
+    from paper_1811_10270_amd import autotune
+    s = W.subset(W.batched_suspension(seed=3), list(range(12)))
+    ctx, f, sg, dev = _setup(E, s)
+    T = ctx.ntargets
+    so = torch.zeros(9, T, dtype=torch.float64, device=dev)
+    fo = torch.zeros_like(so)
+    ref = None
+    for tpt in (1, 2):
+        for nch in (1, 3, 16):
+            ctx.set_far_config(tpt, nch)
+            ctx.layer_potentials(f, None, sg, E.ALL_KINDS, E.FAR_FP64, so, fo)
+            ctx.sync()
+            got = fo.cpu().numpy()
+            if ref is None:
+                ref = got
+            else:
+                err = np.abs(got - ref).max(axis=1) / np.abs(ref).max(axis=1)
+                assert np.all(err < 1e-13), (tpt, nch, err)
+    with pytest.raises(E.EhdError):
+        ctx.set_far_config(3, 1)
+    cache = str(tmp_path / "tune.json")
+    tpt, nch, timings, cached = autotune.autotune_far(ctx, s.p, s.q_far, s.grid_mode, E.FAR_FP32C,
+                                                      cache_path=cache)
+    assert not cached and len(timings) >= 4 and (tpt, nch) == ctx.far_config()
+    tpt2, nch2, _, cached2 = autotune.autotune_far(ctx, s.p, s.q_far, s.grid_mode, E.FAR_FP32C,
+                                                   cache_path=cache)
+    assert cached2 and (tpt2, nch2) == (tpt, nch)
+    ctx.layer_potentials(f, None, sg, E.ALL_KINDS, E.FAR_FP32C, so, fo)
+    ctx.sync()
+    err = np.abs(fo.cpu().numpy() - ref).max(axis=1) / np.abs(ref).max(axis=1)
+    assert np.all(err < 1e-6), err
+    ctx.close()

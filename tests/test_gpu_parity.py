@@ -238,3 +238,46 @@ def test_full_batched_suspension_sampled(E):
     es = normwise(so.numpy()[:, sidx], rs)
     say("batched self err", es)
     assert np.all(es < FP64_TOL), es
+
+
+@pytest.mark.parametrize("name", ["two_drops_p32", "batched_64_mixed_p", "large_256_p32"])
+def test_fp32_far_field_bound_full_size(E, name):
+    """FP32 compensated far field against the FP64 far field at every target
+    of the full workload (the FP64 far field itself is pinned to the oracle
+    on sampled targets below and above): normwise error <= 1e-6 per output."""
+    s = W.WORKLOADS[name](0)
+    _, f64 = run(E, s, kinds=31, far_prec=0)
+    _, f32 = run(E, s, kinds=31, far_prec=1)
+    err = normwise(f32.numpy(), f64.numpy())
+    say(name, "fp32 far normwise err", err)
+    assert np.all(err < 1e-6), err
+
+
+def test_large_suspension_sampled_parity(E):
+    """256 drops at p=32: sampled targets, self and far (FP64) vs the oracle."""
+    s = W.large_suspension(seed=5)
+    so, fo = run(E, s, kinds=31, far_prec=0)
+    rng = np.random.default_rng(6)
+    td, tn = oracle.all_targets(s)
+    idx = np.sort(rng.choice(len(td), size=24, replace=False))
+    rf = oracle.far(s, td[idx], tn[idx])
+    ef = normwise(fo.numpy()[:, idx], rf)
+    rs = oracle.self_(s, td[idx[:8]], tn[idx[:8]])
+    es = normwise(so.numpy()[:, idx[:8]], rs)
+    say("large far err", ef, "self err", es)
+    assert np.all(ef < FP64_TOL) and np.all(es < FP64_TOL), (ef, es)
+
+
+def test_two_drops_near_contact_q96(E):
+    """Two p=32 spheres at gap 0.1, far grid q = 96 (3x), every target of
+    drop 0's first latitude rows and a sample of the rest against the oracle."""
+    s = W.two_drops(32, seed=2)
+    so, fo = run(E, s, kinds=31, far_prec=0)
+    idx = np.concatenate([np.arange(0, 200), np.arange(2178, 2178 + 100)])
+    td, tn = oracle.all_targets(s)
+    rf = oracle.far(s, td[idx], tn[idx])
+    ef = normwise(fo.numpy()[:, idx], rf)
+    rs = oracle.self_(s, td[idx[::25]], tn[idx[::25]])
+    es = normwise(so.numpy()[:, idx[::25]], rs)
+    say("two drops q96 far err", ef, "self err", es)
+    assert np.all(ef < FP64_TOL) and np.all(es < FP64_TOL), (ef, es)
