@@ -47,8 +47,10 @@ struct LegTab {                // degree-p expansions on a degree-Q grid
     const double* trig;        // [nlon][p+1][2] cos(m phi_l), sin(m phi_l)
     const double* afrag;       // MFMA A fragments of the half-period cos/sin
                                // tables: [row tile][k-step (even, odd)][lane]
-    const double* Pc;          // singular grids: [Q+1][cm(m) + n - m] Pbar_n^m, columns
-    const double* dPc;         // of fixed m stored contiguously (cm: column_start)
+    const double* lfrag;       // singular grids: MFMA A fragments of the Legendre sums,
+                               // [latitude block][k-step of degree m][lane]; rows
+                               // 0-7 Pbar, 8-15 dPbar/dtheta at 8 latitudes,
+                               // k = n - m - 4 ks
     int p, Q, nlon, pad;
 };
 
@@ -311,13 +313,36 @@ __host__ __device__ inline HalfGrid half_grid(int p, int nlonq)
 
 // Compile-time bounds of one degree class (all p <= PMAX; the rotated grid
 // has at most 8 row tiles of 16 half-period longitudes).
+constexpr int kLatBlock = 8;          // rotated latitudes per Legendre MFMA block
+
+// Degree columns m = 0..p are dealt to the NW waves in snake order
+// (0,1,..,NW-1, NW-1,..,0, 0,1,..); column m has ceil((p+1-m)/4) k-steps.
+__host__ __device__ constexpr int snake_wave(int m, int nw)
+{
+    return ((m / nw) & 1) ? nw - 1 - (m % nw) : (m % nw);
+}
+
+constexpr int wave_ksteps_max(int PMAX, int nw)   // max over p <= PMAX and waves
+{
+    int best = 0;
+    for (int p = 1; p <= PMAX; ++p)
+        for (int w = 0; w < nw; ++w) {
+            int t = 0;
+            for (int m = 0; m <= p; ++m)
+                if (snake_wave(m, nw) == w) t += (p + 1 - m + 3) / 4;
+            best = t > best ? t : best;
+        }
+    return best;
+}
+
 template <int PMAX>
 struct SelfClass {
     static constexpr int KSE = (2 * (PMAX / 2) + 1 + 3) / 4;   // max even k-steps
     static constexpr int KSO = (2 * ((PMAX + 1) / 2) + 3) / 4; // max odd k-steps
-    static constexpr int NT = PMAX >= 32 ? 512 : 256;          // threads per block
+    static constexpr int NT = 512;                             // threads per block
     static constexpr int NW = NT / 64;                         // waves per block
     static constexpr int TPW = (8 + NW - 1) / NW;              // row tiles per wave (max)
+    static constexpr int KW = wave_ksteps_max(PMAX, NW);       // Legendre k-steps per wave
 };
 
 template <int PMAX, bool HF, bool HU, bool HS>
@@ -334,8 +359,8 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     constexpr int NV = NF + 6;           // + x_theta(3), x_phi/sin(3)
     constexpr int VD = 9;                // first density variant
     using SC = SelfClass<PMAX>;
-    static_assert(NV <= 16, "at most 16 grid quantities per MFMA column tile");
-    constexpr int NT = SC::NT, NW = SC::NW;
+    static_assert(2 * NF <= 16, "at most 8 fields: (field, re/im) fill the 16 MFMA columns");
+    constexpr int NT = SC::NT, NW = SC::NW, LB = kLatBlock;
     extern __shared__ double2 lds[];
     __shared__ double red[NW][9];
 
@@ -349,9 +374,10 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     const LegTab Lp = legs[D.leg_pp];
     const WigTab W = wigs[D.wig];
     const HalfGrid hg = half_grid(p, Lq.nlon);
-    double2* cr = lds;                               // [NF][nc]
-    double* R = reinterpret_cast<double*>(lds + NF * nc);  // Fourier coefs / node values
+    double2* cr = lds;                               // [NF][nc] rotated coefficients
+    double* R = reinterpret_cast<double*>(lds);      // later: Fourier blocks + node values
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    (void)NT;
 
     const __attribute__((address_space(1))) double* fld[NF];
     for (int c = 0; c < 3; ++c) fld[c] = gmem(xcoef + 3 * D.coff + c * 2 * nc);
@@ -359,8 +385,8 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     if (HU) for (int c = 0; c < 3; ++c) fld[UOFF + c] = gmem(ucoef + 3 * D.coff + c * 2 * nc);
     if (HS) fld[SOFF] = gmem(scoef + D.coff);
 
-    // register-resident A operand: cos/sin(m phi_l) fragments of this wave's
-    // row tiles, even-m and odd-m blocks
+    // register-resident A operand of the longitude sums: cos/sin(m phi_l)
+    // fragments of this wave's row tiles, even-m and odd-m blocks
     double afE[SC::TPW][SC::KSE], afO[SC::TPW][SC::KSO];
     {
         const int nks = hg.nKE + hg.nKO;
@@ -377,7 +403,7 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
         }
     }
 
-    // 1. rotation
+    // 1. rotation into LDS (column-major: column m holds n = m..p contiguously)
     {
         const long wb = ehd::wig_block(p);
         const auto A = gmem(W.A + (long long)j * wb);
@@ -399,139 +425,155 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
                     aim[f] += b * (c0 * sm + c1 * cm);
                 }
             }
-            const int cpos = column_start(p, mp) + n - mp;   // column-major position
+            const int cpos = column_start(p, mp) + n - mp;
             for (int f = 0; f < NF; ++f) cr[f * nc + cpos] = make_double2(are[f], aim[f]);
         }
     }
+    __syncthreads();
 
-    double x0[3], n0[3];
-    for (int c = 0; c < 3; ++c) { x0[c] = tx[c * T + tg]; n0[c] = tnrm[c * T + tg]; }
+    // 2. rotated coefficients into registers as the B operand of the Legendre
+    //    MFMA: wave wv owns the degree columns m with snake_wave(m) == wv,
+    //    walked in increasing m as one sequence of k-steps t; lane holds
+    //    c'_f(n, m) (re or im) for column (f, re/im) = lane % 16 and
+    //    n = m + 4 ks + lane / 16.
+    double cB[SC::KW];
+    const int ci = lane & 15, cf_ = ci >> 1, cri = ci & 1;
+    {
+        int m = -1, left = 0, ks = 0;
+#pragma unroll
+        for (int t = 0; t < SC::KW; ++t) {
+            if (left == 0) {            // next column of this wave (wave-uniform)
+                ++m;
+                while (m <= p && snake_wave(m, NW) != wv) ++m;
+                left = (m <= p) ? (p + 1 - m + 3) / 4 : 0;
+                ks = 0;
+            }
+            const int n = m + 4 * ks + (lane >> 4);
+            const bool ok = left > 0 && cf_ < NF && n <= p;
+            const int idx = ok ? cf_ * (int)nc + column_start(p, m) + n - m : 0;
+            const double2 c = cr[idx];
+            cB[t] = ok ? (cri ? c.y : c.x) : 0.0;
+            if (left > 0) { --left; ++ks; }
+        }
+    }
+    __syncthreads();   // LDS free: Fourier blocks and node values from here on
+
+    const int keRows = 4 * hg.nKE, koRows = 4 * hg.nKO;
+    const int gsz = (keRows + koRows) * 16;          // one latitude's Fourier block
+    double* RN = R + LB * gsz;                        // node values of one latitude
+    // Rows and columns of a Fourier block that are not rewritten meet zero A
+    // entries (padding terms) or feed unused output columns; start from zeros.
+    for (int z = threadIdx.x; z < LB * gsz + Lq.nlon * NV; z += blockDim.x) R[z] = 0.0;
+
+    double x0[3], n0v[3];
+    for (int c = 0; c < 3; ++c) { x0[c] = tx[c * T + tg]; n0v[c] = tnrm[c * T + tg]; }
     double acc[9];
     for (int c = 0; c < 9; ++c) acc[c] = 0.0;
     const bool wS = (kinds & EHD_STOKES_SL) && HF;
     const bool wD = (kinds & EHD_STOKES_DL) && (HF || HU);
     const bool wSL = (kinds & EHD_LAP_SL) && HS, wL = (kinds & EHD_LAP_DL) && HS;
     const bool wK = (kinds & EHD_LAP_DLADJ) && HS;
-    const int keRows = 4 * hg.nKE, koRows = 4 * hg.nKO;
-    const int gsz = (keRows + koRows) * 16;            // one latitude's Fourier block
-    // Two latitudes per pass: Fourier blocks G[0], G[1] (even rows, then odd
-    // rows, 16 columns each); afterwards the same memory holds the node values
-    // of one latitude at a time.  Rows and columns a block does not rewrite
-    // hold finite node values later, which meet zero A entries (padding
-    // terms) or feed unused output columns; start from zeros so that no
-    // uninitialised pattern reaches the MFMA.
-    {
-        const int nR = max(2 * gsz, Lq.nlon * NV);
-        for (int z = threadIdx.x; z < nR; z += blockDim.x) R[z] = 0.0;
-    }
+    int ktot = 0;
+    for (int mm = 0; mm <= p; ++mm) ktot += (p + 1 - mm + 3) / 4;
+    const int nblk = (Lq.Q + 1 + LB - 1) / LB;
+    const auto rsin = gmem(Lq.rsin);
 
-    // Legendre work item of this thread: field f (fastest) and degree
-    // column m; it walks n = m..p through contiguous column-major storage.
-    const int f = threadIdx.x % NF, mcol = threadIdx.x / NF;
-    const bool live = mcol <= p;
-    const int cstart = live ? column_start(p, mcol) : 0, clen = live ? p + 1 - mcol : 0;
-
-    for (int i = 0; i <= Lq.Q; i += 2) {
-        const bool two = i + 1 <= Lq.Q;
-        __syncthreads();  // previous node values consumed, c' complete
-        // a. Legendre sums -> real Fourier coefficients of latitudes i, i+1
-        {
-            const int i1 = two ? i + 1 : i;
-            const auto P0 = gmem(Lq.Pc + (long long)i * nc + cstart);
-            const auto D0 = gmem(Lq.dPc + (long long)i * nc + cstart);
-            const auto P1 = gmem(Lq.Pc + (long long)i1 * nc + cstart);
-            const auto D1 = gmem(Lq.dPc + (long long)i1 * nc + cstart);
-            const double2* cf = cr + f * nc + cstart;
-            double ar0 = 0.0, ai0 = 0.0, dr0 = 0.0, di0 = 0.0;
-            double ar1 = 0.0, ai1 = 0.0, dr1 = 0.0, di1 = 0.0;
-            if (f < 3) {
-#pragma unroll 4
-                for (int j = 0; j < clen; ++j) {
-                    const double2 c = cf[j];
-                    const double p0 = P0[j], d0 = D0[j], p1 = P1[j], d1 = D1[j];
-                    ar0 += p0 * c.x;
-                    ai0 += p0 * c.y;
-                    dr0 += d0 * c.x;
-                    di0 += d0 * c.y;
-                    ar1 += p1 * c.x;
-                    ai1 += p1 * c.y;
-                    dr1 += d1 * c.x;
-                    di1 += d1 * c.y;
+    // Legendre sums of degree m for the 8 latitudes of block b, from the
+    // MFMA result (rows: Pbar at latitudes 0..7, then dPbar/dtheta at 0..7;
+    // element r of the lane holds row lane/16 + 4 r, column (field, re/im)),
+    // written as real Fourier coefficients.
+    auto write_G = [&](int b, int m, const dbl4& a) {
+        const int f = cf_;
+        if (f >= NF || m > p) return;
+        const int kc = (m == 0) ? 0 : m - 1, ksr = m;
+        const double sc = (m == 0) ? 1.0 : 2.0;
+        const int v = (f < 3) ? f : VD + (f - 3);
+        for (int h = 0; h < 2; ++h) {
+            const int ll = (lane >> 4) + 4 * h, i = b * LB + ll;
+            if (i > Lq.Q) continue;
+            const double Pv = a[h], Dv = a[h + 2];
+            const double rs = rsin[i];
+            double* Gb = R + ll * gsz + ((m & 1) ? keRows * 16 : 0);
+            if (cri == 0) {
+                Gb[kc * 16 + v] = sc * Pv;
+                if (f < 3) {
+                    Gb[kc * 16 + 3 + f] = sc * Dv;
+                    // x_phi / sin theta, sin coefficient: -m a_m / s
+                    if (m > 0) Gb[ksr * 16 + 6 + f] = -sc * m * Pv * rs;
                 }
             } else {
-#pragma unroll 4
-                for (int j = 0; j < clen; ++j) {
-                    const double2 c = cf[j];
-                    const double p0 = P0[j], p1 = P1[j];
-                    ar0 += p0 * c.x;
-                    ai0 += p0 * c.y;
-                    ar1 += p1 * c.x;
-                    ai1 += p1 * c.y;
+                if (m > 0) Gb[ksr * 16 + v] = -sc * Pv;
+                if (f < 3) {
+                    if (m > 0) Gb[ksr * 16 + 3 + f] = -sc * Dv;
+                    // x_phi / sin theta, cos coefficient: m b_m / s
+                    Gb[kc * 16 + 6 + f] = (m == 0) ? 0.0 : -sc * m * Pv * rs;
                 }
             }
-            if (live) {
-                const int m = mcol;
-                const int kc = (m == 0) ? 0 : m - 1, ks = m;
-                const double sc = (m == 0) ? 1.0 : 2.0;
-                const int v = (f < 3) ? f : VD + (f - 3);
-                for (int sl = 0; sl < 2; ++sl) {
-                    if (sl == 1 && !two) break;
-                    const double ar = sl ? ar1 : ar0, ai = sl ? ai1 : ai0;
-                    const double dr = sl ? dr1 : dr0, di = sl ? di1 : di0;
-                    const double rs = gmem(Lq.rsin)[i + sl];
-                    // rows of the cos and sin terms of degree m in the E / O blocks
-                    double* Gb = R + sl * gsz + ((m & 1) ? keRows * 16 : 0);
-                    Gb[kc * 16 + v] = sc * ar;
-                    if (m > 0) Gb[ks * 16 + v] = -sc * ai;
-                    if (f < 3) {
-                        Gb[kc * 16 + 3 + f] = sc * dr;
-                        if (m > 0) Gb[ks * 16 + 3 + f] = -sc * di;
-                        // x_phi / sin theta: cos coef m b_m / s, sin coef -m a_m / s
-                        Gb[kc * 16 + 6 + f] = (m == 0) ? 0.0 : -sc * m * ai * rs;
-                        if (m > 0) Gb[ks * 16 + 6 + f] = -sc * m * ar * rs;
+        }
+    };
+
+    for (int b = 0; b < nblk; ++b) {
+        __syncthreads();  // Fourier blocks of the previous block fully read; zeroing done
+        // 3a. Legendre sums on MFMA: per degree column of this wave, a chain
+        //     over n of (Pbar; dPbar at 8 latitudes) x (rotated coefficients)
+        {
+            const auto lf = gmem(Lq.lfrag + (long long)b * ktot * 64 + lane);
+            int m = -1, left = 0, kbase = 0, ks = 0;
+            dbl4 a = dbl4{0, 0, 0, 0};
+#pragma unroll
+            for (int t = 0; t < SC::KW; ++t) {
+                if (left == 0) {        // column finished: store it, go to the next one
+                    if (m >= 0 && m <= p) {
+                        write_G(b, m, a);
+                        a = dbl4{0, 0, 0, 0};
+                        __builtin_amdgcn_sched_barrier(0);
                     }
+                    ++m;
+                    while (m <= p && snake_wave(m, NW) != wv) ++m;
+                    left = (m <= p) ? (p + 1 - m + 3) / 4 : 0;
+                    kbase = 0;
+                    for (int mm = 0; mm < m && m <= p; ++mm) kbase += (p + 1 - mm + 3) / 4;
+                    ks = 0;
+                }
+                if (left > 0) {
+                    a = __builtin_amdgcn_mfma_f64_16x16x4f64(lf[(long long)(kbase + ks) * 64], cB[t], a, 0, 0, 0);
+                    --left;
+                    ++ks;
                 }
             }
+            if (m >= 0 && m <= p) write_G(b, m, a);
         }
         __syncthreads();
 
-        // b. longitude sums on MFMA (even and odd chains of both latitudes
-        //    interleaved)
-        dbl4 accE[2][SC::TPW], accO[2][SC::TPW];
-        for (int sl = 0; sl < 2; ++sl)
-            for (int tt = 0; tt < SC::TPW; ++tt) {
-                accE[sl][tt] = dbl4{0, 0, 0, 0};
-                accO[sl][tt] = dbl4{0, 0, 0, 0};
-            }
-        constexpr int KSM = SC::KSE > SC::KSO ? SC::KSE : SC::KSO;
-        const int boff = (4 * 0 + (lane >> 4)) * 16 + (lane & 15);
+        for (int ll = 0; ll < LB; ++ll) {
+            const int i = b * LB + ll;
+            if (i > Lq.Q) break;
+            const double* G = R + ll * gsz;
+            // 3b. longitude sums on MFMA (even and odd chains interleaved)
+            dbl4 accE[SC::TPW], accO[SC::TPW];
+            for (int tt = 0; tt < SC::TPW; ++tt) { accE[tt] = dbl4{0, 0, 0, 0}; accO[tt] = dbl4{0, 0, 0, 0}; }
+            constexpr int KSM = SC::KSE > SC::KSO ? SC::KSE : SC::KSO;
+            const int boff = (lane >> 4) * 16 + (lane & 15);
 #pragma unroll
-        for (int ks = 0; ks < KSM; ++ks) {
-            if (ks < SC::KSE && ks < hg.nKE) {
-                const double b0 = R[ks * 64 + boff], b1 = R[gsz + ks * 64 + boff];
+            for (int ks = 0; ks < KSM; ++ks) {
+                if (ks < SC::KSE && ks < hg.nKE) {
+                    const double bv = G[ks * 64 + boff];
 #pragma unroll
-                for (int tt = 0; tt < SC::TPW; ++tt)
-                    if (wv + NW * tt < hg.nLT) {
-                        const double a = afE[tt][ks < SC::KSE ? ks : 0];
-                        accE[0][tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, accE[0][tt], 0, 0, 0);
-                        accE[1][tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, accE[1][tt], 0, 0, 0);
-                    }
-            }
-            if (ks < SC::KSO && ks < hg.nKO) {
-                const double b0 = R[keRows * 16 + ks * 64 + boff], b1 = R[gsz + keRows * 16 + ks * 64 + boff];
+                    for (int tt = 0; tt < SC::TPW; ++tt)
+                        if (wv + NW * tt < hg.nLT)
+                            accE[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(afE[tt][ks < SC::KSE ? ks : 0], bv,
+                                                                            accE[tt], 0, 0, 0);
+                }
+                if (ks < SC::KSO && ks < hg.nKO) {
+                    const double bv = G[keRows * 16 + ks * 64 + boff];
 #pragma unroll
-                for (int tt = 0; tt < SC::TPW; ++tt)
-                    if (wv + NW * tt < hg.nLT) {
-                        const double a = afO[tt][ks < SC::KSO ? ks : 0];
-                        accO[0][tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, accO[0][tt], 0, 0, 0);
-                        accO[1][tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, accO[1][tt], 0, 0, 0);
-                    }
+                    for (int tt = 0; tt < SC::TPW; ++tt)
+                        if (wv + NW * tt < hg.nLT)
+                            accO[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(afO[tt][ks < SC::KSO ? ks : 0], bv,
+                                                                            accO[tt], 0, 0, 0);
+                }
             }
-        }
-
-        for (int sl = 0; sl < 2; ++sl) {
-            if (sl == 1 && !two) break;
-            __syncthreads();  // B reads (sl = 0) or node reads (sl = 1) done before R is rewritten
+            if (ll > 0) __syncthreads();  // node values of the previous latitude consumed
             {
                 const int v = lane & 15;
                 for (int tt = 0; tt < SC::TPW; ++tt) {
@@ -543,20 +585,18 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
                     for (int r = 0; r < 4; ++r) {
                         const int l = 16 * t + (lane >> 4) + 4 * r;
                         if (l < hg.H) {
-                            const double e = sl ? accE[1][tt][r] : accE[0][tt][r];
-                            const double o = sl ? accO[1][tt][r] : accO[0][tt][r];
-                            R[l * NV + v] = e + o;
-                            R[(l + hg.H) * NV + v] = e - o;
+                            RN[l * NV + v] = accE[tt][r] + accO[tt][r];
+                            RN[(l + hg.H) * NV + v] = accE[tt][r] - accO[tt][r];
                         }
                     }
                 }
             }
             __syncthreads();
 
-            // c. kernels at the nodes of latitude i + sl
-            const double wi = gmem(Lq.wsing)[i + sl];
+            // 3c. kernels at the nodes of latitude i
+            const double wi = gmem(Lq.wsing)[i];
             for (int l = threadIdx.x; l < Lq.nlon; l += blockDim.x) {
-                const double* val = R + l * NV;
+                const double* val = RN + l * NV;
                 const double xt0 = val[3], xt1 = val[4], xt2 = val[5];
                 const double xp0 = val[6], xp1 = val[7], xp2 = val[8];
                 const double cx = xt1 * xp2 - xt2 * xp1;
@@ -583,35 +623,35 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
                     if (wD) {
                         constexpr int uo = VD + (HU ? UOFF : FOFF) - 3;
                         const double hu = hx * val[uo] + hy * val[uo + 1] + hz * val[uo + 2];
-                        const double t = -6.0 * w * hu * hn * ir3 * ir2;
-                        acc[3] += t * hx;
-                        acc[4] += t * hy;
-                        acc[5] += t * hz;
+                        const double tq = -6.0 * w * hu * hn * ir3 * ir2;
+                        acc[3] += tq * hx;
+                        acc[4] += tq * hy;
+                        acc[5] += tq * hz;
                     }
                 }
                 if constexpr (HS) {
                     const double sg = w * val[VD + SOFF - 3];
                     if (wSL) acc[6] += sg * ir;
                     if (wL) acc[7] += sg * hn * ir3;
-                    if (wK) acc[8] += sg * (hx * n0[0] + hy * n0[1] + hz * n0[2]) * ir3;
+                    if (wK) acc[8] += sg * (hx * n0v[0] + hy * n0v[1] + hz * n0v[2]) * ir3;
                 }
             }
         }
     }
     for (int c = 0; c < 9; ++c) {
-        const double s = wave_sum(acc[c]);
-        if (lane == 0) red[wv][c] = s;
+        const double sv = wave_sum(acc[c]);
+        if (lane == 0) red[wv][c] = sv;
     }
     __syncthreads();
     if (threadIdx.x < 9) {
-        double s = 0.0;
-        for (int w = 0; w < NW; ++w) s += red[w][threadIdx.x];
+        double sv = 0.0;
+        for (int w = 0; w < NW; ++w) sv += red[w][threadIdx.x];
         const unsigned bit = threadIdx.x < 3 ? EHD_STOKES_SL : threadIdx.x < 6 ? EHD_STOKES_DL
                              : threadIdx.x == 6 ? EHD_LAP_SL : threadIdx.x == 7 ? EHD_LAP_DL
                                                                                 : EHD_LAP_DLADJ;
         const bool mine = (threadIdx.x < 3 && HF) || (threadIdx.x >= 3 && threadIdx.x < 6 && (HF || HU)) ||
                           (threadIdx.x >= 6 && HS);
-        if ((kinds & bit) && mine) raw[threadIdx.x * T + tg] = s * kInv4Pi;
+        if ((kinds & bit) && mine) raw[threadIdx.x * T + tg] = sv * kInv4Pi;
     }
 }
 
@@ -1007,18 +1047,17 @@ static int degree_class(int p)
     return -1;
 }
 
-// Dynamic LDS of k_self for a set of drops: rotated coefficients of nf
-// fields plus the larger of two latitudes' Fourier blocks and one latitude's
-// node values.
 static size_t self_lds_bytes(const ehd_ctx* ctx, const std::vector<int>& drops, int nf)
 {
+    // rotated coefficients first; afterwards the same memory holds the
+    // Fourier blocks of one latitude block and the node values of one latitude
     size_t best = 0;
     for (int d : drops) {
         const DropInfo& D = ctx->info[d];
         const HalfGrid h = half_grid(D.p, D.nlon_s);
-        const size_t g = (size_t)2 * (4 * h.nKE + 4 * h.nKO) * 16 * 8;  // two latitudes
-        const size_t nodes = (size_t)D.nlon_s * (nf + 6) * 8;
-        best = std::max(best, (size_t)nf * ncoef(D.p) * 16 + std::max(g, nodes));
+        const size_t coef = (size_t)nf * ncoef(D.p) * 16;
+        const size_t work = ((size_t)kLatBlock * (4 * h.nKE + 4 * h.nKO) * 16 + (size_t)D.nlon_s * (nf + 6)) * 8;
+        best = std::max(best, std::max(coef, work));
     }
     return best;
 }
@@ -1221,17 +1260,26 @@ int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
         L.trig = dptr;
         if (singular) {
             const long ncp = ncoef(pp);
-            std::vector<double> Pc((size_t)(Q + 1) * ncp), dPc((size_t)(Q + 1) * ncp);
-            for (int i = 0; i <= Q; ++i)
+            int ktot = 0;
+            std::vector<int> kpre(pp + 1);
+            for (int m = 0; m <= pp; ++m) {
+                kpre[m] = ktot;
+                ktot += (pp + 1 - m + 3) / 4;
+            }
+            const int nblk = (Q + 1 + kLatBlock - 1) / kLatBlock;
+            std::vector<double> lf((size_t)nblk * ktot * 64, 0.0);
+            for (int bb = 0; bb < nblk; ++bb)
                 for (int m = 0; m <= pp; ++m)
-                    for (int n = m; n <= pp; ++n) {
-                        Pc[(size_t)i * ncp + column_start(pp, m) + n - m] = P[(size_t)i * ncp + tri(n, m)];
-                        dPc[(size_t)i * ncp + column_start(pp, m) + n - m] = dP[(size_t)i * ncp + tri(n, m)];
-                    }
-            if (upload(ctx, &dptr, Pc)) return -1;
-            L.Pc = dptr;
-            if (upload(ctx, &dptr, dPc)) return -1;
-            L.dPc = dptr;
+                    for (int ks = 0; ks < (pp + 1 - m + 3) / 4; ++ks)
+                        for (int lane = 0; lane < 64; ++lane) {
+                            const int row = lane & 15, n = m + 4 * ks + (lane >> 4);
+                            const int lat = bb * kLatBlock + (row & 7);
+                            if (lat > Q || n > pp) continue;
+                            const std::vector<double>& tab = (row < 8) ? P : dP;
+                            lf[((size_t)bb * ktot + kpre[m] + ks) * 64 + lane] = tab[(size_t)lat * ncp + tri(n, m)];
+                        }
+            if (upload(ctx, &dptr, lf)) return -1;
+            L.lfrag = dptr;
         }
         L.p = pp;
         L.Q = Q;
@@ -1465,27 +1513,25 @@ static int enqueue_evaluation(ehd_ctx* ctx, const double* fcoef_d, const double*
     EHD_HIP(ctx, hipGetLastError());
 
     ctx->mark(1);
-    // 2. singular self-interaction (one or two passes depending on LDS)
-    const int nf_all = 3 + (needF ? 3 : 0) + (needU ? 3 : 0) + (needLap ? 1 : 0);
-    bool fits = true;
-    for (int c = 0; c < 4; ++c)
-        fits = fits && self_lds_bytes(ctx, ctx->cls_drops[c], nf_all) + 8 * 9 * 8 <= (size_t)ctx->max_lds;
+    // 2. singular self-interaction.  The kernel holds at most 8 fields (its
+    //    Legendre MFMA has 16 columns: field x re/im), so a separate u goes
+    //    through its own pass (x, u) for D while the first pass covers the
+    //    other kinds.
     int rc = EHD_OK;
-    if (fits || !needU || !(needF || needLap)) {
-        if (needF && needU && needLap) rc = launch_self<true, true, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
-        else if (needF && needU) rc = launch_self<true, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
-        else if (needF && needLap) rc = launch_self<true, false, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
-        else if (needU && needLap) rc = launch_self<false, true, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
-        else if (needF) rc = launch_self<true, false, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
-        else if (needU) rc = launch_self<false, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
-        else rc = launch_self<false, false, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
-    } else {
-        // u separate and everything does not fit: D in its own pass
+    if (needU && (needF || needLap)) {
         const unsigned k1 = kinds & ~(unsigned)EHD_STOKES_DL;
         if (needF && needLap) rc = launch_self<true, false, true>(ctx, fcoef_d, nullptr, sigcoef_d, k1);
         else if (needF) rc = launch_self<true, false, false>(ctx, fcoef_d, nullptr, sigcoef_d, k1);
         else rc = launch_self<false, false, true>(ctx, fcoef_d, nullptr, sigcoef_d, k1);
         if (rc == EHD_OK) rc = launch_self<false, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, EHD_STOKES_DL);
+    } else if (needU) {
+        rc = launch_self<false, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
+    } else if (needF && needLap) {
+        rc = launch_self<true, false, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
+    } else if (needF) {
+        rc = launch_self<true, false, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
+    } else {
+        rc = launch_self<false, false, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
     }
     if (rc) return rc;
     ctx->mark(2);
