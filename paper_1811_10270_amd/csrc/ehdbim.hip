@@ -345,6 +345,12 @@ struct SelfClass {
     static constexpr int KW = wave_ksteps_max(PMAX, NW);       // Legendre k-steps per wave
 };
 
+// Legendre k-steps per wave of the degree class of p (table stride per wave).
+static inline int self_kw(int p)
+{
+    return p <= 16 ? SelfClass<16>::KW : p <= 24 ? SelfClass<24>::KW : p <= 32 ? SelfClass<32>::KW : SelfClass<48>::KW;
+}
+
 template <int PMAX, bool HF, bool HU, bool HS>
 __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     const DropInfo* __restrict__ drops, const LegTab* __restrict__ legs,
@@ -360,6 +366,7 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     constexpr int VD = 9;                // first density variant
     using SC = SelfClass<PMAX>;
     static_assert(2 * NF <= 16, "at most 8 fields: (field, re/im) fill the 16 MFMA columns");
+    static_assert(SC::NW >= 8, "one longitude row tile per wave: up to 8 tiles");
     constexpr int NT = SC::NT, NW = SC::NW, LB = kLatBlock;
     extern __shared__ double2 lds[];
     __shared__ double red[NW][9];
@@ -385,22 +392,20 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     if (HU) for (int c = 0; c < 3; ++c) fld[UOFF + c] = gmem(ucoef + 3 * D.coff + c * 2 * nc);
     if (HS) fld[SOFF] = gmem(scoef + D.coff);
 
-    // register-resident A operand of the longitude sums: cos/sin(m phi_l)
-    // fragments of this wave's row tiles, even-m and odd-m blocks
-    double afE[SC::TPW][SC::KSE], afO[SC::TPW][SC::KSO];
+    // register-resident A operand of the longitude sums of this wave's row
+    // tile (rows 16 wv .. 16 wv + 15 of the half period): cos/sin(m phi_l),
+    // even-m and odd-m blocks
+    const bool dft_wave = wv < hg.nLT;
+    double afE[SC::KSE], afO[SC::KSO];
     {
         const int nks = hg.nKE + hg.nKO;
+        const auto src = gmem(Lq.afrag + (long long)(dft_wave ? wv : 0) * nks * 64 + lane);
 #pragma unroll
-        for (int tt = 0; tt < SC::TPW; ++tt) {
-            const int t = wv + NW * tt;
-            const auto src = gmem(Lq.afrag + (long long)t * nks * 64 + lane);
+        for (int ks = 0; ks < SC::KSE; ++ks)
+            afE[ks] = (dft_wave && ks < hg.nKE) ? src[(long long)ks * 64] : 0.0;
 #pragma unroll
-            for (int ks = 0; ks < SC::KSE; ++ks)
-                afE[tt][ks] = (t < hg.nLT && ks < hg.nKE) ? src[(long long)ks * 64] : 0.0;
-#pragma unroll
-            for (int ks = 0; ks < SC::KSO; ++ks)
-                afO[tt][ks] = (t < hg.nLT && ks < hg.nKO) ? src[(long long)(hg.nKE + ks) * 64] : 0.0;
-        }
+        for (int ks = 0; ks < SC::KSO; ++ks)
+            afO[ks] = (dft_wave && ks < hg.nKO) ? src[(long long)(hg.nKE + ks) * 64] : 0.0;
     }
 
     // 1. rotation into LDS (column-major: column m holds n = m..p contiguously)
@@ -456,14 +461,15 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
             if (left > 0) { --left; ++ks; }
         }
     }
-    __syncthreads();   // LDS free: Fourier blocks and node values from here on
+    __syncthreads();   // LDS free: Fourier blocks and per-wave node buffers from here on
 
     const int keRows = 4 * hg.nKE, koRows = 4 * hg.nKO;
     const int gsz = (keRows + koRows) * 16;          // one latitude's Fourier block
-    double* RN = R + LB * gsz;                        // node values of one latitude
+    constexpr int NVP = NV | 1;                       // node record stride (odd: fewer bank conflicts)
+    double* NB = R + LB * gsz + wv * 64 * NVP;        // this wave's node values (64 nodes)
     // Rows and columns of a Fourier block that are not rewritten meet zero A
     // entries (padding terms) or feed unused output columns; start from zeros.
-    for (int z = threadIdx.x; z < LB * gsz + Lq.nlon * NV; z += blockDim.x) R[z] = 0.0;
+    for (int z = threadIdx.x; z < LB * gsz; z += blockDim.x) R[z] = 0.0;
 
     double x0[3], n0v[3];
     for (int c = 0; c < 3; ++c) { x0[c] = tx[c * T + tg]; n0v[c] = tnrm[c * T + tg]; }
@@ -473,10 +479,9 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     const bool wD = (kinds & EHD_STOKES_DL) && (HF || HU);
     const bool wSL = (kinds & EHD_LAP_SL) && HS, wL = (kinds & EHD_LAP_DL) && HS;
     const bool wK = (kinds & EHD_LAP_DLADJ) && HS;
-    int ktot = 0;
-    for (int mm = 0; mm <= p; ++mm) ktot += (p + 1 - mm + 3) / 4;
     const int nblk = (Lq.Q + 1 + LB - 1) / LB;
     const auto rsin = gmem(Lq.rsin);
+    const auto wsing = gmem(Lq.wsing);
 
     // Legendre sums of degree m for the 8 latitudes of block b, from the
     // MFMA result (rows: Pbar at latitudes 0..7, then dPbar/dtheta at 0..7;
@@ -512,131 +517,146 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
         }
     };
 
+    // first degree column of this wave and its number of k-steps
+    const int m_first = wv <= p ? wv : p + 1;
+    constexpr int PF = 6;                                 // Legendre fragments per prefetch batch
+    constexpr int NBATCH = (SC::KW + PF - 1) / PF;
     for (int b = 0; b < nblk; ++b) {
-        __syncthreads();  // Fourier blocks of the previous block fully read; zeroing done
         // 3a. Legendre sums on MFMA: per degree column of this wave, a chain
-        //     over n of (Pbar; dPbar at 8 latitudes) x (rotated coefficients)
+        //     over n of (Pbar; dPbar at 8 latitudes) x (rotated coefficients).
+        //     This wave's A fragments are contiguous in the table (zero past
+        //     its last k-step), so they stream in batches independent of the
+        //     column bookkeeping.
         {
-            const auto lf = gmem(Lq.lfrag + (long long)b * ktot * 64 + lane);
-            int m = -1, left = 0, kbase = 0, ks = 0;
+            const auto lf = gmem(Lq.lfrag + ((long long)b * NW + wv) * SC::KW * 64 + lane);
+            double av[2][PF];
+#pragma unroll
+            for (int u = 0; u < PF; ++u) av[0][u] = (u < SC::KW) ? lf[(long long)u * 64] : 0.0;
+            int m = m_first, left = (m <= p) ? (p + 1 - m + 3) / 4 : 0;
             dbl4 a = dbl4{0, 0, 0, 0};
 #pragma unroll
-            for (int t = 0; t < SC::KW; ++t) {
-                if (left == 0) {        // column finished: store it, go to the next one
-                    if (m >= 0 && m <= p) {
-                        write_G(b, m, a);
-                        a = dbl4{0, 0, 0, 0};
-                        __builtin_amdgcn_sched_barrier(0);
+            for (int g = 0; g < NBATCH; ++g) {
+                if (g + 1 < NBATCH) {
+#pragma unroll
+                    for (int u = 0; u < PF; ++u) {
+                        const int t = (g + 1) * PF + u;
+                        av[(g + 1) & 1][u] = (t < SC::KW) ? lf[(long long)t * 64] : 0.0;
                     }
-                    ++m;
-                    while (m <= p && snake_wave(m, NW) != wv) ++m;
-                    left = (m <= p) ? (p + 1 - m + 3) / 4 : 0;
-                    kbase = 0;
-                    for (int mm = 0; mm < m && m <= p; ++mm) kbase += (p + 1 - mm + 3) / 4;
-                    ks = 0;
                 }
-                if (left > 0) {
-                    a = __builtin_amdgcn_mfma_f64_16x16x4f64(lf[(long long)(kbase + ks) * 64], cB[t], a, 0, 0, 0);
-                    --left;
-                    ++ks;
-                }
-            }
-            if (m >= 0 && m <= p) write_G(b, m, a);
-        }
-        __syncthreads();
-
-        for (int ll = 0; ll < LB; ++ll) {
-            const int i = b * LB + ll;
-            if (i > Lq.Q) break;
-            const double* G = R + ll * gsz;
-            // 3b. longitude sums on MFMA (even and odd chains interleaved)
-            dbl4 accE[SC::TPW], accO[SC::TPW];
-            for (int tt = 0; tt < SC::TPW; ++tt) { accE[tt] = dbl4{0, 0, 0, 0}; accO[tt] = dbl4{0, 0, 0, 0}; }
-            constexpr int KSM = SC::KSE > SC::KSO ? SC::KSE : SC::KSO;
-            const int boff = (lane >> 4) * 16 + (lane & 15);
 #pragma unroll
-            for (int ks = 0; ks < KSM; ++ks) {
-                if (ks < SC::KSE && ks < hg.nKE) {
-                    const double bv = G[ks * 64 + boff];
-#pragma unroll
-                    for (int tt = 0; tt < SC::TPW; ++tt)
-                        if (wv + NW * tt < hg.nLT)
-                            accE[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(afE[tt][ks < SC::KSE ? ks : 0], bv,
-                                                                            accE[tt], 0, 0, 0);
-                }
-                if (ks < SC::KSO && ks < hg.nKO) {
-                    const double bv = G[keRows * 16 + ks * 64 + boff];
-#pragma unroll
-                    for (int tt = 0; tt < SC::TPW; ++tt)
-                        if (wv + NW * tt < hg.nLT)
-                            accO[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(afO[tt][ks < SC::KSO ? ks : 0], bv,
-                                                                            accO[tt], 0, 0, 0);
-                }
-            }
-            if (ll > 0) __syncthreads();  // node values of the previous latitude consumed
-            {
-                const int v = lane & 15;
-                for (int tt = 0; tt < SC::TPW; ++tt) {
-                    const int t = wv + NW * tt;
-                    if (t >= hg.nLT || v >= NV) continue;
-                    // MFMA f64 16x16x4 result layout: element r of lane holds
-                    // row (lane / 16) + 4 r, column lane % 16
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int l = 16 * t + (lane >> 4) + 4 * r;
-                        if (l < hg.H) {
-                            RN[l * NV + v] = accE[tt][r] + accO[tt][r];
-                            RN[(l + hg.H) * NV + v] = accE[tt][r] - accO[tt][r];
+                for (int u = 0; u < PF; ++u) {
+                    const int t = g * PF + u;
+                    if (t < SC::KW && left > 0) {
+                        a = __builtin_amdgcn_mfma_f64_16x16x4f64(av[g & 1][u], cB[t], a, 0, 0, 0);
+                        if (--left == 0) {   // column finished: store it, go to the next one
+                            write_G(b, m, a);
+                            a = dbl4{0, 0, 0, 0};
+                            ++m;
+                            while (m <= p && snake_wave(m, NW) != wv) ++m;
+                            left = (m <= p) ? (p + 1 - m + 3) / 4 : 0;
                         }
                     }
                 }
             }
-            __syncthreads();
+        }
+        __syncthreads();
 
-            // 3c. kernels at the nodes of latitude i
-            const double wi = gmem(Lq.wsing)[i];
-            for (int l = threadIdx.x; l < Lq.nlon; l += blockDim.x) {
-                const double* val = RN + l * NV;
-                const double xt0 = val[3], xt1 = val[4], xt2 = val[5];
-                const double xp0 = val[6], xp1 = val[7], xp2 = val[8];
-                const double cx = xt1 * xp2 - xt2 * xp1;
-                const double cy = xt2 * xp0 - xt0 * xp2;
-                const double cz = xt0 * xp1 - xt1 * xp0;
-                const double J2 = cx * cx + cy * cy + cz * cz;
-                const double iJ = rsqrt_nr(J2);
-                const double w = wi * J2 * iJ;
-                const double nx = cx * iJ, ny = cy * iJ, nz = cz * iJ;
-                const double hx = x0[0] - val[0], hy = x0[1] - val[1], hz = x0[2] - val[2];
-                const double r2 = hx * hx + hy * hy + hz * hz;
-                const double ir = rsqrt_nr(r2), ir2 = ir * ir, ir3 = ir * ir2;
-                const double hn = hx * nx + hy * ny + hz * nz;
-                if constexpr (HF) {
-                    if (wS) {
-                        const double f0 = val[VD], f1 = val[VD + 1], f2 = val[VD + 2];
-                        const double hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
-                        acc[0] += w * (f0 * ir + hx * hf);
-                        acc[1] += w * (f1 * ir + hy * hf);
-                        acc[2] += w * (f2 * ir + hz * hf);
+        // 3b/3c. per pair of latitudes of the block: longitude sums of this
+        //     wave's row tile on MFMA (even and odd chains of both latitudes
+        //     interleaved), node values through the wave's own LDS buffer
+        //     (64 nodes: two latitudes x {phi_l, phi_l + pi} x 16 rows), then
+        //     one node per lane: kernels with the modified weights.
+        if (dft_wave) {
+            const int boff = (lane >> 4) * 16 + (lane & 15);
+            for (int lp = 0; lp < LB; lp += 2) {
+                const int i0 = b * LB + lp;
+                if (i0 > Lq.Q) break;
+                const double* G0 = R + lp * gsz;
+                const double* G1 = G0 + gsz;       // latitude i0 + 1 (unused if past Q)
+                dbl4 e0 = dbl4{0, 0, 0, 0}, o0 = e0, e1 = e0, o1 = e0;
+                constexpr int KSM = SC::KSE > SC::KSO ? SC::KSE : SC::KSO;
+#pragma unroll
+                for (int ks = 0; ks < KSM; ++ks) {
+                    if (ks < SC::KSE && ks < hg.nKE) {
+                        const double b0 = G0[ks * 64 + boff], b1 = G1[ks * 64 + boff];
+                        e0 = __builtin_amdgcn_mfma_f64_16x16x4f64(afE[ks < SC::KSE ? ks : 0], b0, e0, 0, 0, 0);
+                        e1 = __builtin_amdgcn_mfma_f64_16x16x4f64(afE[ks < SC::KSE ? ks : 0], b1, e1, 0, 0, 0);
+                    }
+                    if (ks < SC::KSO && ks < hg.nKO) {
+                        const double b0 = G0[keRows * 16 + ks * 64 + boff];
+                        const double b1 = G1[keRows * 16 + ks * 64 + boff];
+                        o0 = __builtin_amdgcn_mfma_f64_16x16x4f64(afO[ks < SC::KSO ? ks : 0], b0, o0, 0, 0, 0);
+                        o1 = __builtin_amdgcn_mfma_f64_16x16x4f64(afO[ks < SC::KSO ? ks : 0], b1, o1, 0, 0, 0);
                     }
                 }
-                if constexpr (HF || HU) {
-                    if (wD) {
-                        constexpr int uo = VD + (HU ? UOFF : FOFF) - 3;
-                        const double hu = hx * val[uo] + hy * val[uo + 1] + hz * val[uo + 2];
-                        const double tq = -6.0 * w * hu * hn * ir3 * ir2;
-                        acc[3] += tq * hx;
-                        acc[4] += tq * hy;
-                        acc[5] += tq * hz;
+                // node buffer: record s = 32 (latitude of the pair) + 16 (phi + pi) + row
+                {
+                    const int v = lane & 15;
+                    if (v < NV) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int row = (lane >> 4) + 4 * r;
+                            NB[row * NVP + v] = e0[r] + o0[r];
+                            NB[(16 + row) * NVP + v] = e0[r] - o0[r];
+                            NB[(32 + row) * NVP + v] = e1[r] + o1[r];
+                            NB[(48 + row) * NVP + v] = e1[r] - o1[r];
+                        }
                     }
                 }
-                if constexpr (HS) {
-                    const double sg = w * val[VD + SOFF - 3];
-                    if (wSL) acc[6] += sg * ir;
-                    if (wL) acc[7] += sg * hn * ir3;
-                    if (wK) acc[8] += sg * (hx * n0v[0] + hy * n0v[1] + hz * n0v[2]) * ir3;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const int i = i0 + (lane >> 5);
+                const int l = 16 * wv + (lane & 15);
+                if (i <= Lq.Q && l < hg.H) {
+                    const double* val = NB + lane * NVP;
+                    const double wi = wsing[i];
+                    const double xt0 = val[3], xt1 = val[4], xt2 = val[5];
+                    const double xp0 = val[6], xp1 = val[7], xp2 = val[8];
+                    const double cx = xt1 * xp2 - xt2 * xp1;
+                    const double cy = xt2 * xp0 - xt0 * xp2;
+                    const double cz = xt0 * xp1 - xt1 * xp0;
+                    const double J2 = cx * cx + cy * cy + cz * cz;
+                    const double iJ = rsqrt_nr(J2);
+                    const double w = wi * J2 * iJ;
+                    const double nx = cx * iJ, ny = cy * iJ, nz = cz * iJ;
+                    const double hx = x0[0] - val[0], hy = x0[1] - val[1], hz = x0[2] - val[2];
+                    const double r2 = hx * hx + hy * hy + hz * hz;
+                    const double ir = rsqrt_nr(r2), ir2 = ir * ir, ir3 = ir * ir2;
+                    const double hn = hx * nx + hy * ny + hz * nz;
+                    if constexpr (HF) {
+                        if (wS) {
+                            const double f0 = val[VD], f1 = val[VD + 1], f2 = val[VD + 2];
+                            const double hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
+                            acc[0] += w * (f0 * ir + hx * hf);
+                            acc[1] += w * (f1 * ir + hy * hf);
+                            acc[2] += w * (f2 * ir + hz * hf);
+                        }
+                    }
+                    if constexpr (HF || HU) {
+                        if (wD) {
+                            constexpr int uo = VD + (HU ? UOFF : FOFF) - 3;
+                            const double hu = hx * val[uo] + hy * val[uo + 1] + hz * val[uo + 2];
+                            const double tq = -6.0 * w * hu * hn * ir3 * ir2;
+                            acc[3] += tq * hx;
+                            acc[4] += tq * hy;
+                            acc[5] += tq * hz;
+                        }
+                    }
+                    if constexpr (HS) {
+                        const double sg = w * val[VD + SOFF - 3];
+                        if (wSL) acc[6] += sg * ir;
+                        if (wL) acc[7] += sg * hn * ir3;
+                        if (wK) acc[8] += sg * (hx * n0v[0] + hy * n0v[1] + hz * n0v[2]) * ir3;
+                    }
                 }
+                // the buffer is rewritten by the next pair
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
+        __syncthreads();  // Fourier blocks consumed before the next block's Legendre sums
     }
     for (int c = 0; c < 9; ++c) {
         const double sv = wave_sum(acc[c]);
@@ -1050,13 +1070,14 @@ static int degree_class(int p)
 static size_t self_lds_bytes(const ehd_ctx* ctx, const std::vector<int>& drops, int nf)
 {
     // rotated coefficients first; afterwards the same memory holds the
-    // Fourier blocks of one latitude block and the node values of one latitude
+    // Fourier blocks of one latitude block and each wave's node buffer
     size_t best = 0;
     for (int d : drops) {
         const DropInfo& D = ctx->info[d];
         const HalfGrid h = half_grid(D.p, D.nlon_s);
         const size_t coef = (size_t)nf * ncoef(D.p) * 16;
-        const size_t work = ((size_t)kLatBlock * (4 * h.nKE + 4 * h.nKO) * 16 + (size_t)D.nlon_s * (nf + 6)) * 8;
+        const size_t work = ((size_t)kLatBlock * (4 * h.nKE + 4 * h.nKO) * 16 +
+                             (size_t)SelfClass<16>::NW * 64 * ((nf + 6) | 1)) * 8;
         best = std::max(best, std::max(coef, work));
     }
     return best;
@@ -1259,25 +1280,31 @@ int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
         if (upload(ctx, &dptr, trig)) return -1;
         L.trig = dptr;
         if (singular) {
+            // Legendre A fragments, per latitude block and per wave: the
+            // k-steps of the wave's degree columns (snake order, increasing
+            // m) back to back, zero-padded to the class's maximum; lane holds
+            // row lane%16 (Pbar at latitudes 0..7 of the block, then
+            // dPbar/dtheta), degree n = m + 4 ks + lane/16.
             const long ncp = ncoef(pp);
-            int ktot = 0;
-            std::vector<int> kpre(pp + 1);
-            for (int m = 0; m <= pp; ++m) {
-                kpre[m] = ktot;
-                ktot += (pp + 1 - m + 3) / 4;
-            }
+            const int nw = SelfClass<16>::NW, kw = self_kw(pp);
             const int nblk = (Q + 1 + kLatBlock - 1) / kLatBlock;
-            std::vector<double> lf((size_t)nblk * ktot * 64, 0.0);
+            std::vector<double> lf((size_t)nblk * nw * kw * 64, 0.0);
             for (int bb = 0; bb < nblk; ++bb)
-                for (int m = 0; m <= pp; ++m)
-                    for (int ks = 0; ks < (pp + 1 - m + 3) / 4; ++ks)
-                        for (int lane = 0; lane < 64; ++lane) {
-                            const int row = lane & 15, n = m + 4 * ks + (lane >> 4);
-                            const int lat = bb * kLatBlock + (row & 7);
-                            if (lat > Q || n > pp) continue;
-                            const std::vector<double>& tab = (row < 8) ? P : dP;
-                            lf[((size_t)bb * ktot + kpre[m] + ks) * 64 + lane] = tab[(size_t)lat * ncp + tri(n, m)];
-                        }
+                for (int w = 0; w < nw; ++w) {
+                    int t = 0;
+                    for (int m = 0; m <= pp; ++m) {
+                        if (snake_wave(m, nw) != w) continue;
+                        for (int ks = 0; ks < (pp + 1 - m + 3) / 4; ++ks, ++t)
+                            for (int lane = 0; lane < 64; ++lane) {
+                                const int row = lane & 15, n = m + 4 * ks + (lane >> 4);
+                                const int lat = bb * kLatBlock + (row & 7);
+                                if (lat > Q || n > pp) continue;
+                                const std::vector<double>& tab = (row < 8) ? P : dP;
+                                lf[(((size_t)bb * nw + w) * kw + t) * 64 + lane] = tab[(size_t)lat * ncp + tri(n, m)];
+                            }
+                    }
+                    if (t > kw) return -1;
+                }
             if (upload(ctx, &dptr, lf)) return -1;
             L.lfrag = dptr;
         }
