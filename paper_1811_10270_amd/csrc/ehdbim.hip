@@ -279,10 +279,11 @@ __global__ void k_src_dens(const double* __restrict__ synf, const double* __rest
 //         derivative table for x) on the vector ALU, written as real
 //         Fourier coefficients (cos / sin of m phi) of every grid quantity
 //         (x, x_theta, x_phi / sin theta, densities) into LDS;
-//      b. longitude sums as FP64 MFMA products: the nodes phi_l and
-//         phi_l + pi share the even-m and odd-m partial sums E, O
-//         (values E + O and E - O), so two GEMMs of half the rows, with the
-//         cos/sin table as the register-resident A operand, the Fourier
+//      b. longitude sums as FP64 MFMA products: the four nodes phi_l,
+//         pi - phi_l, pi + phi_l and 2 pi - phi_l share the four partial
+//         sums over (even m, odd m) x (cos, sin) terms, so four GEMMs of a
+//         quarter of the rows and a quarter of the terms each, with the
+//         cos/sin table as the register-resident A operand and the Fourier
 //         coefficients as B (columns = grid quantities);
 //      c. per node: normal, area factor, the kernels with the modified
 //         weights, accumulated per thread;
@@ -292,23 +293,36 @@ __global__ void k_src_dens(const double* __restrict__ synf, const double* __rest
 // ---------------------------------------------------------------------------
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-// Longitude-sum geometry of the (p, q) rotated grid:
-//   H = nlon_q / 2 rows per half period, nLT = ceil(H/16) row tiles,
-//   KE = 2*floor(p/2)+1 even-m terms, KO = 2*ceil(p/2) odd-m terms,
-//   nKE = ceil(KE/4), nKO = ceil(KO/4) MFMA k-steps.
-struct HalfGrid {
-    int H, nLT, KE, KO, nKE, nKO;
+// Longitude-sum geometry of the (p, q) rotated grid, N = nlon_q longitudes
+// phi_l = 2 pi l / N, H = N / 2.  With the partial sums
+//   EC = sum_{m even} a_m cos m phi, ES = sum_{m even} b_m sin m phi,
+//   OC = sum_{m odd}  a_m cos m phi, OS = sum_{m odd}  b_m sin m phi,
+// the nodes l, H - l, H + l, N - l take EC + ES + OC + OS, EC - ES - OC + OS,
+// EC + ES - OC - OS and EC - ES + OC - OS (cos m(pi -+ phi) = (-1)^m cos m phi,
+// sin m(pi - phi) = -(-1)^m sin m phi), so rows l = 0..floor(H/2) suffice.
+//   nT row tiles of 16 (padded to nTp in {1, 2, 4, 8} so that the waves
+//   split the tiles evenly); term counts: EC floor(p/2)+1 (m = 0, 2, ..),
+//   ES floor(p/2) (m = 2, 4, ..), OC = OS = ceil(p/2) (m = 1, 3, ..);
+//   k-steps of 4 terms per group, groups stored in the order EC ES OC OS.
+struct QuarterGrid {
+    int H, rows, nT, nTp, nk[4], base[4], nks;
 };
-__host__ __device__ inline HalfGrid half_grid(int p, int nlonq)
+__host__ __device__ inline QuarterGrid quarter_grid(int p, int nlonq)
 {
-    HalfGrid h;
-    h.H = nlonq / 2;
-    h.nLT = (h.H + 15) / 16;
-    h.KE = 2 * (p / 2) + 1;
-    h.KO = 2 * ((p + 1) / 2);
-    h.nKE = (h.KE + 3) / 4;
-    h.nKO = (h.KO + 3) / 4;
-    return h;
+    QuarterGrid g;
+    g.H = nlonq / 2;
+    g.rows = g.H / 2 + 1;
+    g.nT = (g.rows + 15) / 16;
+    g.nTp = g.nT <= 1 ? 1 : g.nT <= 2 ? 2 : g.nT <= 4 ? 4 : 8;
+    const int terms[4] = {p / 2 + 1, p / 2, (p + 1) / 2, (p + 1) / 2};
+    int b = 0;
+    for (int q = 0; q < 4; ++q) {
+        g.nk[q] = (terms[q] + 3) / 4;
+        g.base[q] = 4 * b;                 // first G row of the group
+        b += g.nk[q];
+    }
+    g.nks = b;
+    return g;
 }
 
 // Compile-time bounds of one degree class (all p <= PMAX; the rotated grid
@@ -337,8 +351,9 @@ constexpr int wave_ksteps_max(int PMAX, int nw)   // max over p <= PMAX and wave
 
 template <int PMAX>
 struct SelfClass {
-    static constexpr int KSE = (2 * (PMAX / 2) + 1 + 3) / 4;   // max even k-steps
-    static constexpr int KSO = (2 * ((PMAX + 1) / 2) + 3) / 4; // max odd k-steps
+    static constexpr int KEC = (PMAX / 2 + 1 + 3) / 4;         // max k-steps per group
+    static constexpr int KES = (PMAX / 2 + 3) / 4;
+    static constexpr int KOC = ((PMAX + 1) / 2 + 3) / 4;
     static constexpr int NT = 512;                             // threads per block
     static constexpr int NW = NT / 64;                         // waves per block
     static constexpr int TPW = (8 + NW - 1) / NW;              // row tiles per wave (max)
@@ -366,7 +381,7 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     constexpr int VD = 9;                // first density variant
     using SC = SelfClass<PMAX>;
     static_assert(2 * NF <= 16, "at most 8 fields: (field, re/im) fill the 16 MFMA columns");
-    static_assert(SC::NW >= 8, "one longitude row tile per wave: up to 8 tiles");
+    static_assert(SC::NW == 8, "row tiles (up to 8) are split evenly over 8 waves");
     constexpr int NT = SC::NT, NW = SC::NW, LB = kLatBlock;
     extern __shared__ double2 lds[];
     __shared__ double red[NW][9];
@@ -380,7 +395,7 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     const LegTab Lq = legs[D.leg_ps];
     const LegTab Lp = legs[D.leg_pp];
     const WigTab W = wigs[D.wig];
-    const HalfGrid hg = half_grid(p, Lq.nlon);
+    const QuarterGrid qg = quarter_grid(p, Lq.nlon);
     double2* cr = lds;                               // [NF][nc] rotated coefficients
     double* R = reinterpret_cast<double*>(lds);      // later: Fourier blocks + node values
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -393,19 +408,25 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     if (HS) fld[SOFF] = gmem(scoef + D.coff);
 
     // register-resident A operand of the longitude sums of this wave's row
-    // tile (rows 16 wv .. 16 wv + 15 of the half period): cos/sin(m phi_l),
-    // even-m and odd-m blocks
-    const bool dft_wave = wv < hg.nLT;
-    double afE[SC::KSE], afO[SC::KSO];
+    // tile (rows l = 16 tile .. 16 tile + 15): cos/sin(m phi_l) of the four
+    // term groups.  Waves w, w + nTp, .. share tile w % nTp and split the
+    // latitudes of a block.
+    const int my_tile = wv % qg.nTp;
+    const bool dft_wave = my_tile < qg.nT;
+    double aEC[SC::KEC], aES[SC::KES], aOC[SC::KOC], aOS[SC::KOC];
     {
-        const int nks = hg.nKE + hg.nKO;
-        const auto src = gmem(Lq.afrag + (long long)(dft_wave ? wv : 0) * nks * 64 + lane);
+        const auto src = gmem(Lq.afrag + (long long)(dft_wave ? my_tile : 0) * qg.nks * 64 + lane);
 #pragma unroll
-        for (int ks = 0; ks < SC::KSE; ++ks)
-            afE[ks] = (dft_wave && ks < hg.nKE) ? src[(long long)ks * 64] : 0.0;
+        for (int ks = 0; ks < SC::KEC; ++ks)
+            aEC[ks] = (dft_wave && ks < qg.nk[0]) ? src[(long long)(qg.base[0] / 4 + ks) * 64] : 0.0;
 #pragma unroll
-        for (int ks = 0; ks < SC::KSO; ++ks)
-            afO[ks] = (dft_wave && ks < hg.nKO) ? src[(long long)(hg.nKE + ks) * 64] : 0.0;
+        for (int ks = 0; ks < SC::KES; ++ks)
+            aES[ks] = (dft_wave && ks < qg.nk[1]) ? src[(long long)(qg.base[1] / 4 + ks) * 64] : 0.0;
+#pragma unroll
+        for (int ks = 0; ks < SC::KOC; ++ks) {
+            aOC[ks] = (dft_wave && ks < qg.nk[2]) ? src[(long long)(qg.base[2] / 4 + ks) * 64] : 0.0;
+            aOS[ks] = (dft_wave && ks < qg.nk[3]) ? src[(long long)(qg.base[3] / 4 + ks) * 64] : 0.0;
+        }
     }
 
     // 1. rotation into LDS (column-major: column m holds n = m..p contiguously)
@@ -463,8 +484,7 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     }
     __syncthreads();   // LDS free: Fourier blocks and per-wave node buffers from here on
 
-    const int keRows = 4 * hg.nKE, koRows = 4 * hg.nKO;
-    const int gsz = (keRows + koRows) * 16;          // one latitude's Fourier block
+    const int gsz = qg.nks * 64;                      // one latitude's Fourier block
     constexpr int NVP = NV | 1;                       // node record stride (odd: fewer bank conflicts)
     double* NB = R + LB * gsz + wv * 64 * NVP;        // this wave's node values (64 nodes)
     // Rows and columns of a Fourier block that are not rewritten meet zero A
@@ -490,7 +510,9 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     auto write_G = [&](int b, int m, const dbl4& a) {
         const int f = cf_;
         if (f >= NF || m > p) return;
-        const int kc = (m == 0) ? 0 : m - 1, ksr = m;
+        // G rows of the cos and sin coefficients of column m
+        const int kc = (m & 1) ? qg.base[2] + (m - 1) / 2 : m / 2;
+        const int ksr = (m & 1) ? qg.base[3] + (m - 1) / 2 : qg.base[1] + m / 2 - 1;
         const double sc = (m == 0) ? 1.0 : 2.0;
         const int v = (f < 3) ? f : VD + (f - 3);
         for (int h = 0; h < 2; ++h) {
@@ -498,7 +520,7 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
             if (i > Lq.Q) continue;
             const double Pv = a[h], Dv = a[h + 2];
             const double rs = rsin[i];
-            double* Gb = R + ll * gsz + ((m & 1) ? keRows * 16 : 0);
+            double* Gb = R + ll * gsz;
             if (cri == 0) {
                 Gb[kc * 16 + v] = sc * Pv;
                 if (f < 3) {
@@ -561,54 +583,54 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
         }
         __syncthreads();
 
-        // 3b/3c. per pair of latitudes of the block: longitude sums of this
-        //     wave's row tile on MFMA (even and odd chains of both latitudes
-        //     interleaved), node values through the wave's own LDS buffer
-        //     (64 nodes: two latitudes x {phi_l, phi_l + pi} x 16 rows), then
-        //     one node per lane: kernels with the modified weights.
+        // 3b/3c. per latitude of the block owned by this wave: longitude
+        //     sums of its row tile on MFMA (four term-group chains), node
+        //     values through the wave's own LDS buffer (64 nodes: {l, H - l,
+        //     H + l, N - l} x 16 rows), then one node per lane: kernels with
+        //     the modified weights.
         if (dft_wave) {
             const int boff = (lane >> 4) * 16 + (lane & 15);
-            for (int lp = 0; lp < LB; lp += 2) {
-                const int i0 = b * LB + lp;
-                if (i0 > Lq.Q) break;
-                const double* G0 = R + lp * gsz;
-                const double* G1 = G0 + gsz;       // latitude i0 + 1 (unused if past Q)
-                dbl4 e0 = dbl4{0, 0, 0, 0}, o0 = e0, e1 = e0, o1 = e0;
-                constexpr int KSM = SC::KSE > SC::KSO ? SC::KSE : SC::KSO;
+            for (int ll = wv / qg.nTp; ll < LB; ll += SC::NW / qg.nTp) {
+                const int i = b * LB + ll;
+                if (i > Lq.Q) break;
+                const double* G = R + ll * gsz + boff;
+                dbl4 ec = dbl4{0, 0, 0, 0}, es = ec, oc = ec, os = ec;
 #pragma unroll
-                for (int ks = 0; ks < KSM; ++ks) {
-                    if (ks < SC::KSE && ks < hg.nKE) {
-                        const double b0 = G0[ks * 64 + boff], b1 = G1[ks * 64 + boff];
-                        e0 = __builtin_amdgcn_mfma_f64_16x16x4f64(afE[ks < SC::KSE ? ks : 0], b0, e0, 0, 0, 0);
-                        e1 = __builtin_amdgcn_mfma_f64_16x16x4f64(afE[ks < SC::KSE ? ks : 0], b1, e1, 0, 0, 0);
-                    }
-                    if (ks < SC::KSO && ks < hg.nKO) {
-                        const double b0 = G0[keRows * 16 + ks * 64 + boff];
-                        const double b1 = G1[keRows * 16 + ks * 64 + boff];
-                        o0 = __builtin_amdgcn_mfma_f64_16x16x4f64(afO[ks < SC::KSO ? ks : 0], b0, o0, 0, 0, 0);
-                        o1 = __builtin_amdgcn_mfma_f64_16x16x4f64(afO[ks < SC::KSO ? ks : 0], b1, o1, 0, 0, 0);
-                    }
+                for (int ks = 0; ks < SC::KEC; ++ks) {
+                    if (ks < qg.nk[0])
+                        ec = __builtin_amdgcn_mfma_f64_16x16x4f64(aEC[ks], G[(qg.base[0] / 4 + ks) * 64], ec, 0, 0, 0);
+                    if (ks < SC::KES && ks < qg.nk[1])
+                        es = __builtin_amdgcn_mfma_f64_16x16x4f64(aES[ks < SC::KES ? ks : 0], G[(qg.base[1] / 4 + ks) * 64], es, 0, 0, 0);
+                    if (ks < SC::KOC && ks < qg.nk[2])
+                        oc = __builtin_amdgcn_mfma_f64_16x16x4f64(aOC[ks < SC::KOC ? ks : 0], G[(qg.base[2] / 4 + ks) * 64], oc, 0, 0, 0);
+                    if (ks < SC::KOC && ks < qg.nk[3])
+                        os = __builtin_amdgcn_mfma_f64_16x16x4f64(aOS[ks < SC::KOC ? ks : 0], G[(qg.base[3] / 4 + ks) * 64], os, 0, 0, 0);
                 }
-                // node buffer: record s = 32 (latitude of the pair) + 16 (phi + pi) + row
+                // node buffer: record 16 c + row for the nodes c = 0..3 of the row
                 {
                     const int v = lane & 15;
                     if (v < NV) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const int row = (lane >> 4) + 4 * r;
-                            NB[row * NVP + v] = e0[r] + o0[r];
-                            NB[(16 + row) * NVP + v] = e0[r] - o0[r];
-                            NB[(32 + row) * NVP + v] = e1[r] + o1[r];
-                            NB[(48 + row) * NVP + v] = e1[r] - o1[r];
+                            const double s0 = ec[r] + oc[r], s1 = ec[r] - oc[r];
+                            const double t0 = es[r] + os[r], t1 = es[r] - os[r];
+                            NB[row * NVP + v] = s0 + t0;             // l
+                            NB[(16 + row) * NVP + v] = s1 - t1;      // H - l
+                            NB[(32 + row) * NVP + v] = s1 + t1;      // H + l
+                            NB[(48 + row) * NVP + v] = s0 - t0;      // N - l
                         }
                     }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                const int i = i0 + (lane >> 5);
-                const int l = 16 * wv + (lane & 15);
-                if (i <= Lq.Q && l < hg.H) {
+                // node of this lane; the four images coincide pairwise at l = 0 and at 2 l = H
+                const int c4 = lane >> 4, l = 16 * my_tile + (lane & 15);
+                const bool node_ok = 2 * l <= qg.H &&
+                                     (c4 == 0 || (c4 == 1 && 2 * l < qg.H) || (c4 == 2 && l > 0) ||
+                                      (c4 == 3 && l > 0 && 2 * l < qg.H));
+                if (node_ok) {
                     const double* val = NB + lane * NVP;
                     const double wi = wsing[i];
                     const double xt0 = val[3], xt1 = val[4], xt2 = val[5];
@@ -650,7 +672,7 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
                         if (wK) acc[8] += sg * (hx * n0v[0] + hy * n0v[1] + hz * n0v[2]) * ir3;
                     }
                 }
-                // the buffer is rewritten by the next pair
+                // the buffer is rewritten for the next latitude
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1074,9 +1096,9 @@ static size_t self_lds_bytes(const ehd_ctx* ctx, const std::vector<int>& drops, 
     size_t best = 0;
     for (int d : drops) {
         const DropInfo& D = ctx->info[d];
-        const HalfGrid h = half_grid(D.p, D.nlon_s);
+        const QuarterGrid g = quarter_grid(D.p, D.nlon_s);
         const size_t coef = (size_t)nf * ncoef(D.p) * 16;
-        const size_t work = ((size_t)kLatBlock * (4 * h.nKE + 4 * h.nKO) * 16 +
+        const size_t work = ((size_t)kLatBlock * g.nks * 64 +
                              (size_t)SelfClass<16>::NW * 64 * ((nf + 6) | 1)) * 8;
         best = std::max(best, std::max(coef, work));
     }
@@ -1231,35 +1253,27 @@ int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
                 trig[((size_t)l * (pp + 1) + m) * 2] = std::cos(a);
                 trig[((size_t)l * (pp + 1) + m) * 2 + 1] = std::sin(a);
             }
-        // MFMA A fragments of the half-period cos/sin tables (singular grids):
-        // lane holds A[row 16t + lane%16][term 4ks + lane/16]; even-m terms
-        // (cos 0, then cos m, sin m for m = 2, 4, ...) for ks < nKE, odd-m
-        // terms (cos m, sin m for m = 1, 3, ...) after them.
+        // MFMA A fragments of the quarter-period cos/sin tables (singular
+        // grids): lane holds A[row 16 t + lane%16][term 4 ks + lane/16] of the
+        // term groups EC (cos m, m = 0, 2, ..), ES (sin m, m = 2, 4, ..),
+        // OC (cos m, m = 1, 3, ..), OS (sin m, m = 1, 3, ..), one after the other.
         std::vector<double> afrag;
         if (singular) {
-            const HalfGrid h = half_grid(pp, nl);
-            const int nks = h.nKE + h.nKO;
-            afrag.assign((size_t)h.nLT * nks * 64, 0.0);
-            for (int t = 0; t < h.nLT; ++t)
-                for (int ks = 0; ks < nks; ++ks)
-                    for (int lane = 0; lane < 64; ++lane) {
-                        const int l = 16 * t + (lane & 15);
-                        const bool odd = ks >= h.nKE;
-                        const int term = 4 * (odd ? ks - h.nKE : ks) + (lane >> 4);
-                        if (l >= h.H || term >= (odd ? h.KO : h.KE)) continue;
-                        int m;
-                        bool is_cos;
-                        if (!odd) {
-                            if (term == 0) { m = 0; is_cos = true; }
-                            else if (term & 1) { m = term + 1; is_cos = true; }
-                            else { m = term; is_cos = false; }
-                        } else {
-                            if ((term & 1) == 0) { m = term + 1; is_cos = true; }
-                            else { m = term; is_cos = false; }
+            const QuarterGrid g = quarter_grid(pp, nl);
+            afrag.assign((size_t)g.nT * g.nks * 64, 0.0);
+            const int terms[4] = {pp / 2 + 1, pp / 2, (pp + 1) / 2, (pp + 1) / 2};
+            for (int t = 0; t < g.nT; ++t)
+                for (int grp = 0; grp < 4; ++grp)
+                    for (int ks = 0; ks < g.nk[grp]; ++ks)
+                        for (int lane = 0; lane < 64; ++lane) {
+                            const int l = 16 * t + (lane & 15), term = 4 * ks + (lane >> 4);
+                            if (l >= g.rows || term >= terms[grp]) continue;
+                            const int m = grp == 0 ? 2 * term : grp == 1 ? 2 * term + 2 : 2 * term + 1;
+                            const bool is_cos = grp == 0 || grp == 2;
+                            const double a = 2.0 * kPi * (double)((long)m * l % nl) / nl;
+                            afrag[((size_t)t * g.nks + g.base[grp] / 4 + ks) * 64 + lane] =
+                                is_cos ? std::cos(a) : std::sin(a);
                         }
-                        const double a = 2.0 * kPi * (double)((long)m * l % nl) / nl;
-                        afrag[((size_t)t * nks + ks) * 64 + lane] = is_cos ? std::cos(a) : std::sin(a);
-                    }
         }
         LegTab L{};
         double* dptr;
