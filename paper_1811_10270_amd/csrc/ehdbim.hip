@@ -398,7 +398,8 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     const QuarterGrid qg = quarter_grid(p, Lq.nlon);
     double2* cr = lds;                               // [NF][nc] rotated coefficients
     double* R = reinterpret_cast<double*>(lds);      // later: Fourier blocks + node values
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     (void)NT;
 
     const __attribute__((address_space(1))) double* fld[NF];
@@ -503,43 +504,39 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     const auto rsin = gmem(Lq.rsin);
     const auto wsing = gmem(Lq.wsing);
 
-    // Legendre sums of degree m for the 8 latitudes of block b, from the
-    // MFMA result (rows: Pbar at latitudes 0..7, then dPbar/dtheta at 0..7;
+    // Legendre sums of degree m for the 8 latitudes of a block, from the MFMA
+    // result (rows: Pbar at latitudes 0..7, then dPbar/dtheta at 0..7;
     // element r of the lane holds row lane/16 + 4 r, column (field, re/im)),
-    // written as real Fourier coefficients.
-    auto write_G = [&](int b, int m, const dbl4& a) {
-        const int f = cf_;
-        if (f >= NF || m > p) return;
-        // G rows of the cos and sin coefficients of column m
+    // stored as real Fourier coefficients: field values and x_theta in the
+    // cos row (re) or sin row (im) of m with factors 1 (m = 0) or 2 and -2,
+    // x_phi / sin theta = -m (a_m sin - b_m cos) / sin theta in the other row.
+    // Kept short: it is expanded at every k-step of the unrolled chain.
+    const int f_l = cf_ < NF ? cf_ : 0;
+    const int v_l = (f_l < 3) ? f_l : VD + (f_l - 3);
+    const bool lane_xf = cf_ < 3, lane_field = cf_ < NF;
+    double* const Gl0 = R + (lane >> 4) * gsz;          // this lane's latitudes 0..3 of the block
+    double* const Gl1 = Gl0 + 4 * gsz;                  // and 4..7
+    // alternating steps between the snake-ordered columns of this wave
+    const int dm0 = 2 * NW - 1 - 2 * wv, dm1 = 2 * wv + 1;
+    auto store_col = [&](int m, const dbl4& a, double rs0, double rs1) {
+        if (!lane_field || (m == 0 && cri)) return;
         const int kc = (m & 1) ? qg.base[2] + (m - 1) / 2 : m / 2;
         const int ksr = (m & 1) ? qg.base[3] + (m - 1) / 2 : qg.base[1] + m / 2 - 1;
-        const double sc = (m == 0) ? 1.0 : 2.0;
-        const int v = (f < 3) ? f : VD + (f - 3);
-        for (int h = 0; h < 2; ++h) {
-            const int ll = (lane >> 4) + 4 * h, i = b * LB + ll;
-            if (i > Lq.Q) continue;
-            const double Pv = a[h], Dv = a[h + 2];
-            const double rs = rsin[i];
-            double* Gb = R + ll * gsz;
-            if (cri == 0) {
-                Gb[kc * 16 + v] = sc * Pv;
-                if (f < 3) {
-                    Gb[kc * 16 + 3 + f] = sc * Dv;
-                    // x_phi / sin theta, sin coefficient: -m a_m / s
-                    if (m > 0) Gb[ksr * 16 + 6 + f] = -sc * m * Pv * rs;
-                }
-            } else {
-                if (m > 0) Gb[ksr * 16 + v] = -sc * Pv;
-                if (f < 3) {
-                    if (m > 0) Gb[ksr * 16 + 3 + f] = -sc * Dv;
-                    // x_phi / sin theta, cos coefficient: m b_m / s
-                    Gb[kc * 16 + 6 + f] = (m == 0) ? 0.0 : -sc * m * Pv * rs;
-                }
+        const int r12 = (cri ? ksr : kc) * 16, r3 = (cri ? kc : ksr) * 16;
+        const double sc = (m == 0) ? 1.0 : (cri ? -2.0 : 2.0);
+        Gl0[r12 + v_l] = sc * a[0];
+        Gl1[r12 + v_l] = sc * a[1];
+        if (lane_xf) {
+            Gl0[r12 + 3 + f_l] = sc * a[2];
+            Gl1[r12 + 3 + f_l] = sc * a[3];
+            if (m > 0) {
+                const double sx = -2.0 * m;
+                Gl0[r3 + 6 + f_l] = sx * rs0 * a[0];
+                Gl1[r3 + 6 + f_l] = sx * rs1 * a[1];
             }
         }
     };
 
-    // first degree column of this wave and its number of k-steps
     const int m_first = wv <= p ? wv : p + 1;
     constexpr int PF = 6;                                 // Legendre fragments per prefetch batch
     constexpr int NBATCH = (SC::KW + PF - 1) / PF;
@@ -555,7 +552,11 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
 #pragma unroll
             for (int u = 0; u < PF; ++u) av[0][u] = (u < SC::KW) ? lf[(long long)u * 64] : 0.0;
             int m = m_first, left = (m <= p) ? (p + 1 - m + 3) / 4 : 0;
+            bool odd_step = (m_first / NW) & 1;
             dbl4 a = dbl4{0, 0, 0, 0};
+            // 1 / sin theta at this lane's two latitudes (clamped past the last one)
+            const double rs0 = rsin[min(b * LB + (lane >> 4), Lq.Q)];
+            const double rs1 = rsin[min(b * LB + (lane >> 4) + 4, Lq.Q)];
 #pragma unroll
             for (int g = 0; g < NBATCH; ++g) {
                 if (g + 1 < NBATCH) {
@@ -571,10 +572,10 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
                     if (t < SC::KW && left > 0) {
                         a = __builtin_amdgcn_mfma_f64_16x16x4f64(av[g & 1][u], cB[t], a, 0, 0, 0);
                         if (--left == 0) {   // column finished: store it, go to the next one
-                            write_G(b, m, a);
+                            store_col(m, a, rs0, rs1);
                             a = dbl4{0, 0, 0, 0};
-                            ++m;
-                            while (m <= p && snake_wave(m, NW) != wv) ++m;
+                            m += odd_step ? dm1 : dm0;
+                            odd_step = !odd_step;
                             left = (m <= p) ? (p + 1 - m + 3) / 4 : 0;
                         }
                     }
