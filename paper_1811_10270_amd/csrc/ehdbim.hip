@@ -11,11 +11,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "ehdbim.h"
@@ -774,17 +776,27 @@ __global__ __launch_bounds__(kThreads) void k_far64(const double* __restrict__ t
 // into an FP32 head and tail; sources are stored relative to the same centre.
 // The tile sum is accumulated in FP32 and added to a compensated (Kahan)
 // FP32 running sum.
-template <int TPT>
+// FP32 far field: the kinds KM are a template parameter (no per-interaction
+// branches), sources are read four at a time as float4 from each LDS record
+// row (one broadcast read per record and four sources).  Targets are taken
+// relative to the centre of the tile's drop in FP64 and split into FP32
+// high and low parts (h = (a - x_s) + b), the per-tile sums are FP32 and
+// the tile sums are added with Kahan compensation.  The double-layer
+// factor -6 is applied to the tile sums.
+template <int TPT, unsigned KM>
 __global__ __launch_bounds__(kThreads) void k_far32(const double* __restrict__ tx,
                                                     const double* __restrict__ tnrm,
                                                     const int* __restrict__ tdrop, long long T,
                                                     const float* __restrict__ src, long long Spad,
                                                     const int* __restrict__ tile_drop,
                                                     const double* __restrict__ dcentre, int ntiles,
-                                                    int tiles_per_chunk, unsigned kinds,
-                                                    double* __restrict__ partial)
+                                                    int tiles_per_chunk, double* __restrict__ partial)
 {
-    __shared__ float sm[kRec32][kTile];
+    constexpr bool wS = KM & EHD_STOKES_SL, wD = KM & EHD_STOKES_DL;
+    constexpr bool wSL = KM & EHD_LAP_SL, wL = KM & EHD_LAP_DL, wK = KM & EHD_LAP_DLADJ;
+    constexpr bool needN = wD || wL, needSig = wSL || wL || wK;
+    __shared__ float4 sm[kRec32][kTile / 4];
+    float* const smf = reinterpret_cast<float*>(&sm[0][0]);
     double X0[TPT], Y0[TPT], Z0[TPT];
     float n0x[TPT], n0y[TPT], n0z[TPT], sum[TPT][9], cmp[TPT][9];
     int myd[TPT];
@@ -798,12 +810,10 @@ __global__ __launch_bounds__(kThreads) void k_far32(const double* __restrict__ t
         myd[q] = valid ? tdrop[u] : -1;
         for (int c = 0; c < 9; ++c) { sum[q][c] = 0.0f; cmp[q][c] = 0.0f; }
     }
-    const bool wS = kinds & EHD_STOKES_SL, wD = kinds & EHD_STOKES_DL;
-    const bool wSL = kinds & EHD_LAP_SL, wL = kinds & EHD_LAP_DL, wK = kinds & EHD_LAP_DLADJ;
     const int t0 = blockIdx.y * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
     for (int tile = t0; tile < t1; ++tile) {
         const long long s = (long long)tile * kTile + threadIdx.x;
-        for (int r = 0; r < kRec32; ++r) sm[r][threadIdx.x] = src[r * Spad + s];
+        for (int r = 0; r < kRec32; ++r) smf[r * kTile + threadIdx.x] = src[r * Spad + s];
         __syncthreads();
         const int sd = tile_drop[tile];
         bool other = false;   // some target of this thread is not on the tile's drop
@@ -816,36 +826,46 @@ __global__ __launch_bounds__(kThreads) void k_far32(const double* __restrict__ t
             bx[k] = (float)(dx - ax[k]); by[k] = (float)(dy - ay[k]); bz[k] = (float)(dz - az[k]);
             for (int c = 0; c < 9; ++c) a[k][c] = 0.0f;
         }
-        for (int q = 0; q < (other ? kTile : 0); ++q) {
+        for (int q4 = 0; q4 < (other ? kTile / 4 : 0); ++q4) {
+            const float4 X = sm[0][q4], Y = sm[1][q4], Z = sm[2][q4];
+            float4 NX, NY, NZ, F0, F1, F2, U0, U1, U2, SG;
+            if constexpr (needN) { NX = sm[3][q4]; NY = sm[4][q4]; NZ = sm[5][q4]; }
+            if constexpr (wS) { F0 = sm[6][q4]; F1 = sm[7][q4]; F2 = sm[8][q4]; }
+            if constexpr (wD) { U0 = sm[9][q4]; U1 = sm[10][q4]; U2 = sm[11][q4]; }
+            if constexpr (needSig) SG = sm[12][q4];
 #pragma unroll
-            for (int k = 0; k < TPT; ++k) {
-                const float hx = (ax[k] - sm[0][q]) + bx[k], hy = (ay[k] - sm[1][q]) + by[k],
-                            hz = (az[k] - sm[2][q]) + bz[k];
-                const float r2 = hx * hx + hy * hy + hz * hz;
-                const float ir = __frsqrt_rn(r2), ir2 = ir * ir, ir3 = ir * ir2;
-                const float hn = hx * sm[3][q] + hy * sm[4][q] + hz * sm[5][q];
-                if (wS) {
-                    const float f0 = sm[6][q], f1 = sm[7][q], f2 = sm[8][q];
-                    const float hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
-                    a[k][0] += f0 * ir + hx * hf;
-                    a[k][1] += f1 * ir + hy * hf;
-                    a[k][2] += f2 * ir + hz * hf;
+            for (int j = 0; j < 4; ++j) {
+#pragma unroll
+                for (int k = 0; k < TPT; ++k) {
+                    const float hx = (ax[k] - X[j]) + bx[k], hy = (ay[k] - Y[j]) + by[k],
+                                hz = (az[k] - Z[j]) + bz[k];
+                    const float r2 = fmaf(hx, hx, fmaf(hy, hy, hz * hz));
+                    const float ir = __frsqrt_rn(r2), ir2 = ir * ir, ir3 = ir * ir2;
+                    float hn = 0.0f;
+                    if constexpr (needN) hn = fmaf(hx, NX[j], fmaf(hy, NY[j], hz * NZ[j]));
+                    if constexpr (wS) {
+                        const float hf = fmaf(hx, F0[j], fmaf(hy, F1[j], hz * F2[j])) * ir3;
+                        a[k][0] = fmaf(hx, hf, fmaf(F0[j], ir, a[k][0]));
+                        a[k][1] = fmaf(hy, hf, fmaf(F1[j], ir, a[k][1]));
+                        a[k][2] = fmaf(hz, hf, fmaf(F2[j], ir, a[k][2]));
+                    }
+                    if constexpr (wD) {
+                        const float hu = fmaf(hx, U0[j], fmaf(hy, U1[j], hz * U2[j]));
+                        const float tq = (hu * hn) * (ir3 * ir2);
+                        a[k][3] = fmaf(tq, hx, a[k][3]);
+                        a[k][4] = fmaf(tq, hy, a[k][4]);
+                        a[k][5] = fmaf(tq, hz, a[k][5]);
+                    }
+                    if constexpr (wSL) a[k][6] = fmaf(SG[j], ir, a[k][6]);
+                    if constexpr (wL) a[k][7] = fmaf(SG[j] * hn, ir3, a[k][7]);
+                    if constexpr (wK)
+                        a[k][8] = fmaf(SG[j] * fmaf(hx, n0x[k], fmaf(hy, n0y[k], hz * n0z[k])), ir3, a[k][8]);
                 }
-                if (wD) {
-                    const float hu = hx * sm[9][q] + hy * sm[10][q] + hz * sm[11][q];
-                    const float tq = -6.0f * hu * hn * ir3 * ir2;
-                    a[k][3] += tq * hx;
-                    a[k][4] += tq * hy;
-                    a[k][5] += tq * hz;
-                }
-                const float sg = sm[12][q];
-                if (wSL) a[k][6] += sg * ir;
-                if (wL) a[k][7] += sg * hn * ir3;
-                if (wK) a[k][8] += sg * (hx * n0x[k] + hy * n0y[k] + hz * n0z[k]) * ir3;
             }
         }
         for (int k = 0; k < TPT; ++k) {
             if (sd == myd[k]) continue;      // own drop: tile not counted
+            for (int c = 3; c < 6; ++c) a[k][c] *= -6.0f;
             for (int c = 0; c < 9; ++c) {    // Kahan
                 const float y = a[k][c] - cmp[k][c];
                 const float tsum = sum[k][c] + y;
@@ -1136,6 +1156,29 @@ static int launch_self(ehd_ctx* ctx, const double* f, const double* u, const dou
     if (!rc) rc = launch_self_class<24, HF, HU, HS>(ctx, 1, f, u, s, kinds);
     if (!rc) rc = launch_self_class<16, HF, HU, HS>(ctx, 0, f, u, s, kinds);
     return rc;
+}
+
+// FP32 far-field launchers, one per (targets per thread, kinds mask).
+using Far32Launch = void (*)(dim3, hipStream_t, const double*, const double*, const int*, long long, const float*,
+                             long long, const int*, const double*, int, int, double*);
+template <int TPT, unsigned KM>
+static void launch_far32_km(dim3 grid, hipStream_t st, const double* tx, const double* tn, const int* tdrop,
+                            long long T, const float* src, long long S, const int* tile_drop, const double* centre,
+                            int ntiles, int tpc, double* partial)
+{
+    hipLaunchKernelGGL((k_far32<TPT, KM>), grid, dim3(kThreads), 0, st, tx, tn, tdrop, T, src, S, tile_drop, centre,
+                       ntiles, tpc, partial);
+}
+template <int TPT, std::size_t... I>
+static const std::array<Far32Launch, 32>& far32_table_impl(std::index_sequence<I...>)
+{
+    static const std::array<Far32Launch, 32> t{{&launch_far32_km<TPT, (unsigned)I>...}};
+    return t;
+}
+template <int TPT>
+static const std::array<Far32Launch, 32>& far32_table()
+{
+    return far32_table_impl<TPT>(std::make_index_sequence<32>{});
 }
 
 extern "C" {
@@ -1506,14 +1549,9 @@ static int launch_far(ehd_ctx* ctx, int far_prec, unsigned kinds, int tpt, int n
             hipLaunchKernelGGL(k_far64<1>, grid, dim3(kThreads), 0, ctx->ls, ctx->d_tx, ctx->d_tn, ctx->d_tdrop,
                                T, ctx->d_src64, S, ctx->d_tile_drop, ctx->ntiles, tpc, kinds, ctx->d_partial);
     } else {
-        if (tpt == 2)
-            hipLaunchKernelGGL(k_far32<2>, grid, dim3(kThreads), 0, ctx->ls, ctx->d_tx, ctx->d_tn, ctx->d_tdrop,
-                               T, ctx->d_src32, S, ctx->d_tile_drop, ctx->d_centre, ctx->ntiles, tpc, kinds,
-                               ctx->d_partial);
-        else
-            hipLaunchKernelGGL(k_far32<1>, grid, dim3(kThreads), 0, ctx->ls, ctx->d_tx, ctx->d_tn, ctx->d_tdrop,
-                               T, ctx->d_src32, S, ctx->d_tile_drop, ctx->d_centre, ctx->ntiles, tpc, kinds,
-                               ctx->d_partial);
+        const Far32Launch fn = (tpt == 2 ? far32_table<2>() : far32_table<1>())[kinds & EHD_ALL_KINDS];
+        fn(grid, ctx->ls, ctx->d_tx, ctx->d_tn, ctx->d_tdrop, T, ctx->d_src32, S, ctx->d_tile_drop, ctx->d_centre,
+           ctx->ntiles, tpc, ctx->d_partial);
     }
     EHD_HIP(ctx, hipGetLastError());
     return EHD_OK;
