@@ -44,6 +44,24 @@ def self_flops_per_drop(p: int, q: int, grid_mode: int) -> float:
     return float(rot + leg + dft + ker)
 
 
+# HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs
+# recorded in profiles/hbm_traffic_batched_64_mixed_p.md (counters scaled by a
+# 1 GiB copy), valid only for the kernel source they were taken with.
+TRAFFIC_SOURCE_SHA256 = "2cd01f140322a8158411a45f2161a9eed2fa83bafe5ed97f20b7b72f83dc2398"
+TRAFFIC_WORKLOAD = "batched_64_mixed_p"
+TRAFFIC_BYTES = {"k_self<48>": 1.0304e10, "k_self<32>": 9.023e8, "k_self<24>": 4.905e7,
+                 "k_self<16>": 1.835e7, "k_far32": 8.066e8}
+
+
+def measured_traffic(kernel: str, workload: str):
+    import hashlib
+    path = os.path.join(ROOT, "paper_1811_10270_amd", "csrc", "ehdbim.hip")
+    with open(path, "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != TRAFFIC_SOURCE_SHA256 or workload != TRAFFIC_WORKLOAD:
+            return None
+    return TRAFFIC_BYTES.get(kernel.split(" ")[0])
+
+
 def far_interactions(s) -> float:
     tot = 0.0
     nt = []
@@ -93,12 +111,15 @@ def main(argv=None):
                              "single_drop_p16"])
     ap.add_argument("--far-prec", default="fp32c", choices=["fp32c", "fp64"])
     ap.add_argument("--grid-mode", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=96)
+    ap.add_argument("--cpu-sample", type=int, default=320)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="replay the evaluation as a recorded HIP graph (stage times then hold "
                          "the whole evaluation in the first stage)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, copy a MIB-mebibyte device buffer once (a plain "
+                         "copy kernel of known size, to scale hardware byte counters)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -150,27 +171,37 @@ def main(argv=None):
     dt = t1 - t0
     stages = [ctx.stage_times(i) for i in range(K)]
     avg = [sum(st[k] for st in stages) / K for k in range(4)]
+    cls_times = [ctx.self_class_times(i) for i in range(K)] if not args.graph else None
 
-    # roofline of the dominant kernel
+    # per-kernel rooflines; the dominant kernel's goes to "roofline"
     self_flops = sum(self_flops_per_drop(int(s.p[d]), int(s.q_self[d]), s.grid_mode)
                      for d in range(s.ndrops))
     far_flops = far_interactions(s) * FAR_FLOPS_PER_INTERACTION
-    if args.graph:
-        roof = None
-    elif avg[1] >= avg[2]:
-        achieved = self_flops / (avg[1] * 1e-3) / 1e12
-        roof = {"kernel": "k_self (rotation + rotated-grid synthesis + singular reduction, FP64)",
-                "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                "algorithmic_flops": self_flops, "avg_ms": avg[1]}
-    else:
-        peak = PEAK_FP32_UNPACKED_TFLOPS if far_prec == E.FAR_FP32C else PEAK_FP64_TFLOPS
-        achieved = far_flops / (avg[2] * 1e-3) / 1e12
-        roof = {"kernel": "k_far32 (far-field direct sums)" if far_prec == E.FAR_FP32C
-                else "k_far64 (far-field direct sums)",
-                "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None, "algorithmic_flops": far_flops,
-                "avg_ms": avg[2]}
+    kernels = []
+    if cls_times is not None:
+        for c, pmax in enumerate(E.DEGREE_CLASSES):
+            ms = sum(ct[c] for ct in cls_times) / K
+            lo = E.DEGREE_CLASSES[c - 1] if c else 0
+            fl = sum(self_flops_per_drop(int(s.p[d]), int(s.q_self[d]), s.grid_mode)
+                     for d in range(s.ndrops) if lo < int(s.p[d]) <= pmax)
+            if ms > 0 and fl > 0:
+                kernels.append({"kernel": f"k_self<{pmax}> (singular self-interaction, p <= {pmax}, FP64)",
+                                "bound": "alu", "algorithmic_flops": fl, "avg_ms": ms,
+                                "achieved": fl / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS})
+        far_peak = PEAK_FP32_UNPACKED_TFLOPS if far_prec == E.FAR_FP32C else PEAK_FP64_TFLOPS
+        kernels.append({"kernel": ("k_far32" if far_prec == E.FAR_FP32C else "k_far64")
+                        + " (far-field direct sums)", "bound": "alu", "algorithmic_flops": far_flops,
+                        "avg_ms": avg[2], "achieved": far_flops / (avg[2] * 1e-3) / 1e12, "peak": far_peak})
+        for k in kernels:
+            k["unit"] = "TFLOP/s"
+            k["frac"] = k["achieved"] / k["peak"]
+            k["traffic"] = measured_traffic(k["kernel"], args.workload)
+    roof = None
+    if kernels:
+        dom = max(kernels, key=lambda k: k["avg_ms"])
+        roof = {"kernel": dom["kernel"], "bound": dom["bound"], "achieved": dom["achieved"],
+                "peak": dom["peak"], "unit": "TFLOP/s", "frac": dom["frac"], "traffic": dom["traffic"],
+                "algorithmic_flops": dom["algorithmic_flops"], "avg_ms": dom["avg_ms"]}
 
     res = {
         "metric": "layer-potential target evals/sec (singular+far) FP64 self + "
@@ -197,8 +228,18 @@ def main(argv=None):
         "self_tflops": self_flops / (avg[1] * 1e-3) / 1e12,
         "far_tflops": far_flops / (avg[2] * 1e-3) / 1e12,
         "roofline": roof,
+        "kernels": kernels,
     }
     ctx.close()
+    if args.copy_probe > 0:
+        n = args.copy_probe * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        res["copy_probe_bytes"] = {"read": n * 8, "written": n * 8}
+        del a, b
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(s, args.cpu_sample)
     print(json.dumps(res), flush=True)

@@ -161,6 +161,14 @@ int ehd_set_timing(ehd_ctx* ctx, int nslots);
  * Waits for the recorded events.  EHD_E_STATE if the slot holds no call. */
 int ehd_stage_times(ehd_ctx* ctx, int slot, double* ms);
 
+/* Elapsed milliseconds of the singular self-interaction kernel of each
+ * degree class (p <= 16, <= 24, <= 32, <= 48; one launch per class) in the
+ * call recorded in `slot`; 0 for a class without drops.  When the call runs
+ * the self-interaction in two passes (a separate u together with S or the
+ * Laplace kinds), the times are those of the second pass.  Not recorded in
+ * graph mode (all 0).  EHD_E_STATE if the slot holds no call. */
+int ehd_self_class_times(ehd_ctx* ctx, int slot, double* ms);
+
 /* Graph mode (enable != 0): ehd_layer_potentials records its launch
  * sequence as a HIP graph the first time it is called with a given argument
  * set (pointers, kinds, far_prec, far-field tile shape) and replays the graph

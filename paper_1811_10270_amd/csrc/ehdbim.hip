@@ -1024,8 +1024,10 @@ struct ehd_ctx {
 
     // stage timing
     static constexpr int kStages = 4;
-    std::vector<hipEvent_t> events;  // [nslots][kStages + 1]
+    static constexpr int kEv = kStages + 1 + 8;   // stage marks, then (start, end) per degree class
+    std::vector<hipEvent_t> events;  // [nslots][kEv]
     std::vector<int> slot_used;
+    std::vector<int> class_used;     // [nslots][4]
     int nslots = 0;
     long long ncalls = 0;
 
@@ -1034,11 +1036,23 @@ struct ehd_ctx {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         events.clear();
         slot_used.clear();
+        class_used.clear();
         nslots = 0;
     }
     void mark(int stage)
     {
-        if (nslots && !capturing) (void)hipEventRecord(events[(ncalls % nslots) * (kStages + 1) + stage], stream);
+        if (!nslots || capturing) return;
+        const long long slot = ncalls % nslots;
+        if (stage == 0)
+            for (int c = 0; c < 4; ++c) class_used[slot * 4 + c] = 0;
+        (void)hipEventRecord(events[slot * kEv + stage], stream);
+    }
+    void mark_class(int cls, int end)
+    {
+        if (!nslots || capturing) return;
+        const long long slot = ncalls % nslots;
+        (void)hipEventRecord(events[slot * kEv + kStages + 1 + 2 * cls + end], stream);
+        class_used[slot * 4 + cls] = 1;
     }
     DropInfo* d_info_tmp = nullptr;  // per-field views for ehd_synthesize
 
@@ -1140,11 +1154,13 @@ static int launch_self_class(ehd_ctx* ctx, int cls, const double* f, const doubl
     if (lds > 65536)
         EHD_HIP(ctx, hipFuncSetAttribute((const void*)k_self<PMAX, HF, HU, HS>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    ctx->mark_class(cls, 0);
     hipLaunchKernelGGL((k_self<PMAX, HF, HU, HS>), dim3((unsigned)count), dim3(SelfClass<PMAX>::NT), lds,
                        ctx->ls,
                        ctx->d_info, ctx->d_legs, ctx->d_wigs, ctx->d_order + ctx->cls_off[cls], ctx->d_tdrop,
                        ctx->d_x, f, u, s, ctx->d_tx, ctx->d_tn, ctx->T, kinds, ctx->d_raw);
     EHD_HIP(ctx, hipGetLastError());
+    ctx->mark_class(cls, 1);
     return EHD_OK;
 }
 
@@ -1687,7 +1703,10 @@ int ehd_layer_potentials(ehd_ctx* ctx, const double* fcoef_d, const double* ucoe
         rc = EHD_OK;
     }
     if (rc) return rc;
-    if (ctx->nslots) ctx->slot_used[ctx->ncalls % ctx->nslots] = 1;
+    if (ctx->nslots) {
+        const long long slot = ctx->ncalls % ctx->nslots;
+        ctx->slot_used[slot] = 1;
+    }
     ++ctx->ncalls;
     return EHD_OK;
 }
@@ -1810,9 +1829,10 @@ int ehd_set_timing(ehd_ctx* ctx, int nslots)
     if (ctx->stream) EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
     ctx->free_events();
     if (nslots == 0) return EHD_OK;
-    ctx->events.resize((size_t)nslots * (ehd_ctx::kStages + 1));
+    ctx->events.resize((size_t)nslots * ehd_ctx::kEv);
     for (auto& e : ctx->events) EHD_HIP(ctx, hipEventCreate(&e));
     ctx->slot_used.assign(nslots, 0);
+    ctx->class_used.assign((size_t)nslots * 4, 0);
     ctx->nslots = nslots;
     ctx->ncalls = 0;
     return EHD_OK;
@@ -1823,12 +1843,29 @@ int ehd_stage_times(ehd_ctx* ctx, int slot, double* ms)
     if (!ctx) return EHD_E_ARG;
     if (!ms || slot < 0 || slot >= ctx->nslots) EHD_FAIL(ctx, EHD_E_ARG, "invalid slot or ms pointer");
     if (!ctx->slot_used[slot]) EHD_FAIL(ctx, EHD_E_STATE, "slot %d holds no recorded call", slot);
-    hipEvent_t* ev = &ctx->events[(size_t)slot * (ehd_ctx::kStages + 1)];
+    hipEvent_t* ev = &ctx->events[(size_t)slot * ehd_ctx::kEv];
     EHD_HIP(ctx, hipEventSynchronize(ev[ehd_ctx::kStages]));
     for (int k = 0; k < ehd_ctx::kStages; ++k) {
         float t = 0.0f;
         EHD_HIP(ctx, hipEventElapsedTime(&t, ev[k], ev[k + 1]));
         ms[k] = t;
+    }
+    return EHD_OK;
+}
+
+int ehd_self_class_times(ehd_ctx* ctx, int slot, double* ms)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ms || slot < 0 || slot >= ctx->nslots) EHD_FAIL(ctx, EHD_E_ARG, "invalid slot or ms pointer");
+    if (!ctx->slot_used[slot]) EHD_FAIL(ctx, EHD_E_STATE, "slot %d holds no recorded call", slot);
+    hipEvent_t* ev = &ctx->events[(size_t)slot * ehd_ctx::kEv];
+    EHD_HIP(ctx, hipEventSynchronize(ev[ehd_ctx::kStages]));
+    for (int c = 0; c < 4; ++c) {
+        ms[c] = 0.0;
+        if (!ctx->class_used[(size_t)slot * 4 + c]) continue;
+        float t = 0.0f;
+        EHD_HIP(ctx, hipEventElapsedTime(&t, ev[ehd_ctx::kStages + 1 + 2 * c], ev[ehd_ctx::kStages + 2 + 2 * c]));
+        ms[c] = t;
     }
     return EHD_OK;
 }

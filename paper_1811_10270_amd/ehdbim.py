@@ -29,9 +29,10 @@ _KIND_OF_COMP = (STOKES_SL,) * 3 + (STOKES_DL,) * 3 + (LAP_SL, LAP_DL, LAP_DLADJ
 EXPORTED = ("ehd_create", "ehd_destroy", "ehd_last_error", "ehd_grid_dims", "ehd_set_drops",
             "ehd_num_targets", "ehd_layer_potentials", "ehd_synthesize", "ehd_analyze",
             "ehd_target_geometry", "ehd_sync", "ehd_wigner_d", "ehd_set_timing",
-            "ehd_stage_times", "ehd_set_graph", "ehd_set_far_config", "ehd_get_far_config",
-            "ehd_time_far")
+            "ehd_stage_times", "ehd_self_class_times", "ehd_set_graph", "ehd_set_far_config",
+            "ehd_get_far_config", "ehd_time_far")
 STAGES = ("densities", "self", "far", "combine")
+DEGREE_CLASSES = (16, 24, 32, 48)   # largest p of each self-interaction kernel class
 
 _lib = None
 
@@ -68,6 +69,7 @@ def load(path: str = LIB_PATH):
     lib.ehd_wigner_d.argtypes = [C.c_int, C.c_double, dp]
     lib.ehd_set_timing.argtypes = [vp, C.c_int]
     lib.ehd_stage_times.argtypes = [vp, C.c_int, dp]
+    lib.ehd_self_class_times.argtypes = [vp, C.c_int, dp]
     lib.ehd_set_graph.argtypes = [vp, C.c_int]
     lib.ehd_set_far_config.argtypes = [vp, C.c_int, C.c_int]
     lib.ehd_get_far_config.argtypes = [vp, ip, ip]
@@ -192,6 +194,13 @@ class Context:
         self._check(self._lib.ehd_time_far(self._h, far_prec, targets_per_thread, nchunk, reps,
                                            C.byref(ms)))
         return ms.value
+
+    def self_class_times(self, slot: int):
+        """Milliseconds of the self-interaction kernel of each degree class
+        (DEGREE_CLASSES) in a recorded call; 0 for a class without drops."""
+        ms = (C.c_double * 4)()
+        self._check(self._lib.ehd_self_class_times(self._h, slot, ms))
+        return list(ms)
 
     def stage_times(self, slot: int):
         """Milliseconds of (densities, self, far, combine) of a recorded call."""

@@ -106,3 +106,30 @@ def test_far_tile_shapes_agree_and_autotune(E, tmp_path):
     err = np.abs(fo.cpu().numpy() - ref).max(axis=1) / np.abs(ref).max(axis=1)
     assert np.all(err < 1e-6), err
     ctx.close()
+
+
+def test_self_class_times(E):
+    """Per-degree-class kernel times: recorded for the classes present,
+    zero for absent ones, and together within the self stage's time."""
+    import torch
+    s = W.batched_suspension(seed=3)
+    # two drops of degree 16 and two of degree 32: classes 24 and 48 stay empty
+    keep = ([d for d in range(s.ndrops) if int(s.p[d]) == 16][:2]
+            + [d for d in range(s.ndrops) if int(s.p[d]) == 32][:2])
+    sub = W.subset(s, keep)
+    ctx, f, sg, dev = _setup(E, sub)
+    out = torch.zeros(8, ctx.ntargets, dtype=torch.float64, device=dev)
+    ctx.set_timing(2)
+    for _ in range(2):
+        ctx.layer_potentials(f, None, sg, E.METRIC_KINDS, E.FAR_FP32C, out)
+    ctx.sync()
+    for slot in range(2):
+        ms = ctx.self_class_times(slot)
+        st = ctx.stage_times(slot)
+        present = {pm for pm in E.DEGREE_CLASSES for d in range(sub.ndrops)
+                   if (E.DEGREE_CLASSES[E.DEGREE_CLASSES.index(pm) - 1] if pm != 16 else 0)
+                   < int(sub.p[d]) <= pm}
+        for c, pm in enumerate(E.DEGREE_CLASSES):
+            assert (ms[c] > 0) == (pm in present), (pm, ms)
+        assert sum(ms) <= st[1] * 1.02 + 0.05
+    ctx.close()
