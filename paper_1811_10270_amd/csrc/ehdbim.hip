@@ -410,52 +410,61 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     if (HU) for (int c = 0; c < 3; ++c) fld[UOFF + c] = gmem(ucoef + 3 * D.coff + c * 2 * nc);
     if (HS) fld[SOFF] = gmem(scoef + D.coff);
 
-    // register-resident A operand of the longitude sums of this wave's row
-    // tile (rows l = 16 tile .. 16 tile + 15): cos/sin(m phi_l) of the four
-    // term groups.  Waves w, w + nTp, .. share tile w % nTp and split the
-    // latitudes of a block.
-    const int my_tile = wv % qg.nTp;
-    const bool dft_wave = my_tile < qg.nT;
-    double aEC[SC::KEC], aES[SC::KES], aOC[SC::KOC], aOS[SC::KOC];
+    // 1. rotation, into LDS (column-major: column m holds n = m..p
+    //    contiguously).
+    //    a. z_nm = c_nm e^{i m phi_t} of every field, in the slots the rotated
+    //       coefficients of degree n will take;
+    //    b. each degree n belongs to one wave (snake order over the waves),
+    //       lane m' computes Re c'_nm' = sum_m A_mm' Re z_nm and
+    //       Im c'_nm' = sum_m B_mm' Im z_nm for all fields (z read as LDS
+    //       broadcasts, the rows of A and B coalesced over the lanes), then
+    //       overwrites the degree's slots: only this wave reads them.
+    static_assert(PMAX < 64, "one lane per order m' of a degree");
+    double* crd = reinterpret_cast<double*>(cr);
     {
-        const auto src = gmem(Lq.afrag + (long long)(dft_wave ? my_tile : 0) * qg.nks * 64 + lane);
+        const auto ph = gmem(Lp.trig + (long long)k * (p + 1) * 2);
+        for (int it = threadIdx.x; it < nc; it += blockDim.x) {
+            const int n = tri_n(it), m = it - n * (n + 1) / 2;
+            const int cpos = column_start(p, m) + n - m;
+            const double cm = ph[2 * m], sm = ph[2 * m + 1];
 #pragma unroll
-        for (int ks = 0; ks < SC::KEC; ++ks)
-            aEC[ks] = (dft_wave && ks < qg.nk[0]) ? src[(long long)(qg.base[0] / 4 + ks) * 64] : 0.0;
-#pragma unroll
-        for (int ks = 0; ks < SC::KES; ++ks)
-            aES[ks] = (dft_wave && ks < qg.nk[1]) ? src[(long long)(qg.base[1] / 4 + ks) * 64] : 0.0;
-#pragma unroll
-        for (int ks = 0; ks < SC::KOC; ++ks) {
-            aOC[ks] = (dft_wave && ks < qg.nk[2]) ? src[(long long)(qg.base[2] / 4 + ks) * 64] : 0.0;
-            aOS[ks] = (dft_wave && ks < qg.nk[3]) ? src[(long long)(qg.base[3] / 4 + ks) * 64] : 0.0;
+            for (int f = 0; f < NF; ++f) {
+                const double c0 = fld[f][2 * it], c1 = m ? fld[f][2 * it + 1] : 0.0;
+                cr[f * nc + cpos] = make_double2(c0 * cm - c1 * sm, c0 * sm + c1 * cm);
+            }
         }
     }
-
-    // 1. rotation into LDS (column-major: column m holds n = m..p contiguously)
+    __syncthreads();
     {
         const long wb = ehd::wig_block(p);
         const auto A = gmem(W.A + (long long)j * wb);
         const auto B = gmem(W.B + (long long)j * wb);
-        const auto ph = gmem(Lp.trig + (long long)k * (p + 1) * 2);
-        for (int it = threadIdx.x; it < nc; it += blockDim.x) {
-            const int n = tri_n(it), mp = it - n * (n + 1) / 2;
+        const int dn0 = 2 * NW - 1 - 2 * wv, dn1 = 2 * wv + 1;
+        bool odd = false;
+        for (int n = wv; n <= p; n += odd ? dn1 : dn0, odd = !odd) {
+            const int mp = lane <= n ? lane : n;            // lanes past n repeat m' = n, store nothing
+            const auto An = A + ehd::wig_off(n) + mp;
+            const auto Bn = B + ehd::wig_off(n) + mp;
             double are[NF], aim[NF];
+#pragma unroll
             for (int f = 0; f < NF; ++f) { are[f] = 0.0; aim[f] = 0.0; }
-            const auto An = A + ehd::wig_off(n);
-            const auto Bn = B + ehd::wig_off(n);
+            const double2* zn = cr + column_start(p, 0) + n;   // z_n0 of field 0; z_nm at + column_start(p, m) - m
+#pragma unroll 4
             for (int m = 0; m <= n; ++m) {
-                const double a = An[m * (n + 1) + mp], b = Bn[m * (n + 1) + mp];
-                const double cm = ph[2 * m], sm = ph[2 * m + 1];
-                const long kk = 2 * tri(n, m);
+                const double a = An[m * (n + 1)], b = Bn[m * (n + 1)];
+                const int zo = column_start(p, m) - m;
+#pragma unroll
                 for (int f = 0; f < NF; ++f) {
-                    const double c0 = fld[f][kk], c1 = (m == 0) ? 0.0 : fld[f][kk + 1];
-                    are[f] += a * (c0 * cm - c1 * sm);
-                    aim[f] += b * (c0 * sm + c1 * cm);
+                    const double2 z = zn[f * nc + zo];
+                    are[f] = fma(a, z.x, are[f]);
+                    aim[f] = fma(b, z.y, aim[f]);
                 }
             }
-            const int cpos = column_start(p, mp) + n - mp;
-            for (int f = 0; f < NF; ++f) cr[f * nc + cpos] = make_double2(are[f], aim[f]);
+            if (lane <= n) {
+                const int cpos = column_start(p, lane) + n - lane;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) cr[f * nc + cpos] = make_double2(are[f], aim[f]);
+            }
         }
     }
     __syncthreads();
@@ -486,6 +495,28 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
         }
     }
     __syncthreads();   // LDS free: Fourier blocks and per-wave node buffers from here on
+
+    // register-resident A operand of the longitude sums of this wave's row
+    // tile (rows l = 16 tile .. 16 tile + 15): cos/sin(m phi_l) of the four
+    // term groups.  Waves w, w + nTp, .. share tile w % nTp and split the
+    // latitudes of a block.
+    const int my_tile = wv % qg.nTp;
+    const bool dft_wave = my_tile < qg.nT;
+    double aEC[SC::KEC], aES[SC::KES], aOC[SC::KOC], aOS[SC::KOC];
+    {
+        const auto src = gmem(Lq.afrag + (long long)(dft_wave ? my_tile : 0) * qg.nks * 64 + lane);
+#pragma unroll
+        for (int ks = 0; ks < SC::KEC; ++ks)
+            aEC[ks] = (dft_wave && ks < qg.nk[0]) ? src[(long long)(qg.base[0] / 4 + ks) * 64] : 0.0;
+#pragma unroll
+        for (int ks = 0; ks < SC::KES; ++ks)
+            aES[ks] = (dft_wave && ks < qg.nk[1]) ? src[(long long)(qg.base[1] / 4 + ks) * 64] : 0.0;
+#pragma unroll
+        for (int ks = 0; ks < SC::KOC; ++ks) {
+            aOC[ks] = (dft_wave && ks < qg.nk[2]) ? src[(long long)(qg.base[2] / 4 + ks) * 64] : 0.0;
+            aOS[ks] = (dft_wave && ks < qg.nk[3]) ? src[(long long)(qg.base[3] / 4 + ks) * 64] : 0.0;
+        }
+    }
 
     const int gsz = qg.nks * 64;                      // one latitude's Fourier block
     constexpr int NVP = NV | 1;                       // node record stride (odd: fewer bank conflicts)
