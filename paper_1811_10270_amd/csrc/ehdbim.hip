@@ -628,17 +628,24 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
                 const int i = b * LB + ll;
                 if (i > Lq.Q) break;
                 const double* G = R + ll * gsz + boff;
+                // k-steps up to the class maximum without guards: past a
+                // group's last k-step the A fragment is zero and the B address
+                // is clamped to the group's last k-step
                 dbl4 ec = dbl4{0, 0, 0, 0}, es = ec, oc = ec, os = ec;
+                const int kl0 = qg.nk[0] - 1, kl1 = qg.nk[1] - 1, kl2 = qg.nk[2] - 1, kl3 = qg.nk[3] - 1;
+                const int g0 = qg.base[0] / 4, g1 = qg.base[1] / 4, g2 = qg.base[2] / 4, g3 = qg.base[3] / 4;
 #pragma unroll
                 for (int ks = 0; ks < SC::KEC; ++ks) {
-                    if (ks < qg.nk[0])
-                        ec = __builtin_amdgcn_mfma_f64_16x16x4f64(aEC[ks], G[(qg.base[0] / 4 + ks) * 64], ec, 0, 0, 0);
-                    if (ks < SC::KES && ks < qg.nk[1])
-                        es = __builtin_amdgcn_mfma_f64_16x16x4f64(aES[ks < SC::KES ? ks : 0], G[(qg.base[1] / 4 + ks) * 64], es, 0, 0, 0);
-                    if (ks < SC::KOC && ks < qg.nk[2])
-                        oc = __builtin_amdgcn_mfma_f64_16x16x4f64(aOC[ks < SC::KOC ? ks : 0], G[(qg.base[2] / 4 + ks) * 64], oc, 0, 0, 0);
-                    if (ks < SC::KOC && ks < qg.nk[3])
-                        os = __builtin_amdgcn_mfma_f64_16x16x4f64(aOS[ks < SC::KOC ? ks : 0], G[(qg.base[3] / 4 + ks) * 64], os, 0, 0, 0);
+                    ec = __builtin_amdgcn_mfma_f64_16x16x4f64(aEC[ks], G[(g0 + min(ks, kl0)) * 64], ec, 0, 0, 0);
+                    if (ks < SC::KES)
+                        es = __builtin_amdgcn_mfma_f64_16x16x4f64(aES[ks < SC::KES ? ks : 0],
+                                                                  G[(g1 + max(min(ks, kl1), 0)) * 64], es, 0, 0, 0);
+                    if (ks < SC::KOC) {
+                        oc = __builtin_amdgcn_mfma_f64_16x16x4f64(aOC[ks < SC::KOC ? ks : 0], G[(g2 + min(ks, kl2)) * 64],
+                                                                  oc, 0, 0, 0);
+                        os = __builtin_amdgcn_mfma_f64_16x16x4f64(aOS[ks < SC::KOC ? ks : 0], G[(g3 + min(ks, kl3)) * 64],
+                                                                  os, 0, 0, 0);
+                    }
                 }
                 // node buffer: record 16 c + row for the nodes c = 0..3 of the row
                 {
