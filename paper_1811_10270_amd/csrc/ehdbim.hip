@@ -351,6 +351,16 @@ constexpr int wave_ksteps_max(int PMAX, int nw)   // max over p <= PMAX and wave
     return best;
 }
 
+// Slot of workgroup `bid` when the workgroups of a grid of `nb` are dealt to
+// the kXcd XCDs round-robin and XCD x takes the contiguous slots
+// [x q + min(x, r), ...), q = nb / kXcd, r = nb % kXcd (a bijection).
+constexpr int kXcd = 8;
+__device__ __forceinline__ unsigned xcd_slot(unsigned bid, unsigned nb)
+{
+    const unsigned q = nb / kXcd, r = nb % kXcd, x = bid % kXcd, pos = bid / kXcd;
+    return x * q + (x < r ? x : r) + pos;
+}
+
 template <int PMAX>
 struct SelfClass {
     static constexpr int KEC = (PMAX / 2 + 1 + 3) / 4;         // max k-steps per group
@@ -388,7 +398,10 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     extern __shared__ double2 lds[];
     __shared__ double red[NW][9];
 
-    const long long tg = order[blockIdx.x];
+    // Workgroups go to the 8 XCDs round-robin; give each XCD a contiguous
+    // range of the cost-ordered target list, so that the blocks sharing an
+    // L2 work on neighbouring targets (same rotation tables).
+    const long long tg = order[xcd_slot(blockIdx.x, gridDim.x)];
     const int d = tdrop[tg];
     const DropInfo D = drops[d];
     const int p = D.p;
