@@ -120,6 +120,10 @@ int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
 /* Number of target nodes (sum over drops of nlat*nlon) of the current drops. */
 int ehd_num_targets(const ehd_ctx* ctx, long long* ntargets);
 
+/* Number of doubles of one packed field of the current drops,
+ * sum over drops of (p+1)(p+2). */
+int ehd_num_coefs(const ehd_ctx* ctx, long long* ncoef);
+
 /* Evaluate the layer potentials of the requested `kinds` (EHD_* bit mask)
  * for densities fcoef_d (3 fields; needed for EHD_STOKES_SL), ucoef_d (3
  * fields, NULL: u = f; needed for EHD_STOKES_DL) and sigcoef_d (1 field;
@@ -191,6 +195,32 @@ int ehd_get_far_config(const ehd_ctx* ctx, int* targets_per_thread, int* nchunk)
  * source records, timed with HIP events (all kinds).  Overwrites the far
  * field's partial sums (not the caller's outputs).  Synchronous. */
 int ehd_time_far(ehd_ctx* ctx, int far_prec, int targets_per_thread, int nchunk, int reps, double* ms);
+
+/* Galerkin solvers (Sec. 2, eq. galerkin_En and eq. BIM_galerkin) by
+ * restarted GMRES in FP64 on the device.  Each iteration is one
+ * ehd_layer_potentials call (far field in far_prec) and one ehd_analyze.
+ * restart in [1, 200], maxit >= 1 (mat-vecs), tol > 0: stop when the true
+ * residual |b - A x| <= tol |b| (Euclidean norm of the packed coefficient
+ * vector).  *iters receives the number of mat-vecs, *relres the final true
+ * relative residual; not converging within maxit is not an error (check
+ * *relres).  The solution vector holds the initial guess on entry (zeros
+ * for none).  Synchronous; the solver allocates its own workspace.
+ *
+ * ehd_solve_En: the normal electric field E_n (1 packed field, en_coef_d) of
+ *   (1/2)(E_n, Y) - (R-1)/(R+1) sum_j (K*_j[E_n], Y) = R/(R+1) (E_inf . n, Y)
+ *   for all Y = Y_nm, n <= p, with the adjoint double layer K* (the
+ *   operator of eq. E_n taken with the target normal, as the equation is
+ *   eq. BIE01 dotted with n(x0)), conductivity ratio R > 0 and the applied
+ *   field E_inf = -grad phi_inf, phi_inf = -(E_u z + E_q (z^2 - (x^2+y^2)/2))
+ *   (uniform and quadrupole parts, Sec. 1).
+ * ehd_solve_velocity: the interface velocity u (3 packed fields, ucoef_d)
+ *   of (lambda+1)(u, Y) = sum_j (S_j[f], Y) + (lambda-1) sum_j (D_j[u], Y)
+ *   for the force density fcoef_d (3 packed fields, the signed density of
+ *   eq. BIM_galerkin) and viscosity ratio lambda >= 0. */
+int ehd_solve_En(ehd_ctx* ctx, double R, double Eu, double Eq, int far_prec, int restart, int maxit,
+                 double tol, double* en_coef_d, int* iters, double* relres);
+int ehd_solve_velocity(ehd_ctx* ctx, double lambda, const double* fcoef_d, int far_prec, int restart,
+                       int maxit, double tol, double* ucoef_d, int* iters, double* relres);
 
 /* Host-only: Wigner small-d matrix d^n_{m m'}(beta), m, m' = -n..n, written
  * row-major to out[(m+n)*(2n+1) + (m'+n)], with

@@ -6,7 +6,8 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", "ehdbim.hip"), os.path.join(HERE, "csrc", "tables.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", "ehdbim.hip"), os.path.join(HERE, "csrc", "solve.hip"),
+           os.path.join(HERE, "csrc", "tables.cpp")]
 LIB = os.path.join(HERE, "libehdbim.so")
 
 HIPCC_FLAGS = [

@@ -22,6 +22,7 @@
 
 #include "ehdbim.h"
 #include "tables.h"
+#include "ctx_access.h"
 
 using ehd::ncoef;
 using ehd::nlon_of;
@@ -1248,6 +1249,16 @@ static const std::array<Far32Launch, 32>& far32_table()
     return far32_table_impl<TPT>(std::make_index_sequence<32>{});
 }
 
+// Accessors for the solvers (ctx_access.h).
+hipStream_t ehd_ctx_stream(const ehd_ctx* ctx) { return ctx->stream; }
+int ehd_ctx_device(const ehd_ctx* ctx) { return ctx->device; }
+int ehd_ctx_ndrops(const ehd_ctx* ctx) { return ctx->nd; }
+int ehd_ctx_fail(ehd_ctx* ctx, int code, const char* msg)
+{
+    ctx->err = msg;
+    return code;
+}
+
 extern "C" {
 
 int ehd_create(ehd_ctx** out, int device, void* stream)
@@ -1598,6 +1609,16 @@ int ehd_num_targets(const ehd_ctx* ctx, long long* ntargets)
     if (!ctx || !ntargets) return EHD_E_ARG;
     *ntargets = ctx->T;
     return ctx->nd ? EHD_OK : EHD_E_STATE;
+}
+
+int ehd_num_coefs(const ehd_ctx* ctx, long long* ncoef)
+{
+    if (!ctx || !ncoef) return EHD_E_ARG;
+    if (!ctx->nd) return EHD_E_STATE;
+    long long n = 0;
+    for (int d = 0; d < ctx->nd; ++d) n += (long long)(ctx->info[d].p + 1) * (ctx->info[d].p + 2);
+    *ncoef = n;
+    return EHD_OK;
 }
 
 // Far-field launch with the context's tile shape (targets per thread, source

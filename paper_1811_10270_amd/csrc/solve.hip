@@ -1,0 +1,294 @@
+// Galerkin solvers built on the layer-potential evaluation (paper Sec. 2,
+// eq. galerkin_En and eq. BIM_galerkin): restarted GMRES in FP64 on the
+// device, whose mat-vec is one ehd_layer_potentials call followed by the
+// Galerkin projection ehd_analyze.  Orthogonalisation is classical
+// Gram-Schmidt applied twice (CGS2), with the dot products of a step batched
+// in one launch; the small Hessenberg least-squares problem (Givens
+// rotations) lives on the host.
+//
+// The unknowns are packed SH coefficient vectors (the layout of
+// include/ehdbim.h); the imaginary slots of the m = 0 coefficients are
+// carried along and stay zero (the projection writes zeros there and the
+// right-hand sides have zeros there).
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "ctx_access.h"
+#include "ehdbim.h"
+
+namespace {
+
+constexpr int kT = 256;
+
+// out[i] = <V_i, w>, one block per vector, fixed summation order.
+__global__ __launch_bounds__(kT) void k_dots(const double* __restrict__ V, long long ld, const double* __restrict__ w,
+                                             long long n, double* __restrict__ out)
+{
+    const double* v = V + (long long)blockIdx.x * ld;
+    double s = 0.0;
+    for (long long t = threadIdx.x; t < n; t += kT) s = fma(v[t], w[t], s);
+    __shared__ double sh[kT];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = kT / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
+// w -= sum_{i<k} h[i] V_i
+__global__ void k_subtract(double* __restrict__ w, const double* __restrict__ V, long long ld, int k,
+                           const double* __restrict__ h, long long n)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    double s = w[t];
+    for (int i = 0; i < k; ++i) s = fma(-h[i], V[(long long)i * ld + t], s);
+    w[t] = s;
+}
+
+__global__ void k_fill(double* __restrict__ y, double v, long long n)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = v;
+}
+
+// y = a x + b y
+__global__ void k_axpby(double a, const double* __restrict__ x, double b, double* __restrict__ y, long long n)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = a * x[t] + b * y[t];
+}
+
+// g = E_inf(x0) . n0 with E_inf = -grad phi_inf,
+// phi_inf = -(E_u z + E_q (z^2 - (x^2 + y^2) / 2))  (uniform + quadrupole)
+__global__ void k_einf_dot_n(const double* __restrict__ x0, const double* __restrict__ n0, long long T, double Eu,
+                             double Eq, double* __restrict__ g)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const double x = x0[t], y = x0[T + t], z = x0[2 * T + t];
+    g[t] = -Eq * x * n0[t] - Eq * y * n0[T + t] + (Eu + 2.0 * Eq * z) * n0[2 * T + t];
+}
+
+unsigned nblocks(long long n) { return (unsigned)((n + kT - 1) / kT); }
+
+struct DevBuf {
+    double* p = nullptr;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+#define SOLVE_HIP(call)                                                                              \
+    do {                                                                                             \
+        hipError_t _e = (call);                                                                      \
+        if (_e != hipSuccess) {                                                                      \
+            char _b[256];                                                                            \
+            snprintf(_b, sizeof(_b), "%s failed: %s", #call, hipGetErrorString(_e));                 \
+            return ehd_ctx_fail(ctx, EHD_E_HIP, _b);                                                 \
+        }                                                                                            \
+    } while (0)
+
+using Op = std::function<int(const double* in, double* out)>;
+
+// Restarted GMRES(m) for A x = b on device vectors of length n; x holds the
+// initial guess on entry.  Converged when the true relative residual
+// |b - A x| / |b| <= tol.
+int gmres(ehd_ctx* ctx, long long n, const Op& A, const double* b, double* x, int m, int maxit, double tol,
+          int* iters, double* relres)
+{
+    hipStream_t st = ehd_ctx_stream(ctx);
+    DevBuf Vb, wb, hb;
+    SOLVE_HIP(hipMalloc(&Vb.p, sizeof(double) * (size_t)(m + 1) * n));
+    SOLVE_HIP(hipMalloc(&wb.p, sizeof(double) * (size_t)n));
+    SOLVE_HIP(hipMalloc(&hb.p, sizeof(double) * (size_t)(m + 2)));
+    double* V = Vb.p;
+    double* w = wb.p;
+    double* hd = hb.p;
+    auto dots = [&](int k, const double* vec, double* host) -> int {
+        hipLaunchKernelGGL(k_dots, dim3(k), dim3(kT), 0, st, V, n, vec, n, hd);
+        SOLVE_HIP(hipGetLastError());
+        SOLVE_HIP(hipMemcpyAsync(host, hd, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+        SOLVE_HIP(hipStreamSynchronize(st));
+        return EHD_OK;
+    };
+    auto norm = [&](const double* vec, double* out) -> int {
+        hipLaunchKernelGGL(k_dots, dim3(1), dim3(kT), 0, st, vec, n, vec, n, hd);
+        SOLVE_HIP(hipGetLastError());
+        SOLVE_HIP(hipMemcpyAsync(out, hd, sizeof(double), hipMemcpyDeviceToHost, st));
+        SOLVE_HIP(hipStreamSynchronize(st));
+        *out = std::sqrt(*out);
+        return EHD_OK;
+    };
+    double bnorm;
+    int rc = norm(b, &bnorm);
+    if (rc) return rc;
+    *iters = 0;
+    if (bnorm == 0.0) {
+        hipLaunchKernelGGL(k_fill, dim3(nblocks(n)), dim3(kT), 0, st, x, 0.0, n);
+        SOLVE_HIP(hipGetLastError());
+        SOLVE_HIP(hipStreamSynchronize(st));
+        *relres = 0.0;
+        return EHD_OK;
+    }
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1), h2(m + 1), y(m);
+    for (;;) {
+        // true residual r = b - A x, into V_0
+        if ((rc = A(x, w))) return rc;
+        SOLVE_HIP(hipMemcpyAsync(V, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(k_axpby, dim3(nblocks(n)), dim3(kT), 0, st, -1.0, w, 1.0, V, n);
+        SOLVE_HIP(hipGetLastError());
+        double beta;
+        if ((rc = norm(V, &beta))) return rc;
+        *relres = beta / bnorm;
+        if (*relres <= tol || *iters >= maxit) return EHD_OK;
+        hipLaunchKernelGGL(k_axpby, dim3(nblocks(n)), dim3(kT), 0, st, 0.0, V, 1.0 / beta, V, n);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int jl = -1;
+        for (int j = 0; j < m; ++j) {
+            if ((rc = A(V + (size_t)j * n, w))) return rc;
+            ++*iters;
+            // CGS2: two passes of h = V^T w, w -= V h
+            if ((rc = dots(j + 1, w, h.data()))) return rc;
+            SOLVE_HIP(hipMemcpyAsync(hd, h.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL(k_subtract, dim3(nblocks(n)), dim3(kT), 0, st, w, V, n, j + 1, hd, n);
+            SOLVE_HIP(hipGetLastError());
+            if ((rc = dots(j + 1, w, h2.data()))) return rc;
+            SOLVE_HIP(hipMemcpyAsync(hd, h2.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL(k_subtract, dim3(nblocks(n)), dim3(kT), 0, st, w, V, n, j + 1, hd, n);
+            SOLVE_HIP(hipGetLastError());
+            double hn;
+            if ((rc = norm(w, &hn))) return rc;
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i] + h2[i];
+            H[(size_t)(j + 1) * m + j] = hn;
+            // previous Givens rotations, then a new one zeroing H[j+1][j]
+            for (int i = 0; i < j; ++i) {
+                const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+            }
+            const double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
+            const double rr = std::hypot(a, c);
+            cs[j] = rr > 0.0 ? a / rr : 1.0;
+            sn[j] = rr > 0.0 ? c / rr : 0.0;
+            H[(size_t)j * m + j] = rr;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            jl = j;
+            if (hn > 0.0) {
+                hipLaunchKernelGGL(k_axpby, dim3(nblocks(n)), dim3(kT), 0, st, 1.0 / hn, w, 0.0, V + (size_t)(j + 1) * n,
+                                   n);
+                SOLVE_HIP(hipGetLastError());
+            }
+            if (std::fabs(g[j + 1]) / bnorm <= tol || *iters >= maxit || hn == 0.0) break;
+        }
+        // y = H^{-1} g (upper triangular), x += V y
+        for (int i = jl; i >= 0; --i) {
+            double s = g[i];
+            for (int k = i + 1; k <= jl; ++k) s -= H[(size_t)i * m + k] * y[k];
+            y[i] = s / H[(size_t)i * m + i];
+        }
+        for (int i = 0; i <= jl; ++i) h[i] = -y[i];
+        SOLVE_HIP(hipMemcpyAsync(hd, h.data(), sizeof(double) * (jl + 1), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_subtract, dim3(nblocks(n)), dim3(kT), 0, st, x, V, n, jl + 1, hd, n);
+        SOLVE_HIP(hipGetLastError());
+    }
+}
+
+int check_opts(ehd_ctx* ctx, int far_prec, int restart, int maxit, double tol)
+{
+    if (far_prec != EHD_FAR_FP64 && far_prec != EHD_FAR_FP32C)
+        return ehd_ctx_fail(ctx, EHD_E_ARG, "invalid far_prec");
+    if (restart < 1 || restart > 200) return ehd_ctx_fail(ctx, EHD_E_ARG, "restart must be in [1, 200]");
+    if (maxit < 1) return ehd_ctx_fail(ctx, EHD_E_ARG, "maxit must be >= 1");
+    if (!(tol > 0.0)) return ehd_ctx_fail(ctx, EHD_E_ARG, "tol must be > 0");
+    return EHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ehd_solve_En(ehd_ctx* ctx, double R, double Eu, double Eq, int far_prec, int restart, int maxit, double tol,
+                 double* en_coef_d, int* iters, double* relres)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ehd_ctx_ndrops(ctx)) return ehd_ctx_fail(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if (!en_coef_d || !iters || !relres) return ehd_ctx_fail(ctx, EHD_E_ARG, "NULL argument");
+    if (!(R > 0.0) || !std::isfinite(Eu) || !std::isfinite(Eq))
+        return ehd_ctx_fail(ctx, EHD_E_ARG, "R must be > 0 and E_u, E_q finite");
+    int rc = check_opts(ctx, far_prec, restart, maxit, tol);
+    if (rc) return rc;
+    SOLVE_HIP(hipSetDevice(ehd_ctx_device(ctx)));
+    long long T, n;
+    if ((rc = ehd_num_targets(ctx, &T)) || (rc = ehd_num_coefs(ctx, &n))) return rc;
+    hipStream_t st = ehd_ctx_stream(ctx);
+    DevBuf grid, proj, rhs, geo;
+    SOLVE_HIP(hipMalloc(&grid.p, sizeof(double) * (size_t)T));
+    SOLVE_HIP(hipMalloc(&proj.p, sizeof(double) * (size_t)n));
+    SOLVE_HIP(hipMalloc(&rhs.p, sizeof(double) * (size_t)n));
+    SOLVE_HIP(hipMalloc(&geo.p, sizeof(double) * (size_t)6 * T));
+    // right-hand side R/(R+1) P[E_inf . n]
+    if ((rc = ehd_target_geometry(ctx, geo.p, geo.p + 3 * T))) return rc;
+    hipLaunchKernelGGL(k_einf_dot_n, dim3(nblocks(T)), dim3(kT), 0, st, geo.p, geo.p + 3 * T, T, Eu, Eq, grid.p);
+    SOLVE_HIP(hipGetLastError());
+    if ((rc = ehd_analyze(ctx, 1, grid.p, rhs.p))) return rc;
+    hipLaunchKernelGGL(k_axpby, dim3(nblocks(n)), dim3(kT), 0, st, 0.0, rhs.p, R / (R + 1.0), rhs.p, n);
+    SOLVE_HIP(hipGetLastError());
+    // operator E -> E/2 - (R-1)/(R+1) P[K*[E]]
+    const double c = (R - 1.0) / (R + 1.0);
+    const Op A = [&](const double* in, double* out) -> int {
+        int r = ehd_layer_potentials(ctx, nullptr, nullptr, in, EHD_LAP_DLADJ, far_prec, grid.p, nullptr);
+        if (!r) r = ehd_analyze(ctx, 1, grid.p, out);
+        if (r) return r;
+        hipLaunchKernelGGL(k_axpby, dim3(nblocks(n)), dim3(kT), 0, st, 0.5, in, -c, out, n);
+        SOLVE_HIP(hipGetLastError());
+        return EHD_OK;
+    };
+    return gmres(ctx, n, A, rhs.p, en_coef_d, restart, maxit, tol, iters, relres);
+}
+
+int ehd_solve_velocity(ehd_ctx* ctx, double lambda, const double* fcoef_d, int far_prec, int restart, int maxit,
+                       double tol, double* ucoef_d, int* iters, double* relres)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ehd_ctx_ndrops(ctx)) return ehd_ctx_fail(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if (!fcoef_d || !ucoef_d || !iters || !relres) return ehd_ctx_fail(ctx, EHD_E_ARG, "NULL argument");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return ehd_ctx_fail(ctx, EHD_E_ARG, "lambda must be >= 0");
+    int rc = check_opts(ctx, far_prec, restart, maxit, tol);
+    if (rc) return rc;
+    SOLVE_HIP(hipSetDevice(ehd_ctx_device(ctx)));
+    long long T, nc;
+    if ((rc = ehd_num_targets(ctx, &T)) || (rc = ehd_num_coefs(ctx, &nc))) return rc;
+    const long long n = 3 * nc;
+    hipStream_t st = ehd_ctx_stream(ctx);
+    DevBuf grid, rhs;
+    SOLVE_HIP(hipMalloc(&grid.p, sizeof(double) * (size_t)3 * T));
+    SOLVE_HIP(hipMalloc(&rhs.p, sizeof(double) * (size_t)n));
+    // right-hand side P[S[f]]
+    if ((rc = ehd_layer_potentials(ctx, fcoef_d, nullptr, nullptr, EHD_STOKES_SL, far_prec, grid.p, nullptr))) return rc;
+    if ((rc = ehd_analyze(ctx, 3, grid.p, rhs.p))) return rc;
+    // operator u -> (lambda+1) u - (lambda-1) P[D[u]]
+    const Op A = [&](const double* in, double* out) -> int {
+        int r = ehd_layer_potentials(ctx, nullptr, in, nullptr, EHD_STOKES_DL, far_prec, grid.p, nullptr);
+        if (!r) r = ehd_analyze(ctx, 3, grid.p, out);
+        if (r) return r;
+        hipLaunchKernelGGL(k_axpby, dim3(nblocks(n)), dim3(kT), 0, st, lambda + 1.0, in, -(lambda - 1.0), out, n);
+        SOLVE_HIP(hipGetLastError());
+        return EHD_OK;
+    };
+    return gmres(ctx, n, A, rhs.p, ucoef_d, restart, maxit, tol, iters, relres);
+}
+
+}  // extern "C"

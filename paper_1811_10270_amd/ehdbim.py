@@ -30,7 +30,8 @@ EXPORTED = ("ehd_create", "ehd_destroy", "ehd_last_error", "ehd_grid_dims", "ehd
             "ehd_num_targets", "ehd_layer_potentials", "ehd_synthesize", "ehd_analyze",
             "ehd_target_geometry", "ehd_sync", "ehd_wigner_d", "ehd_set_timing",
             "ehd_stage_times", "ehd_self_class_times", "ehd_set_graph", "ehd_set_far_config",
-            "ehd_get_far_config", "ehd_time_far")
+            "ehd_get_far_config", "ehd_time_far", "ehd_num_coefs", "ehd_solve_En",
+            "ehd_solve_velocity")
 STAGES = ("densities", "self", "far", "combine")
 DEGREE_CLASSES = (16, 24, 32, 48)   # largest p of each self-interaction kernel class
 
@@ -74,6 +75,11 @@ def load(path: str = LIB_PATH):
     lib.ehd_set_far_config.argtypes = [vp, C.c_int, C.c_int]
     lib.ehd_get_far_config.argtypes = [vp, ip, ip]
     lib.ehd_time_far.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, dp]
+    lib.ehd_num_coefs.argtypes = [vp, C.POINTER(C.c_longlong)]
+    lib.ehd_solve_En.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
+                                 C.c_double, vp, ip, dp]
+    lib.ehd_solve_velocity.argtypes = [vp, C.c_double, vp, C.c_int, C.c_int, C.c_int, C.c_double, vp,
+                                       ip, dp]
     _lib = lib
     return lib
 
@@ -201,6 +207,31 @@ class Context:
         ms = (C.c_double * 4)()
         self._check(self._lib.ehd_self_class_times(self._h, slot, ms))
         return list(ms)
+
+    def num_coefs(self) -> int:
+        """Doubles of one packed field of the current drops."""
+        n = C.c_longlong()
+        self._check(self._lib.ehd_num_coefs(self._h, C.byref(n)))
+        return n.value
+
+    def solve_En(self, R: float, Eu: float, Eq: float, en: torch.Tensor, far_prec: int = FAR_FP64,
+                 restart: int = 30, maxit: int = 200, tol: float = 1e-12):
+        """GMRES solve of the E_n Galerkin system; `en` (1 packed field) holds
+        the initial guess and receives the solution.  Returns (iters, relres)."""
+        it, rr = C.c_int(), C.c_double()
+        self._check(self._lib.ehd_solve_En(self._h, float(R), float(Eu), float(Eq), far_prec, restart,
+                                           maxit, float(tol), _ptr(en), C.byref(it), C.byref(rr)))
+        return it.value, rr.value
+
+    def solve_velocity(self, lam: float, fcoef: torch.Tensor, u: torch.Tensor, far_prec: int = FAR_FP64,
+                       restart: int = 30, maxit: int = 200, tol: float = 1e-12):
+        """GMRES solve of the velocity Galerkin system for the force density
+        `fcoef`; `u` (3 packed fields) holds the initial guess and receives
+        the solution.  Returns (iters, relres)."""
+        it, rr = C.c_int(), C.c_double()
+        self._check(self._lib.ehd_solve_velocity(self._h, float(lam), _ptr(fcoef), far_prec, restart,
+                                                 maxit, float(tol), _ptr(u), C.byref(it), C.byref(rr)))
+        return it.value, rr.value
 
     def stage_times(self, slot: int):
         """Milliseconds of (densities, self, far, combine) of a recorded call."""

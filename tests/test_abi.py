@@ -25,7 +25,7 @@ def lib():
 def declared_symbols():
     txt = open(os.path.join(ROOT, "include", "ehdbim.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(ehd_[a-z_0-9]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(ehd_[A-Za-z_0-9]+)\s*\(", txt)))
 
 
 def test_exports_every_declared_symbol(lib):

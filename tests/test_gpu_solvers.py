@@ -1,0 +1,132 @@
+"""GPU: Galerkin solvers (eq. galerkin_En, eq. BIM_galerkin) by GMRES on the
+device, against the oracle's dense solutions of the same systems and against
+the unit-sphere closed forms."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import galerkin as G
+from paper_1811_10270_amd import workloads as W
+from test_oracle_pins import make_susp, sphere_x, tri
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1811_10270_amd import ehdbim
+    ehdbim.load()
+    return ehdbim
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _ctx(E, s):
+    import torch
+    dev = torch.device("cuda", 0)
+    ctx = E.Context(0)
+    ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+    return ctx, dev
+
+
+def gpu_En(E, s, R, Eu, Eq, far_prec=0, restart=30, guess=None):
+    import torch
+    ctx, dev = _ctx(E, s)
+    n = ctx.num_coefs()
+    en = torch.zeros(n, dtype=torch.float64, device=dev) if guess is None else torch.from_numpy(guess).to(dev)
+    it, rr = ctx.solve_En(R, Eu, Eq, en, far_prec=far_prec, restart=restart, tol=1e-13)
+    out = en.cpu().numpy()
+    ctx.close()
+    return out, it, rr
+
+
+def gpu_velocity(E, s, lam, f, far_prec=0, restart=30):
+    import torch
+    ctx, dev = _ctx(E, s)
+    n = ctx.num_coefs()
+    u = torch.zeros(3 * n, dtype=torch.float64, device=dev)
+    it, rr = ctx.solve_velocity(lam, torch.from_numpy(np.ascontiguousarray(f)).to(dev), u,
+                                far_prec=far_prec, restart=restart, tol=1e-13)
+    out = u.cpu().numpy()
+    ctx.close()
+    return out, it, rr
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.mark.parametrize("R", [0.2, 3.0])
+def test_En_two_drops_matches_oracle(E, R):
+    s = W.two_drops(6, seed=11, gap=0.3)
+    ref = G.solve_En_dense(s, R, 1.0, 0.4)
+    en, it, rr = gpu_En(E, s, R, 1.0, 0.4)
+    err = rel(en, ref)
+    say("E_n R", R, "iters", it, "relres", rr, "err vs oracle", err)
+    assert rr <= 1e-13 and err < TOL
+
+
+@pytest.mark.parametrize("lam", [0.3, 2.0])
+def test_velocity_two_drops_matches_oracle(E, lam):
+    s = W.two_drops(6, seed=12, gap=0.3)
+    ref = G.solve_velocity_dense(s, lam, s.fcoef)
+    u, it, rr = gpu_velocity(E, s, lam, s.fcoef)
+    err = rel(u, ref)
+    say("velocity lambda", lam, "iters", it, "relres", rr, "err vs oracle", err)
+    assert rr <= 1e-13 and err < TOL
+
+
+def test_sphere_closed_forms(E):
+    p = 8
+    s = make_susp(p, sphere_x(p), q_self=16)
+    R, Eq = 3.0, 0.6
+    en, it, rr = gpu_En(E, s, R, 1.0, Eq)
+    expect = np.zeros_like(en)
+    expect[2 * tri(1, 0)] = 3 * R / (R + 2) * math.sqrt(4 * math.pi / 3)
+    expect[2 * tri(2, 0)] = 10 * R * Eq / (2 * R + 3) * math.sqrt(4 * math.pi / 5)
+    assert np.abs(en - expect).max() < 1e-11, np.abs(en - expect).max()
+    nc2 = (p + 1) * (p + 2)
+    e = np.array([0.3, -1.1, 0.7])
+    f = np.zeros(3 * nc2)
+    for c in range(3):
+        f[c * nc2] = e[c] * math.sqrt(4 * math.pi)
+    u, it, rr = gpu_velocity(E, make_susp(p, sphere_x(p), f=f, q_self=16), 2.0, f)
+    assert np.abs(u - 2.0 / 3.0 * f).max() < 1e-11
+
+
+def test_restart_and_initial_guess(E):
+    s = W.two_drops(5, seed=13, gap=0.3)
+    a, it_a, _ = gpu_En(E, s, 0.5, 1.0, 0.2)
+    b, it_b, rr_b = gpu_En(E, s, 0.5, 1.0, 0.2, restart=2)
+    assert rel(b, a) < TOL and rr_b <= 1e-13
+    c, it_c, rr_c = gpu_En(E, s, 0.5, 1.0, 0.2, guess=a)
+    assert it_c <= 1 and rel(c, a) < TOL
+
+
+def test_fp32_far_field_in_the_solver(E):
+    s = W.two_drops(6, seed=14, gap=0.3)
+    a, _, _ = gpu_En(E, s, 3.0, 1.0, 0.0)
+    b, _, rr = gpu_En(E, s, 3.0, 1.0, 0.0, far_prec=1)
+    say("E_n FP32 far vs FP64 far", rel(b, a))
+    assert rel(b, a) < 1e-6
+
+
+def test_solver_argument_errors(E):
+    import torch
+    s = W.two_drops(4, seed=15)
+    ctx, dev = _ctx(E, s)
+    en = torch.zeros(ctx.num_coefs(), dtype=torch.float64, device=dev)
+    for kw in ({"restart": 0}, {"maxit": 0}, {"tol": 0.0}, {"far_prec": 7}):
+        with pytest.raises(E.EhdError):
+            ctx.solve_En(1.5, 1.0, 0.0, en, **kw)
+    with pytest.raises(E.EhdError):
+        ctx.solve_En(-1.0, 1.0, 0.0, en)
+    ctx.close()
