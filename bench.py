@@ -101,15 +101,79 @@ def cpu_baseline(s, nsample: int, seed: int = 0):
     }
 
 
+def bench_solve(args, torch, E, W, dev):
+    """Galerkin GMRES solves (tol 1e-12 true relative residual, restart 30)
+    from a zero initial guess; also one mat-vec (evaluation + projection)
+    timed alone."""
+    s = W.WORKLOADS[args.workload](args.grid_mode)
+    far_prec = E.FAR_FP32C if args.far_prec == "fp32c" else E.FAR_FP64
+    ctx = E.Context(0)
+    ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+    nc = ctx.num_coefs()
+    T = ctx.ntargets
+    f = torch.from_numpy(s.fcoef).to(dev)
+    nf = 1 if args.solve == "en" else 3
+    x = torch.zeros(nf * nc, dtype=torch.float64, device=dev)
+    grid = torch.empty(nf, T, dtype=torch.float64, device=dev)
+    proj = torch.empty(nf * nc, dtype=torch.float64, device=dev)
+
+    def solve():
+        x.zero_()
+        if args.solve == "en":
+            return ctx.solve_En(0.5, 1.0, 0.0, x, far_prec=far_prec, tol=1e-12)
+        return ctx.solve_velocity(2.0, f, x, far_prec=far_prec, tol=1e-12)
+
+    def matvec():
+        if args.solve == "en":
+            ctx.layer_potentials(None, None, x, E.LAP_DLADJ, far_prec, grid)
+        else:
+            ctx.layer_potentials(None, x, None, E.STOKES_DL, far_prec, grid)
+        ctx.analyze(nf, grid, proj)
+
+    for _ in range(max(args.warmup, 1)):
+        its, rr = solve()
+    K = args.steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        its, rr = solve()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / K
+    for _ in range(3):
+        matvec()
+    ctx.sync()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        matvec()
+    ctx.sync()
+    mv = (time.perf_counter() - t0) / 10
+    ctx.close()
+    res = {
+        "metric": "Galerkin GMRES solve (" + ("E_n, adjoint double layer" if args.solve == "en"
+                                               else "velocity, Stokes double layer") + "), tol 1e-12",
+        "value": 1.0 / dt, "unit": "solves/s", "n_gpus": 1, "steps": K, "warmup": max(args.warmup, 1),
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if far_prec == E.FAR_FP64 else "f64+f32", "data": "synthetic",
+        "config": {"workload": args.workload, "ndrops": s.ndrops, "p": sorted(set(int(v) for v in s.p)),
+                   "targets": T, "unknowns": nf * nc, "far_prec": "fp64" if far_prec == E.FAR_FP64 else "fp32c",
+                   "R" if args.solve == "en" else "lambda": 0.5 if args.solve == "en" else 2.0},
+        "iterations": its, "relres": rr, "matvec_ms": mv * 1e3,
+        "matvec_share": its * mv / dt,
+    }
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="batched_64_mixed_p",
+    ap.add_argument("--workload", default=None,
                     choices=["batched_64_mixed_p", "large_256_p32", "two_drops_p32",
                              "single_drop_p16"])
-    ap.add_argument("--far-prec", default="fp32c", choices=["fp32c", "fp64"])
+    ap.add_argument("--far-prec", default=None, choices=["fp32c", "fp64"],
+                    help="far-field precision (default: fp32c for the evaluation, fp64 for --solve)")
     ap.add_argument("--grid-mode", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=320)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -117,6 +181,10 @@ def main(argv=None):
                     help="replay the evaluation as a recorded HIP graph (stage times then hold "
                          "the whole evaluation in the first stage)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--solve", choices=["en", "velocity"], default=None,
+                    help="time the Galerkin GMRES solve (E_n with R = 0.5, E_u = 1; velocity with "
+                         "lambda = 2 for the workload's f) instead of the evaluation; default workload "
+                         "two_drops_p32, FP64 far field")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy a MIB-mebibyte device buffer once (a plain "
                          "copy kernel of known size, to scale hardware byte counters)")
@@ -135,6 +203,12 @@ def main(argv=None):
         print(json.dumps({"error": "no GPU available"}))
         return 1
     dev = torch.device("cuda", 0)
+    if args.workload is None:
+        args.workload = "two_drops_p32" if args.solve else "batched_64_mixed_p"
+    if args.far_prec is None:
+        args.far_prec = "fp64" if args.solve else "fp32c"
+    if args.solve:
+        return bench_solve(args, torch, E, W, dev)
     s = W.WORKLOADS[args.workload](args.grid_mode)
     far_prec = E.FAR_FP32C if args.far_prec == "fp32c" else E.FAR_FP64
     kinds = E.METRIC_KINDS

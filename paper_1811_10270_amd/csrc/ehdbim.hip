@@ -758,16 +758,22 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
 // over blockIdx.y.  partial[chunk][comp][T] (unscaled).  TPT and the number
 // of chunks are the tile-shape parameters the autotuner picks.
 // ---------------------------------------------------------------------------
-template <int TPT>
+// FP64 far field: as the FP32 kernel below (kinds a template parameter,
+// sources read two at a time as double2 broadcasts from each LDS record
+// row), with absolute coordinates and plain FP64 sums.
+template <int TPT, unsigned KM>
 __global__ __launch_bounds__(kThreads) void k_far64(const double* __restrict__ tx,
                                                     const double* __restrict__ tnrm,
                                                     const int* __restrict__ tdrop, long long T,
                                                     const double* __restrict__ src, long long Spad,
                                                     const int* __restrict__ tile_drop, int ntiles,
-                                                    int tiles_per_chunk, unsigned kinds,
-                                                    double* __restrict__ partial)
+                                                    int tiles_per_chunk, double* __restrict__ partial)
 {
-    __shared__ double sm[kRec64][kTile];
+    constexpr bool wS = KM & EHD_STOKES_SL, wD = KM & EHD_STOKES_DL;
+    constexpr bool wSL = KM & EHD_LAP_SL, wL = KM & EHD_LAP_DL, wK = KM & EHD_LAP_DLADJ;
+    constexpr bool needN = wD || wL, needSig = wSL || wL || wK;
+    __shared__ double2 sm[kRec64][kTile / 2];
+    double* const smd = reinterpret_cast<double*>(&sm[0][0]);
     double x0[TPT], y0[TPT], z0[TPT], n0x[TPT], n0y[TPT], n0z[TPT], acc[TPT][9];
     int myd[TPT];
     long long tt[TPT];
@@ -780,41 +786,63 @@ __global__ __launch_bounds__(kThreads) void k_far64(const double* __restrict__ t
         myd[q] = valid ? tdrop[u] : -1;
         for (int c = 0; c < 9; ++c) acc[q][c] = 0.0;
     }
-    const bool wS = kinds & EHD_STOKES_SL, wD = kinds & EHD_STOKES_DL;
-    const bool wSL = kinds & EHD_LAP_SL, wL = kinds & EHD_LAP_DL, wK = kinds & EHD_LAP_DLADJ;
     const int t0 = blockIdx.y * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
     for (int tile = t0; tile < t1; ++tile) {
         const long long s = (long long)tile * kTile + threadIdx.x;
-        for (int r = 0; r < kRec64; ++r) sm[r][threadIdx.x] = src[r * Spad + s];
+        for (int r = 0; r < kRec64; ++r) smd[r * kTile + threadIdx.x] = src[r * Spad + s];
         __syncthreads();
         const int sd = tile_drop[tile];
-        for (int q = 0; q < kTile; ++q) {
+        bool other = false;   // some target of this thread is not on the tile's drop
+        for (int k = 0; k < TPT; ++k) other = other || (sd != myd[k]);
+        double a[TPT][9];
+        for (int k = 0; k < TPT; ++k)
+            for (int c = 0; c < 9; ++c) a[k][c] = 0.0;
+        for (int q2 = 0; q2 < (other ? kTile / 2 : 0); ++q2) {
+            const double2 X = sm[0][q2], Y = sm[1][q2], Z = sm[2][q2];
+            double2 NX, NY, NZ, F0, F1, F2, U0, U1, U2, SG;
+            if constexpr (needN) { NX = sm[3][q2]; NY = sm[4][q2]; NZ = sm[5][q2]; }
+            if constexpr (wS) { F0 = sm[7][q2]; F1 = sm[8][q2]; F2 = sm[9][q2]; }
+            if constexpr (wD) { U0 = sm[10][q2]; U1 = sm[11][q2]; U2 = sm[12][q2]; }
+            if constexpr (needSig) SG = sm[13][q2];
 #pragma unroll
-            for (int k = 0; k < TPT; ++k) {
-                if (sd == myd[k]) continue;
-                const double hx = x0[k] - sm[0][q], hy = y0[k] - sm[1][q], hz = z0[k] - sm[2][q];
-                const double r2 = hx * hx + hy * hy + hz * hz;
-                const double ir = rsqrt_nr(r2), ir2 = ir * ir, ir3 = ir * ir2;
-                const double hn = hx * sm[3][q] + hy * sm[4][q] + hz * sm[5][q];
-                if (wS) {
-                    const double f0 = sm[7][q], f1 = sm[8][q], f2 = sm[9][q];
-                    const double hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
-                    acc[k][0] += f0 * ir + hx * hf;
-                    acc[k][1] += f1 * ir + hy * hf;
-                    acc[k][2] += f2 * ir + hz * hf;
+            for (int j = 0; j < 2; ++j) {
+                const double xs = j ? X.y : X.x, ys = j ? Y.y : Y.x, zs = j ? Z.y : Z.x;
+#pragma unroll
+                for (int k = 0; k < TPT; ++k) {
+                    const double hx = x0[k] - xs, hy = y0[k] - ys, hz = z0[k] - zs;
+                    const double r2 = fma(hx, hx, fma(hy, hy, hz * hz));
+                    const double ir = rsqrt_nr(r2), ir2 = ir * ir, ir3 = ir * ir2;
+                    double hn = 0.0;
+                    if constexpr (needN)
+                        hn = fma(hx, j ? NX.y : NX.x, fma(hy, j ? NY.y : NY.x, hz * (j ? NZ.y : NZ.x)));
+                    if constexpr (wS) {
+                        const double f0 = j ? F0.y : F0.x, f1 = j ? F1.y : F1.x, f2 = j ? F2.y : F2.x;
+                        const double hf = fma(hx, f0, fma(hy, f1, hz * f2)) * ir3;
+                        a[k][0] = fma(hx, hf, fma(f0, ir, a[k][0]));
+                        a[k][1] = fma(hy, hf, fma(f1, ir, a[k][1]));
+                        a[k][2] = fma(hz, hf, fma(f2, ir, a[k][2]));
+                    }
+                    if constexpr (wD) {
+                        const double hu =
+                            fma(hx, j ? U0.y : U0.x, fma(hy, j ? U1.y : U1.x, hz * (j ? U2.y : U2.x)));
+                        const double tq = (hu * hn) * (ir3 * ir2);
+                        a[k][3] = fma(tq, hx, a[k][3]);
+                        a[k][4] = fma(tq, hy, a[k][4]);
+                        a[k][5] = fma(tq, hz, a[k][5]);
+                    }
+                    if constexpr (needSig) {
+                        const double sg = j ? SG.y : SG.x;
+                        if constexpr (wSL) a[k][6] = fma(sg, ir, a[k][6]);
+                        if constexpr (wL) a[k][7] = fma(sg * hn, ir3, a[k][7]);
+                        if constexpr (wK)
+                            a[k][8] = fma(sg * fma(hx, n0x[k], fma(hy, n0y[k], hz * n0z[k])), ir3, a[k][8]);
+                    }
                 }
-                if (wD) {
-                    const double hu = hx * sm[10][q] + hy * sm[11][q] + hz * sm[12][q];
-                    const double tq = -6.0 * hu * hn * ir3 * ir2;
-                    acc[k][3] += tq * hx;
-                    acc[k][4] += tq * hy;
-                    acc[k][5] += tq * hz;
-                }
-                const double sg = sm[13][q];
-                if (wSL) acc[k][6] += sg * ir;
-                if (wL) acc[k][7] += sg * hn * ir3;
-                if (wK) acc[k][8] += sg * (hx * n0x[k] + hy * n0y[k] + hz * n0z[k]) * ir3;
             }
+        }
+        for (int k = 0; k < TPT; ++k) {
+            if (sd == myd[k]) continue;      // own drop: tile not counted
+            for (int c = 0; c < 9; ++c) acc[k][c] += (c >= 3 && c < 6) ? -6.0 * a[k][c] : a[k][c];
         }
         __syncthreads();
     }
@@ -823,11 +851,6 @@ __global__ __launch_bounds__(kThreads) void k_far64(const double* __restrict__ t
             for (int c = 0; c < 9; ++c) partial[((long long)blockIdx.y * 9 + c) * T + tt[k]] = acc[k][c];
 }
 
-// Far field, FP32 with drop-centred coordinates: per tile, each target's
-// position relative to the source drop's centre is formed in FP64 and split
-// into an FP32 head and tail; sources are stored relative to the same centre.
-// The tile sum is accumulated in FP32 and added to a compensated (Kahan)
-// FP32 running sum.
 // FP32 far field: the kinds KM are a template parameter (no per-interaction
 // branches), sources are read four at a time as float4 from each LDS record
 // row (one broadcast read per record and four sources).  Targets are taken
@@ -1224,6 +1247,29 @@ static int launch_self(ehd_ctx* ctx, const double* f, const double* u, const dou
     if (!rc) rc = launch_self_class<24, HF, HU, HS>(ctx, 1, f, u, s, kinds);
     if (!rc) rc = launch_self_class<16, HF, HU, HS>(ctx, 0, f, u, s, kinds);
     return rc;
+}
+
+// FP64 far-field launchers, one per (targets per thread, kinds mask).
+using Far64Launch = void (*)(dim3, hipStream_t, const double*, const double*, const int*, long long, const double*,
+                             long long, const int*, int, int, double*);
+template <int TPT, unsigned KM>
+static void launch_far64_km(dim3 grid, hipStream_t st, const double* tx, const double* tn, const int* tdrop,
+                            long long T, const double* src, long long S, const int* tile_drop, int ntiles, int tpc,
+                            double* partial)
+{
+    hipLaunchKernelGGL((k_far64<TPT, KM>), grid, dim3(kThreads), 0, st, tx, tn, tdrop, T, src, S, tile_drop, ntiles,
+                       tpc, partial);
+}
+template <int TPT, std::size_t... I>
+static const std::array<Far64Launch, 32>& far64_table_impl(std::index_sequence<I...>)
+{
+    static const std::array<Far64Launch, 32> t{{&launch_far64_km<TPT, (unsigned)I>...}};
+    return t;
+}
+template <int TPT>
+static const std::array<Far64Launch, 32>& far64_table()
+{
+    return far64_table_impl<TPT>(std::make_index_sequence<32>{});
 }
 
 // FP32 far-field launchers, one per (targets per thread, kinds mask).
@@ -1630,12 +1676,9 @@ static int launch_far(ehd_ctx* ctx, int far_prec, unsigned kinds, int tpt, int n
     const int tpc = (ctx->ntiles + nchunk - 1) / nchunk;
     dim3 grid((unsigned)tblocks, (unsigned)nchunk);
     if (far_prec == EHD_FAR_FP64) {
-        if (tpt == 2)
-            hipLaunchKernelGGL(k_far64<2>, grid, dim3(kThreads), 0, ctx->ls, ctx->d_tx, ctx->d_tn, ctx->d_tdrop,
-                               T, ctx->d_src64, S, ctx->d_tile_drop, ctx->ntiles, tpc, kinds, ctx->d_partial);
-        else
-            hipLaunchKernelGGL(k_far64<1>, grid, dim3(kThreads), 0, ctx->ls, ctx->d_tx, ctx->d_tn, ctx->d_tdrop,
-                               T, ctx->d_src64, S, ctx->d_tile_drop, ctx->ntiles, tpc, kinds, ctx->d_partial);
+        const Far64Launch fn = (tpt == 2 ? far64_table<2>() : far64_table<1>())[kinds & EHD_ALL_KINDS];
+        fn(grid, ctx->ls, ctx->d_tx, ctx->d_tn, ctx->d_tdrop, T, ctx->d_src64, S, ctx->d_tile_drop, ctx->ntiles, tpc,
+           ctx->d_partial);
     } else {
         const Far32Launch fn = (tpt == 2 ? far32_table<2>() : far32_table<1>())[kinds & EHD_ALL_KINDS];
         fn(grid, ctx->ls, ctx->d_tx, ctx->d_tn, ctx->d_tdrop, T, ctx->d_src32, S, ctx->d_tile_drop, ctx->d_centre,
