@@ -304,20 +304,27 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // the nodes l, H - l, H + l, N - l take EC + ES + OC + OS, EC - ES - OC + OS,
 // EC + ES - OC - OS and EC - ES + OC - OS (cos m(pi -+ phi) = (-1)^m cos m phi,
 // sin m(pi - phi) = -(-1)^m sin m phi), so rows l = 0..floor(H/2) suffice.
+// Row 0 (phi = 0 and pi) has no sine terms and all cosines 1: its values
+// EC + OC and EC - OC are plain sums.  Where the degree class allows it
+// (row0), row 0 is taken apart from the GEMM rows (which then start at
+// l0 = 1) when that lowers the padded tile count.
 //   nT row tiles of 16 (padded to nTp in {1, 2, 4, 8} so that the waves
 //   split the tiles evenly); term counts: EC floor(p/2)+1 (m = 0, 2, ..),
 //   ES floor(p/2) (m = 2, 4, ..), OC = OS = ceil(p/2) (m = 1, 3, ..);
 //   k-steps of 4 terms per group, groups stored in the order EC ES OC OS.
 struct QuarterGrid {
-    int H, rows, nT, nTp, nk[4], base[4], nks;
+    int H, l0, rows, nT, nTp, nk[4], base[4], nks;
 };
-__host__ __device__ inline QuarterGrid quarter_grid(int p, int nlonq)
+__host__ __device__ inline int padded_tiles(int nt) { return nt <= 1 ? 1 : nt <= 2 ? 2 : nt <= 4 ? 4 : 8; }
+__host__ __device__ inline QuarterGrid quarter_grid(int p, int nlonq, bool row0)
 {
     QuarterGrid g;
     g.H = nlonq / 2;
-    g.rows = g.H / 2 + 1;
+    const int with0 = padded_tiles((g.H / 2 + 1 + 15) / 16), without0 = padded_tiles((g.H / 2 + 15) / 16);
+    g.l0 = (row0 && without0 < with0) ? 1 : 0;
+    g.rows = g.H / 2 + 1 - g.l0;           // GEMM rows l = l0 .. floor(H/2)
     g.nT = (g.rows + 15) / 16;
-    g.nTp = g.nT <= 1 ? 1 : g.nT <= 2 ? 2 : g.nT <= 4 ? 4 : 8;
+    g.nTp = padded_tiles(g.nT);
     const int terms[4] = {p / 2 + 1, p / 2, (p + 1) / 2, (p + 1) / 2};
     int b = 0;
     for (int q = 0; q < 4; ++q) {
@@ -372,12 +379,20 @@ struct SelfClass {
     static constexpr int NW = NT / 64;                         // waves per block
     static constexpr int TPW = (8 + NW - 1) / NW;              // row tiles per wave (max)
     static constexpr int KW = wave_ksteps_max(PMAX, NW);       // Legendre k-steps per wave
+    // row 0 of the longitude sums may be taken apart (pays at q = 2p for
+    // p = 16 and 32: one tile less; elsewhere the tile count is unchanged)
+    static constexpr bool ROW0 = PMAX == 16 || PMAX == 32;
 };
 
 // Legendre k-steps per wave of the degree class of p (table stride per wave).
 static inline int self_kw(int p)
 {
     return p <= 16 ? SelfClass<16>::KW : p <= 24 ? SelfClass<24>::KW : p <= 32 ? SelfClass<32>::KW : SelfClass<48>::KW;
+}
+// Whether the degree class of p may take row 0 of the longitude sums apart.
+static inline bool self_row0(int p)
+{
+    return p <= 16 ? SelfClass<16>::ROW0 : p <= 24 ? SelfClass<24>::ROW0 : p <= 32 ? SelfClass<32>::ROW0 : SelfClass<48>::ROW0;
 }
 
 template <int PMAX, bool HF, bool HU, bool HS>
@@ -412,7 +427,7 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     const LegTab Lq = legs[D.leg_ps];
     const LegTab Lp = legs[D.leg_pp];
     const WigTab W = wigs[D.wig];
-    const QuarterGrid qg = quarter_grid(p, Lq.nlon);
+    const QuarterGrid qg = quarter_grid(p, Lq.nlon, SC::ROW0);
     double2* cr = lds;                               // [NF][nc] rotated coefficients
     double* R = reinterpret_cast<double*>(lds);      // later: Fourier blocks + node values
     const int lane = threadIdx.x & 63;
@@ -632,6 +647,49 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
         }
         __syncthreads();
 
+        // kernels at one node (this lane's record of the wave's node buffer)
+        // with the modified weight wi of its latitude, accumulated per lane
+        auto eval_node = [&](const double* val, double wi) {
+            const double xt0 = val[3], xt1 = val[4], xt2 = val[5];
+            const double xp0 = val[6], xp1 = val[7], xp2 = val[8];
+            const double cx = xt1 * xp2 - xt2 * xp1;
+            const double cy = xt2 * xp0 - xt0 * xp2;
+            const double cz = xt0 * xp1 - xt1 * xp0;
+            const double J2 = cx * cx + cy * cy + cz * cz;
+            const double iJ = rsqrt_nr(J2);
+            const double w = wi * J2 * iJ;
+            const double nx = cx * iJ, ny = cy * iJ, nz = cz * iJ;
+            const double hx = x0[0] - val[0], hy = x0[1] - val[1], hz = x0[2] - val[2];
+            const double r2 = hx * hx + hy * hy + hz * hz;
+            const double ir = rsqrt_nr(r2), ir2 = ir * ir, ir3 = ir * ir2;
+            const double hn = hx * nx + hy * ny + hz * nz;
+            if constexpr (HF) {
+                if (wS) {
+                    const double f0 = val[VD], f1 = val[VD + 1], f2 = val[VD + 2];
+                    const double hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
+                    acc[0] += w * (f0 * ir + hx * hf);
+                    acc[1] += w * (f1 * ir + hy * hf);
+                    acc[2] += w * (f2 * ir + hz * hf);
+                }
+            }
+            if constexpr (HF || HU) {
+                if (wD) {
+                    constexpr int uo = VD + (HU ? UOFF : FOFF) - 3;
+                    const double hu = hx * val[uo] + hy * val[uo + 1] + hz * val[uo + 2];
+                    const double tq = -6.0 * w * hu * hn * ir3 * ir2;
+                    acc[3] += tq * hx;
+                    acc[4] += tq * hy;
+                    acc[5] += tq * hz;
+                }
+            }
+            if constexpr (HS) {
+                const double sg = w * val[VD + SOFF - 3];
+                if (wSL) acc[6] += sg * ir;
+                if (wL) acc[7] += sg * hn * ir3;
+                if (wK) acc[8] += sg * (hx * n0v[0] + hy * n0v[1] + hz * n0v[2]) * ir3;
+            }
+        };
+
         // 3b/3c. per latitude of the block owned by this wave: longitude
         //     sums of its row tile on MFMA (four term-group chains), node
         //     values through the wave's own LDS buffer (64 nodes: {l, H - l,
@@ -682,57 +740,40 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 // node of this lane; the four images coincide pairwise at l = 0 and at 2 l = H
-                const int c4 = lane >> 4, l = 16 * my_tile + (lane & 15);
+                const int c4 = lane >> 4, l = qg.l0 + 16 * my_tile + (lane & 15);
                 const bool node_ok = 2 * l <= qg.H &&
                                      (c4 == 0 || (c4 == 1 && 2 * l < qg.H) || (c4 == 2 && l > 0) ||
                                       (c4 == 3 && l > 0 && 2 * l < qg.H));
-                if (node_ok) {
-                    const double* val = NB + lane * NVP;
-                    const double wi = wsing[i];
-                    const double xt0 = val[3], xt1 = val[4], xt2 = val[5];
-                    const double xp0 = val[6], xp1 = val[7], xp2 = val[8];
-                    const double cx = xt1 * xp2 - xt2 * xp1;
-                    const double cy = xt2 * xp0 - xt0 * xp2;
-                    const double cz = xt0 * xp1 - xt1 * xp0;
-                    const double J2 = cx * cx + cy * cy + cz * cz;
-                    const double iJ = rsqrt_nr(J2);
-                    const double w = wi * J2 * iJ;
-                    const double nx = cx * iJ, ny = cy * iJ, nz = cz * iJ;
-                    const double hx = x0[0] - val[0], hy = x0[1] - val[1], hz = x0[2] - val[2];
-                    const double r2 = hx * hx + hy * hy + hz * hz;
-                    const double ir = rsqrt_nr(r2), ir2 = ir * ir, ir3 = ir * ir2;
-                    const double hn = hx * nx + hy * ny + hz * nz;
-                    if constexpr (HF) {
-                        if (wS) {
-                            const double f0 = val[VD], f1 = val[VD + 1], f2 = val[VD + 2];
-                            const double hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
-                            acc[0] += w * (f0 * ir + hx * hf);
-                            acc[1] += w * (f1 * ir + hy * hf);
-                            acc[2] += w * (f2 * ir + hz * hf);
-                        }
-                    }
-                    if constexpr (HF || HU) {
-                        if (wD) {
-                            constexpr int uo = VD + (HU ? UOFF : FOFF) - 3;
-                            const double hu = hx * val[uo] + hy * val[uo + 1] + hz * val[uo + 2];
-                            const double tq = -6.0 * w * hu * hn * ir3 * ir2;
-                            acc[3] += tq * hx;
-                            acc[4] += tq * hy;
-                            acc[5] += tq * hz;
-                        }
-                    }
-                    if constexpr (HS) {
-                        const double sg = w * val[VD + SOFF - 3];
-                        if (wSL) acc[6] += sg * ir;
-                        if (wL) acc[7] += sg * hn * ir3;
-                        if (wK) acc[8] += sg * (hx * n0v[0] + hy * n0v[1] + hz * n0v[2]) * ir3;
-                    }
-                }
+                if (node_ok) eval_node(NB + lane * NVP, wsing[i]);
                 // the buffer is rewritten for the next latitude
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
+        }
+        // 3d. when row 0 is apart: row 0 of latitude wv of the block, phi = 0
+        //     and pi take EC + OC and EC - OC, the sums of the cos rows of even
+        //     and odd m; lane (column v, part) sums every fourth row, shuffles
+        //     add the parts.
+        if (SC::ROW0 && qg.l0 == 1 && b * LB + wv <= Lq.Q) {
+            const double* G = R + wv * gsz + (lane & 15);
+            const int part = lane >> 4;
+            double ecs = 0.0, ocs = 0.0;
+            for (int k = 0; k < qg.nk[0]; ++k) ecs += G[(qg.base[0] + 4 * k + part) * 16];
+            for (int k = 0; k < qg.nk[2]; ++k) ocs += G[(qg.base[2] + 4 * k + part) * 16];
+            ecs += __shfl_xor(ecs, 16);
+            ecs += __shfl_xor(ecs, 32);
+            ocs += __shfl_xor(ocs, 16);
+            ocs += __shfl_xor(ocs, 32);
+            const int v = lane & 15;
+            if (part < 2 && v < NV) NB[part * NVP + v] = part ? ecs - ocs : ecs + ocs;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (lane < 2) eval_node(NB + lane * NVP, wsing[b * LB + wv]);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         __syncthreads();  // Fourier blocks consumed before the next block's Legendre sums
     }
@@ -1207,7 +1248,7 @@ static size_t self_lds_bytes(const ehd_ctx* ctx, const std::vector<int>& drops, 
     size_t best = 0;
     for (int d : drops) {
         const DropInfo& D = ctx->info[d];
-        const QuarterGrid g = quarter_grid(D.p, D.nlon_s);
+        const QuarterGrid g = quarter_grid(D.p, D.nlon_s, self_row0(D.p));
         const size_t coef = (size_t)nf * ncoef(D.p) * 16;
         const size_t work = ((size_t)kLatBlock * g.nks * 64 +
                              (size_t)SelfClass<16>::NW * 64 * ((nf + 6) | 1)) * 8;
@@ -1423,20 +1464,20 @@ int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
                 trig[((size_t)l * (pp + 1) + m) * 2 + 1] = std::sin(a);
             }
         // MFMA A fragments of the quarter-period cos/sin tables (singular
-        // grids): lane holds A[row 16 t + lane%16][term 4 ks + lane/16] of the
+        // grids): lane holds A[row l = l0 + 16 t + lane%16][term 4 ks + lane/16] of the
         // term groups EC (cos m, m = 0, 2, ..), ES (sin m, m = 2, 4, ..),
         // OC (cos m, m = 1, 3, ..), OS (sin m, m = 1, 3, ..), one after the other.
         std::vector<double> afrag;
         if (singular) {
-            const QuarterGrid g = quarter_grid(pp, nl);
+            const QuarterGrid g = quarter_grid(pp, nl, self_row0(pp));
             afrag.assign((size_t)g.nT * g.nks * 64, 0.0);
             const int terms[4] = {pp / 2 + 1, pp / 2, (pp + 1) / 2, (pp + 1) / 2};
             for (int t = 0; t < g.nT; ++t)
                 for (int grp = 0; grp < 4; ++grp)
                     for (int ks = 0; ks < g.nk[grp]; ++ks)
                         for (int lane = 0; lane < 64; ++lane) {
-                            const int l = 16 * t + (lane & 15), term = 4 * ks + (lane >> 4);
-                            if (l >= g.rows || term >= terms[grp]) continue;
+                            const int l = g.l0 + 16 * t + (lane & 15), term = 4 * ks + (lane >> 4);
+                            if (l > g.H / 2 || term >= terms[grp]) continue;
                             const int m = grp == 0 ? 2 * term : grp == 1 ? 2 * term + 2 : 2 * term + 1;
                             const bool is_cos = grp == 0 || grp == 2;
                             const double a = 2.0 * kPi * (double)((long)m * l % nl) / nl;
