@@ -141,6 +141,14 @@ int ehd_layer_potentials(ehd_ctx* ctx, const double* fcoef_d, const double* ucoe
  * drops' own grid nodes, grid_d[field][global target]. */
 int ehd_synthesize(ehd_ctx* ctx, int nfields, const double* coef_d, double* grid_d);
 
+/* Surface quantities at the target nodes (Sec. 1, eq. interfacial_force):
+ * H_d[T] the mean curvature H = (1/2) div_S n (n outward: 1/a on a sphere
+ * of radius a) and, for ng in {0, 1, 2} packed scalar fields gcoef_d (ng
+ * fields per drop), grad_d[g][3][T] their surface gradients
+ * (I - n n) grad g.  From the SH derivatives of x and g up to second order;
+ * gcoef_d and grad_d may be NULL when ng = 0. */
+int ehd_surface(ehd_ctx* ctx, int ng, const double* gcoef_d, double* H_d, double* grad_d);
+
 /* Galerkin analysis (Sec. 2, the inner product before eq. BIM_galerkin):
  * coef_d receives (y, Y_nm) = int_{S^2} y conj(Y_nm) ds for n <= p, m >= 0,
  * computed with the Gaussian grid quadrature from grid_d[field][global target]. */

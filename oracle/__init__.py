@@ -32,6 +32,8 @@ def _load():
         _b.build()
     lib = C.CDLL(_LIB_PATH)
     lib.ora_gauss_legendre.argtypes = [C.c_int, _dp, _dp]
+    lib.ora_surface_point.argtypes = [C.c_int, _dp, C.c_int, _dp, C.c_double, C.c_double, _dp]
+    lib.ora_surface_point.restype = None
     lib.ora_pbar.argtypes = [C.c_int, C.c_double, C.c_double, _dp, _dp, _dp]
     lib.ora_pbar.restype = None
     lib.ora_synth_grid.argtypes = [C.c_int, C.c_int, _dp, C.c_int, C.c_int, _dp]
@@ -107,6 +109,16 @@ def geom_point(p: int, xcoef: np.ndarray, theta: float, phi: float):
     _load().ora_geom_point(p, _d(xcoef), float(np.cos(theta)), float(np.sin(theta)),
                            float(np.cos(phi)), float(np.sin(phi)), _d(x), _d(n), _d(J))
     return x, n, float(J[0])
+
+
+def surface_point(p: int, xcoef: np.ndarray, theta: float, phi: float, gcoef=None, ng: int = 0):
+    """x(3), outward normal n(3), mean curvature H = (1/2) div_S n and the
+    surface gradients (3 each) of ng scalar fields, at one parameter point."""
+    xcoef = _f64(xcoef)
+    gc = _f64(gcoef) if ng else np.zeros(2)
+    out = np.zeros(7 + 3 * ng)
+    _load().ora_surface_point(p, _d(xcoef), ng, _d(gc), float(theta), float(phi), _d(out))
+    return out[0:3], out[3:6], float(out[6]), out[7:].reshape(ng, 3)
 
 
 def synth_grid(p: int, coef: np.ndarray, Q: int, grid_mode: int = 0, nf: int = 1):

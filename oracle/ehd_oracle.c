@@ -537,6 +537,104 @@ void ora_geom_point(int p, const double* xcoef, double t, double s, double cphi,
     free(Qw); free(dQw);
 }
 
+/* Q, dQ/dt and d2Q/dt2 of Pbar_n^m = s^m Q(t) by the recurrence in n and
+ * its first and second t-derivatives. */
+static void leg_eval2(int p, double t, double* Q, double* dQ, double* d2Q)
+{
+    double qmm = 1.0 / sqrt(4.0 * ORA_PI);
+    for (int m = 0; m <= p; ++m) {
+        if (m > 0) qmm *= -sqrt((2.0 * m + 1.0) / (2.0 * m));
+        Q[tri(m, m)] = qmm;
+        dQ[tri(m, m)] = 0.0;
+        d2Q[tri(m, m)] = 0.0;
+        if (m + 1 <= p) {
+            double c = sqrt(2.0 * m + 3.0);
+            Q[tri(m + 1, m)] = c * t * qmm;
+            dQ[tri(m + 1, m)] = c * qmm;
+            d2Q[tri(m + 1, m)] = 0.0;
+        }
+        for (int n = m + 2; n <= p; ++n) {
+            double a = sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m));
+            double b = sqrt(((n - 1.0) * (n - 1.0) - (double)m * m) / (4.0 * (n - 1.0) * (n - 1.0) - 1.0));
+            long k = tri(n, m), k1 = tri(n - 1, m), k2 = tri(n - 2, m);
+            Q[k] = a * (t * Q[k1] - b * Q[k2]);
+            dQ[k] = a * (Q[k1] + t * dQ[k1] - b * dQ[k2]);
+            d2Q[k] = a * (2.0 * dQ[k1] + t * d2Q[k1] - b * d2Q[k2]);
+        }
+    }
+}
+
+/* Surface quantities at the point (theta, phi) of a drop x (3 fields) and of
+ * ng scalar fields g (packed, degree p):
+ *   out[0..2] x, out[3..5] n (outward unit normal), out[6] mean curvature
+ *   H = (1/2) div_S n (Sec. 1, after eq. interfacial_force), out[7 + 3 g ..]
+ *   the surface gradient of field g.
+ * With x_a, x_ab the parameter derivatives, E, F, G and L, M, N the first
+ * and second fundamental forms (L = x_tt . n, ...), W^2 = EG - F^2:
+ *   H = -(E N - 2 F M + G L) / (2 W^2)   (positive on a sphere with outward n),
+ *   grad_S g = ((G g_t - F g_p) x_t + (E g_p - F g_t) x_p) / W^2.
+ * Derivatives of Pbar = s^m Q(t), t = cos theta, s = sin theta:
+ *   d/dtheta   = m s^(m-1) t Q - s^(m+1) Q',
+ *   d2/dtheta2 = m(m-1) s^(m-2) t^2 Q - m s^m Q - (2m+1) s^m t Q' + s^(m+2) Q''. */
+void ora_surface_point(int p, const double* xcoef, int ng, const double* gcoef, double theta, double phi,
+                       double* out)
+{
+    long nc = ncoef_of(p);
+    double* Q = (double*)malloc(sizeof(double) * nc);
+    double* dQ = (double*)malloc(sizeof(double) * nc);
+    double* d2Q = (double*)malloc(sizeof(double) * nc);
+    double t = cos(theta), s = sin(theta);
+    leg_eval2(p, t, Q, dQ, d2Q);
+    int nf = 3 + ng;
+    double v[64], vt[64], vp[64], vtt[3], vtp[3], vpp[3];
+    for (int f = 0; f < nf; ++f) { v[f] = vt[f] = vp[f] = 0.0; }
+    for (int c = 0; c < 3; ++c) { vtt[c] = vtp[c] = vpp[c] = 0.0; }
+    for (int m = 0; m <= p; ++m) {
+        double cm = cos(m * phi), sm_ = sin(m * phi);
+        double mult = (m == 0) ? 1.0 : 2.0;
+        double sm0 = pow(s, m), sm1 = m >= 1 ? pow(s, m - 1) : 0.0, sm2 = m >= 2 ? pow(s, m - 2) : 0.0;
+        for (int n = m; n <= p; ++n) {
+            long k = tri(n, m);
+            double P = sm0 * Q[k];
+            double dP = m * sm1 * t * Q[k] - sm0 * s * dQ[k];
+            double d2P = m * (m - 1) * sm2 * t * t * Q[k] - m * sm0 * Q[k] - (2.0 * m + 1.0) * sm0 * t * dQ[k] +
+                         sm0 * s * s * d2Q[k];
+            for (int f = 0; f < nf; ++f) {
+                const double* cf = f < 3 ? xcoef + 2 * (f * nc + k) : gcoef + 2 * ((f - 3) * nc + k);
+                double cr = cf[0], ci = (m == 0) ? 0.0 : cf[1];
+                double re = cr * cm - ci * sm_;          /* Re(c e^{i m phi})   */
+                double im = cr * sm_ + ci * cm;          /* Im(c e^{i m phi})   */
+                v[f] += mult * re * P;
+                vt[f] += mult * re * dP;
+                vp[f] += mult * (-(double)m) * im * P;   /* d/dphi: Re(i m c e^{i m phi}) */
+                if (f < 3) {
+                    vtt[f] += mult * re * d2P;
+                    vtp[f] += mult * (-(double)m) * im * dP;
+                    vpp[f] += mult * (-(double)m * m) * re * P;
+                }
+            }
+        }
+    }
+    double E = 0, F = 0, G = 0;
+    for (int c = 0; c < 3; ++c) { E += vt[c] * vt[c]; F += vt[c] * vp[c]; G += vp[c] * vp[c]; }
+    double nx = vt[1] * vp[2] - vt[2] * vp[1], ny = vt[2] * vp[0] - vt[0] * vp[2], nz = vt[0] * vp[1] - vt[1] * vp[0];
+    double W = sqrt(nx * nx + ny * ny + nz * nz);
+    nx /= W; ny /= W; nz /= W;
+    double L = vtt[0] * nx + vtt[1] * ny + vtt[2] * nz;
+    double M = vtp[0] * nx + vtp[1] * ny + vtp[2] * nz;
+    double N = vpp[0] * nx + vpp[1] * ny + vpp[2] * nz;
+    double W2 = E * G - F * F;
+    for (int c = 0; c < 3; ++c) out[c] = v[c];
+    out[3] = nx; out[4] = ny; out[5] = nz;
+    out[6] = -(E * N - 2.0 * F * M + G * L) / (2.0 * W2);
+    for (int g = 0; g < ng; ++g) {
+        double gt = vt[3 + g], gp = vp[3 + g];
+        double a = (G * gt - F * gp) / W2, b = (E * gp - F * gt) / W2;
+        for (int c = 0; c < 3; ++c) out[7 + 3 * g + c] = a * vt[c] + b * vp[c];
+    }
+    free(Q); free(dQ); free(d2Q);
+}
+
 int ora_num_threads(void)
 {
 #ifdef _OPENMP

@@ -47,13 +47,13 @@ struct LegTab {                // degree-p expansions on a degree-Q grid
     const double* wq;          // [Q+1] (2 pi / nlon) * w_i^G
     const double* wsing;       // [Q+1] (2 pi / nlon) * w_i^G * 2 sin(theta_i/2) sum_{n<=Q} P_n
     const double* rsin;        // [Q+1] 1 / sin theta_i
+    const double* cth;         // [Q+1] cos theta_i
     const double* trig;        // [nlon][p+1][2] cos(m phi_l), sin(m phi_l)
-    const double* afrag;       // MFMA A fragments of the half-period cos/sin
-                               // tables: [row tile][k-step (even, odd)][lane]
+    const double* afrag;       // singular grids: MFMA A fragments of the quarter-period
+                               // cos/sin tables: [row tile][k-step (EC ES OC OS)][lane]
     const double* lfrag;       // singular grids: MFMA A fragments of the Legendre sums,
-                               // [latitude block][k-step of degree m][lane]; rows
-                               // 0-7 Pbar, 8-15 dPbar/dtheta at 8 latitudes,
-                               // k = n - m - 4 ks
+                               // [latitude block][wave][k-step][lane]; rows 0-7 Pbar,
+                               // 8-15 dPbar/dtheta at 8 latitudes
     int p, Q, nlon, pad;
 };
 
@@ -183,6 +183,98 @@ __global__ __launch_bounds__(kThreads) void k_synth(const DropInfo* __restrict__
                 out[(K + f) * vstride + node0 + l] = vt[f];
                 out[(2 * K + f) * vstride + node0 + l] = vp[f] * rs;
             }
+        }
+    }
+}
+
+// Surface quantities at the target nodes (Sec. 1, eq. interfacial_force):
+// mean curvature H = (1/2) div_S n and surface gradients of NG scalar fields.
+// One block per (drop, latitude i) of the drop's own grid.  Per order m the
+// partial sums over n of c Pbar, c dPbar/dtheta and c n(n+1) Pbar; the second
+// theta-derivative follows from the associated Legendre equation,
+//   d2Pbar/dtheta2 = -cot(theta) dPbar/dtheta - (n(n+1) - m^2/sin^2) Pbar.
+// With x_t, x_p, x_tt, x_tp, x_pp the parameter derivatives of x, E F G and
+// L M N the fundamental forms and W^2 = EG - F^2:
+//   H = -(E N - 2 F M + G L) / (2 W^2),
+//   grad_S g = ((G g_t - F g_p) x_t + (E g_p - F g_t) x_p) / W^2.
+// Outputs H[T], grad[g][3][T].
+template <int NG>
+__global__ __launch_bounds__(kThreads) void k_surface(const DropInfo* __restrict__ drops,
+                                                      const LegTab* __restrict__ legs,
+                                                      const int2* __restrict__ rows,
+                                                      const double* __restrict__ xcoef,
+                                                      const double* __restrict__ gcoef, long long T,
+                                                      double* __restrict__ Hout, double* __restrict__ grad)
+{
+    constexpr int K = 3 + NG;
+    __shared__ double2 G0[K][EHD_MAX_P + 1], G1[K][EHD_MAX_P + 1], G2[3][EHD_MAX_P + 1];
+    const int2 r = rows[blockIdx.x];
+    const DropInfo D = drops[r.x];
+    const LegTab L = legs[D.leg_pp];
+    const int p = L.p, i = r.y;
+    const long nc = ncoef(p);
+    const double* Prow = L.P + (long long)i * nc;
+    const double* dProw = L.dP + (long long)i * nc;
+    for (int it = threadIdx.x; it < K * (p + 1); it += blockDim.x) {
+        const int f = it / (p + 1), m = it % (p + 1);
+        const double* cf = f < 3 ? xcoef + 3 * D.coff + f * 2 * nc : gcoef + (long long)NG * D.coff + (f - 3) * 2 * nc;
+        double a0 = 0, b0 = 0, a1 = 0, b1 = 0, a2 = 0, b2 = 0;
+        for (int n = m; n <= p; ++n) {
+            const long k = tri(n, m);
+            const double cr = cf[2 * k], ci = (m == 0) ? 0.0 : cf[2 * k + 1];
+            const double pv = Prow[k], dv = dProw[k], nn = (double)n * (n + 1);
+            a0 += pv * cr; b0 += pv * ci;
+            a1 += dv * cr; b1 += dv * ci;
+            a2 += nn * pv * cr; b2 += nn * pv * ci;
+        }
+        G0[f][m] = make_double2(a0, b0);
+        G1[f][m] = make_double2(a1, b1);
+        if (f < 3) G2[f][m] = make_double2(a2, b2);
+    }
+    __syncthreads();
+    const double rs = L.rsin[i];                           // 1 / sin theta
+    const double ct = L.cth[i] * rs;                       // cot theta
+    const long long node0 = D.toff + (long long)i * L.nlon;
+    for (int l = threadIdx.x; l < L.nlon; l += blockDim.x) {
+        const double* tr = L.trig + (long long)l * (p + 1) * 2;
+        double vt[K], vp[K], vtt[3], vtp[3], vpp[3];
+        for (int f = 0; f < K; ++f) { vt[f] = G1[f][0].x; vp[f] = 0.0; }
+        for (int f = 0; f < 3; ++f) {
+            vtt[f] = -ct * G1[f][0].x - G2[f][0].x;
+            vtp[f] = 0.0;
+            vpp[f] = 0.0;
+        }
+        for (int m = 1; m <= p; ++m) {
+            const double c = tr[2 * m], sn = tr[2 * m + 1], mm = (double)m * m * rs * rs;
+            for (int f = 0; f < K; ++f) {
+                const double2 g0 = G0[f][m], g1 = G1[f][m];
+                vt[f] += 2.0 * (g1.x * c - g1.y * sn);
+                vp[f] -= 2.0 * m * (g0.x * sn + g0.y * c);
+                if (f < 3) {
+                    const double2 g2 = G2[f][m];
+                    const double er = -ct * g1.x - g2.x + mm * g0.x, ei = -ct * g1.y - g2.y + mm * g0.y;
+                    vtt[f] += 2.0 * (er * c - ei * sn);
+                    vtp[f] -= 2.0 * m * (g1.x * sn + g1.y * c);
+                    vpp[f] -= 2.0 * (double)m * m * (g0.x * c - g0.y * sn);
+                }
+            }
+        }
+        const double E = vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2];
+        const double F = vt[0] * vp[0] + vt[1] * vp[1] + vt[2] * vp[2];
+        const double Gg = vp[0] * vp[0] + vp[1] * vp[1] + vp[2] * vp[2];
+        double nx = vt[1] * vp[2] - vt[2] * vp[1], ny = vt[2] * vp[0] - vt[0] * vp[2], nz = vt[0] * vp[1] - vt[1] * vp[0];
+        const double iw = rsqrt_nr(nx * nx + ny * ny + nz * nz);
+        nx *= iw; ny *= iw; nz *= iw;
+        const double Lf = vtt[0] * nx + vtt[1] * ny + vtt[2] * nz;
+        const double Mf = vtp[0] * nx + vtp[1] * ny + vtp[2] * nz;
+        const double Nf = vpp[0] * nx + vpp[1] * ny + vpp[2] * nz;
+        const double iW2 = 1.0 / (E * Gg - F * F);
+        const long long t = node0 + l;
+        Hout[t] = -(E * Nf - 2.0 * F * Mf + Gg * Lf) * 0.5 * iW2;
+        for (int g = 0; g < NG; ++g) {
+            const double gt = vt[3 + g], gp = vp[3 + g];
+            const double a = (Gg * gt - F * gp) * iW2, b = (E * gp - F * gt) * iW2;
+            for (int c = 0; c < 3; ++c) grad[((long long)g * 3 + c) * T + t] = a * vt[c] + b * vp[c];
         }
     }
 }
@@ -1501,6 +1593,8 @@ int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
         L.wsing = dptr;
         if (upload(ctx, &dptr, rs)) return -1;
         L.rsin = dptr;
+        if (upload(ctx, &dptr, t)) return -1;
+        L.cth = dptr;
         if (upload(ctx, &dptr, trig)) return -1;
         L.trig = dptr;
         if (singular) {
@@ -1928,6 +2022,27 @@ int ehd_time_far(ehd_ctx* ctx, int far_prec, int targets_per_thread, int nchunk,
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
+}
+
+int ehd_surface(ehd_ctx* ctx, int ng, const double* gcoef_d, double* H_d, double* grad_d)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ctx->nd) EHD_FAIL(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if (ng < 0 || ng > 2) EHD_FAIL(ctx, EHD_E_ARG, "ng must be 0, 1 or 2");
+    if (!H_d || (ng > 0 && (!gcoef_d || !grad_d))) EHD_FAIL(ctx, EHD_E_ARG, "NULL pointer");
+    EHD_HIP(ctx, hipSetDevice(ctx->device));
+    const dim3 grid(ctx->nrows_p), block(kThreads);
+    if (ng == 0)
+        hipLaunchKernelGGL(k_surface<0>, grid, block, 0, ctx->stream, ctx->d_info, ctx->d_legs, ctx->d_rows_p, ctx->d_x,
+                           gcoef_d, ctx->T, H_d, grad_d);
+    else if (ng == 1)
+        hipLaunchKernelGGL(k_surface<1>, grid, block, 0, ctx->stream, ctx->d_info, ctx->d_legs, ctx->d_rows_p, ctx->d_x,
+                           gcoef_d, ctx->T, H_d, grad_d);
+    else
+        hipLaunchKernelGGL(k_surface<2>, grid, block, 0, ctx->stream, ctx->d_info, ctx->d_legs, ctx->d_rows_p, ctx->d_x,
+                           gcoef_d, ctx->T, H_d, grad_d);
+    EHD_HIP(ctx, hipGetLastError());
+    return EHD_OK;
 }
 
 int ehd_synthesize(ehd_ctx* ctx, int nfields, const double* coef_d, double* grid_d)

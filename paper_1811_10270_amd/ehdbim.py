@@ -31,7 +31,7 @@ EXPORTED = ("ehd_create", "ehd_destroy", "ehd_last_error", "ehd_grid_dims", "ehd
             "ehd_target_geometry", "ehd_sync", "ehd_wigner_d", "ehd_set_timing",
             "ehd_stage_times", "ehd_self_class_times", "ehd_set_graph", "ehd_set_far_config",
             "ehd_get_far_config", "ehd_time_far", "ehd_num_coefs", "ehd_solve_En",
-            "ehd_solve_velocity")
+            "ehd_solve_velocity", "ehd_surface")
 STAGES = ("densities", "self", "far", "combine")
 DEGREE_CLASSES = (16, 24, 32, 48)   # largest p of each self-interaction kernel class
 
@@ -76,6 +76,7 @@ def load(path: str = LIB_PATH):
     lib.ehd_get_far_config.argtypes = [vp, ip, ip]
     lib.ehd_time_far.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, dp]
     lib.ehd_num_coefs.argtypes = [vp, C.POINTER(C.c_longlong)]
+    lib.ehd_surface.argtypes = [vp, C.c_int, vp, vp, vp]
     lib.ehd_solve_En.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
                                  C.c_double, vp, ip, dp]
     lib.ehd_solve_velocity.argtypes = [vp, C.c_double, vp, C.c_int, C.c_int, C.c_int, C.c_double, vp,
@@ -207,6 +208,12 @@ class Context:
         ms = (C.c_double * 4)()
         self._check(self._lib.ehd_self_class_times(self._h, slot, ms))
         return list(ms)
+
+    def surface(self, H: torch.Tensor, gcoef: torch.Tensor | None = None, grad: torch.Tensor | None = None,
+                ng: int = 0):
+        """Mean curvature H[T] and surface gradients grad[ng][3][T] of ng packed
+        scalar fields at the target nodes."""
+        self._check(self._lib.ehd_surface(self._h, ng, _ptr(gcoef), _ptr(H), _ptr(grad)))
 
     def num_coefs(self) -> int:
         """Doubles of one packed field of the current drops."""
