@@ -230,6 +230,50 @@ int ehd_solve_En(ehd_ctx* ctx, double R, double Eu, double Eq, int far_prec, int
 int ehd_solve_velocity(ehd_ctx* ctx, double lambda, const double* fcoef_d, int far_prec, int restart,
                        int maxit, double tol, double* ucoef_d, int* iters, double* relres);
 
+/* Copy of the current drops' surface coefficients (3 packed fields, as
+ * passed to ehd_set_drops) into xcoef_d. */
+int ehd_drop_coefs(ehd_ctx* ctx, double* xcoef_d);
+
+/* Equations of state gamma(Gamma) (Sec. 1, eq. langmuir and
+ * eq. lin_eq_state), surface tension scaled by its equilibrium value:
+ *   EHD_EOS_CLEAN     gamma = 1 (Gamma unused),
+ *   EHD_EOS_LINEAR    gamma = 1 + beta (1 - Gamma),
+ *   EHD_EOS_LANGMUIR  gamma = (1 + beta ln(1 - x_s Gamma)) / (1 + beta ln(1 - x_s)). */
+enum { EHD_EOS_CLEAN = 0, EHD_EOS_LINEAR = 1, EHD_EOS_LANGMUIR = 2 };
+
+typedef struct ehd_step_params {
+    double lambda;     /* viscosity ratio mu_i / mu_0                        */
+    double R;          /* conductivity ratio sigma_i / sigma_0 (> 0)         */
+    double Q;          /* permittivity ratio eps_i / eps_0                   */
+    double CaE;        /* electric capillary number (> 0)                    */
+    double Eu, Eq;     /* applied field: uniform and quadrupole strengths    */
+    int eos;           /* EHD_EOS_*                                          */
+    double beta;       /* elasticity number (beta~ of the linear law)        */
+    double xs;         /* surface coverage of the Langmuir law, [0, 1)       */
+    double dt;         /* time step of the position update                  */
+    int far_prec;      /* far-field precision of every evaluation            */
+    int restart, maxit;
+    double tol;        /* GMRES controls of both solves (ehd_solve_En)       */
+} ehd_step_params;
+
+/* One explicit step of the method (Sec. 1, steps i-vii) for the current
+ * drops and surfactant concentration gamma_coef_d (1 packed field; NULL:
+ * Gamma = 1):
+ *   i.   E_n by ehd_solve_En (en_coef_d: initial guess in, solution out);
+ *   ii-iii. the tangential field E_t = -grad_S (phi_inf + S_L[q]) with the
+ *        charge q = [[E_n]] = (1 - 1/R) E_n (the potential of eq. BIE01
+ *        read with the sign that yields eq. E_n: E = E_inf + sum_j
+ *        int xh q / (4 pi r^3) dS);
+ *   iv.  the electric force f^E of eq. el_force (units with eps~ eps_0 = 1);
+ *   v.   gamma(Gamma) and f = 2 gamma H n - grad_S gamma (eq. interfacial_force);
+ *   vi.  the velocity u of eq. main_eq (ehd_solve_velocity with the force
+ *        density -(f / Ca_E - f^E), projected; ucoef_d: guess in, solution out);
+ *   vii. xnew_coef_d = x + dt u (forward Euler, eq. dxdtugualeu).
+ * iters (may be NULL) receives the GMRES iterations of the two solves.
+ * Synchronous.  The caller moves to the new shape with ehd_set_drops. */
+int ehd_explicit_step(ehd_ctx* ctx, const ehd_step_params* params, const double* gamma_coef_d,
+                      double* en_coef_d, double* ucoef_d, double* xnew_coef_d, int* iters);
+
 /* Host-only: Wigner small-d matrix d^n_{m m'}(beta), m, m' = -n..n, written
  * row-major to out[(m+n)*(2n+1) + (m'+n)], with
  * Y_nm(Ry(beta) v) = sum_m' d^n_{m m'}(beta) Y_nm'(v)

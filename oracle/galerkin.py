@@ -25,7 +25,7 @@ import dataclasses
 
 import numpy as np
 
-from . import all_targets, analyze_grid, far, nlon_of, self_, targets
+from . import all_targets, analyze_grid, far, gauss_legendre, nlon_of, self_, targets
 
 ROW_S, ROW_D, ROW_SL, ROW_L, ROW_KSTAR = 0, 3, 6, 7, 8
 
@@ -103,3 +103,75 @@ def solve_En_dense(s, R: float, Eu: float, Eq: float) -> np.ndarray:
 
 def solve_velocity_dense(s, lam: float, f: np.ndarray) -> np.ndarray:
     return _dense_solve(lambda v: velocity_apply(s, lam, v), velocity_rhs(s, f), unknown_mask(s, 3))
+
+
+# ---------------------------------------------------------------------------
+# One explicit step (Sec. 1, steps i-vii): E_n, tangential field, electric
+# and interfacial forces, velocity, position update.
+# ---------------------------------------------------------------------------
+def node_angles(s):
+    """(drop, theta, phi) of every target node in the global order."""
+    out = []
+    for d, p in enumerate(int(x) for x in s.p):
+        nl = nlon_of(p, s.grid_mode)
+        t, _ = gauss_legendre(p + 1)
+        for j in range(p + 1):
+            for k in range(nl):
+                out.append((d, float(np.arccos(t[j])), 2.0 * np.pi * k / nl))
+    return out
+
+
+def _drop_block(s, vec: np.ndarray, d: int, nf: int) -> np.ndarray:
+    off = np.concatenate([[0], np.cumsum([(int(p) + 1) * (int(p) + 2) for p in s.p])])
+    return vec[nf * off[d]:nf * off[d + 1]]
+
+
+def gamma_eos(G: float, eos: int, beta: float, xs: float):
+    """gamma and dgamma/dGamma (eq. langmuir, eq. lin_eq_state), gamma(1) = 1."""
+    if eos == 1:
+        return 1.0 + beta * (1.0 - G), -beta
+    if eos == 2:
+        nrm = 1.0 + beta * np.log(1.0 - xs)
+        return (1.0 + beta * np.log(1.0 - xs * G)) / nrm, -beta * xs / (1.0 - xs * G) / nrm
+    return 1.0, 0.0
+
+
+def forces(s, R, Q, CaE, Eu, Eq, en, gamma=None, eos=0, beta=0.0, xs=0.0):
+    """Force density -(f / Ca_E - f^E) and the tangential field E_t at the
+    target nodes ([3][T] each).  E_t = (I - n n) E_inf - grad_S S_L[q] with
+    q = (1 - 1/R) E_n (the potential phi_inf + S_L[q] of eq. BIE01);
+    f^E of eq. el_force with eps~ eps_0 = 1; f = 2 gamma H n - grad_S gamma."""
+    from . import sh_point, surface_point
+    q = (1.0 - 1.0 / R) * np.asarray(en, float)
+    slq = potentials(dataclasses.replace(s, sigcoef=q))[ROW_SL]
+    phq = project(s, slq[None, :], 1)
+    nodes = node_angles(s)
+    T = len(nodes)
+    ftot, Et = np.zeros((3, T)), np.zeros((3, T))
+    for i, (d, th, ph) in enumerate(nodes):
+        p = int(s.p[d])
+        xd = _drop_block(s, s.xcoef, d, 3)
+        x, n, H, gq = surface_point(p, xd, th, ph, gcoef=_drop_block(s, phq, d, 1), ng=1)
+        e = sh_point(p, _drop_block(s, en, d, 1), th, ph)[0][0]
+        einf = np.array([-Eq * x[0], -Eq * x[1], Eu + 2.0 * Eq * x[2]])
+        et = einf - (einf @ n) * n - gq[0]
+        fE = 0.5 * ((1.0 - Q / R**2) * e * e - (1.0 - Q) * (et @ et)) * n + (1.0 - Q / R) * e * et
+        G, gG = 1.0, np.zeros(3)
+        if gamma is not None and eos != 0:
+            gd = _drop_block(s, gamma, d, 1)
+            G = sh_point(p, gd, th, ph)[0][0]
+            gG = surface_point(p, xd, th, ph, gcoef=gd, ng=1)[3][0]
+        g, dg = gamma_eos(G, eos, beta, xs)
+        f = 2.0 * g * H * n - dg * gG
+        ftot[:, i] = fE - f / CaE
+        Et[:, i] = et
+    return ftot, Et
+
+
+def explicit_step(s, lam, R, Q, CaE, Eu, Eq, dt, gamma=None, eos=0, beta=0.0, xs=0.0):
+    """(E_n, u, x + dt u) as packed coefficient vectors."""
+    en = solve_En_dense(s, R, Eu, Eq)
+    ftot, _ = forces(s, R, Q, CaE, Eu, Eq, en, gamma, eos, beta, xs)
+    fc = project(s, ftot, 3)
+    u = solve_velocity_dense(s, lam, fc)
+    return en, u, s.xcoef + dt * u

@@ -2082,6 +2082,18 @@ int ehd_analyze(ehd_ctx* ctx, int nfields, const double* grid_d, double* coef_d)
     return EHD_OK;
 }
 
+int ehd_drop_coefs(ehd_ctx* ctx, double* xcoef_d)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ctx->nd) EHD_FAIL(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if (!xcoef_d) EHD_FAIL(ctx, EHD_E_ARG, "xcoef_d is NULL");
+    long long n = 0;
+    for (int d = 0; d < ctx->nd; ++d) n += (long long)(ctx->info[d].p + 1) * (ctx->info[d].p + 2);
+    EHD_HIP(ctx, hipSetDevice(ctx->device));
+    EHD_HIP(ctx, hipMemcpyAsync(xcoef_d, ctx->d_x, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, ctx->stream));
+    return EHD_OK;
+}
+
 int ehd_target_geometry(ehd_ctx* ctx, double* x_d, double* n_d)
 {
     if (!ctx) return EHD_E_ARG;

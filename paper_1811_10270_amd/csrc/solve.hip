@@ -80,6 +80,58 @@ __global__ void k_einf_dot_n(const double* __restrict__ x0, const double* __rest
 
 unsigned nblocks(long long n) { return (unsigned)((n + kT - 1) / kT); }
 
+// Interface force density of the velocity equation at the target nodes
+// (Sec. 1: eq. interfacial_force, eq. el_force with the Maxwell stress in
+// units where eps~ eps_0 = 1, and the density -(f / Ca_E - f^E) of
+// eq. main_eq):
+//   E_t  = (I - n n) E_inf(x) - grad_S S_L[q]        (tangential field)
+//   f^E  = ((1 - Q/R^2) E_n^2 - (1 - Q) |E_t|^2) / 2 n + (1 - Q/R) E_n E_t
+//   f    = 2 gamma H n - gamma'(Gamma) grad_S Gamma
+// gamma: clean 1; linear 1 + beta (1 - Gamma); Langmuir
+// (1 + beta ln(1 - x_s Gamma)) / (1 + beta ln(1 - x_s)) (scaled so that
+// gamma(1) = 1).  Inputs [c][T]: x, n, gradq = grad_S S_L[q], gradG =
+// grad_S Gamma; H, En, Gam [T] (Gam NULL: Gamma = 1).  Output ftot[3][T].
+struct ForceParams {
+    double R, Q, CaE, Eu, Eq, beta, xs;
+    int eos;
+};
+__global__ void k_forces(const double* __restrict__ x, const double* __restrict__ n, const double* __restrict__ H,
+                         const double* __restrict__ gradq, const double* __restrict__ gradG,
+                         const double* __restrict__ En, const double* __restrict__ Gam, long long T, ForceParams fp,
+                         double* __restrict__ ftot)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const double X = x[t], Y = x[T + t], Z = x[2 * T + t];
+    const double nx = n[t], ny = n[T + t], nz = n[2 * T + t];
+    // applied field E_inf = -grad phi_inf, phi_inf = -(E_u z + E_q (z^2 - (x^2 + y^2)/2))
+    const double ex = -fp.Eq * X, ey = -fp.Eq * Y, ez = fp.Eu + 2.0 * fp.Eq * Z;
+    const double en_inf = ex * nx + ey * ny + ez * nz;
+    const double tx = ex - en_inf * nx - gradq[t], ty = ey - en_inf * ny - gradq[T + t],
+                 tz = ez - en_inf * nz - gradq[2 * T + t];
+    const double e = En[t], et2 = tx * tx + ty * ty + tz * tz;
+    const double fn = 0.5 * ((1.0 - fp.Q / (fp.R * fp.R)) * e * e - (1.0 - fp.Q) * et2);
+    const double ft = (1.0 - fp.Q / fp.R) * e;
+    double g = 1.0, dg = 0.0;
+    const double G = Gam ? Gam[t] : 1.0;
+    if (fp.eos == EHD_EOS_LINEAR) {
+        g = 1.0 + fp.beta * (1.0 - G);
+        dg = -fp.beta;
+    } else if (fp.eos == EHD_EOS_LANGMUIR) {
+        const double norm = 1.0 / (1.0 + fp.beta * log(1.0 - fp.xs));
+        g = (1.0 + fp.beta * log(1.0 - fp.xs * G)) * norm;
+        dg = -fp.beta * fp.xs / (1.0 - fp.xs * G) * norm;
+    }
+    const double hn = 2.0 * g * H[t];
+    const double inv = 1.0 / fp.CaE;
+    const double gx = gradG ? gradG[t] : 0.0, gy = gradG ? gradG[T + t] : 0.0, gz = gradG ? gradG[2 * T + t] : 0.0;
+    ftot[t] = fn * nx + ft * tx - inv * (hn * nx - dg * gx);
+    ftot[T + t] = fn * ny + ft * ty - inv * (hn * ny - dg * gy);
+    ftot[2 * T + t] = fn * nz + ft * tz - inv * (hn * nz - dg * gz);
+}
+
+
+
 struct DevBuf {
     double* p = nullptr;
     ~DevBuf()
@@ -289,6 +341,78 @@ int ehd_solve_velocity(ehd_ctx* ctx, double lambda, const double* fcoef_d, int f
         return EHD_OK;
     };
     return gmres(ctx, n, A, rhs.p, ucoef_d, restart, maxit, tol, iters, relres);
+}
+
+int ehd_explicit_step(ehd_ctx* ctx, const ehd_step_params* prm, const double* gamma_coef_d, double* en_coef_d,
+                      double* ucoef_d, double* xnew_coef_d, int* iters)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ehd_ctx_ndrops(ctx)) return ehd_ctx_fail(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if (!prm || !en_coef_d || !ucoef_d || !xnew_coef_d) return ehd_ctx_fail(ctx, EHD_E_ARG, "NULL argument");
+    if (!(prm->CaE > 0.0) || !(prm->R > 0.0) || !std::isfinite(prm->dt) || !std::isfinite(prm->Q))
+        return ehd_ctx_fail(ctx, EHD_E_ARG, "CaE and R must be > 0, Q and dt finite");
+    if (prm->eos != EHD_EOS_CLEAN && prm->eos != EHD_EOS_LINEAR && prm->eos != EHD_EOS_LANGMUIR)
+        return ehd_ctx_fail(ctx, EHD_E_ARG, "invalid eos");
+    if (prm->eos == EHD_EOS_LANGMUIR && !(prm->xs >= 0.0 && prm->xs < 1.0))
+        return ehd_ctx_fail(ctx, EHD_E_ARG, "Langmuir coverage x_s must be in [0, 1)");
+    int rc;
+    int it_en = 0, it_u = 0;
+    double rr;
+    // i. E_n
+    if ((rc = ehd_solve_En(ctx, prm->R, prm->Eu, prm->Eq, prm->far_prec, prm->restart, prm->maxit, prm->tol,
+                           en_coef_d, &it_en, &rr)))
+        return rc;
+    long long T, nc;
+    if ((rc = ehd_num_targets(ctx, &T)) || (rc = ehd_num_coefs(ctx, &nc))) return rc;
+    hipStream_t st = ehd_ctx_stream(ctx);
+    DevBuf q, val, geo, H, gq, gG, En, Gm, ft, fc;
+    SOLVE_HIP(hipMalloc(&q.p, sizeof(double) * (size_t)nc));
+    SOLVE_HIP(hipMalloc(&val.p, sizeof(double) * (size_t)T));
+    SOLVE_HIP(hipMalloc(&geo.p, sizeof(double) * (size_t)6 * T));
+    SOLVE_HIP(hipMalloc(&H.p, sizeof(double) * (size_t)T));
+    SOLVE_HIP(hipMalloc(&gq.p, sizeof(double) * (size_t)3 * T));
+    SOLVE_HIP(hipMalloc(&En.p, sizeof(double) * (size_t)T));
+    SOLVE_HIP(hipMalloc(&ft.p, sizeof(double) * (size_t)3 * T));
+    SOLVE_HIP(hipMalloc(&fc.p, sizeof(double) * (size_t)3 * nc));
+    // ii-iii. tangential field: the surface potential phi_inf + S_L[q],
+    // q = [[E_n]] = (1 - 1/R) E_n, projected; its surface gradient
+    hipLaunchKernelGGL(k_axpby, dim3(nblocks(nc)), dim3(kT), 0, st, 1.0 - 1.0 / prm->R, en_coef_d, 0.0, q.p, nc);
+    SOLVE_HIP(hipGetLastError());
+    if ((rc = ehd_layer_potentials(ctx, nullptr, nullptr, q.p, EHD_LAP_SL, prm->far_prec, val.p, nullptr))) return rc;
+    if ((rc = ehd_analyze(ctx, 1, val.p, q.p))) return rc;
+    if ((rc = ehd_surface(ctx, 1, q.p, H.p, gq.p))) return rc;
+    if ((rc = ehd_target_geometry(ctx, geo.p, geo.p + 3 * T))) return rc;
+    if ((rc = ehd_synthesize(ctx, 1, en_coef_d, En.p))) return rc;
+    const double* gG_ptr = nullptr;
+    const double* Gm_ptr = nullptr;
+    if (gamma_coef_d && prm->eos != EHD_EOS_CLEAN) {
+        SOLVE_HIP(hipMalloc(&gG.p, sizeof(double) * (size_t)3 * T));
+        SOLVE_HIP(hipMalloc(&Gm.p, sizeof(double) * (size_t)T));
+        if ((rc = ehd_surface(ctx, 1, gamma_coef_d, H.p, gG.p))) return rc;
+        if ((rc = ehd_synthesize(ctx, 1, gamma_coef_d, Gm.p))) return rc;
+        gG_ptr = gG.p;
+        Gm_ptr = Gm.p;
+    }
+    // iv-v. forces at the nodes, projected
+    ForceParams fp{prm->R, prm->Q, prm->CaE, prm->Eu, prm->Eq, prm->beta, prm->xs, prm->eos};
+    hipLaunchKernelGGL(k_forces, dim3(nblocks(T)), dim3(kT), 0, st, geo.p, geo.p + 3 * T, H.p, gq.p, gG_ptr, En.p,
+                       Gm_ptr, T, fp, ft.p);
+    SOLVE_HIP(hipGetLastError());
+    if ((rc = ehd_analyze(ctx, 3, ft.p, fc.p))) return rc;
+    // vi. velocity
+    if ((rc = ehd_solve_velocity(ctx, prm->lambda, fc.p, prm->far_prec, prm->restart, prm->maxit, prm->tol, ucoef_d,
+                                 &it_u, &rr)))
+        return rc;
+    // vii. x + dt u
+    if ((rc = ehd_drop_coefs(ctx, xnew_coef_d))) return rc;
+    hipLaunchKernelGGL(k_axpby, dim3(nblocks(3 * nc)), dim3(kT), 0, st, prm->dt, ucoef_d, 1.0, xnew_coef_d, 3 * nc);
+    SOLVE_HIP(hipGetLastError());
+    SOLVE_HIP(hipStreamSynchronize(st));
+    if (iters) {
+        iters[0] = it_en;
+        iters[1] = it_u;
+    }
+    return EHD_OK;
 }
 
 }  // extern "C"

@@ -20,6 +20,7 @@ ALL_KINDS = 31
 METRIC_KINDS = STOKES_SL | STOKES_DL | LAP_SL | LAP_DL
 FAR_FP64, FAR_FP32C = 0, 1
 GRID_PAPER, GRID_2P = 0, 1
+EOS_CLEAN, EOS_LINEAR, EOS_LANGMUIR = 0, 1, 2
 MAX_P = 48
 MAX_Q = 160
 
@@ -31,11 +32,19 @@ EXPORTED = ("ehd_create", "ehd_destroy", "ehd_last_error", "ehd_grid_dims", "ehd
             "ehd_target_geometry", "ehd_sync", "ehd_wigner_d", "ehd_set_timing",
             "ehd_stage_times", "ehd_self_class_times", "ehd_set_graph", "ehd_set_far_config",
             "ehd_get_far_config", "ehd_time_far", "ehd_num_coefs", "ehd_solve_En",
-            "ehd_solve_velocity", "ehd_surface")
+            "ehd_solve_velocity", "ehd_surface", "ehd_drop_coefs", "ehd_explicit_step")
 STAGES = ("densities", "self", "far", "combine")
 DEGREE_CLASSES = (16, 24, 32, 48)   # largest p of each self-interaction kernel class
 
 _lib = None
+
+
+class StepParams(C.Structure):
+    """ehd_step_params (include/ehdbim.h)."""
+    _fields_ = [("lam", C.c_double), ("R", C.c_double), ("Q", C.c_double), ("CaE", C.c_double),
+                ("Eu", C.c_double), ("Eq", C.c_double), ("eos", C.c_int), ("beta", C.c_double),
+                ("xs", C.c_double), ("dt", C.c_double), ("far_prec", C.c_int), ("restart", C.c_int),
+                ("maxit", C.c_int), ("tol", C.c_double)]
 
 
 class EhdError(RuntimeError):
@@ -77,6 +86,8 @@ def load(path: str = LIB_PATH):
     lib.ehd_time_far.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, dp]
     lib.ehd_num_coefs.argtypes = [vp, C.POINTER(C.c_longlong)]
     lib.ehd_surface.argtypes = [vp, C.c_int, vp, vp, vp]
+    lib.ehd_drop_coefs.argtypes = [vp, vp]
+    lib.ehd_explicit_step.argtypes = [vp, C.POINTER(StepParams), vp, vp, vp, vp, ip]
     lib.ehd_solve_En.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
                                  C.c_double, vp, ip, dp]
     lib.ehd_solve_velocity.argtypes = [vp, C.c_double, vp, C.c_int, C.c_int, C.c_int, C.c_double, vp,
@@ -214,6 +225,23 @@ class Context:
         """Mean curvature H[T] and surface gradients grad[ng][3][T] of ng packed
         scalar fields at the target nodes."""
         self._check(self._lib.ehd_surface(self._h, ng, _ptr(gcoef), _ptr(H), _ptr(grad)))
+
+    def drop_coefs(self, x: torch.Tensor):
+        """Copy of the current drops' surface coefficients (3 packed fields)."""
+        self._check(self._lib.ehd_drop_coefs(self._h, _ptr(x)))
+
+    def explicit_step(self, lam: float, R: float, Q: float, CaE: float, Eu: float, Eq: float, dt: float,
+                      en: torch.Tensor, u: torch.Tensor, xnew: torch.Tensor, gamma: torch.Tensor | None = None,
+                      eos: int = EOS_CLEAN, beta: float = 0.0, xs: float = 0.0, far_prec: int = FAR_FP64,
+                      restart: int = 30, maxit: int = 200, tol: float = 1e-12):
+        """One explicit step (ehd_explicit_step).  en (1 field) and u (3 fields)
+        hold initial guesses and receive E_n and the velocity; xnew receives
+        x + dt u.  Returns the GMRES iterations (E_n, velocity)."""
+        prm = StepParams(lam, R, Q, CaE, Eu, Eq, eos, beta, xs, dt, far_prec, restart, maxit, tol)
+        its = (C.c_int * 2)()
+        self._check(self._lib.ehd_explicit_step(self._h, C.byref(prm), _ptr(gamma), _ptr(en), _ptr(u),
+                                                _ptr(xnew), its))
+        return its[0], its[1]
 
     def num_coefs(self) -> int:
         """Doubles of one packed field of the current drops."""

@@ -130,3 +130,40 @@ def test_solver_argument_errors(E):
     with pytest.raises(E.EhdError):
         ctx.solve_En(-1.0, 1.0, 0.0, en)
     ctx.close()
+
+
+@pytest.mark.parametrize("eos", [0, 2])
+def test_explicit_step_matches_oracle(E, eos):
+    """One explicit step (E_n, E_t, forces, velocity, x update) on two
+    deformed drops with a non-uniform surfactant, against the oracle's step."""
+    import torch
+    s = W.suspension(2, [5], side=3.5, seed=31, amp=0.08, gap=0.3)
+    rng = np.random.default_rng(32)
+    gam = np.zeros(len(s.sigcoef))
+    off = 0
+    for p in (int(x) for x in s.p):
+        gam[off] = math.sqrt(4 * math.pi)
+        for n in range(1, p + 1):
+            for m in range(n + 1):
+                k = off + 2 * (n * (n + 1) // 2 + m)
+                gam[k] = 0.05 * rng.standard_normal() / n**2
+                if m:
+                    gam[k + 1] = 0.05 * rng.standard_normal() / n**2
+        off += (p + 1) * (p + 2)
+    prm = dict(lam=2.0, R=0.5, Q=2.0, CaE=0.3, Eu=1.0, Eq=0.2, dt=0.01)
+    kw = dict(gamma=gam, eos=eos, beta=0.5, xs=0.3) if eos else {}
+    ref_en, ref_u, ref_x = G.explicit_step(s, prm["lam"], prm["R"], prm["Q"], prm["CaE"], prm["Eu"], prm["Eq"],
+                                           prm["dt"], **kw)
+    ctx, dev = _ctx(E, s)
+    nc = ctx.num_coefs()
+    en = torch.zeros(nc, dtype=torch.float64, device=dev)
+    u = torch.zeros(3 * nc, dtype=torch.float64, device=dev)
+    xn = torch.zeros(3 * nc, dtype=torch.float64, device=dev)
+    gdev = torch.from_numpy(gam).to(dev) if eos else None
+    its = ctx.explicit_step(prm["lam"], prm["R"], prm["Q"], prm["CaE"], prm["Eu"], prm["Eq"], prm["dt"], en, u, xn,
+                            gamma=gdev, eos=eos, beta=0.5, xs=0.3, tol=1e-13)
+    en, u, xn = en.cpu().numpy(), u.cpu().numpy(), xn.cpu().numpy()
+    ctx.close()
+    e1, e2, e3 = rel(en, ref_en), rel(u, ref_u), rel(xn, ref_x)
+    say("explicit step eos", eos, "iters", its, "err E_n", e1, "u", e2, "x", e3)
+    assert e1 < TOL and e2 < TOL and e3 < TOL

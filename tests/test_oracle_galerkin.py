@@ -70,3 +70,39 @@ def test_dense_solution_satisfies_the_system():
     res = G.En_apply(s, R, en) - G.En_rhs(s, R, 1.0, 0.2)
     assert np.abs(res[G.unknown_mask(s, 1)]).max() < 1e-12
     assert np.all(en[~G.unknown_mask(s, 1)] == 0.0)
+
+
+@pytest.mark.parametrize("R", [0.5, 3.0])
+def test_tangential_field_on_sphere(R):
+    """Unit sphere in a uniform field: the interior field is uniform,
+    3/(R+2) E_u z, and E_t is its tangential part."""
+    p = 4
+    s = make_susp(p, sphere_x(p), q_self=8)
+    en = G.solve_En_dense(s, R, 1.0, 0.0)
+    _, Et = G.forces(s, R, 2.0, 1.0, 1.0, 0.0, en)
+    for i, (d, th, ph) in enumerate(G.node_angles(s)):
+        n = np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+        ez = np.array([0.0, 0.0, 1.0])
+        assert np.abs(Et[:, i] - 3.0 / (R + 2) * (ez - math.cos(th) * n)).max() < 1e-12
+
+
+def test_clean_sphere_without_field_stays_at_rest():
+    p = 4
+    s = make_susp(p, sphere_x(p, R=1.3), q_self=8)
+    en, u, xnew = G.explicit_step(s, 2.0, 0.5, 2.0, 0.4, 0.0, 0.0, 0.05)
+    assert np.abs(en).max() < 1e-13 and np.abs(u).max() < 1e-12
+    assert np.abs(xnew - s.xcoef).max() < 1e-13
+
+
+def test_uniform_surfactant_matches_clean_drop():
+    """Gamma = 1 everywhere: gamma = 1 and grad_S gamma = 0 for every law."""
+    s = W.two_drops(3, seed=21, gap=0.4)
+    g1 = np.zeros(len(s.sigcoef))
+    off = 0
+    for p in (int(x) for x in s.p):
+        g1[off] = math.sqrt(4 * math.pi)
+        off += (p + 1) * (p + 2)
+    en = G.solve_En_dense(s, 0.5, 1.0, 0.0)
+    a, _ = G.forces(s, 0.5, 2.0, 0.3, 1.0, 0.0, en)
+    b, _ = G.forces(s, 0.5, 2.0, 0.3, 1.0, 0.0, en, gamma=g1, eos=2, beta=0.5, xs=0.3)
+    assert np.abs(a - b).max() < 1e-12
