@@ -117,11 +117,13 @@ def bench_solve(args, torch, E, W, dev):
     grid = torch.empty(nf, T, dtype=torch.float64, device=dev)
     proj = torch.empty(nf * nc, dtype=torch.float64, device=dev)
 
+    tol = 1e-12 if far_prec == E.FAR_FP64 else 1e-6
+
     def solve():
         x.zero_()
         if args.solve == "en":
-            return ctx.solve_En(0.5, 1.0, 0.0, x, far_prec=far_prec, tol=1e-12)
-        return ctx.solve_velocity(2.0, f, x, far_prec=far_prec, tol=1e-12)
+            return ctx.solve_En(0.5, 1.0, 0.0, x, far_prec=far_prec, tol=tol)
+        return ctx.solve_velocity(2.0, f, x, far_prec=far_prec, tol=tol)
 
     def matvec():
         if args.solve == "en":
@@ -150,7 +152,7 @@ def bench_solve(args, torch, E, W, dev):
     ctx.close()
     res = {
         "metric": "Galerkin GMRES solve (" + ("E_n, adjoint double layer" if args.solve == "en"
-                                               else "velocity, Stokes double layer") + "), tol 1e-12",
+                                               else "velocity, Stokes double layer") + "), tol %g" % tol,
         "value": 1.0 / dt, "unit": "solves/s", "n_gpus": 1, "steps": K, "warmup": max(args.warmup, 1),
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if far_prec == E.FAR_FP64 else "f64+f32", "data": "synthetic",
@@ -159,6 +161,50 @@ def bench_solve(args, torch, E, W, dev):
                    "R" if args.solve == "en" else "lambda": 0.5 if args.solve == "en" else 2.0},
         "iterations": its, "relres": rr, "matvec_ms": mv * 1e3,
         "matvec_share": its * mv / dt,
+    }
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def bench_step(args, torch, E, W, dev):
+    """One explicit step per timed iteration, each from zero initial guesses."""
+    s = W.WORKLOADS[args.workload](args.grid_mode)
+    far_prec = E.FAR_FP32C if args.far_prec == "fp32c" else E.FAR_FP64
+    ctx = E.Context(0)
+    ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+    nc = ctx.num_coefs()
+    en = torch.zeros(nc, dtype=torch.float64, device=dev)
+    u = torch.zeros(3 * nc, dtype=torch.float64, device=dev)
+    xn = torch.zeros(3 * nc, dtype=torch.float64, device=dev)
+
+    # the FP32 far field perturbs the operator at the 1e-7 level: GMRES stops there
+    tol = 1e-12 if far_prec == E.FAR_FP64 else 1e-6
+
+    def step():
+        en.zero_()
+        u.zero_()
+        return ctx.explicit_step(2.0, 0.5, 2.0, 0.3, 1.0, 0.0, 0.01, en, u, xn, far_prec=far_prec, tol=tol)
+
+    for _ in range(max(args.warmup, 1)):
+        its = step()
+    K = args.steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        its = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / K
+    ctx.close()
+    res = {
+        "metric": "explicit time step (E_n GMRES + forces + velocity GMRES + x update), tol %g" % tol,
+        "value": 1.0 / dt, "unit": "steps/s", "n_gpus": 1, "steps": K, "warmup": max(args.warmup, 1),
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if far_prec == E.FAR_FP64 else "f64+f32", "data": "synthetic",
+        "config": {"workload": args.workload, "ndrops": s.ndrops, "p": sorted(set(int(v) for v in s.p)),
+                   "targets": ctx.ntargets, "lambda": 2.0, "R": 0.5, "Q": 2.0, "CaE": 0.3, "E_u": 1.0,
+                   "eos": "clean", "dt": 0.01,
+                   "far_prec": "fp64" if far_prec == E.FAR_FP64 else "fp32c"},
+        "gmres_iterations": {"E_n": its[0], "velocity": its[1]},
     }
     print(json.dumps(res), flush=True)
     return 0
@@ -185,6 +231,10 @@ def main(argv=None):
                     help="time the Galerkin GMRES solve (E_n with R = 0.5, E_u = 1; velocity with "
                          "lambda = 2 for the workload's f) instead of the evaluation; default workload "
                          "two_drops_p32, FP64 far field")
+    ap.add_argument("--step", action="store_true",
+                    help="time one explicit step of the method (E_n solve, forces, velocity solve, "
+                         "position update) on two_drops_p32 with lambda = 2, R = 0.5, Q = 2, uniform "
+                         "field E_u = 1, Ca_E = 0.3, clean drops, dt = 0.01")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy a MIB-mebibyte device buffer once (a plain "
                          "copy kernel of known size, to scale hardware byte counters)")
@@ -204,9 +254,11 @@ def main(argv=None):
         return 1
     dev = torch.device("cuda", 0)
     if args.workload is None:
-        args.workload = "two_drops_p32" if args.solve else "batched_64_mixed_p"
+        args.workload = "two_drops_p32" if (args.solve or args.step) else "batched_64_mixed_p"
     if args.far_prec is None:
-        args.far_prec = "fp64" if args.solve else "fp32c"
+        args.far_prec = "fp64" if (args.solve or args.step) else "fp32c"
+    if args.step:
+        return bench_step(args, torch, E, W, dev)
     if args.solve:
         return bench_solve(args, torch, E, W, dev)
     s = W.WORKLOADS[args.workload](args.grid_mode)

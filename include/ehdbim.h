@@ -213,6 +213,8 @@ int ehd_time_far(ehd_ctx* ctx, int far_prec, int targets_per_thread, int nchunk,
  * relative residual; not converging within maxit is not an error (check
  * *relres).  The solution vector holds the initial guess on entry (zeros
  * for none).  Synchronous; the solver allocates its own workspace.
+ * With EHD_FAR_FP32C the operator carries the FP32 far field's rounding
+ * (relative 1e-7): residuals stagnate there, so tol should be >= 1e-6. 
  *
  * ehd_solve_En: the normal electric field E_n (1 packed field, en_coef_d) of
  *   (1/2)(E_n, Y) - (R-1)/(R+1) sum_j (K*_j[E_n], Y) = R/(R+1) (E_inf . n, Y)
