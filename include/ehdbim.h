@@ -145,9 +145,10 @@ int ehd_synthesize(ehd_ctx* ctx, int nfields, const double* coef_d, double* grid
  * H_d[T] the mean curvature H = (1/2) div_S n (n outward: 1/a on a sphere
  * of radius a) and, for ng in {0, 1, 2} packed scalar fields gcoef_d (ng
  * fields per drop), grad_d[g][3][T] their surface gradients
- * (I - n n) grad g.  From the SH derivatives of x and g up to second order;
- * gcoef_d and grad_d may be NULL when ng = 0. */
-int ehd_surface(ehd_ctx* ctx, int ng, const double* gcoef_d, double* H_d, double* grad_d);
+ * (I - n n) grad g and, if lap_d is not NULL, lap_d[g][T] their
+ * Laplace-Beltrami values div_S grad_S g.  From the SH derivatives of x and
+ * g up to second order; gcoef_d and grad_d may be NULL when ng = 0. */
+int ehd_surface(ehd_ctx* ctx, int ng, const double* gcoef_d, double* H_d, double* grad_d, double* lap_d);
 
 /* Galerkin analysis (Sec. 2, the inner product before eq. BIM_galerkin):
  * coef_d receives (y, Y_nm) = int_{S^2} y conj(Y_nm) ds for n <= p, m >= 0,
@@ -231,6 +232,20 @@ int ehd_solve_En(ehd_ctx* ctx, double R, double Eu, double Eq, int far_prec, int
                  double tol, double* en_coef_d, int* iters, double* relres);
 int ehd_solve_velocity(ehd_ctx* ctx, double lambda, const double* fcoef_d, int far_prec, int restart,
                        int maxit, double tol, double* ucoef_d, int* iters, double* relres);
+
+/* Implicit surfactant-diffusion solve (Sec. 2.2, the implicit half of the
+ * IMEX step of Algorithm 1: (I - dt/(2 Pe) Lap_S) Gamma = b), in Galerkin
+ * form on the current drops: c - kappa (Lap_S Gamma[c], Y) = b for all
+ * Y = Y_nm, n <= p, with kappa = dt / (2 Pe) >= 0, the Laplace-Beltrami
+ * operator of each drop's surface (ehd_surface) and the projection
+ * ehd_analyze.  rhs_d, gamma_d: 1 packed field; gamma_d holds the initial
+ * guess on entry and receives the solution.  precond != 0: right
+ * preconditioning by diag(1 + kappa n(n+1)), the operator's inverse on the
+ * unit sphere (the spherical-harmonic eigenfunction preconditioner of
+ * Sec. 2.2).  GMRES controls and outputs as for ehd_solve_En (residual of
+ * the unpreconditioned system).  Synchronous. */
+int ehd_solve_surfactant(ehd_ctx* ctx, double kappa, const double* rhs_d, int precond, int restart, int maxit,
+                         double tol, double* gamma_d, int* iters, double* relres);
 
 /* Copy of the current drops' surface coefficients (3 packed fields, as
  * passed to ehd_set_drops) into xcoef_d. */

@@ -111,14 +111,19 @@ def geom_point(p: int, xcoef: np.ndarray, theta: float, phi: float):
     return x, n, float(J[0])
 
 
-def surface_point(p: int, xcoef: np.ndarray, theta: float, phi: float, gcoef=None, ng: int = 0):
+def surface_point(p: int, xcoef: np.ndarray, theta: float, phi: float, gcoef=None, ng: int = 0,
+                  lap: bool = False):
     """x(3), outward normal n(3), mean curvature H = (1/2) div_S n and the
-    surface gradients (3 each) of ng scalar fields, at one parameter point."""
+    surface gradients (3 each) of ng scalar fields, at one parameter point.
+    With lap=True also their Laplace-Beltrami values (a fifth result)."""
     xcoef = _f64(xcoef)
     gc = _f64(gcoef) if ng else np.zeros(2)
-    out = np.zeros(7 + 3 * ng)
+    out = np.zeros(7 + 4 * ng)
     _load().ora_surface_point(p, _d(xcoef), ng, _d(gc), float(theta), float(phi), _d(out))
-    return out[0:3], out[3:6], float(out[6]), out[7:].reshape(ng, 3)
+    g = out[7:].reshape(ng, 4)
+    if lap:
+        return out[0:3], out[3:6], float(out[6]), g[:, :3].copy(), g[:, 3].copy()
+    return out[0:3], out[3:6], float(out[6]), g[:, :3].copy()
 
 
 def synth_grid(p: int, coef: np.ndarray, Q: int, grid_mode: int = 0, nf: int = 1):

@@ -567,8 +567,10 @@ static void leg_eval2(int p, double t, double* Q, double* dQ, double* d2Q)
 /* Surface quantities at the point (theta, phi) of a drop x (3 fields) and of
  * ng scalar fields g (packed, degree p):
  *   out[0..2] x, out[3..5] n (outward unit normal), out[6] mean curvature
- *   H = (1/2) div_S n (Sec. 1, after eq. interfacial_force), out[7 + 3 g ..]
- *   the surface gradient of field g.
+ *   H = (1/2) div_S n (Sec. 1, after eq. interfacial_force), out[7 + 4 g ..]
+ *   the surface gradient of field g (3) and its Laplace-Beltrami (1),
+ *   Lap_S g = g^{ij} (g_{,ij} - x_{,ij} . grad_S g), the trace of the
+ *   surface Hessian (Christoffel terms x_{,ij} . x^{,k} g_{,k}).
  * With x_a, x_ab the parameter derivatives, E, F, G and L, M, N the first
  * and second fundamental forms (L = x_tt . n, ...), W^2 = EG - F^2:
  *   H = -(E N - 2 F M + G L) / (2 W^2)   (positive on a sphere with outward n),
@@ -586,9 +588,8 @@ void ora_surface_point(int p, const double* xcoef, int ng, const double* gcoef, 
     double t = cos(theta), s = sin(theta);
     leg_eval2(p, t, Q, dQ, d2Q);
     int nf = 3 + ng;
-    double v[64], vt[64], vp[64], vtt[3], vtp[3], vpp[3];
-    for (int f = 0; f < nf; ++f) { v[f] = vt[f] = vp[f] = 0.0; }
-    for (int c = 0; c < 3; ++c) { vtt[c] = vtp[c] = vpp[c] = 0.0; }
+    double v[64], vt[64], vp[64], vtt[64], vtp[64], vpp[64];
+    for (int f = 0; f < nf; ++f) { v[f] = vt[f] = vp[f] = 0.0; vtt[f] = vtp[f] = vpp[f] = 0.0; }
     for (int m = 0; m <= p; ++m) {
         double cm = cos(m * phi), sm_ = sin(m * phi);
         double mult = (m == 0) ? 1.0 : 2.0;
@@ -607,11 +608,9 @@ void ora_surface_point(int p, const double* xcoef, int ng, const double* gcoef, 
                 v[f] += mult * re * P;
                 vt[f] += mult * re * dP;
                 vp[f] += mult * (-(double)m) * im * P;   /* d/dphi: Re(i m c e^{i m phi}) */
-                if (f < 3) {
-                    vtt[f] += mult * re * d2P;
-                    vtp[f] += mult * (-(double)m) * im * dP;
-                    vpp[f] += mult * (-(double)m * m) * re * P;
-                }
+                vtt[f] += mult * re * d2P;
+                vtp[f] += mult * (-(double)m) * im * dP;
+                vpp[f] += mult * (-(double)m * m) * re * P;
             }
         }
     }
@@ -630,7 +629,18 @@ void ora_surface_point(int p, const double* xcoef, int ng, const double* gcoef, 
     for (int g = 0; g < ng; ++g) {
         double gt = vt[3 + g], gp = vp[3 + g];
         double a = (G * gt - F * gp) / W2, b = (E * gp - F * gt) / W2;
-        for (int c = 0; c < 3; ++c) out[7 + 3 * g + c] = a * vt[c] + b * vp[c];
+        double gr[3];
+        for (int c = 0; c < 3; ++c) {
+            gr[c] = a * vt[c] + b * vp[c];
+            out[7 + 4 * g + c] = gr[c];
+        }
+        double htt = vtt[3 + g], htp = vtp[3 + g], hpp = vpp[3 + g];
+        for (int c = 0; c < 3; ++c) {
+            htt -= vtt[c] * gr[c];
+            htp -= vtp[c] * gr[c];
+            hpp -= vpp[c] * gr[c];
+        }
+        out[7 + 4 * g + 3] = (G * htt - 2.0 * F * htp + E * hpp) / W2;
     }
     free(Q); free(dQ); free(d2Q);
 }

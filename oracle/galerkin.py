@@ -175,3 +175,26 @@ def explicit_step(s, lam, R, Q, CaE, Eu, Eq, dt, gamma=None, eos=0, beta=0.0, xs
     fc = project(s, ftot, 3)
     u = solve_velocity_dense(s, lam, fc)
     return en, u, s.xcoef + dt * u
+
+
+# ---------------------------------------------------------------------------
+# Implicit surfactant diffusion (Sec. 2.2, Algorithm 1): (I - kappa Lap_S) Gamma = b
+# in Galerkin form, kappa = dt / (2 Pe).
+# ---------------------------------------------------------------------------
+def lap_values(s, c: np.ndarray) -> np.ndarray:
+    """Laplace-Beltrami of the packed field c at every target node."""
+    from . import surface_point
+    out = []
+    for d, th, ph in node_angles(s):
+        p = int(s.p[d])
+        out.append(surface_point(p, _drop_block(s, s.xcoef, d, 3), th, ph,
+                                 gcoef=_drop_block(s, c, d, 1), ng=1, lap=True)[4][0])
+    return np.array(out)
+
+
+def surfactant_apply(s, kappa: float, c: np.ndarray) -> np.ndarray:
+    return c - kappa * project(s, lap_values(s, c)[None, :], 1)
+
+
+def solve_surfactant_dense(s, kappa: float, b: np.ndarray) -> np.ndarray:
+    return _dense_solve(lambda v: surfactant_apply(s, kappa, v), np.asarray(b, float), unknown_mask(s, 1))

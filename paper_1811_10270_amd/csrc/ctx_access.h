@@ -10,6 +10,7 @@
 hipStream_t ehd_ctx_stream(const ehd_ctx* ctx);
 int ehd_ctx_device(const ehd_ctx* ctx);
 int ehd_ctx_ndrops(const ehd_ctx* ctx);
+int ehd_ctx_drop_p(const ehd_ctx* ctx, int d);
 // Record `msg` as the context's last error and return `code`.
 int ehd_ctx_fail(ehd_ctx* ctx, int code, const char* msg);
 

@@ -196,18 +196,21 @@ __global__ __launch_bounds__(kThreads) void k_synth(const DropInfo* __restrict__
 // With x_t, x_p, x_tt, x_tp, x_pp the parameter derivatives of x, E F G and
 // L M N the fundamental forms and W^2 = EG - F^2:
 //   H = -(E N - 2 F M + G L) / (2 W^2),
-//   grad_S g = ((G g_t - F g_p) x_t + (E g_p - F g_t) x_p) / W^2.
-// Outputs H[T], grad[g][3][T].
+//   grad_S g = ((G g_t - F g_p) x_t + (E g_p - F g_t) x_p) / W^2,
+//   Lap_S g = (G h_tt - 2 F h_tp + E h_pp) / W^2,  h_ab = g_ab - x_ab . grad_S g
+// (the trace of the surface Hessian).  Outputs H[T], grad[g][3][T] and, if
+// lap is not NULL, lap[g][T].
 template <int NG>
 __global__ __launch_bounds__(kThreads) void k_surface(const DropInfo* __restrict__ drops,
                                                       const LegTab* __restrict__ legs,
                                                       const int2* __restrict__ rows,
                                                       const double* __restrict__ xcoef,
                                                       const double* __restrict__ gcoef, long long T,
-                                                      double* __restrict__ Hout, double* __restrict__ grad)
+                                                      double* __restrict__ Hout, double* __restrict__ grad,
+                                                      double* __restrict__ lap)
 {
     constexpr int K = 3 + NG;
-    __shared__ double2 G0[K][EHD_MAX_P + 1], G1[K][EHD_MAX_P + 1], G2[3][EHD_MAX_P + 1];
+    __shared__ double2 G0[K][EHD_MAX_P + 1], G1[K][EHD_MAX_P + 1], G2[K][EHD_MAX_P + 1];
     const int2 r = rows[blockIdx.x];
     const DropInfo D = drops[r.x];
     const LegTab L = legs[D.leg_pp];
@@ -229,7 +232,7 @@ __global__ __launch_bounds__(kThreads) void k_surface(const DropInfo* __restrict
         }
         G0[f][m] = make_double2(a0, b0);
         G1[f][m] = make_double2(a1, b1);
-        if (f < 3) G2[f][m] = make_double2(a2, b2);
+        G2[f][m] = make_double2(a2, b2);
     }
     __syncthreads();
     const double rs = L.rsin[i];                           // 1 / sin theta
@@ -237,9 +240,10 @@ __global__ __launch_bounds__(kThreads) void k_surface(const DropInfo* __restrict
     const long long node0 = D.toff + (long long)i * L.nlon;
     for (int l = threadIdx.x; l < L.nlon; l += blockDim.x) {
         const double* tr = L.trig + (long long)l * (p + 1) * 2;
-        double vt[K], vp[K], vtt[3], vtp[3], vpp[3];
-        for (int f = 0; f < K; ++f) { vt[f] = G1[f][0].x; vp[f] = 0.0; }
-        for (int f = 0; f < 3; ++f) {
+        double vt[K], vp[K], vtt[K], vtp[K], vpp[K];
+        for (int f = 0; f < K; ++f) {
+            vt[f] = G1[f][0].x;
+            vp[f] = 0.0;
             vtt[f] = -ct * G1[f][0].x - G2[f][0].x;
             vtp[f] = 0.0;
             vpp[f] = 0.0;
@@ -250,13 +254,11 @@ __global__ __launch_bounds__(kThreads) void k_surface(const DropInfo* __restrict
                 const double2 g0 = G0[f][m], g1 = G1[f][m];
                 vt[f] += 2.0 * (g1.x * c - g1.y * sn);
                 vp[f] -= 2.0 * m * (g0.x * sn + g0.y * c);
-                if (f < 3) {
-                    const double2 g2 = G2[f][m];
-                    const double er = -ct * g1.x - g2.x + mm * g0.x, ei = -ct * g1.y - g2.y + mm * g0.y;
-                    vtt[f] += 2.0 * (er * c - ei * sn);
-                    vtp[f] -= 2.0 * m * (g1.x * sn + g1.y * c);
-                    vpp[f] -= 2.0 * (double)m * m * (g0.x * c - g0.y * sn);
-                }
+                const double2 g2 = G2[f][m];
+                const double er = -ct * g1.x - g2.x + mm * g0.x, ei = -ct * g1.y - g2.y + mm * g0.y;
+                vtt[f] += 2.0 * (er * c - ei * sn);
+                vtp[f] -= 2.0 * m * (g1.x * sn + g1.y * c);
+                vpp[f] -= 2.0 * (double)m * m * (g0.x * c - g0.y * sn);
             }
         }
         const double E = vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2];
@@ -274,7 +276,15 @@ __global__ __launch_bounds__(kThreads) void k_surface(const DropInfo* __restrict
         for (int g = 0; g < NG; ++g) {
             const double gt = vt[3 + g], gp = vp[3 + g];
             const double a = (Gg * gt - F * gp) * iW2, b = (E * gp - F * gt) * iW2;
-            for (int c = 0; c < 3; ++c) grad[((long long)g * 3 + c) * T + t] = a * vt[c] + b * vp[c];
+            double htt = vtt[3 + g], htp = vtp[3 + g], hpp = vpp[3 + g];
+            for (int c = 0; c < 3; ++c) {
+                const double gr = a * vt[c] + b * vp[c];
+                grad[((long long)g * 3 + c) * T + t] = gr;
+                htt -= vtt[c] * gr;
+                htp -= vtp[c] * gr;
+                hpp -= vpp[c] * gr;
+            }
+            if (lap) lap[(long long)g * T + t] = (Gg * htt - 2.0 * F * htp + E * hpp) * iW2;
         }
     }
 }
@@ -1433,6 +1443,7 @@ static const std::array<Far32Launch, 32>& far32_table()
 hipStream_t ehd_ctx_stream(const ehd_ctx* ctx) { return ctx->stream; }
 int ehd_ctx_device(const ehd_ctx* ctx) { return ctx->device; }
 int ehd_ctx_ndrops(const ehd_ctx* ctx) { return ctx->nd; }
+int ehd_ctx_drop_p(const ehd_ctx* ctx, int d) { return ctx->info[d].p; }
 int ehd_ctx_fail(ehd_ctx* ctx, int code, const char* msg)
 {
     ctx->err = msg;
@@ -2024,7 +2035,7 @@ int ehd_time_far(ehd_ctx* ctx, int far_prec, int targets_per_thread, int nchunk,
     return rc;
 }
 
-int ehd_surface(ehd_ctx* ctx, int ng, const double* gcoef_d, double* H_d, double* grad_d)
+int ehd_surface(ehd_ctx* ctx, int ng, const double* gcoef_d, double* H_d, double* grad_d, double* lap_d)
 {
     if (!ctx) return EHD_E_ARG;
     if (!ctx->nd) EHD_FAIL(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
@@ -2034,13 +2045,13 @@ int ehd_surface(ehd_ctx* ctx, int ng, const double* gcoef_d, double* H_d, double
     const dim3 grid(ctx->nrows_p), block(kThreads);
     if (ng == 0)
         hipLaunchKernelGGL(k_surface<0>, grid, block, 0, ctx->stream, ctx->d_info, ctx->d_legs, ctx->d_rows_p, ctx->d_x,
-                           gcoef_d, ctx->T, H_d, grad_d);
+                           gcoef_d, ctx->T, H_d, grad_d, lap_d);
     else if (ng == 1)
         hipLaunchKernelGGL(k_surface<1>, grid, block, 0, ctx->stream, ctx->d_info, ctx->d_legs, ctx->d_rows_p, ctx->d_x,
-                           gcoef_d, ctx->T, H_d, grad_d);
+                           gcoef_d, ctx->T, H_d, grad_d, lap_d);
     else
         hipLaunchKernelGGL(k_surface<2>, grid, block, 0, ctx->stream, ctx->d_info, ctx->d_legs, ctx->d_rows_p, ctx->d_x,
-                           gcoef_d, ctx->T, H_d, grad_d);
+                           gcoef_d, ctx->T, H_d, grad_d, lap_d);
     EHD_HIP(ctx, hipGetLastError());
     return EHD_OK;
 }

@@ -60,6 +60,13 @@ __global__ void k_fill(double* __restrict__ y, double v, long long n)
     if (t < n) y[t] = v;
 }
 
+// y = d * x (elementwise)
+__global__ void k_mul(const double* __restrict__ d, const double* __restrict__ x, double* __restrict__ y, long long n)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = d[t] * x[t];
+}
+
 // y = a x + b y
 __global__ void k_axpby(double a, const double* __restrict__ x, double b, double* __restrict__ y, long long n)
 {
@@ -380,7 +387,7 @@ int ehd_explicit_step(ehd_ctx* ctx, const ehd_step_params* prm, const double* ga
     SOLVE_HIP(hipGetLastError());
     if ((rc = ehd_layer_potentials(ctx, nullptr, nullptr, q.p, EHD_LAP_SL, prm->far_prec, val.p, nullptr))) return rc;
     if ((rc = ehd_analyze(ctx, 1, val.p, q.p))) return rc;
-    if ((rc = ehd_surface(ctx, 1, q.p, H.p, gq.p))) return rc;
+    if ((rc = ehd_surface(ctx, 1, q.p, H.p, gq.p, nullptr))) return rc;
     if ((rc = ehd_target_geometry(ctx, geo.p, geo.p + 3 * T))) return rc;
     if ((rc = ehd_synthesize(ctx, 1, en_coef_d, En.p))) return rc;
     const double* gG_ptr = nullptr;
@@ -388,7 +395,7 @@ int ehd_explicit_step(ehd_ctx* ctx, const ehd_step_params* prm, const double* ga
     if (gamma_coef_d && prm->eos != EHD_EOS_CLEAN) {
         SOLVE_HIP(hipMalloc(&gG.p, sizeof(double) * (size_t)3 * T));
         SOLVE_HIP(hipMalloc(&Gm.p, sizeof(double) * (size_t)T));
-        if ((rc = ehd_surface(ctx, 1, gamma_coef_d, H.p, gG.p))) return rc;
+        if ((rc = ehd_surface(ctx, 1, gamma_coef_d, H.p, gG.p, nullptr))) return rc;
         if ((rc = ehd_synthesize(ctx, 1, gamma_coef_d, Gm.p))) return rc;
         gG_ptr = gG.p;
         Gm_ptr = Gm.p;
@@ -412,6 +419,64 @@ int ehd_explicit_step(ehd_ctx* ctx, const ehd_step_params* prm, const double* ga
         iters[0] = it_en;
         iters[1] = it_u;
     }
+    return EHD_OK;
+}
+
+int ehd_solve_surfactant(ehd_ctx* ctx, double kappa, const double* rhs_d, int precond, int restart, int maxit,
+                         double tol, double* gamma_d, int* iters, double* relres)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ehd_ctx_ndrops(ctx)) return ehd_ctx_fail(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if (!rhs_d || !gamma_d || !iters || !relres) return ehd_ctx_fail(ctx, EHD_E_ARG, "NULL argument");
+    if (!(kappa >= 0.0) || !std::isfinite(kappa)) return ehd_ctx_fail(ctx, EHD_E_ARG, "kappa must be >= 0");
+    int rc = check_opts(ctx, EHD_FAR_FP64, restart, maxit, tol);
+    if (rc) return rc;
+    SOLVE_HIP(hipSetDevice(ehd_ctx_device(ctx)));
+    long long T, n;
+    if ((rc = ehd_num_targets(ctx, &T)) || (rc = ehd_num_coefs(ctx, &n))) return rc;
+    hipStream_t st = ehd_ctx_stream(ctx);
+    // diagonal preconditioner on the packed layout: 1 / (1 + kappa n(n+1)),
+    // the inverse of the operator on the unit sphere (Lap_S Y_nm = -n(n+1) Y_nm)
+    std::vector<double> dinv((size_t)n, 1.0), dfwd((size_t)n, 1.0);
+    if (precond) {
+        size_t o = 0;
+        for (int d = 0; d < ehd_ctx_ndrops(ctx); ++d) {
+            const int p = ehd_ctx_drop_p(ctx, d);
+            for (int nn = 0; nn <= p; ++nn)
+                for (int m = 0; m <= nn; ++m)
+                    for (int part = 0; part < 2; ++part, ++o) {
+                        dfwd[o] = 1.0 + kappa * nn * (nn + 1.0);
+                        dinv[o] = 1.0 / dfwd[o];
+                    }
+        }
+    }
+    DevBuf lap, H, grad, proj, tmp, di, df;
+    SOLVE_HIP(hipMalloc(&lap.p, sizeof(double) * (size_t)T));
+    SOLVE_HIP(hipMalloc(&H.p, sizeof(double) * (size_t)T));
+    SOLVE_HIP(hipMalloc(&grad.p, sizeof(double) * (size_t)3 * T));
+    SOLVE_HIP(hipMalloc(&proj.p, sizeof(double) * (size_t)n));
+    SOLVE_HIP(hipMalloc(&tmp.p, sizeof(double) * (size_t)n));
+    SOLVE_HIP(hipMalloc(&di.p, sizeof(double) * (size_t)n));
+    SOLVE_HIP(hipMalloc(&df.p, sizeof(double) * (size_t)n));
+    SOLVE_HIP(hipMemcpyAsync(di.p, dinv.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+    SOLVE_HIP(hipMemcpyAsync(df.p, dfwd.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+    // operator c -> c - kappa P[Lap_S c], applied to M^{-1} y (right preconditioning)
+    const Op A = [&](const double* in, double* out) -> int {
+        hipLaunchKernelGGL(k_mul, dim3(nblocks(n)), dim3(kT), 0, st, di.p, in, tmp.p, n);
+        int r = ehd_surface(ctx, 1, tmp.p, H.p, grad.p, lap.p);
+        if (!r) r = ehd_analyze(ctx, 1, lap.p, out);
+        if (r) return r;
+        hipLaunchKernelGGL(k_axpby, dim3(nblocks(n)), dim3(kT), 0, st, 1.0, tmp.p, -kappa, out, n);
+        SOLVE_HIP(hipGetLastError());
+        return EHD_OK;
+    };
+    // y0 = M c0, solve, c = M^{-1} y
+    hipLaunchKernelGGL(k_mul, dim3(nblocks(n)), dim3(kT), 0, st, df.p, gamma_d, gamma_d, n);
+    SOLVE_HIP(hipGetLastError());
+    if ((rc = gmres(ctx, n, A, rhs_d, gamma_d, restart, maxit, tol, iters, relres))) return rc;
+    hipLaunchKernelGGL(k_mul, dim3(nblocks(n)), dim3(kT), 0, st, di.p, gamma_d, gamma_d, n);
+    SOLVE_HIP(hipGetLastError());
+    SOLVE_HIP(hipStreamSynchronize(st));
     return EHD_OK;
 }
 

@@ -32,7 +32,8 @@ EXPORTED = ("ehd_create", "ehd_destroy", "ehd_last_error", "ehd_grid_dims", "ehd
             "ehd_target_geometry", "ehd_sync", "ehd_wigner_d", "ehd_set_timing",
             "ehd_stage_times", "ehd_self_class_times", "ehd_set_graph", "ehd_set_far_config",
             "ehd_get_far_config", "ehd_time_far", "ehd_num_coefs", "ehd_solve_En",
-            "ehd_solve_velocity", "ehd_surface", "ehd_drop_coefs", "ehd_explicit_step")
+            "ehd_solve_velocity", "ehd_surface", "ehd_drop_coefs", "ehd_explicit_step",
+            "ehd_solve_surfactant")
 STAGES = ("densities", "self", "far", "combine")
 DEGREE_CLASSES = (16, 24, 32, 48)   # largest p of each self-interaction kernel class
 
@@ -85,8 +86,9 @@ def load(path: str = LIB_PATH):
     lib.ehd_get_far_config.argtypes = [vp, ip, ip]
     lib.ehd_time_far.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, dp]
     lib.ehd_num_coefs.argtypes = [vp, C.POINTER(C.c_longlong)]
-    lib.ehd_surface.argtypes = [vp, C.c_int, vp, vp, vp]
+    lib.ehd_surface.argtypes = [vp, C.c_int, vp, vp, vp, vp]
     lib.ehd_drop_coefs.argtypes = [vp, vp]
+    lib.ehd_solve_surfactant.argtypes = [vp, C.c_double, vp, C.c_int, C.c_int, C.c_int, C.c_double, vp, ip, dp]
     lib.ehd_explicit_step.argtypes = [vp, C.POINTER(StepParams), vp, vp, vp, vp, ip]
     lib.ehd_solve_En.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
                                  C.c_double, vp, ip, dp]
@@ -221,10 +223,21 @@ class Context:
         return list(ms)
 
     def surface(self, H: torch.Tensor, gcoef: torch.Tensor | None = None, grad: torch.Tensor | None = None,
-                ng: int = 0):
-        """Mean curvature H[T] and surface gradients grad[ng][3][T] of ng packed
-        scalar fields at the target nodes."""
-        self._check(self._lib.ehd_surface(self._h, ng, _ptr(gcoef), _ptr(H), _ptr(grad)))
+                ng: int = 0, lap: torch.Tensor | None = None):
+        """Mean curvature H[T], surface gradients grad[ng][3][T] and, if given,
+        Laplace-Beltrami values lap[ng][T] of ng packed scalar fields at the
+        target nodes."""
+        self._check(self._lib.ehd_surface(self._h, ng, _ptr(gcoef), _ptr(H), _ptr(grad), _ptr(lap)))
+
+    def solve_surfactant(self, kappa: float, rhs: torch.Tensor, gamma: torch.Tensor, precond: bool = True,
+                         restart: int = 30, maxit: int = 200, tol: float = 1e-10):
+        """GMRES solve of (I - kappa Lap_S) Gamma = rhs in Galerkin form; gamma
+        holds the initial guess and receives the solution.  Returns
+        (iters, relres)."""
+        it, rr = C.c_int(), C.c_double()
+        self._check(self._lib.ehd_solve_surfactant(self._h, float(kappa), _ptr(rhs), 1 if precond else 0, restart,
+                                                   maxit, float(tol), _ptr(gamma), C.byref(it), C.byref(rr)))
+        return it.value, rr.value
 
     def drop_coefs(self, x: torch.Tensor):
         """Copy of the current drops' surface coefficients (3 packed fields)."""

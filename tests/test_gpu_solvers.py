@@ -167,3 +167,48 @@ def test_explicit_step_matches_oracle(E, eos):
     e1, e2, e3 = rel(en, ref_en), rel(u, ref_u), rel(xn, ref_x)
     say("explicit step eos", eos, "iters", its, "err E_n", e1, "u", e2, "x", e3)
     assert e1 < TOL and e2 < TOL and e3 < TOL
+
+
+def _random_field(s, seed, amp=1.0):
+    rng = np.random.default_rng(seed)
+    out = np.zeros(len(s.sigcoef))
+    off = 0
+    for p in (int(x) for x in s.p):
+        for n in range(p + 1):
+            for m in range(n + 1):
+                k = off + 2 * (n * (n + 1) // 2 + m)
+                out[k] = amp * rng.standard_normal() / (n + 1) ** 2
+                if m:
+                    out[k + 1] = amp * rng.standard_normal() / (n + 1) ** 2
+        off += (p + 1) * (p + 2)
+    return out
+
+
+@pytest.mark.parametrize("kappa", [0.003, 0.05])
+def test_surfactant_solve_matches_oracle(E, kappa):
+    import torch
+    s = W.suspension(2, [5], side=3.5, seed=33, amp=0.1, gap=0.3)
+    b = _random_field(s, 34)
+    ref = G.solve_surfactant_dense(s, kappa, b)
+    ctx, dev = _ctx(E, s)
+    res = {}
+    for pre in (True, False):
+        g = torch.zeros(ctx.num_coefs(), dtype=torch.float64, device=dev)
+        it, rr = ctx.solve_surfactant(kappa, torch.from_numpy(b).to(dev), g, precond=pre, tol=1e-13)
+        res[pre] = (rel(g.cpu().numpy(), ref), it, rr)
+    ctx.close()
+    say("surfactant kappa", kappa, "preconditioned (err, iters, relres)", res[True], "plain", res[False])
+    assert res[True][0] < TOL and res[False][0] < TOL
+    assert res[True][1] <= res[False][1]
+
+
+def test_surfactant_preconditioner_exact_on_sphere(E):
+    import torch
+    p = 8
+    s = make_susp(p, sphere_x(p), q_self=16)
+    b = _random_field(s, 35)
+    ctx, dev = _ctx(E, s)
+    g = torch.zeros(ctx.num_coefs(), dtype=torch.float64, device=dev)
+    it, rr = ctx.solve_surfactant(0.2, torch.from_numpy(b).to(dev), g, precond=True, tol=1e-12)
+    ctx.close()
+    assert it <= 1 and rr < 1e-12, (it, rr)

@@ -36,13 +36,14 @@ def test_surface_quantities_match_oracle(E, grid_mode):
                         for o, p in zip(W.drop_offsets(s.p)[:-1], s.p)])
     H = torch.zeros(T, dtype=torch.float64, device=dev)
     grad = torch.zeros(ng, 3, T, dtype=torch.float64, device=dev)
-    ctx.surface(H, torch.from_numpy(g).to(dev), grad, ng=ng)
+    lap = torch.zeros(ng, T, dtype=torch.float64, device=dev)
+    ctx.surface(H, torch.from_numpy(g).to(dev), grad, ng=ng, lap=lap)
     ctx.sync()
-    H, grad = H.cpu().numpy(), grad.cpu().numpy()
+    H, grad, lap = H.cpu().numpy(), grad.cpu().numpy(), lap.cpu().numpy()
     ctx.close()
     offs = W.drop_offsets(s.p)
     t0 = 0
-    errH, errG = 0.0, 0.0
+    errH, errG, errL = 0.0, 0.0, 0.0
     for d, p in enumerate(int(x) for x in s.p):
         nl = 2 * p + 2 if grid_mode == 0 else 2 * p
         t, _ = oracle.gauss_legendre(p + 1)
@@ -50,10 +51,12 @@ def test_surface_quantities_match_oracle(E, grid_mode):
         xd = s.xcoef[3 * int(offs[d]):3 * int(offs[d]) + 3 * (p + 1) * (p + 2)]
         for j in range(0, p + 1, 3):
             for k in range(0, nl, 5):
-                _, _, Hr, gr = oracle.surface_point(p, xd, math.acos(t[j]), 2 * math.pi * k / nl, gcoef=gd, ng=ng)
+                _, _, Hr, gr, lr = oracle.surface_point(p, xd, math.acos(t[j]), 2 * math.pi * k / nl, gcoef=gd,
+                                                        ng=ng, lap=True)
                 tt = t0 + j * nl + k
                 errH = max(errH, abs(H[tt] - Hr) / abs(Hr))
                 errG = max(errG, np.abs(grad[:, :, tt] - gr).max() / max(1e-3, np.abs(gr).max()))
+                errL = max(errL, np.abs(lap[:, tt] - lr).max() / max(1e-3, np.abs(lr).max()))
         t0 += (p + 1) * nl
-    print("surface: max rel err H", errH, "grad", errG, flush=True)
-    assert errH < 1e-11 and errG < 1e-10
+    print("surface: max rel err H", errH, "grad", errG, "Laplace-Beltrami", errL, flush=True)
+    assert errH < 1e-11 and errG < 1e-10 and errL < 1e-10

@@ -106,3 +106,20 @@ def test_uniform_surfactant_matches_clean_drop():
     a, _ = G.forces(s, 0.5, 2.0, 0.3, 1.0, 0.0, en)
     b, _ = G.forces(s, 0.5, 2.0, 0.3, 1.0, 0.0, en, gamma=g1, eos=2, beta=0.5, xs=0.3)
     assert np.abs(a - b).max() < 1e-12
+
+
+def test_surfactant_system_on_unit_sphere_is_diagonal():
+    """Lap_S Y_nm = -n(n+1) Y_nm: the Galerkin system is diag(1 + kappa n(n+1))."""
+    p = 5
+    s = make_susp(p, sphere_x(p), q_self=10)
+    rng = np.random.default_rng(41)
+    b = rng.standard_normal((p + 1) * (p + 2))
+    for n in range(p + 1):
+        b[2 * tri(n, 0) + 1] = 0.0
+    kappa = 0.07
+    c = G.solve_surfactant_dense(s, kappa, b)
+    expect = b.copy()
+    for n in range(p + 1):
+        for m in range(n + 1):
+            expect[2 * tri(n, m):2 * tri(n, m) + 2] /= 1 + kappa * n * (n + 1)
+    assert np.abs(c - expect).max() < 1e-12

@@ -82,3 +82,52 @@ def test_surface_divergence_identity_on_deformed_drop():
                 rhs += wt * 2 * H * gv * nrm
         errs.append(np.abs(lhs - rhs).max())
     assert errs[-1] < 1e-11 and errs[-1] <= errs[0] + 1e-14, errs
+
+
+@pytest.mark.parametrize("nm", [(1, 1), (2, 0), (4, 3)])
+def test_sphere_laplace_beltrami_eigenvalues(nm):
+    """Lap_S Y_nm = -n(n+1)/a^2 Y_nm on a sphere of radius a."""
+    n, m = nm
+    p, a = 6, 1.7
+    g = field(p, y_entry(n, m))
+    x = sphere_x(p, R=a, centre=(0.2, 0.1, -0.4))
+    for th, ph in [(0.5, 0.2), (1.4, 3.0), (2.7, 5.5)]:
+        _, _, _, _, lap = oracle.surface_point(p, x, th, ph, gcoef=g, ng=1, lap=True)
+        val = oracle.sh_point(p, g, th, ph)[0][0]
+        assert abs(lap[0] + n * (n + 1) / a**2 * val) < 1e-12
+
+
+def test_laplace_beltrami_green_identities_on_deformed_drop():
+    """int Lap_S g dA = 0, int f Lap_S g dA = int g Lap_S f dA and
+    int g Lap_S g dA = -int |grad_S g|^2 dA on a closed deformed surface."""
+    s = W.single_drop(p=7, seed=5, eps_y20=0.25, amp=0.03)
+    p = 7
+    rng = np.random.default_rng(8)
+    fg = np.zeros(2 * (p + 1) * (p + 2))
+    for c in range(2):
+        for n in range(p + 1):
+            for m in range(n + 1):
+                k = c * (p + 1) * (p + 2) + 2 * (n * (n + 1) // 2 + m)
+                fg[k] = rng.standard_normal() / (n + 1) ** 2
+                if m:
+                    fg[k + 1] = rng.standard_normal() / (n + 1) ** 2
+    Q = 36
+    t, w = oracle.gauss_legendre(Q + 1)
+    nl = 2 * Q + 2
+    i_lap = i_sym1 = i_sym2 = i_e1 = i_e2 = 0.0
+    for j in range(Q + 1):
+        th = math.acos(t[j])
+        for k in range(nl):
+            ph = 2 * math.pi * k / nl
+            _, _, _, grad, lap = oracle.surface_point(p, s.xcoef, th, ph, gcoef=fg, ng=2, lap=True)
+            _, _, J = oracle.geom_point(p, s.xcoef, th, ph)
+            wt = 2 * math.pi / nl * w[j] * J
+            fv, gv = oracle.sh_point(p, fg, th, ph, nf=2)[0]
+            i_lap += wt * lap[1]
+            i_sym1 += wt * fv * lap[1]
+            i_sym2 += wt * gv * lap[0]
+            i_e1 += wt * gv * lap[1]
+            i_e2 -= wt * float(grad[1] @ grad[1])
+    assert abs(i_lap) < 1e-10
+    assert abs(i_sym1 - i_sym2) < 1e-10
+    assert abs(i_e1 - i_e2) < 1e-10
