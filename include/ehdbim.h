@@ -291,6 +291,42 @@ typedef struct ehd_step_params {
 int ehd_explicit_step(ehd_ctx* ctx, const ehd_step_params* params, const double* gamma_coef_d,
                       double* en_coef_d, double* ucoef_d, double* xnew_coef_d, int* iters);
 
+/* ------------------------------------------------------------------------
+ * Learned initial guess for the surfactant solve: a multilayer perceptron
+ * (nlayers hidden ReLU layers of nhidden units, linear output; FP32) whose
+ * forward pass, backward pass, mean-squared-error loss and Adam update run
+ * in the library's kernels (GEMMs on FP32 MFMA).  The network is a device
+ * object bound to a HIP device and stream; all calls are asynchronous on
+ * that stream except where stated.  Parameter layout (host buffers of
+ * ehd_mlp_num_params floats): for each layer l = 0..nlayers, the weights
+ * W_l[in][out] row-major, then the bias b_l[out]; layer l computes
+ * h_{l+1} = ReLU(h_l W_l + b_l) (no ReLU on the output layer).
+ * x_d [batch][nin], y_d and t_d [batch][nout]: FP32 device buffers.
+ * ------------------------------------------------------------------------ */
+typedef struct ehd_mlp ehd_mlp;
+
+/* He-uniform weights from `seed`, zero biases and Adam moments. */
+int ehd_mlp_create(ehd_mlp** out, int device, void* stream, int nin, int nhidden, int nlayers, int nout,
+                   unsigned long long seed);
+void ehd_mlp_destroy(ehd_mlp* mlp);
+const char* ehd_mlp_last_error(const ehd_mlp* mlp);
+int ehd_mlp_num_params(const ehd_mlp* mlp, long long* n);
+/* Synchronous copies of the parameters / of the last backward pass's gradients. */
+int ehd_mlp_get_params(ehd_mlp* mlp, float* host);
+int ehd_mlp_set_params(ehd_mlp* mlp, const float* host);
+int ehd_mlp_get_grads(ehd_mlp* mlp, float* host);
+/* Forward pass of `batch` rows (kept for the backward pass); y_d may be NULL. */
+int ehd_mlp_forward(ehd_mlp* mlp, int batch, const float* x_d, float* y_d);
+/* Gradients of the parameters for the output gradient dy_d of the last
+ * forward pass (same batch). */
+int ehd_mlp_backward(ehd_mlp* mlp, int batch, const float* dy_d);
+/* Mean-squared error L = mean((y - t)^2) over batch*nout entries and its
+ * gradient dy_d = 2 (y - t) / (batch nout); *loss (if not NULL) is set
+ * synchronously. */
+int ehd_mlp_mse(ehd_mlp* mlp, int batch, const float* y_d, const float* t_d, float* dy_d, double* loss);
+/* One Adam step with the current gradients (bias-corrected moments). */
+int ehd_mlp_adam(ehd_mlp* mlp, float lr, float beta1, float beta2, float eps);
+
 /* Host-only: Wigner small-d matrix d^n_{m m'}(beta), m, m' = -n..n, written
  * row-major to out[(m+n)*(2n+1) + (m'+n)], with
  * Y_nm(Ry(beta) v) = sum_m' d^n_{m m'}(beta) Y_nm'(v)

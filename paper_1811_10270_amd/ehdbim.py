@@ -33,7 +33,9 @@ EXPORTED = ("ehd_create", "ehd_destroy", "ehd_last_error", "ehd_grid_dims", "ehd
             "ehd_stage_times", "ehd_self_class_times", "ehd_set_graph", "ehd_set_far_config",
             "ehd_get_far_config", "ehd_time_far", "ehd_num_coefs", "ehd_solve_En",
             "ehd_solve_velocity", "ehd_surface", "ehd_drop_coefs", "ehd_explicit_step",
-            "ehd_solve_surfactant")
+            "ehd_solve_surfactant", "ehd_mlp_create", "ehd_mlp_destroy", "ehd_mlp_last_error",
+            "ehd_mlp_num_params", "ehd_mlp_get_params", "ehd_mlp_set_params", "ehd_mlp_get_grads",
+            "ehd_mlp_forward", "ehd_mlp_backward", "ehd_mlp_mse", "ehd_mlp_adam")
 STAGES = ("densities", "self", "far", "combine")
 DEGREE_CLASSES = (16, 24, 32, 48)   # largest p of each self-interaction kernel class
 
@@ -88,6 +90,21 @@ def load(path: str = LIB_PATH):
     lib.ehd_num_coefs.argtypes = [vp, C.POINTER(C.c_longlong)]
     lib.ehd_surface.argtypes = [vp, C.c_int, vp, vp, vp, vp]
     lib.ehd_drop_coefs.argtypes = [vp, vp]
+    fp = C.POINTER(C.c_float)
+    lib.ehd_mlp_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, vp, C.c_int, C.c_int, C.c_int, C.c_int,
+                                   C.c_ulonglong]
+    lib.ehd_mlp_destroy.argtypes = [vp]
+    lib.ehd_mlp_destroy.restype = None
+    lib.ehd_mlp_last_error.argtypes = [vp]
+    lib.ehd_mlp_last_error.restype = C.c_char_p
+    lib.ehd_mlp_num_params.argtypes = [vp, C.POINTER(C.c_longlong)]
+    lib.ehd_mlp_get_params.argtypes = [vp, fp]
+    lib.ehd_mlp_set_params.argtypes = [vp, fp]
+    lib.ehd_mlp_get_grads.argtypes = [vp, fp]
+    lib.ehd_mlp_forward.argtypes = [vp, C.c_int, vp, vp]
+    lib.ehd_mlp_backward.argtypes = [vp, C.c_int, vp]
+    lib.ehd_mlp_mse.argtypes = [vp, C.c_int, vp, vp, vp, dp]
+    lib.ehd_mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float]
     lib.ehd_solve_surfactant.argtypes = [vp, C.c_double, vp, C.c_int, C.c_int, C.c_int, C.c_double, vp, ip, dp]
     lib.ehd_explicit_step.argtypes = [vp, C.POINTER(StepParams), vp, vp, vp, vp, ip]
     lib.ehd_solve_En.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
@@ -96,6 +113,82 @@ def load(path: str = LIB_PATH):
                                        ip, dp]
     _lib = lib
     return lib
+
+
+def _fptr(t):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("device tensors (torch, on the GPU) are required")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError("contiguous float32 tensors are required")
+    return C.c_void_p(t.data_ptr())
+
+
+class MLP:
+    """The library's perceptron (ehd_mlp_*): forward/backward/loss/Adam kernels."""
+
+    def __init__(self, nin: int, nhidden: int, nlayers: int, nout: int, seed: int = 1, device: int = 0,
+                 stream=None):
+        import numpy as np
+        lib = load()
+        self._lib = lib
+        self._np = np
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        rc = lib.ehd_mlp_create(C.byref(h), device, C.c_void_p(stream.cuda_stream), nin, nhidden, nlayers, nout,
+                                seed)
+        if rc:
+            raise EhdError(rc, "ehd_mlp_create failed")
+        self._h = h
+        self.nin, self.nout = nin, nout
+        n = C.c_longlong()
+        lib.ehd_mlp_num_params(h, C.byref(n))
+        self.nparams = n.value
+
+    def _check(self, rc):
+        if rc:
+            raise EhdError(rc, self._lib.ehd_mlp_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ehd_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        out = self._np.zeros(self.nparams, self._np.float32)
+        self._check(self._lib.ehd_mlp_get_params(self._h, out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def set_params(self, p):
+        p = self._np.ascontiguousarray(p, self._np.float32)
+        self._check(self._lib.ehd_mlp_set_params(self._h, p.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def grads(self):
+        out = self._np.zeros(self.nparams, self._np.float32)
+        self._check(self._lib.ehd_mlp_get_grads(self._h, out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def forward(self, x: torch.Tensor, y: torch.Tensor | None = None):
+        self._check(self._lib.ehd_mlp_forward(self._h, x.shape[0], _fptr(x), _fptr(y) if y is not None else None))
+
+    def backward(self, dy: torch.Tensor):
+        self._check(self._lib.ehd_mlp_backward(self._h, dy.shape[0], _fptr(dy)))
+
+    def mse(self, y: torch.Tensor, t: torch.Tensor, dy: torch.Tensor, want_loss: bool = True):
+        loss = C.c_double()
+        self._check(self._lib.ehd_mlp_mse(self._h, y.shape[0], _fptr(y), _fptr(t), _fptr(dy),
+                                          C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        self._check(self._lib.ehd_mlp_adam(self._h, lr, beta1, beta2, eps))
 
 
 def rows_for_kinds(kinds: int) -> list[int]:
