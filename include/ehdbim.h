@@ -208,7 +208,8 @@ int ehd_time_far(ehd_ctx* ctx, int far_prec, int targets_per_thread, int nchunk,
 /* Galerkin solvers (Sec. 2, eq. galerkin_En and eq. BIM_galerkin) by
  * restarted GMRES in FP64 on the device.  Each iteration is one
  * ehd_layer_potentials call (far field in far_prec) and one ehd_analyze.
- * restart in [1, 200], maxit >= 1 (mat-vecs), tol > 0: stop when the true
+ * restart in [1, 200], maxit >= 0 (mat-vecs; 0 only evaluates the true
+ * residual of the initial guess into *relres), tol > 0: stop when the true
  * residual |b - A x| <= tol |b| (Euclidean norm of the packed coefficient
  * vector).  *iters receives the number of mat-vecs, *relres the final true
  * relative residual; not converging within maxit is not an error (check
@@ -236,7 +237,8 @@ int ehd_solve_velocity(ehd_ctx* ctx, double lambda, const double* fcoef_d, int f
 /* Implicit surfactant-diffusion solve (Sec. 2.2, the implicit half of the
  * IMEX step of Algorithm 1: (I - dt/(2 Pe) Lap_S) Gamma = b), in Galerkin
  * form on the current drops: c - kappa (Lap_S Gamma[c], Y) = b for all
- * Y = Y_nm, n <= p, with kappa = dt / (2 Pe) >= 0, the Laplace-Beltrami
+ * Y = Y_nm, n <= p, with kappa = dt / (2 Pe) >= 0 per drop (kappa_h[ndrops],
+ * host; the drops' systems are independent), the Laplace-Beltrami
  * operator of each drop's surface (ehd_surface) and the projection
  * ehd_analyze.  rhs_d, gamma_d: 1 packed field; gamma_d holds the initial
  * guess on entry and receives the solution.  precond != 0: right
@@ -244,8 +246,8 @@ int ehd_solve_velocity(ehd_ctx* ctx, double lambda, const double* fcoef_d, int f
  * unit sphere (the spherical-harmonic eigenfunction preconditioner of
  * Sec. 2.2).  GMRES controls and outputs as for ehd_solve_En (residual of
  * the unpreconditioned system).  Synchronous. */
-int ehd_solve_surfactant(ehd_ctx* ctx, double kappa, const double* rhs_d, int precond, int restart, int maxit,
-                         double tol, double* gamma_d, int* iters, double* relres);
+int ehd_solve_surfactant(ehd_ctx* ctx, const double* kappa_h, const double* rhs_d, int precond, int restart,
+                         int maxit, double tol, double* gamma_d, int* iters, double* relres);
 
 /* Copy of the current drops' surface coefficients (3 packed fields, as
  * passed to ehd_set_drops) into xcoef_d. */

@@ -67,6 +67,13 @@ __global__ void k_mul(const double* __restrict__ d, const double* __restrict__ x
     if (t < n) y[t] = d[t] * x[t];
 }
 
+// y = x - k * y (elementwise k)
+__global__ void k_xmky(const double* __restrict__ x, const double* __restrict__ k, double* __restrict__ y, long long n)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = x[t] - k[t] * y[t];
+}
+
 // y = a x + b y
 __global__ void k_axpby(double a, const double* __restrict__ x, double b, double* __restrict__ y, long long n)
 {
@@ -270,7 +277,7 @@ int check_opts(ehd_ctx* ctx, int far_prec, int restart, int maxit, double tol)
     if (far_prec != EHD_FAR_FP64 && far_prec != EHD_FAR_FP32C)
         return ehd_ctx_fail(ctx, EHD_E_ARG, "invalid far_prec");
     if (restart < 1 || restart > 200) return ehd_ctx_fail(ctx, EHD_E_ARG, "restart must be in [1, 200]");
-    if (maxit < 1) return ehd_ctx_fail(ctx, EHD_E_ARG, "maxit must be >= 1");
+    if (maxit < 0) return ehd_ctx_fail(ctx, EHD_E_ARG, "maxit must be >= 0");
     if (!(tol > 0.0)) return ehd_ctx_fail(ctx, EHD_E_ARG, "tol must be > 0");
     return EHD_OK;
 }
@@ -422,13 +429,15 @@ int ehd_explicit_step(ehd_ctx* ctx, const ehd_step_params* prm, const double* ga
     return EHD_OK;
 }
 
-int ehd_solve_surfactant(ehd_ctx* ctx, double kappa, const double* rhs_d, int precond, int restart, int maxit,
-                         double tol, double* gamma_d, int* iters, double* relres)
+int ehd_solve_surfactant(ehd_ctx* ctx, const double* kappa_h, const double* rhs_d, int precond, int restart,
+                         int maxit, double tol, double* gamma_d, int* iters, double* relres)
 {
     if (!ctx) return EHD_E_ARG;
     if (!ehd_ctx_ndrops(ctx)) return ehd_ctx_fail(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
-    if (!rhs_d || !gamma_d || !iters || !relres) return ehd_ctx_fail(ctx, EHD_E_ARG, "NULL argument");
-    if (!(kappa >= 0.0) || !std::isfinite(kappa)) return ehd_ctx_fail(ctx, EHD_E_ARG, "kappa must be >= 0");
+    if (!kappa_h || !rhs_d || !gamma_d || !iters || !relres) return ehd_ctx_fail(ctx, EHD_E_ARG, "NULL argument");
+    for (int d = 0; d < ehd_ctx_ndrops(ctx); ++d)
+        if (!(kappa_h[d] >= 0.0) || !std::isfinite(kappa_h[d]))
+            return ehd_ctx_fail(ctx, EHD_E_ARG, "kappa must be >= 0 for every drop");
     int rc = check_opts(ctx, EHD_FAR_FP64, restart, maxit, tol);
     if (rc) return rc;
     SOLVE_HIP(hipSetDevice(ehd_ctx_device(ctx)));
@@ -437,20 +446,23 @@ int ehd_solve_surfactant(ehd_ctx* ctx, double kappa, const double* rhs_d, int pr
     hipStream_t st = ehd_ctx_stream(ctx);
     // diagonal preconditioner on the packed layout: 1 / (1 + kappa n(n+1)),
     // the inverse of the operator on the unit sphere (Lap_S Y_nm = -n(n+1) Y_nm)
-    std::vector<double> dinv((size_t)n, 1.0), dfwd((size_t)n, 1.0);
-    if (precond) {
+    std::vector<double> dinv((size_t)n, 1.0), dfwd((size_t)n, 1.0), kv((size_t)n);
+    {
         size_t o = 0;
         for (int d = 0; d < ehd_ctx_ndrops(ctx); ++d) {
             const int p = ehd_ctx_drop_p(ctx, d);
             for (int nn = 0; nn <= p; ++nn)
                 for (int m = 0; m <= nn; ++m)
                     for (int part = 0; part < 2; ++part, ++o) {
-                        dfwd[o] = 1.0 + kappa * nn * (nn + 1.0);
-                        dinv[o] = 1.0 / dfwd[o];
+                        kv[o] = kappa_h[d];
+                        if (precond) {
+                            dfwd[o] = 1.0 + kappa_h[d] * nn * (nn + 1.0);
+                            dinv[o] = 1.0 / dfwd[o];
+                        }
                     }
         }
     }
-    DevBuf lap, H, grad, proj, tmp, di, df;
+    DevBuf lap, H, grad, proj, tmp, di, df, kd;
     SOLVE_HIP(hipMalloc(&lap.p, sizeof(double) * (size_t)T));
     SOLVE_HIP(hipMalloc(&H.p, sizeof(double) * (size_t)T));
     SOLVE_HIP(hipMalloc(&grad.p, sizeof(double) * (size_t)3 * T));
@@ -458,6 +470,8 @@ int ehd_solve_surfactant(ehd_ctx* ctx, double kappa, const double* rhs_d, int pr
     SOLVE_HIP(hipMalloc(&tmp.p, sizeof(double) * (size_t)n));
     SOLVE_HIP(hipMalloc(&di.p, sizeof(double) * (size_t)n));
     SOLVE_HIP(hipMalloc(&df.p, sizeof(double) * (size_t)n));
+    SOLVE_HIP(hipMalloc(&kd.p, sizeof(double) * (size_t)n));
+    SOLVE_HIP(hipMemcpyAsync(kd.p, kv.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
     SOLVE_HIP(hipMemcpyAsync(di.p, dinv.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
     SOLVE_HIP(hipMemcpyAsync(df.p, dfwd.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
     // operator c -> c - kappa P[Lap_S c], applied to M^{-1} y (right preconditioning)
@@ -466,7 +480,7 @@ int ehd_solve_surfactant(ehd_ctx* ctx, double kappa, const double* rhs_d, int pr
         int r = ehd_surface(ctx, 1, tmp.p, H.p, grad.p, lap.p);
         if (!r) r = ehd_analyze(ctx, 1, lap.p, out);
         if (r) return r;
-        hipLaunchKernelGGL(k_axpby, dim3(nblocks(n)), dim3(kT), 0, st, 1.0, tmp.p, -kappa, out, n);
+        hipLaunchKernelGGL(k_xmky, dim3(nblocks(n)), dim3(kT), 0, st, tmp.p, kd.p, out, n);
         SOLVE_HIP(hipGetLastError());
         return EHD_OK;
     };

@@ -105,7 +105,7 @@ def load(path: str = LIB_PATH):
     lib.ehd_mlp_backward.argtypes = [vp, C.c_int, vp]
     lib.ehd_mlp_mse.argtypes = [vp, C.c_int, vp, vp, vp, dp]
     lib.ehd_mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float]
-    lib.ehd_solve_surfactant.argtypes = [vp, C.c_double, vp, C.c_int, C.c_int, C.c_int, C.c_double, vp, ip, dp]
+    lib.ehd_solve_surfactant.argtypes = [vp, dp, vp, C.c_int, C.c_int, C.c_int, C.c_double, vp, ip, dp]
     lib.ehd_explicit_step.argtypes = [vp, C.POINTER(StepParams), vp, vp, vp, vp, ip]
     lib.ehd_solve_En.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
                                  C.c_double, vp, ip, dp]
@@ -322,14 +322,17 @@ class Context:
         target nodes."""
         self._check(self._lib.ehd_surface(self._h, ng, _ptr(gcoef), _ptr(H), _ptr(grad), _ptr(lap)))
 
-    def solve_surfactant(self, kappa: float, rhs: torch.Tensor, gamma: torch.Tensor, precond: bool = True,
+    def solve_surfactant(self, kappa, rhs: torch.Tensor, gamma: torch.Tensor, precond: bool = True,
                          restart: int = 30, maxit: int = 200, tol: float = 1e-10):
-        """GMRES solve of (I - kappa Lap_S) Gamma = rhs in Galerkin form; gamma
-        holds the initial guess and receives the solution.  Returns
-        (iters, relres)."""
+        """GMRES solve of (I - kappa Lap_S) Gamma = rhs in Galerkin form; kappa
+        is one value or one per drop; gamma holds the initial guess and
+        receives the solution.  Returns (iters, relres)."""
+        import numpy as np
+        k = np.broadcast_to(np.asarray(kappa, np.float64), (len(self.p),)).copy()
         it, rr = C.c_int(), C.c_double()
-        self._check(self._lib.ehd_solve_surfactant(self._h, float(kappa), _ptr(rhs), 1 if precond else 0, restart,
-                                                   maxit, float(tol), _ptr(gamma), C.byref(it), C.byref(rr)))
+        self._check(self._lib.ehd_solve_surfactant(self._h, k.ctypes.data_as(C.POINTER(C.c_double)), _ptr(rhs),
+                                                   1 if precond else 0, restart, maxit, float(tol), _ptr(gamma),
+                                                   C.byref(it), C.byref(rr)))
         return it.value, rr.value
 
     def drop_coefs(self, x: torch.Tensor):

@@ -124,7 +124,7 @@ def test_solver_argument_errors(E):
     s = W.two_drops(4, seed=15)
     ctx, dev = _ctx(E, s)
     en = torch.zeros(ctx.num_coefs(), dtype=torch.float64, device=dev)
-    for kw in ({"restart": 0}, {"maxit": 0}, {"tol": 0.0}, {"far_prec": 7}):
+    for kw in ({"restart": 0}, {"maxit": -1}, {"tol": 0.0}, {"far_prec": 7}):
         with pytest.raises(E.EhdError):
             ctx.solve_En(1.5, 1.0, 0.0, en, **kw)
     with pytest.raises(E.EhdError):
