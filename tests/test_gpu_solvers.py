@@ -169,6 +169,41 @@ def test_explicit_step_matches_oracle(E, eos):
     assert e1 < TOL and e2 < TOL and e3 < TOL
 
 
+@pytest.mark.parametrize("R,Q", [(2.0, 1.0), (0.5, 2.0)])
+def test_explicit_step_taylor_shape(E, R, Q):
+    """Taylor's first-order shape (clean drop, lambda = 1, uniform field; the
+    oracle's pin in test_oracle_taylor) at p = 12: the normal velocity of
+    one GPU step is O(Ca_E) there and O(1) on the sphere."""
+    import torch
+    from test_oracle_taylor import p2_shape, taylor_f20
+    from test_oracle_pins import make_susp
+    p = 12
+    F = taylor_f20(R, Q)
+
+    def un_rms(a, Ca):
+        s = make_susp(p, p2_shape(p, a))
+        ctx, dev = _ctx(E, s)
+        nc, T = ctx.num_coefs(), ctx.ntargets
+        en = torch.zeros(nc, dtype=torch.float64, device=dev)
+        u = torch.zeros(3 * nc, dtype=torch.float64, device=dev)
+        xn = torch.zeros(3 * nc, dtype=torch.float64, device=dev)
+        ctx.explicit_step(1.0, R, Q, Ca, 1.0, 0.0, 0.0, en, u, xn, tol=1e-13)
+        ug = torch.empty(3, T, dtype=torch.float64, device=dev)
+        x0 = torch.empty(3, T, dtype=torch.float64, device=dev)
+        n0 = torch.empty(3, T, dtype=torch.float64, device=dev)
+        ctx.synthesize(3, u, ug)
+        ctx.target_geometry(x0, n0)
+        un = (ug * n0).sum(0).cpu().numpy()
+        ctx.close()
+        return math.sqrt(np.mean(un * un))
+
+    r = [un_rms(Ca * F, Ca) for Ca in (0.04, 0.02, 0.01)]
+    sph = un_rms(0.0, 0.01)
+    say("taylor R", R, "Q", Q, "|u.n|", r, "sphere", sph)
+    assert 1.8 < r[0] / r[1] < 2.2 and 1.8 < r[1] / r[2] < 2.2
+    assert sph > 50.0 * r[2]
+
+
 def _random_field(s, seed, amp=1.0):
     rng = np.random.default_rng(seed)
     out = np.zeros(len(s.sigcoef))
