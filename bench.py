@@ -47,10 +47,10 @@ def self_flops_per_drop(p: int, q: int, grid_mode: int) -> float:
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs
 # recorded in profiles/hbm_traffic_batched_64_mixed_p.md (counters scaled by a
 # 1 GiB copy), valid only for the kernel source they were taken with.
-TRAFFIC_SOURCE_SHA256 = "2cd01f140322a8158411a45f2161a9eed2fa83bafe5ed97f20b7b72f83dc2398"
+TRAFFIC_SOURCE_SHA256 = "aca12525b1109307c1d11fe726d1dcb49f28803489ad1edc7236537ad25d42ee"
 TRAFFIC_WORKLOAD = "batched_64_mixed_p"
-TRAFFIC_BYTES = {"k_self<48>": 1.0304e10, "k_self<32>": 9.023e8, "k_self<24>": 4.905e7,
-                 "k_self<16>": 1.835e7, "k_far32": 8.066e8}
+TRAFFIC_BYTES = {"k_self<48>": 7.058e8, "k_self<32>": 1.201e8, "k_self<24>": 2.541e7,
+                 "k_self<16>": 7.353e6, "k_far32": 8.133e8}
 
 
 def measured_traffic(kernel: str, workload: str):
