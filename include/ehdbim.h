@@ -144,7 +144,7 @@ int ehd_synthesize(ehd_ctx* ctx, int nfields, const double* coef_d, double* grid
 /* Surface quantities at the target nodes (Sec. 1, eq. interfacial_force):
  * H_d[T] the mean curvature H = (1/2) div_S n (n outward: 1/a on a sphere
  * of radius a) and, for ng in {0, 1, 2} packed scalar fields gcoef_d (ng
- * fields per drop), grad_d[g][3][T] their surface gradients
+ * fields per drop; also 3, e.g. a velocity), grad_d[g][3][T] their surface gradients
  * (I - n n) grad g and, if lap_d is not NULL, lap_d[g][T] their
  * Laplace-Beltrami values div_S grad_S g.  From the SH derivatives of x and
  * g up to second order; gcoef_d and grad_d may be NULL when ng = 0. */
@@ -158,6 +158,18 @@ int ehd_analyze(ehd_ctx* ctx, int nfields, const double* grid_d, double* coef_d)
 /* Positions x0 and outward unit normals n0 at the target nodes,
  * x_d[3][ntargets], n_d[3][ntargets]. */
 int ehd_target_geometry(ehd_ctx* ctx, double* x_d, double* n_d);
+
+/* Area quadrature weights at the target nodes (eq. reg_quadrature):
+ * w_d[T] = (2 pi / n_lon) w_j J, so that the sum of w_d[t] g[t] over a
+ * drop's nodes is the surface integral of g over that drop. */
+int ehd_area_weights(ehd_ctx* ctx, double* w_d);
+
+/* New surface coefficients for the same drops, degrees and grids (e.g. a
+ * time step): copies xcoef_d (3 packed fields per drop, as for
+ * ehd_set_drops) and recomputes the drop centres and the target and
+ * far-source geometry, keeping every table.  Drops a recorded graph.
+ * Synchronous. */
+int ehd_update_shape(ehd_ctx* ctx, const double* xcoef_d);
 
 /* Wait for the context's stream; reports asynchronous HIP failures. */
 int ehd_sync(ehd_ctx* ctx);
@@ -292,6 +304,63 @@ typedef struct ehd_step_params {
  * Synchronous.  The caller moves to the new shape with ehd_set_drops. */
 int ehd_explicit_step(ehd_ctx* ctx, const ehd_step_params* params, const double* gamma_coef_d,
                       double* en_coef_d, double* ucoef_d, double* xnew_coef_d, int* iters);
+
+/* ------------------------------------------------------------------------
+ * Time stepping (Sec. 2.2, Algorithm 1).  Surface points move with the
+ * full velocity (x' = u); following them, eq. surfactant0 reads
+ * dGamma/dt = g_E + g_I with g_E = -Gamma div_S u (its convective terms
+ * plus the frame term u_t . grad_S Gamma) and g_I = Pe^-1 Lap_S Gamma.
+ * ------------------------------------------------------------------------ */
+
+/* g_E = P[-Gamma div_S u] (if gE_d) and g_I = P[inv_pe Lap_S Gamma] (if
+ * gI_d) on the current drops, P the Galerkin projection (ehd_analyze).
+ * ucoef_d: 3 packed fields (may be NULL when gE_d is NULL); gamma_d, gE_d,
+ * gI_d: 1 packed field.  Synchronous. */
+int ehd_surfactant_terms(ehd_ctx* ctx, const double* ucoef_d, const double* gamma_d, double inv_pe, double* gE_d,
+                         double* gI_d);
+
+typedef struct ehd_step_report {
+    double err_drop;   /* max over nodes |dt (u^{n+1/2} - u^n)|                     */
+    double err_surf;   /* max over nodes |dt ((g_E+g_I)^{n+1/2} - (g_E+g_I)^n)|      */
+    int iters[4];      /* GMRES iterations: E_n and u at x^n, E_n and u at the half step */
+    int iters_gamma;   /* GMRES iterations of the implicit surfactant stage          */
+} ehd_step_report;
+
+/* One step of Algorithm 1 from the current drops x^n and gamma_d = Gamma^n
+ * (1 packed field) with physical and solver parameters `params` (its dt is
+ * not used; eos, beta, xs give gamma(Gamma); tol is also the tolerance of
+ * the surfactant solve) and inv_pe = 1/Pe >= 0:
+ *   u^n = velocity at (x^n, Gamma^n)                    (ehd_explicit_step)
+ *   x^{n+1/2} = x^n + dt/2 u^n
+ *   (I - dt/(2 Pe) Lap_S) Gamma^{n+1/2} = Gamma^n + dt/2 g_E(x^n, u^n, Gamma^n)
+ *                                       on x^{n+1/2}   (ehd_solve_surfactant)
+ *   u^{n+1/2} = velocity at (x^{n+1/2}, Gamma^{n+1/2})
+ *   xnew_d    = x^n + dt u^{n+1/2}                                  (midpoint rule)
+ *   gnew_d    = Gamma^n + dt (g_E + g_I)(x^{n+1/2}, u^{n+1/2}, Gamma^{n+1/2})
+ * (the second-order IMEX Runge-Kutta scheme whose implicit stage sits at
+ * the half step).  rep receives the error estimates (differences to the
+ * first-order updates x^n + dt u^n and Gamma^n + dt (g_E + g_I)^n) and the
+ * iteration counts.  The context is left at x^n; accept with
+ * ehd_update_shape(xnew_d).  Synchronous. */
+int ehd_evolve_step(ehd_ctx* ctx, const ehd_step_params* params, double inv_pe, double dt, const double* gamma_d,
+                    double* xnew_d, double* gnew_d, ehd_step_report* rep);
+
+typedef struct ehd_evolve_stats {
+    double t;          /* time reached                                   */
+    double dt;         /* step size proposed for the next step           */
+    double max_err;    /* largest error estimate of an accepted step     */
+    int accepted, rejected;
+    long long matvecs; /* GMRES mat-vecs over all solves                 */
+} ehd_evolve_stats;
+
+/* Adaptive time stepping from t = 0 to t_end (the adaptivity part of
+ * Algorithm 1): a step with error estimate err = max(err_drop, err_surf)
+ * is accepted if err < tol; either way the next step size is
+ * dt (0.9 tol / err)^(1/2), bounded to [0.2 dt, 5 dt]; at most max_steps
+ * attempts.  The context's drops and gamma_d advance in place (accepted
+ * steps only); reparametrisation is not part of it.  Synchronous. */
+int ehd_evolve(ehd_ctx* ctx, const ehd_step_params* params, double inv_pe, double t_end, double dt0, double tol,
+               int max_steps, double* gamma_d, ehd_evolve_stats* stats);
 
 /* ------------------------------------------------------------------------
  * Learned initial guess for the surfactant solve: a multilayer perceptron

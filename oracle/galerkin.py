@@ -198,3 +198,68 @@ def surfactant_apply(s, kappa: float, c: np.ndarray) -> np.ndarray:
 
 def solve_surfactant_dense(s, kappa: float, b: np.ndarray) -> np.ndarray:
     return _dense_solve(lambda v: surfactant_apply(s, kappa, v), np.asarray(b, float), unknown_mask(s, 1))
+
+
+# ---------------------------------------------------------------------------
+# Time stepping (Sec. 2.2, Algorithm 1).  Surface points move with the full
+# velocity u; following them, eq. surfactant0 becomes
+#   dGamma/dt = -Gamma div_S u + Pe^-1 Lap_S Gamma
+# (its convective terms plus the frame term u_t . grad_S Gamma).
+# ---------------------------------------------------------------------------
+def area_weights(s) -> np.ndarray:
+    """(2 pi / nlon) w_j J at every target node (eq. reg_quadrature)."""
+    from . import geom_point
+    out = []
+    for d, th, ph in node_angles(s):
+        p = int(s.p[d])
+        t, w = gauss_legendre(p + 1)
+        j = int(np.argmin(np.abs(np.arccos(t) - th)))
+        _, _, J = geom_point(p, _drop_block(s, s.xcoef, d, 3), th, ph)
+        out.append(2.0 * np.pi / nlon_of(p, s.grid_mode) * w[j] * J)
+    return np.array(out)
+
+
+def surfactant_terms(s, u: np.ndarray, gamma: np.ndarray, inv_pe: float):
+    """g_E = P[-Gamma div_S u] and g_I = P[inv_pe Lap_S Gamma], div_S u the
+    trace of the surface gradients of the three velocity components."""
+    from . import sh_point, surface_point
+    gE, gI = [], []
+    for d, th, ph in node_angles(s):
+        p = int(s.p[d])
+        xd = _drop_block(s, s.xcoef, d, 3)
+        gd = _drop_block(s, gamma, d, 1)
+        gu = surface_point(p, xd, th, ph, gcoef=_drop_block(s, u, d, 3), ng=3)[3]
+        G = sh_point(p, gd, th, ph)[0][0]
+        lapG = surface_point(p, xd, th, ph, gcoef=gd, ng=1, lap=True)[4][0]
+        gE.append(-G * (gu[0][0] + gu[1][1] + gu[2][2]))
+        gI.append(inv_pe * lapG)
+    return project(s, np.array(gE)[None, :], 1), project(s, np.array(gI)[None, :], 1)
+
+
+def _node_values(s, c: np.ndarray, nf: int) -> np.ndarray:
+    from . import sh_point
+    return np.array([sh_point(int(s.p[d]), _drop_block(s, c, d, nf), th, ph, nf=nf)[0]
+                     for d, th, ph in node_angles(s)])
+
+
+def evolve_step(s, lam, R, Q, CaE, Eu, Eq, inv_pe, dt, gamma, eos=0, beta=0.0, xs=0.0):
+    """One step of Algorithm 1: the midpoint rule for x and the second-order
+    IMEX Runge-Kutta scheme for Gamma (implicit stage at the half step):
+        u0 = u(x, Gamma);  xh = x + dt/2 u0
+        (I - dt/(2 Pe) Lap_S(xh)) Gh = Gamma + dt/2 g_E(x, u0, Gamma)
+        uh = u(xh, Gh);  x' = x + dt uh;  Gamma' = Gamma + dt (g_E + g_I)(xh, uh, Gh)
+    Returns (x', Gamma', err_drop, err_surf) with the errors the largest node
+    values of x' - (x + dt u0) and Gamma' - (Gamma + dt (g_E + g_I)(x, u0, Gamma))."""
+    gamma = np.asarray(gamma, float)
+    _, u0, _ = explicit_step(s, lam, R, Q, CaE, Eu, Eq, 0.0, gamma, eos, beta, xs)
+    gE0, gI0 = surfactant_terms(s, u0, gamma, inv_pe)
+    sh = dataclasses.replace(s, xcoef=s.xcoef + 0.5 * dt * u0)
+    rhs = gamma + 0.5 * dt * gE0
+    Gh = solve_surfactant_dense(sh, 0.5 * dt * inv_pe, rhs) if inv_pe > 0 else rhs
+    _, uh, _ = explicit_step(sh, lam, R, Q, CaE, Eu, Eq, 0.0, Gh, eos, beta, xs)
+    gEh, gIh = surfactant_terms(sh, uh, Gh, inv_pe)
+    xnew = s.xcoef + dt * uh
+    gnew = gamma + dt * (gEh + gIh)
+    err_drop = np.abs(_node_values(s, dt * (uh - u0), 3)).max()
+    err_surf = dt * np.abs(_node_values(s, (gEh + gIh) - (gE0 + gI0), 1)).max()
+    return xnew, gnew, err_drop, err_surf

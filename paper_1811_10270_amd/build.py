@@ -6,7 +6,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", "ehdbim.hip"), os.path.join(HERE, "csrc", "solve.hip"),
+SOURCES = [os.path.join(HERE, "csrc", "ehdbim.hip"), os.path.join(HERE, "csrc", "solve.hip"), os.path.join(HERE, "csrc", "evolve.hip"),
            os.path.join(HERE, "csrc", "mlp.hip"), os.path.join(HERE, "csrc", "tables.cpp")]
 LIB = os.path.join(HERE, "libehdbim.so")
 

@@ -312,6 +312,28 @@ __global__ void k_geom_targets(const double* __restrict__ syn, long long vstride
     n0[2 * T + t] = cz * ij;
 }
 
+// Area quadrature weights at the target nodes: w = (2 pi / nlon) w_j J, so
+// that sum_t w[t] g[t] over a drop's nodes is the integral of g over its
+// surface (eq. reg_quadrature).
+__global__ void k_area_weights(const DropInfo* __restrict__ drops, const LegTab* __restrict__ legs,
+                               const int* __restrict__ tdrop, const double* __restrict__ syn, long long vstride,
+                               long long T, double* __restrict__ w)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const DropInfo D = drops[tdrop[t]];
+    const int j = (int)((t - D.toff) / D.nlon_p);
+    double xt[3], xp[3];
+    for (int c = 0; c < 3; ++c) {
+        xt[c] = syn[(3 + c) * vstride + t];
+        xp[c] = syn[(6 + c) * vstride + t];
+    }
+    const double cx = xt[1] * xp[2] - xt[2] * xp[1];
+    const double cy = xt[2] * xp[0] - xt[0] * xp[2];
+    const double cz = xt[0] * xp[1] - xt[1] * xp[0];
+    w[t] = legs[D.leg_pp].wq[j] * sqrt(cx * cx + cy * cy + cz * cz);
+}
+
 __global__ void k_geom_sources(const DropInfo* __restrict__ drops, const LegTab* __restrict__ legs,
                                const int* __restrict__ slot_drop, const double* __restrict__ syn,
                                long long vstride, long long Spad, double* __restrict__ src64,
@@ -1509,6 +1531,41 @@ int ehd_wigner_d(int n, double beta, double* out)
     return EHD_OK;
 }
 
+// Drop centres (the degree-0 coefficients of x over sqrt(4 pi)) into
+// ctx->info, read from the context's copy of x.
+static int read_centres(ehd_ctx* ctx)
+{
+    std::vector<double> c00(3 * ctx->nd);
+    for (int d = 0; d < ctx->nd; ++d)
+        for (int c = 0; c < 3; ++c)
+            EHD_HIP(ctx, hipMemcpyAsync(&c00[3 * d + c],
+                                        ctx->d_x + 3 * ctx->info[d].coff +
+                                            (long long)c * (ctx->info[d].p + 1) * (ctx->info[d].p + 2),
+                                        sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int d = 0; d < ctx->nd; ++d)
+        for (int c = 0; c < 3; ++c) ctx->info[d].c[c] = c00[3 * d + c] / std::sqrt(4.0 * kPi);
+    return EHD_OK;
+}
+
+// Target geometry on the own grids and far-source geometry on the far grids
+// from the context's copy of x.  Synchronous.
+static int build_geometry(ehd_ctx* ctx)
+{
+    const long long T = ctx->T, S = ctx->Spad, vs = ctx->syn_stride;
+    hipLaunchKernelGGL((k_synth<3, true>), dim3(ctx->nrows_p), dim3(kThreads), 0, ctx->stream,
+                       ctx->d_info, ctx->d_legs, 0, ctx->d_rows_p, ctx->d_x, ctx->d_syn, vs);
+    hipLaunchKernelGGL(k_geom_targets, dim3((T + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_syn, vs, T,
+                       ctx->d_tx, ctx->d_tn);
+    hipLaunchKernelGGL((k_synth<3, true>), dim3(ctx->nrows_f), dim3(kThreads), 0, ctx->stream,
+                       ctx->d_info, ctx->d_legs, 1, ctx->d_rows_f, ctx->d_x, ctx->d_syn, vs);
+    hipLaunchKernelGGL(k_geom_sources, dim3((S + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_info,
+                       ctx->d_legs, ctx->d_slot_drop, ctx->d_syn, vs, S, ctx->d_src64, ctx->d_src32);
+    EHD_HIP(ctx, hipGetLastError());
+    EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return EHD_OK;
+}
+
 int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h, const int* q_far_h,
                   int grid_mode, const double* xcoef_d)
 {
@@ -1702,17 +1759,8 @@ int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
     if ((rc = dev_alloc(ctx, &ctx->d_x, 3 * coff))) return rc;
     EHD_HIP(ctx, hipMemcpyAsync(ctx->d_x, xcoef_d, sizeof(double) * 3 * coff, hipMemcpyDeviceToDevice,
                                 ctx->stream));
+    if ((rc = read_centres(ctx))) return rc;
     {
-        std::vector<double> c00(3 * ndrops);
-        for (int d = 0; d < ndrops; ++d)
-            for (int c = 0; c < 3; ++c)
-                EHD_HIP(ctx, hipMemcpyAsync(&c00[3 * d + c],
-                                            xcoef_d + 3 * ctx->info[d].coff +
-                                                (long long)c * (ctx->info[d].p + 1) * (ctx->info[d].p + 2),
-                                            sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-        EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
-        for (int d = 0; d < ndrops; ++d)
-            for (int c = 0; c < 3; ++c) ctx->info[d].c[c] = c00[3 * d + c] / std::sqrt(4.0 * kPi);
         std::vector<double> cen(3 * ndrops);
         for (int d = 0; d < ndrops; ++d)
             for (int c = 0; c < 3; ++c) cen[3 * d + c] = ctx->info[d].c[c];
@@ -1783,18 +1831,30 @@ int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
     if ((rc = dev_alloc(ctx, &ctx->d_info_tmp, ndrops))) return rc;
 
     // --- target geometry (own grids) and far-source geometry
-    const long long vs = ctx->syn_stride;
-    hipLaunchKernelGGL((k_synth<3, true>), dim3(ctx->nrows_p), dim3(kThreads), 0, ctx->stream,
-                       ctx->d_info, ctx->d_legs, 0, ctx->d_rows_p, ctx->d_x, ctx->d_syn, vs);
-    hipLaunchKernelGGL(k_geom_targets, dim3((T + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_syn, vs, T,
-                       ctx->d_tx, ctx->d_tn);
-    hipLaunchKernelGGL((k_synth<3, true>), dim3(ctx->nrows_f), dim3(kThreads), 0, ctx->stream,
-                       ctx->d_info, ctx->d_legs, 1, ctx->d_rows_f, ctx->d_x, ctx->d_syn, vs);
-    hipLaunchKernelGGL(k_geom_sources, dim3((S + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_info,
-                       ctx->d_legs, ctx->d_slot_drop, ctx->d_syn, vs, S, ctx->d_src64, ctx->d_src32);
-    EHD_HIP(ctx, hipGetLastError());
+    return build_geometry(ctx);
+}
+
+int ehd_update_shape(ehd_ctx* ctx, const double* xcoef_d)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ctx->nd) EHD_FAIL(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if (!xcoef_d || ((uintptr_t)xcoef_d) % 8) EHD_FAIL(ctx, EHD_E_ARG, "xcoef_d must be non-NULL and 8-byte aligned");
+    EHD_HIP(ctx, hipSetDevice(ctx->device));
     EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    return EHD_OK;
+    ctx->drop_graph();
+    if (xcoef_d != ctx->d_x)
+        EHD_HIP(ctx, hipMemcpyAsync(ctx->d_x, xcoef_d, sizeof(double) * 3 * ctx->ncoef_total, hipMemcpyDeviceToDevice,
+                                    ctx->stream));
+    int rc = read_centres(ctx);
+    if (rc) return rc;
+    std::vector<double> cen(3 * ctx->nd);
+    for (int d = 0; d < ctx->nd; ++d)
+        for (int c = 0; c < 3; ++c) cen[3 * d + c] = ctx->info[d].c[c];
+    EHD_HIP(ctx, hipMemcpyAsync(ctx->d_centre, cen.data(), sizeof(double) * cen.size(), hipMemcpyHostToDevice,
+                                ctx->stream));
+    EHD_HIP(ctx, hipMemcpyAsync(ctx->d_info, ctx->info.data(), sizeof(DropInfo) * ctx->info.size(),
+                                hipMemcpyHostToDevice, ctx->stream));
+    return build_geometry(ctx);
 }
 
 int ehd_num_targets(const ehd_ctx* ctx, long long* ntargets)
@@ -2039,7 +2099,7 @@ int ehd_surface(ehd_ctx* ctx, int ng, const double* gcoef_d, double* H_d, double
 {
     if (!ctx) return EHD_E_ARG;
     if (!ctx->nd) EHD_FAIL(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
-    if (ng < 0 || ng > 2) EHD_FAIL(ctx, EHD_E_ARG, "ng must be 0, 1 or 2");
+    if (ng < 0 || ng > 3) EHD_FAIL(ctx, EHD_E_ARG, "ng must be 0, 1, 2 or 3");
     if (!H_d || (ng > 0 && (!gcoef_d || !grad_d))) EHD_FAIL(ctx, EHD_E_ARG, "NULL pointer");
     EHD_HIP(ctx, hipSetDevice(ctx->device));
     const dim3 grid(ctx->nrows_p), block(kThreads);
@@ -2049,9 +2109,27 @@ int ehd_surface(ehd_ctx* ctx, int ng, const double* gcoef_d, double* H_d, double
     else if (ng == 1)
         hipLaunchKernelGGL(k_surface<1>, grid, block, 0, ctx->stream, ctx->d_info, ctx->d_legs, ctx->d_rows_p, ctx->d_x,
                            gcoef_d, ctx->T, H_d, grad_d, lap_d);
-    else
+    else if (ng == 2)
         hipLaunchKernelGGL(k_surface<2>, grid, block, 0, ctx->stream, ctx->d_info, ctx->d_legs, ctx->d_rows_p, ctx->d_x,
                            gcoef_d, ctx->T, H_d, grad_d, lap_d);
+    else
+        hipLaunchKernelGGL(k_surface<3>, grid, block, 0, ctx->stream, ctx->d_info, ctx->d_legs, ctx->d_rows_p, ctx->d_x,
+                           gcoef_d, ctx->T, H_d, grad_d, lap_d);
+    EHD_HIP(ctx, hipGetLastError());
+    return EHD_OK;
+}
+
+int ehd_area_weights(ehd_ctx* ctx, double* w_d)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ctx->nd) EHD_FAIL(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if (!w_d) EHD_FAIL(ctx, EHD_E_ARG, "w_d is NULL");
+    EHD_HIP(ctx, hipSetDevice(ctx->device));
+    const long long vs = ctx->syn_stride;
+    hipLaunchKernelGGL((k_synth<3, true>), dim3(ctx->nrows_p), dim3(kThreads), 0, ctx->stream,
+                       ctx->d_info, ctx->d_legs, 0, ctx->d_rows_p, ctx->d_x, ctx->d_syn, vs);
+    hipLaunchKernelGGL(k_area_weights, dim3((ctx->T + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_info,
+                       ctx->d_legs, ctx->d_tdrop, ctx->d_syn, vs, ctx->T, w_d);
     EHD_HIP(ctx, hipGetLastError());
     return EHD_OK;
 }

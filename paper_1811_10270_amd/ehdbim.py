@@ -35,7 +35,8 @@ EXPORTED = ("ehd_create", "ehd_destroy", "ehd_last_error", "ehd_grid_dims", "ehd
             "ehd_solve_velocity", "ehd_surface", "ehd_drop_coefs", "ehd_explicit_step",
             "ehd_solve_surfactant", "ehd_mlp_create", "ehd_mlp_destroy", "ehd_mlp_last_error",
             "ehd_mlp_num_params", "ehd_mlp_get_params", "ehd_mlp_set_params", "ehd_mlp_get_grads",
-            "ehd_mlp_forward", "ehd_mlp_backward", "ehd_mlp_mse", "ehd_mlp_adam")
+            "ehd_mlp_forward", "ehd_mlp_backward", "ehd_mlp_mse", "ehd_mlp_adam", "ehd_area_weights",
+            "ehd_update_shape", "ehd_surfactant_terms", "ehd_evolve_step", "ehd_evolve")
 STAGES = ("densities", "self", "far", "combine")
 DEGREE_CLASSES = (16, 24, 32, 48)   # largest p of each self-interaction kernel class
 
@@ -48,6 +49,18 @@ class StepParams(C.Structure):
                 ("Eu", C.c_double), ("Eq", C.c_double), ("eos", C.c_int), ("beta", C.c_double),
                 ("xs", C.c_double), ("dt", C.c_double), ("far_prec", C.c_int), ("restart", C.c_int),
                 ("maxit", C.c_int), ("tol", C.c_double)]
+
+
+class StepReport(C.Structure):
+    """ehd_step_report (include/ehdbim.h)."""
+    _fields_ = [("err_drop", C.c_double), ("err_surf", C.c_double), ("iters", C.c_int * 4),
+                ("iters_gamma", C.c_int)]
+
+
+class EvolveStats(C.Structure):
+    """ehd_evolve_stats (include/ehdbim.h)."""
+    _fields_ = [("t", C.c_double), ("dt", C.c_double), ("max_err", C.c_double), ("accepted", C.c_int),
+                ("rejected", C.c_int), ("matvecs", C.c_longlong)]
 
 
 class EhdError(RuntimeError):
@@ -107,6 +120,13 @@ def load(path: str = LIB_PATH):
     lib.ehd_mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float]
     lib.ehd_solve_surfactant.argtypes = [vp, dp, vp, C.c_int, C.c_int, C.c_int, C.c_double, vp, ip, dp]
     lib.ehd_explicit_step.argtypes = [vp, C.POINTER(StepParams), vp, vp, vp, vp, ip]
+    lib.ehd_area_weights.argtypes = [vp, vp]
+    lib.ehd_update_shape.argtypes = [vp, vp]
+    lib.ehd_surfactant_terms.argtypes = [vp, vp, vp, C.c_double, vp, vp]
+    lib.ehd_evolve_step.argtypes = [vp, C.POINTER(StepParams), C.c_double, C.c_double, vp, vp, vp,
+                                    C.POINTER(StepReport)]
+    lib.ehd_evolve.argtypes = [vp, C.POINTER(StepParams), C.c_double, C.c_double, C.c_double, C.c_double, C.c_int,
+                               vp, C.POINTER(EvolveStats)]
     lib.ehd_solve_En.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
                                  C.c_double, vp, ip, dp]
     lib.ehd_solve_velocity.argtypes = [vp, C.c_double, vp, C.c_int, C.c_int, C.c_int, C.c_double, vp,
@@ -351,6 +371,43 @@ class Context:
         self._check(self._lib.ehd_explicit_step(self._h, C.byref(prm), _ptr(gamma), _ptr(en), _ptr(u),
                                                 _ptr(xnew), its))
         return its[0], its[1]
+
+    def area_weights(self, w: torch.Tensor):
+        """Area quadrature weights at the target nodes (ehd_area_weights)."""
+        self._check(self._lib.ehd_area_weights(self._h, _ptr(w)))
+
+    def update_shape(self, x: torch.Tensor):
+        """New surface coefficients for the same drops (ehd_update_shape)."""
+        self._check(self._lib.ehd_update_shape(self._h, _ptr(x)))
+
+    def surfactant_terms(self, u: torch.Tensor | None, gamma: torch.Tensor, inv_pe: float,
+                         gE: torch.Tensor | None, gI: torch.Tensor | None):
+        """g_E = P[-Gamma div_S u] and g_I = P[inv_pe Lap_S Gamma] (ehd_surfactant_terms)."""
+        self._check(self._lib.ehd_surfactant_terms(self._h, _ptr(u), _ptr(gamma), float(inv_pe), _ptr(gE),
+                                                   _ptr(gI)))
+
+    @staticmethod
+    def step_params(lam, R, Q, CaE, Eu, Eq, eos=EOS_CLEAN, beta=0.0, xs=0.0, far_prec=FAR_FP64, restart=30,
+                    maxit=200, tol=1e-12) -> StepParams:
+        return StepParams(lam, R, Q, CaE, Eu, Eq, eos, beta, xs, 0.0, far_prec, restart, maxit, tol)
+
+    def evolve_step(self, prm: StepParams, inv_pe: float, dt: float, gamma: torch.Tensor, xnew: torch.Tensor,
+                    gnew: torch.Tensor) -> dict:
+        """One step of Algorithm 1 (ehd_evolve_step); the context stays at x^n."""
+        rep = StepReport()
+        self._check(self._lib.ehd_evolve_step(self._h, C.byref(prm), float(inv_pe), float(dt), _ptr(gamma),
+                                              _ptr(xnew), _ptr(gnew), C.byref(rep)))
+        return {"err_drop": rep.err_drop, "err_surf": rep.err_surf, "iters": list(rep.iters),
+                "iters_gamma": rep.iters_gamma}
+
+    def evolve(self, prm: StepParams, inv_pe: float, t_end: float, dt0: float, tol: float, max_steps: int,
+               gamma: torch.Tensor) -> dict:
+        """Adaptive time stepping to t_end (ehd_evolve); drops and gamma advance in place."""
+        st = EvolveStats()
+        self._check(self._lib.ehd_evolve(self._h, C.byref(prm), float(inv_pe), float(t_end), float(dt0),
+                                         float(tol), int(max_steps), _ptr(gamma), C.byref(st)))
+        return {"t": st.t, "dt": st.dt, "max_err": st.max_err, "accepted": st.accepted, "rejected": st.rejected,
+                "matvecs": st.matvecs}
 
     def num_coefs(self) -> int:
         """Doubles of one packed field of the current drops."""

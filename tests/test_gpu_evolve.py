@@ -1,0 +1,172 @@
+"""GPU: time stepping of Algorithm 1 (Sec. 2.2) against the oracle's step,
+the closed-form diffusion factor on a sphere at rest, and Taylor's
+small-deformation theory for a clean drop relaxing in a uniform field
+(Sec. 3 and the time-scale model of Sec. 4)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import galerkin as G
+from paper_1811_10270_amd import workloads as W
+from test_oracle_evolve import rough_gamma
+from test_oracle_pins import make_susp, sphere_x, tri
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1811_10270_amd import ehdbim
+    ehdbim.load()
+    return ehdbim
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _ctx(E, s):
+    import torch
+    dev = torch.device("cuda", 0)
+    ctx = E.Context(0)
+    ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+    return ctx, dev
+
+
+def _two_drops_with_surfactant():
+    s = W.suspension(2, [5], side=3.5, seed=31, amp=0.08, gap=0.3)
+    g = np.concatenate([rough_gamma(5, 0.05, 40 + d) for d in range(2)])
+    return s, g
+
+
+def test_area_weights(E):
+    import torch
+    p = 8
+    s = make_susp(p, sphere_x(p, R=1.3, centre=(0.5, -0.2, 0.1)))
+    ctx, dev = _ctx(E, s)
+    w = torch.empty(ctx.ntargets, dtype=torch.float64, device=dev)
+    ctx.area_weights(w)
+    area = float(w.sum())
+    ctx.close()
+    assert abs(area - 4 * math.pi * 1.3**2) < 1e-12
+
+
+def test_surfactant_terms_match_oracle(E):
+    import torch
+    s, g = _two_drops_with_surfactant()
+    u = np.concatenate([rough_gamma(5, 0.3, 50 + k) for k in range(6)])      # 3 fields per drop
+    ref_E, ref_I = G.surfactant_terms(s, u, g, 0.3)
+    ctx, dev = _ctx(E, s)
+    nc = ctx.num_coefs()
+    gE = torch.empty(nc, dtype=torch.float64, device=dev)
+    gI = torch.empty(nc, dtype=torch.float64, device=dev)
+    ctx.surfactant_terms(torch.from_numpy(u).to(dev), torch.from_numpy(g).to(dev), 0.3, gE, gI)
+    e1, e2 = rel(gE.cpu().numpy(), ref_E), rel(gI.cpu().numpy(), ref_I)
+    ctx.close()
+    say("surfactant terms err g_E", e1, "g_I", e2)
+    assert e1 < TOL and e2 < TOL
+
+
+def test_evolve_step_matches_oracle(E):
+    import torch
+    s, g = _two_drops_with_surfactant()
+    prm = dict(lam=2.0, R=0.5, Q=2.0, CaE=0.3, Eu=1.0, Eq=0.2)
+    inv_pe, dt = 0.2, 0.02
+    rx, rg, red, res = G.evolve_step(s, prm["lam"], prm["R"], prm["Q"], prm["CaE"], prm["Eu"], prm["Eq"], inv_pe, dt,
+                                     g, eos=1, beta=0.3)
+    ctx, dev = _ctx(E, s)
+    nc = ctx.num_coefs()
+    xn = torch.empty(3 * nc, dtype=torch.float64, device=dev)
+    gn = torch.empty(nc, dtype=torch.float64, device=dev)
+    sp = E.Context.step_params(prm["lam"], prm["R"], prm["Q"], prm["CaE"], prm["Eu"], prm["Eq"], eos=E.EOS_LINEAR,
+                               beta=0.3, tol=1e-13)
+    rep = ctx.evolve_step(sp, inv_pe, dt, torch.from_numpy(g).to(dev), xn, gn)
+    x_back = torch.empty(3 * nc, dtype=torch.float64, device=dev)
+    ctx.drop_coefs(x_back)
+    ctx.close()
+    e1, e2 = rel(xn.cpu().numpy(), rx), rel(gn.cpu().numpy(), rg)
+    say("evolve step err x", e1, "Gamma", e2, "err est", rep["err_drop"], red, rep["err_surf"], res, "iters", rep)
+    assert e1 < TOL and e2 < TOL
+    assert abs(rep["err_drop"] - red) < 1e-9 * red and abs(rep["err_surf"] - res) < 1e-9 * res
+    assert np.array_equal(x_back.cpu().numpy(), s.xcoef)          # the context is left at x^n
+
+
+def test_diffusion_on_a_sphere_at_rest(E):
+    import torch
+    p, dt, inv_pe = 10, 0.05, 0.4
+    s = make_susp(p, sphere_x(p))
+    g = rough_gamma(p, 0.1, 3)
+    ctx, dev = _ctx(E, s)
+    nc = ctx.num_coefs()
+    xn = torch.empty(3 * nc, dtype=torch.float64, device=dev)
+    gn = torch.empty(nc, dtype=torch.float64, device=dev)
+    sp = E.Context.step_params(1.0, 2.0, 1.0, 0.2, 0.0, 0.0, tol=1e-13)
+    ctx.evolve_step(sp, inv_pe, dt, torch.from_numpy(g).to(dev), xn, gn)
+    ctx.close()
+    expect = g.copy()
+    for n in range(p + 1):
+        k = 0.5 * dt * inv_pe * n * (n + 1)
+        for m in range(n + 1):
+            expect[2 * tri(n, m):2 * tri(n, m) + 2] *= (1.0 - k) / (1.0 + k)
+    assert np.abs(gn.cpu().numpy() - expect).max() < 1e-12
+    assert np.abs(xn.cpu().numpy() - s.xcoef).max() < 1e-12
+
+
+def deformation(x: np.ndarray, p: int, T: int, xg: np.ndarray) -> float:
+    """D = (a_par - a_perp)/(a_par + a_perp) of an axisymmetric drop about z:
+    a_par from the poles (only m = 0 terms: P_n0(+-1) = (+-1)^n sqrt((2n+1)/4pi)),
+    a_perp the mean distance from the z axis of the equator nodes (p even)."""
+    nc2 = (p + 1) * (p + 2)
+    z = x[2 * nc2:3 * nc2]
+    top = sum(z[2 * tri(n, 0)] * math.sqrt((2 * n + 1) / (4 * math.pi)) for n in range(p + 1))
+    bot = sum(z[2 * tri(n, 0)] * (-1) ** n * math.sqrt((2 * n + 1) / (4 * math.pi)) for n in range(p + 1))
+    nlon = T // (p + 1)
+    eq = xg[:, (p // 2) * nlon:(p // 2 + 1) * nlon]
+    a_par, a_perp = 0.5 * (top - bot), float(np.mean(np.hypot(eq[0], eq[1])))
+    return (a_par - a_perp) / (a_par + a_perp)
+
+
+def test_clean_drop_relaxes_to_taylor_deformation(E):
+    """Clean drop, lambda = 1, (R, Q) = (2, 1), Ca_E = 0.1, E_u = 1, from the
+    sphere.  Taylor's theory to second order (Sec. 3): D = 9(2 + 3R + 2R^2 - 7Q)
+    / (32 (2+R)^2) (Ca_E + c2 Ca_E^2) with c2 = 3(-308 + 293R^2 + 278R^3 + 184R
+    - 1157RQ + 710Q)/(640 (R+2)^3); the relaxation D(t) = D_T (1 - exp(-t/tau_D)),
+    tau_D = Ca_E (19 lam + 16)(2 lam + 3) / (40 (lam + 1)) in the time unit of
+    the electric velocity scale (Sec. 4)."""
+    import torch
+    p, R, Q, Ca = 12, 2.0, 1.0, 0.1
+    s = make_susp(p, sphere_x(p))
+    ctx, dev = _ctx(E, s)
+    nc, T = ctx.num_coefs(), ctx.ntargets
+    g = torch.zeros(nc, dtype=torch.float64, device=dev)
+    g[0] = math.sqrt(4 * math.pi)
+    sp = E.Context.step_params(1.0, R, Q, Ca, 1.0, 0.0, tol=1e-10)
+    tau = Ca * 35.0 * 5.0 / 80.0
+    x = torch.empty(3 * nc, dtype=torch.float64, device=dev)
+    xg = torch.empty(3, T, dtype=torch.float64, device=dev)
+    hist, t = [], 0.0
+    for t_next in (tau, 8.0 * tau):
+        st = ctx.evolve(sp, 0.0, t_next - t, 1e-3, 1e-5, 20000, g)
+        t += st["t"]
+        ctx.drop_coefs(x)
+        ctx.synthesize(3, x, xg)
+        hist.append((t, deformation(x.cpu().numpy(), p, T, xg.cpu().numpy()), st))
+    ctx.close()
+    c1 = 9.0 * (2 + 3 * R + 2 * R * R - 7 * Q) / (32.0 * (2 + R) ** 2)
+    c2 = 3.0 * (-308 + 293 * R * R + 278 * R ** 3 + 184 * R - 1157 * R * Q + 710 * Q) / (640.0 * (R + 2) ** 3)
+    D1, D2 = c1 * Ca, c1 * (Ca + c2 * Ca * Ca)
+    say("taylor relaxation", hist, "D first order", D1, "second order", D2)
+    (t1, Dtau, _), (t2, Dend, st) = hist
+    assert abs(t2 - 8.0 * tau) < 1e-9
+    assert abs(Dend - D2) < 0.03 * D2
+    assert abs(Dtau / Dend - (1.0 - math.exp(-1.0))) < 0.1
