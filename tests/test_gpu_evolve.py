@@ -170,3 +170,61 @@ def test_clean_drop_relaxes_to_taylor_deformation(E):
     assert abs(t2 - 8.0 * tau) < 1e-9
     assert abs(Dend - D2) < 0.03 * D2
     assert abs(Dtau / Dend - (1.0 - math.exp(-1.0))) < 0.1
+
+
+def test_surfactant_covered_drop_steady_state(E):
+    """Non-diffusing surfactant (Pe = infinity, linear equation of state,
+    beta = 0.5), lambda = 1, (R, Q) = (3, 1), Ca_E = 0.1, E_u = 1, from the
+    sphere with Gamma = 1.  At steady state the Marangoni stress balances the
+    tangential electric stress: no flow (Sec. 3 and Sec. 4), and D follows
+    the second-order theory of Sec. 3, D = 9((1+R)^2 - 4Q)/(16 (2+R)^2) (Ca_E
+    + c2 Ca_E^2), c2 = (R(R(139R + 264) - 696Q + 111) + 336Q - 154)/(80 (R+2)^3).
+    Surfactant mass and drop volume stay constant."""
+    import torch
+    p, R, Q, Ca = 12, 3.0, 1.0, 0.1
+    s = make_susp(p, sphere_x(p))
+    ctx, dev = _ctx(E, s)
+    nc, T = ctx.num_coefs(), ctx.ntargets
+    g = torch.zeros(nc, dtype=torch.float64, device=dev)
+    g[0] = math.sqrt(4 * math.pi)
+    sp = E.Context.step_params(1.0, R, Q, Ca, 1.0, 0.0, eos=E.EOS_LINEAR, beta=0.5, tol=1e-10)
+    w = torch.empty(T, dtype=torch.float64, device=dev)
+    gv = torch.empty(1, T, dtype=torch.float64, device=dev)
+    x0 = torch.empty(3, T, dtype=torch.float64, device=dev)
+    n0 = torch.empty(3, T, dtype=torch.float64, device=dev)
+
+    def invariants():
+        ctx.area_weights(w)
+        ctx.synthesize(1, g, gv)
+        ctx.target_geometry(x0, n0)
+        return float((w * gv[0]).sum()), float((w * (x0 * n0).sum(0)).sum()) / 3.0
+
+    x = torch.empty(3 * nc, dtype=torch.float64, device=dev)
+    xg = torch.empty(3, T, dtype=torch.float64, device=dev)
+
+    def speed():
+        en = torch.zeros(nc, dtype=torch.float64, device=dev)
+        u = torch.zeros(3 * nc, dtype=torch.float64, device=dev)
+        ctx.explicit_step(1.0, R, Q, Ca, 1.0, 0.0, 0.0, en, u, torch.empty_like(x), gamma=g, eos=E.EOS_LINEAR,
+                          beta=0.5, tol=1e-10)
+        ctx.synthesize(3, u, xg)
+        return float(xg.abs().max())
+
+    m0, v0 = invariants()
+    u0 = speed()
+    st = ctx.evolve(sp, 0.0, 6.0, 1e-3, 1e-5, 20000, g)
+    m1, v1 = invariants()
+    umax = speed()
+    ctx.drop_coefs(x)
+    ctx.synthesize(3, x, xg)
+    D = deformation(x.cpu().numpy(), p, T, xg.cpu().numpy())
+    ctx.close()
+    c1 = 9.0 * ((1 + R) ** 2 - 4 * Q) / (16.0 * (2 + R) ** 2)
+    c2 = (R * (R * (139 * R + 264) - 696 * Q + 111) + 336 * Q - 154) / (80.0 * (R + 2) ** 3)
+    D2 = c1 * (Ca + c2 * Ca * Ca)
+    say("surfactant-covered drop", st, "D", D, "second order", D2, "first order", c1 * Ca, "mass", m1 / m0 - 1,
+        "volume", v1 / v0 - 1, "max |u| at the start", u0, "at the end", umax)
+    assert abs(st["t"] - 6.0) < 1e-9
+    assert abs(D - D2) < 0.01 * D2
+    assert abs(m1 / m0 - 1) < 1e-6 and abs(v1 / v0 - 1) < 1e-6
+    assert umax < 1e-2 * u0                                       # the flow has stopped
