@@ -210,6 +210,61 @@ def bench_step(args, torch, E, W, dev):
     return 0
 
 
+def bench_evolve(args, torch, E, W, dev):
+    """Steps of Algorithm 1 (ehd_evolve_step: two E_n solves, two velocity
+    solves, the implicit surfactant solve, surface terms, midpoint and IMEX
+    updates) from the workload's drops with a non-uniform surfactant."""
+    import numpy as np
+    s = W.WORKLOADS[args.workload](args.grid_mode)
+    far_prec = E.FAR_FP32C if args.far_prec == "fp32c" else E.FAR_FP64
+    ctx = E.Context(0)
+    ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+    nc = ctx.num_coefs()
+    rng = np.random.default_rng(7)
+    g = np.zeros(nc)
+    off = 0
+    for p in (int(v) for v in s.p):
+        g[off] = math.sqrt(4 * math.pi)
+        for n in range(1, p + 1):
+            for m in range(n + 1):
+                k = off + 2 * (n * (n + 1) // 2 + m)
+                g[k] = 0.05 * rng.standard_normal() / n ** 2
+                if m:
+                    g[k + 1] = 0.05 * rng.standard_normal() / n ** 2
+        off += (p + 1) * (p + 2)
+    gd = torch.from_numpy(g).to(dev)
+    xn = torch.empty(3 * nc, dtype=torch.float64, device=dev)
+    gn = torch.empty(nc, dtype=torch.float64, device=dev)
+    tol = 1e-10 if far_prec == E.FAR_FP64 else 1e-6
+    prm = dict(lam=2.0, R=0.5, Q=2.0, CaE=0.3, Eu=1.0, Eq=0.0, eos="linear", beta=0.5, Pe=10.0, dt=0.01)
+    sp = E.Context.step_params(prm["lam"], prm["R"], prm["Q"], prm["CaE"], prm["Eu"], prm["Eq"], eos=E.EOS_LINEAR,
+                               beta=prm["beta"], far_prec=far_prec, tol=tol)
+    for _ in range(max(args.warmup, 1)):
+        rep = ctx.evolve_step(sp, 1.0 / prm["Pe"], prm["dt"], gd, xn, gn)
+    K = args.steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        rep = ctx.evolve_step(sp, 1.0 / prm["Pe"], prm["dt"], gd, xn, gn)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / K
+    ctx.close()
+    res = {
+        "metric": "time steps of Algorithm 1 (midpoint drops + IMEX-RK2 surfactant), tol %g" % tol,
+        "value": 1.0 / dt, "unit": "steps/s", "n_gpus": 1, "steps": K, "warmup": max(args.warmup, 1),
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if far_prec == E.FAR_FP64 else "f64+f32", "data": "synthetic",
+        "config": dict({"workload": args.workload, "ndrops": s.ndrops, "p": sorted(set(int(v) for v in s.p)),
+                        "targets": ctx.ntargets,
+                        "far_prec": "fp64" if far_prec == E.FAR_FP64 else "fp32c"}, **prm),
+        "gmres_iterations": {"E_n": [rep["iters"][0], rep["iters"][2]], "velocity": [rep["iters"][1], rep["iters"][3]],
+                             "surfactant": rep["iters_gamma"]},
+        "error_estimates": {"drop": rep["err_drop"], "surfactant": rep["err_surf"]},
+    }
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def bench_learned(args, torch, E, W, dev):
     """Learned initial guess for the implicit surfactant-diffusion solve:
     generate the training solves with the library's preconditioned GMRES,
@@ -277,6 +332,9 @@ def main(argv=None):
                     help="time one explicit step of the method (E_n solve, forces, velocity solve, "
                          "position update) on two_drops_p32 with lambda = 2, R = 0.5, Q = 2, uniform "
                          "field E_u = 1, Ca_E = 0.3, clean drops, dt = 0.01")
+    ap.add_argument("--evolve", action="store_true",
+                    help="time steps of Algorithm 1 (ehd_evolve_step) on two_drops_p32 with a linear-law "
+                         "surfactant, Pe = 10, lambda = 2, R = 0.5, Q = 2, Ca_E = 0.3, E_u = 1, dt = 0.01")
     ap.add_argument("--learned", action="store_true",
                     help="train the learned initial guess of the implicit surfactant solve and count "
                          "GMRES iterations to 1e-10 with and without it (--steps = test solves)")
@@ -302,11 +360,13 @@ def main(argv=None):
         return 1
     dev = torch.device("cuda", 0)
     if args.workload is None:
-        args.workload = "two_drops_p32" if (args.solve or args.step) else "batched_64_mixed_p"
+        args.workload = "two_drops_p32" if (args.solve or args.step or args.evolve) else "batched_64_mixed_p"
     if args.far_prec is None:
-        args.far_prec = "fp64" if (args.solve or args.step) else "fp32c"
+        args.far_prec = "fp64" if (args.solve or args.step or args.evolve) else "fp32c"
     if args.learned:
         return bench_learned(args, torch, E, W, dev)
+    if args.evolve:
+        return bench_evolve(args, torch, E, W, dev)
     if args.step:
         return bench_step(args, torch, E, W, dev)
     if args.solve:
