@@ -47,10 +47,10 @@ def self_flops_per_drop(p: int, q: int, grid_mode: int) -> float:
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs
 # recorded in profiles/hbm_traffic_batched_64_mixed_p.md (counters scaled by a
 # 1 GiB copy), valid only for the kernel source they were taken with.
-TRAFFIC_SOURCE_SHA256 = "aca12525b1109307c1d11fe726d1dcb49f28803489ad1edc7236537ad25d42ee"
+TRAFFIC_SOURCE_SHA256 = "fe685c2f641df51e831a8d171ca5434b644905fbce47bee7401f6d6ecd1661d4"
 TRAFFIC_WORKLOAD = "batched_64_mixed_p"
-TRAFFIC_BYTES = {"k_self<48>": 7.058e8, "k_self<32>": 1.201e8, "k_self<24>": 2.541e7,
-                 "k_self<16>": 7.353e6, "k_far32": 8.133e8}
+TRAFFIC_BYTES = {"k_self<48>": 6.505e8, "k_self<32>": 1.201e8, "k_self<24>": 2.540e7,
+                 "k_self<16>": 7.367e6, "k_far32": 7.981e8}
 
 
 def measured_traffic(kernel: str, workload: str):

@@ -228,3 +228,35 @@ def test_surfactant_covered_drop_steady_state(E):
     assert abs(D - D2) < 0.01 * D2
     assert abs(m1 / m0 - 1) < 1e-6 and abs(v1 / v0 - 1) < 1e-6
     assert umax < 1e-2 * u0                                       # the flow has stopped
+
+
+def test_evolve_argument_errors(E):
+    import torch
+    p = 4
+    s = make_susp(p, sphere_x(p))
+    ctx, dev = _ctx(E, s)
+    nc = ctx.num_coefs()
+    g = torch.zeros(nc, dtype=torch.float64, device=dev)
+    g[0] = math.sqrt(4 * math.pi)
+    xn = torch.empty(3 * nc, dtype=torch.float64, device=dev)
+    gn = torch.empty(nc, dtype=torch.float64, device=dev)
+    sp = E.Context.step_params(1.0, 2.0, 1.0, 0.2, 1.0, 0.0)
+    for kw in (dict(dt=0.0), dict(dt=-1.0), dict(inv_pe=-0.1)):
+        a = dict(dt=0.01, inv_pe=0.0)
+        a.update(kw)
+        with pytest.raises(E.EhdError):
+            ctx.evolve_step(sp, a["inv_pe"], a["dt"], g, xn, gn)
+    for args in ((1.0, -1.0, 1e-3, 1e-5, 10), (1.0, 1.0, 0.0, 1e-5, 10), (1.0, 1.0, 1e-3, 0.0, 10),
+                 (1.0, 1.0, 1e-3, 1e-5, 0), (-1.0, 1.0, 1e-3, 1e-5, 10)):      # (inv_pe, t_end, dt0, tol, max_steps)
+        with pytest.raises(E.EhdError):
+            ctx.evolve(sp, *args, g)
+    bad = E.Context.step_params(1.0, 2.0, 1.0, 0.0, 1.0, 0.0)       # Ca_E = 0
+    with pytest.raises(E.EhdError):
+        ctx.evolve_step(bad, 0.0, 0.01, g, xn, gn)
+    with pytest.raises(E.EhdError):
+        ctx.surfactant_terms(None, g, 0.0, gn, None)                  # g_E needs a velocity
+    with pytest.raises(TypeError):
+        ctx.update_shape(torch.zeros(3 * nc, dtype=torch.float64))   # host tensor
+    st = ctx.evolve(sp, 0.0, 0.0, 1e-3, 1e-5, 10, g)                 # t_end = 0: nothing to do
+    assert st["t"] == 0.0 and st["accepted"] == 0
+    ctx.close()
