@@ -89,6 +89,7 @@ enum { EHD_GRID_PAPER = 0, EHD_GRID_2P = 1 };
 #define EHD_MAX_P 48
 /* Largest upsampled grid degree. */
 #define EHD_MAX_Q 160
+#define EHD_MAX_Q_CHECK 400   /* check grids of nearly singular targets (ehd_set_near) */
 
 /* Create a context on HIP device `device`; `stream` is a hipStream_t (NULL:
  * the null stream), e.g. torch.cuda.current_stream().cuda_stream.
@@ -163,6 +164,34 @@ int ehd_target_geometry(ehd_ctx* ctx, double* x_d, double* n_d);
  * w_d[T] = (2 pi / n_lon) w_j J, so that the sum of w_d[t] g[t] over a
  * drop's nodes is the surface integral of g over that drop. */
 int ehd_area_weights(ehd_ctx* ctx, double* w_d);
+
+/* Nearly singular targets (Sec. 2.1, the interpolation approach).  With
+ * delta > 0, every later ehd_layer_potentials call corrects, for each
+ * target x0 closer than delta to the surface of another drop j, drop j's
+ * contribution to the far part:
+ *   y: the point of drop j closest to x0 (damped Gauss-Newton in the
+ *      surface parameters from the nearest grid node), s_t = |x0 - y|,
+ *      nu = (x0 - y) / s_t;
+ *   the exterior limit at y: drop j's on-surface singular-rule values,
+ *      projected to degree p and evaluated at y, plus the jumps (S, S_L
+ *      continuous; D: -u(y); L: +sigma(y)/2; K* with the target normal n0:
+ *      -n0 . grad_S S_L(y) + (K*(y) + sigma(y)/2)(n0 . n_y));
+ *   m check points y + s_k nu, s_k = s_check (1 + k/2), k = 0..m-1, where
+ *      drop j's regular rule on a degree-q_check grid is summed (FP64);
+ *   the Lagrange polynomial through (0, limit) and (s_k, values), at s_t,
+ *      replaces drop j's regular-rule value at x0.
+ * The pairs are found for the current shapes here and again by
+ * ehd_update_shape; ehd_set_drops switches the correction off.  delta = 0
+ * switches it off.  m in [2, 12], q_check in [p, EHD_MAX_Q_CHECK] for every
+ * drop, s_check > 0 and delta <= s_check (1 + (m-1)/2) (no extrapolation).
+ * The regular rule on a degree-q grid of a drop of radius a is accurate
+ * beyond about 3 pi a / q: delta should exceed that distance for q_far
+ * (targets farther out keep the plain sums) and s_check for q_check.
+ * Synchronous. */
+int ehd_set_near(ehd_ctx* ctx, double delta, double s_check, int m, int q_check);
+
+/* Number of (target, drop) pairs the nearly singular correction treats. */
+int ehd_near_pairs(const ehd_ctx* ctx, long long* npairs);
 
 /* New surface coefficients for the same drops, degrees and grids (e.g. a
  * time step): copies xcoef_d (3 packed fields per drop, as for

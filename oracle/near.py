@@ -5,7 +5,7 @@ target farther out, and a 1D Lagrange interpolation at the target).
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``): plain FP64, no code
 shared with the HIP path.
 
-For a target x0 outside drop j, closer than delta to its surface:
+For a target x0 outside drop j (closer than a threshold to its surface):
   1. y = x(theta*, phi*) the closest point of drop j's surface (least
      squares in the surface parameters), s_t = |x0 - y|, nu = (x0 - y) / s_t;
   2. the limit at y, from the exterior, of drop j's layer potentials: the
@@ -14,7 +14,7 @@ For a target x0 outside drop j, closer than delta to its surface:
      (S, S_L continuous; D: -u(y); L: +sigma(y)/2; K* with the target normal
      n0: -n0 . grad_S S_L(y) + (K*(y) + sigma(y)/2)(n0 . n_y), since K* is
      -n0 . grad S_L and the normal derivative of S_L jumps by -sigma/2);
-  3. drop j's regular-rule sums at y + s_k nu, s_k = delta (1 + (k - 1)/2),
+  3. drop j's regular-rule sums at y + s_k nu, s_k = s_check (1 + (k - 1)/2),
      k = 1..m (the target's normal n0 for K*), on an upsampled grid;
   4. the Lagrange polynomial through (0, limit) and (s_k, values), at s_t.
 Returns drop j's corrected contribution at x0 and its plain regular-rule
@@ -96,7 +96,7 @@ def surface_limit(s, j: int, th: float, ph: float, n0: np.ndarray) -> np.ndarray
     return out
 
 
-def near_value(s, j: int, x0: np.ndarray, n0: np.ndarray, delta: float, m: int = 4, q_check: int | None = None):
+def near_value(s, j: int, x0: np.ndarray, n0: np.ndarray, s_check: float, m: int = 4, q_check: int | None = None):
     """(corrected, plain) contribution of drop j at the target x0 (normal n0);
     the check points use drop j's regular rule on a degree-q_check grid
     (default its q_far)."""
@@ -107,7 +107,7 @@ def near_value(s, j: int, x0: np.ndarray, n0: np.ndarray, delta: float, m: int =
     y = sh_point(p, sj.xcoef, th, ph, nf=3)[0]
     st = float(np.linalg.norm(x0 - y))
     nu = (x0 - y) / st
-    sk = delta * (1.0 + 0.5 * np.arange(m))
+    sk = s_check * (1.0 + 0.5 * np.arange(m))
     pts = y[:, None] + nu[:, None] * sk[None, :]
     chk = far_points(sc, pts, np.repeat(n0[:, None], m, axis=1))
     nodes = np.concatenate([[0.0], sk])

@@ -35,6 +35,7 @@ constexpr double kInv4Pi = 0.25 / kPi;
 constexpr int kThreads = 256;
 constexpr int kTile = 256;        // far-field sources per LDS tile
 constexpr int kRec64 = 14;        // x(3) n(3) w(1) wf(3) wu(3) wsig(1)
+constexpr int kNearMaxM = 12;     // nearly singular targets: most check points per line
 constexpr int kRec32 = 13;        // x-c(3) n(3) wf(3) wu(3) wsig(1)
 constexpr int kMaxChunks = 16;    // far field: largest number of source chunks
 
@@ -1188,6 +1189,233 @@ __global__ void k_analyze(const DropInfo* __restrict__ drops, const LegTab* __re
     }
 }
 
+// ---------------------------------------------------------------------------
+// Nearly singular targets (Sec. 2.1, the interpolation approach): for a
+// target x0 closer than delta to the surface of another drop j, drop j's
+// contribution is replaced by the value at x0 of the polynomial through
+//   s = 0:   the limit from outside at the closest surface point y, i.e. the
+//            on-surface singular-rule values of drop j projected to degree p
+//            and evaluated at y, plus the jumps (S, S_L continuous; D: -u(y);
+//            L: +sigma(y)/2; K* with the target normal n0:
+//            -n0 . grad_S S_L(y) + (K*(y) + sigma(y)/2)(n0 . n_y));
+//   s = s_k: drop j's regular-rule sums at y + s_k nu on a finer check grid,
+//            s_k = s_check (1 + k/2), k = 0..m-1, nu = (x0 - y)/|x0 - y|;
+// at s = |x0 - y|; the regular-rule value of drop j at x0 (what the far sum
+// added) is subtracted.
+// ---------------------------------------------------------------------------
+struct NearPair {
+    int t, j;                 // target, source drop
+    double th, ph;            // closest point parameters on drop j
+    double y[3], ny[3], xt[3], xp[3], nu[3];   // point, unit normal, d/dtheta, d/dphi, line direction
+    double st;                // |x0 - y|
+    long long legoff;         // Pbar then dPbar/dtheta at cos(th): 2 ncoef(p_j) doubles
+};
+
+// Check-grid geometry from synthesized x, x_theta, x_phi/sin: records
+// x(3) n(3) w(1) in the layout of the far-source records.
+__global__ void k_fine_geom(const DropInfo* __restrict__ fdrops, const LegTab* __restrict__ flegs,
+                            const int* __restrict__ node_drop, const double* __restrict__ syn, long long N,
+                            double* __restrict__ rec)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= N) return;
+    const DropInfo D = fdrops[node_drop[s]];
+    const LegTab L = flegs[D.leg_pf];
+    const int i = (int)((s - D.soff) / L.nlon);
+    double xt[3], xp[3];
+    for (int c = 0; c < 3; ++c) {
+        rec[c * N + s] = syn[c * N + s];
+        xt[c] = syn[(3 + c) * N + s];
+        xp[c] = syn[(6 + c) * N + s];
+    }
+    const double cx = xt[1] * xp[2] - xt[2] * xp[1];
+    const double cy = xt[2] * xp[0] - xt[0] * xp[2];
+    const double cz = xt[0] * xp[1] - xt[1] * xp[0];
+    const double J = sqrt(cx * cx + cy * cy + cz * cz);
+    rec[3 * N + s] = cx / J;
+    rec[4 * N + s] = cy / J;
+    rec[5 * N + s] = cz / J;
+    rec[6 * N + s] = L.wq[i] * J;
+}
+
+// Weighted densities of the check-grid records (u = f when no u is given).
+__global__ void k_fine_dens(const double* __restrict__ synf, const double* __restrict__ synu,
+                            const double* __restrict__ syns, long long N, double* __restrict__ rec)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= N) return;
+    const double w = rec[6 * N + s];
+    for (int c = 0; c < 3; ++c) {
+        const double f = synf ? w * synf[c * N + s] : 0.0;
+        rec[(7 + c) * N + s] = f;
+        rec[(10 + c) * N + s] = synu ? w * synu[c * N + s] : f;
+    }
+    rec[13 * N + s] = syns ? w * syns[s] : 0.0;
+}
+
+// Exterior limits at the closest points, one block per pair.  selfc: the
+// projected on-surface self values (9 fields per drop); u: u or f (3 fields),
+// sig (1 field), each in the packed per-drop layout; lim[pair][9].
+__global__ __launch_bounds__(kThreads) void k_near_limit(const NearPair* __restrict__ pairs,
+                                                         const DropInfo* __restrict__ drops,
+                                                         const double* __restrict__ legv,
+                                                         const double* __restrict__ selfc,
+                                                         const double* __restrict__ ucoef,
+                                                         const double* __restrict__ scoef,
+                                                         const double* __restrict__ tnrm, long long T,
+                                                         double* __restrict__ lim)
+{
+    constexpr int NA = 9 + 3 + 1 + 2;     // self fields, u, sigma, d/dtheta and d/dphi of S_L
+    const NearPair P = pairs[blockIdx.x];
+    const DropInfo D = drops[P.j];
+    const int p = D.p;
+    const long nc = ncoef(p);
+    const double* Pb = legv + P.legoff;
+    const double* dPb = Pb + nc;
+    double acc[NA];
+    for (int a = 0; a < NA; ++a) acc[a] = 0.0;
+    for (long k = threadIdx.x; k < nc; k += blockDim.x) {
+        const int n = tri_n((int)k), m = (int)k - n * (n + 1) / 2;
+        double sm, cm;
+        sincos(m * P.ph, &sm, &cm);
+        const double mult = m ? 2.0 : 1.0, pv = Pb[k], dv = dPb[k];
+        auto re = [&](const double* c) { return c[2 * k] * cm - (m ? c[2 * k + 1] : 0.0) * sm; };
+        for (int f = 0; f < 9; ++f) acc[f] += mult * pv * re(selfc + 9 * D.coff + f * 2 * nc);
+        for (int c = 0; c < 3; ++c) acc[9 + c] += mult * pv * re(ucoef + 3 * D.coff + c * 2 * nc);
+        acc[12] += mult * pv * re(scoef + D.coff);
+        const double* sl = selfc + 9 * D.coff + 6 * 2 * nc;
+        acc[13] += mult * dv * re(sl);
+        acc[14] -= mult * m * pv * (sl[2 * k] * sm + (m ? sl[2 * k + 1] : 0.0) * cm);
+    }
+    __shared__ double red[kThreads / 64][NA];
+    for (int a = 0; a < NA; ++a) {
+        const double v = wave_sum(acc[a]);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][a] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double v[NA];
+    for (int a = 0; a < NA; ++a) {
+        v[a] = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) v[a] += red[w][a];
+    }
+    const double E = P.xt[0] * P.xt[0] + P.xt[1] * P.xt[1] + P.xt[2] * P.xt[2];
+    const double F = P.xt[0] * P.xp[0] + P.xt[1] * P.xp[1] + P.xt[2] * P.xp[2];
+    const double G = P.xp[0] * P.xp[0] + P.xp[1] * P.xp[1] + P.xp[2] * P.xp[2];
+    const double iW2 = 1.0 / (E * G - F * F);
+    const double a = (G * v[13] - F * v[14]) * iW2, b = (E * v[14] - F * v[13]) * iW2;
+    double n0g = 0.0, n0n = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        const double n0 = tnrm[c * T + P.t];
+        n0g += n0 * (a * P.xt[c] + b * P.xp[c]);
+        n0n += n0 * P.ny[c];
+    }
+    double* o = lim + 9 * (long long)blockIdx.x;
+    for (int c = 0; c < 3; ++c) {
+        o[c] = v[c];
+        o[3 + c] = v[3 + c] - v[9 + c];
+    }
+    o[6] = v[6];
+    o[7] = v[7] + 0.5 * v[12];
+    o[8] = -n0g + (v[8] + 0.5 * v[12]) * n0n;
+}
+
+// Regular-rule sums of one drop at one point, one block per (pair, k):
+// k < m the check points y + s_k nu on the check grid, k = m the target x0
+// on drop j's far-grid records.  out[pair][k][9], scaled by 1/(4 pi).
+__global__ __launch_bounds__(kThreads) void k_near_check(const NearPair* __restrict__ pairs, int m, double sc,
+                                                         const double* __restrict__ frec, long long Nf,
+                                                         const long long* __restrict__ foff,
+                                                         const int* __restrict__ fidx,
+                                                         const double* __restrict__ src, long long Spad,
+                                                         const DropInfo* __restrict__ drops,
+                                                         const double* __restrict__ tx,
+                                                         const double* __restrict__ tnrm, long long T,
+                                                         double* __restrict__ out)
+{
+    const int pi = blockIdx.x / (m + 1), k = blockIdx.x % (m + 1);
+    const NearPair P = pairs[pi];
+    double x0[3], n0[3];
+    for (int c = 0; c < 3; ++c) {
+        n0[c] = tnrm[c * T + P.t];
+        x0[c] = k < m ? P.y[c] + sc * (1.0 + 0.5 * k) * P.nu[c] : tx[c * T + P.t];
+    }
+    const double* rec;
+    long long ld, s0, s1;
+    if (k < m) {
+        const int fd = fidx[P.j];
+        rec = frec;
+        ld = Nf;
+        s0 = foff[fd];
+        s1 = foff[fd + 1];
+    } else {
+        const DropInfo D = drops[P.j];
+        rec = src;
+        ld = Spad;
+        s0 = D.soff;
+        s1 = D.soff + D.ns;
+    }
+    double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (long long s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
+        const double hx = x0[0] - rec[s], hy = x0[1] - rec[ld + s], hz = x0[2] - rec[2 * ld + s];
+        const double ir = 1.0 / sqrt(hx * hx + hy * hy + hz * hz), ir2 = ir * ir, ir3 = ir * ir2;
+        const double hn = hx * rec[3 * ld + s] + hy * rec[4 * ld + s] + hz * rec[5 * ld + s];
+        const double f0 = rec[7 * ld + s], f1 = rec[8 * ld + s], f2 = rec[9 * ld + s];
+        const double hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
+        a[0] += f0 * ir + hx * hf;
+        a[1] += f1 * ir + hy * hf;
+        a[2] += f2 * ir + hz * hf;
+        const double hu = hx * rec[10 * ld + s] + hy * rec[11 * ld + s] + hz * rec[12 * ld + s];
+        const double tq = -6.0 * hu * hn * ir3 * ir2;
+        a[3] += tq * hx;
+        a[4] += tq * hy;
+        a[5] += tq * hz;
+        const double sg = rec[13 * ld + s];
+        a[6] += sg * ir;
+        a[7] += sg * hn * ir3;
+        a[8] += sg * (hx * n0[0] + hy * n0[1] + hz * n0[2]) * ir3;
+    }
+    __shared__ double red[kThreads / 64][9];
+    for (int c = 0; c < 9; ++c) {
+        const double v = wave_sum(a[c]);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        double v = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) v += red[w][threadIdx.x];
+        out[(long long)blockIdx.x * 9 + threadIdx.x] = v * kInv4Pi;
+    }
+}
+
+// Lagrange interpolation and the correction of the output rows, one thread
+// per pair (pairs sharing a target add atomically).
+__global__ void k_near_apply(const NearPair* __restrict__ pairs, int npairs, int m, double sc,
+                             const double* __restrict__ lim, const double* __restrict__ chk, RowMap rows,
+                             long long T, double* __restrict__ out)
+{
+    const int pi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pi >= npairs) return;
+    const NearPair P = pairs[pi];
+    double nodes[kNearMaxM + 1];
+    nodes[0] = 0.0;
+    for (int k = 0; k < m; ++k) nodes[k + 1] = sc * (1.0 + 0.5 * k);
+    double w[kNearMaxM + 1];
+    for (int k = 0; k <= m; ++k) {
+        double l = 1.0;
+        for (int i = 0; i <= m; ++i)
+            if (i != k) l *= (P.st - nodes[i]) / (nodes[k] - nodes[i]);
+        w[k] = l;
+    }
+    const double* c0 = chk + (long long)pi * (m + 1) * 9;
+    for (int r = 0; r < rows.n; ++r) {
+        const int c = rows.comp[r];
+        double v = w[0] * lim[9 * (long long)pi + c];
+        for (int k = 0; k < m; ++k) v += w[k + 1] * c0[k * 9 + c];
+        atomicAdd(out + (long long)r * T + P.t, v - c0[m * 9 + c]);
+    }
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1297,8 +1525,41 @@ struct ehd_ctx {
     }
     DropInfo* d_info_tmp = nullptr;  // per-field views for ehd_synthesize
 
+    // nearly singular targets (ehd_set_near); its buffers live in near_allocs
+    struct Near {
+        double delta = 0.0, sc = 0.0;
+        int m = 0, qc = 0;
+        bool on = false;
+        int npairs = 0, nfd = 0;         // pairs, drops with a check grid
+        long long nf = 0;                // check-grid nodes
+        std::vector<void*> allocs;
+        NearPair* d_pairs = nullptr;
+        double* d_legv = nullptr;        // Pbar, dPbar at the closest points
+        DropInfo* d_fdrops = nullptr;    // check-grid views of the drops (leg_pf, soff)
+        LegTab* d_flegs = nullptr;
+        int2* d_frows = nullptr;
+        int nfrows = 0;
+        int* d_node_drop = nullptr;      // [nf] check-grid drop of each node
+        long long* d_foff = nullptr;     // [nfd + 1] first node of each check grid
+        int* d_fidx = nullptr;           // [nd] check grid of each drop (-1: none)
+        double* d_frec = nullptr;        // [kRec64][nf]
+        double* d_fsyn = nullptr;        // [9][nf]
+        double* d_selfc = nullptr;       // [9][ncoef_total] projected self values
+        double* d_lim = nullptr;         // [npairs][9]
+        double* d_chk = nullptr;         // [npairs][m+1][9]
+        void release()
+        {
+            for (void* a : allocs) (void)hipFree(a);
+            allocs.clear();
+            npairs = nfd = nfrows = 0;
+            nf = 0;
+        }
+    } near;
+
     void free_all()
     {
+        near.release();
+        near.on = false;
         for (void* a : allocs) (void)hipFree(a);
         allocs.clear();
         d_info = nullptr;
@@ -1470,6 +1731,267 @@ int ehd_ctx_fail(ehd_ctx* ctx, int code, const char* msg)
 {
     ctx->err = msg;
     return code;
+}
+
+// --- nearly singular targets: host set-up ---------------------------------
+template <typename T>
+static int near_upload(ehd_ctx* ctx, T** out, const std::vector<T>& h)
+{
+    void* p = nullptr;
+    EHD_HIP(ctx, hipMalloc(&p, sizeof(T) * std::max<size_t>(h.size(), 1)));
+    ctx->near.allocs.push_back(p);
+    if (!h.empty())
+        EHD_HIP(ctx, hipMemcpyAsync(p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, ctx->stream));
+    *out = (T*)p;
+    return EHD_OK;
+}
+
+// x, dx/dtheta and dx/dphi of one drop's surface (3 packed fields) at (th, ph).
+static void host_surface_point(int p, const double* xc, double th, double ph, double x[3], double xt[3], double xp[3],
+                               std::vector<double>* Pout = nullptr, std::vector<double>* dPout = nullptr)
+{
+    std::vector<double> P, dP;
+    ehd::legendre_tables(p, std::vector<double>{std::cos(th)}, P, dP);
+    const long nc = ncoef(p);
+    for (int c = 0; c < 3; ++c) x[c] = xt[c] = xp[c] = 0.0;
+    for (int m = 0; m <= p; ++m) {
+        const double cm = std::cos(m * ph), sm = std::sin(m * ph), mult = m ? 2.0 : 1.0;
+        for (int n = m; n <= p; ++n) {
+            const long k = tri(n, m);
+            for (int c = 0; c < 3; ++c) {
+                const double cr = xc[2 * (c * nc + k)], ci = m ? xc[2 * (c * nc + k) + 1] : 0.0;
+                const double re = cr * cm - ci * sm;
+                x[c] += mult * re * P[k];
+                xt[c] += mult * re * dP[k];
+                xp[c] -= mult * m * (cr * sm + ci * cm) * P[k];
+            }
+        }
+    }
+    if (Pout) *Pout = P;
+    if (dPout) *dPout = dP;
+}
+
+// Near pairs of the current shapes, closest points, check grids.
+static int near_build(ehd_ctx* ctx)
+{
+    ehd_ctx::Near& N = ctx->near;
+    EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    N.release();
+    if (!N.on) return EHD_OK;
+    const long long T = ctx->T;
+    std::vector<double> xh(3 * ctx->ncoef_total), tx(3 * T);
+    EHD_HIP(ctx, hipMemcpyAsync(xh.data(), ctx->d_x, sizeof(double) * xh.size(), hipMemcpyDeviceToHost, ctx->stream));
+    EHD_HIP(ctx, hipMemcpyAsync(tx.data(), ctx->d_tx, sizeof(double) * tx.size(), hipMemcpyDeviceToHost, ctx->stream));
+    EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const int nd = ctx->nd;
+    // radius of each drop about its centre over its grid nodes
+    std::vector<double> rho(nd, 0.0);
+    std::vector<int> tdrop(T);
+    for (int d = 0; d < nd; ++d) {
+        const DropInfo& D = ctx->info[d];
+        const long long n = (long long)(D.p + 1) * D.nlon_p;
+        for (long long t = D.toff; t < D.toff + n; ++t) {
+            tdrop[t] = d;
+            double r2 = 0.0;
+            for (int c = 0; c < 3; ++c) r2 += (tx[c * T + t] - D.c[c]) * (tx[c * T + t] - D.c[c]);
+            rho[d] = std::max(rho[d], std::sqrt(r2));
+        }
+    }
+    std::vector<NearPair> pairs;
+    std::vector<double> legv;
+    for (long long t = 0; t < T; ++t) {
+        const double x0[3] = {tx[t], tx[T + t], tx[2 * T + t]};
+        for (int j = 0; j < nd; ++j) {
+            if (j == tdrop[t]) continue;
+            const DropInfo& D = ctx->info[j];
+            double d0 = 0.0;
+            for (int c = 0; c < 3; ++c) d0 += (x0[c] - D.c[c]) * (x0[c] - D.c[c]);
+            if (std::sqrt(d0) > 1.2 * rho[j] + N.delta) continue;
+            // nearest grid node of drop j, then damped Gauss-Newton in (theta, phi)
+            const long long n = (long long)(D.p + 1) * D.nlon_p;
+            long long best = D.toff;
+            double bd = 1e300;
+            for (long long q = D.toff; q < D.toff + n; ++q) {
+                double e = 0.0;
+                for (int c = 0; c < 3; ++c) e += (tx[c * T + q] - x0[c]) * (tx[c * T + q] - x0[c]);
+                if (e < bd) { bd = e; best = q; }
+            }
+            std::vector<double> tg, wg;
+            ehd::gauss_legendre(D.p + 1, tg, wg);
+            const long long loc = best - D.toff;
+            double th = std::acos(tg[loc / D.nlon_p]), ph = 2.0 * kPi * (double)(loc % D.nlon_p) / D.nlon_p;
+            const double* xc = xh.data() + 3 * D.coff;
+            double x[3], xt[3], xp[3];
+            for (int it = 0; it < 60; ++it) {
+                host_surface_point(D.p, xc, th, ph, x, xt, xp);
+                double r[3], A00 = 0, A01 = 0, A11 = 0, g0 = 0, g1 = 0;
+                for (int c = 0; c < 3; ++c) {
+                    r[c] = x[c] - x0[c];
+                    A00 += xt[c] * xt[c]; A01 += xt[c] * xp[c]; A11 += xp[c] * xp[c];
+                    g0 += xt[c] * r[c]; g1 += xp[c] * r[c];
+                }
+                const double mu = 1e-14 * (A00 + A11);
+                A00 += mu; A11 += mu;
+                const double det = A00 * A11 - A01 * A01;
+                const double d_th = -(A11 * g0 - A01 * g1) / det, d_ph = -(A00 * g1 - A01 * g0) / det;
+                th = std::min(kPi - 1e-9, std::max(1e-9, th + d_th));
+                ph += d_ph;
+                if (std::fabs(d_th) + std::fabs(d_ph) < 1e-15) break;
+            }
+            std::vector<double> P, dP;
+            host_surface_point(D.p, xc, th, ph, x, xt, xp, &P, &dP);
+            double dist = 0.0;
+            for (int c = 0; c < 3; ++c) dist += (x0[c] - x[c]) * (x0[c] - x[c]);
+            dist = std::sqrt(dist);
+            if (!(dist < N.delta) || dist < 1e-12) continue;
+            NearPair pr{};
+            pr.t = (int)t;
+            pr.j = j;
+            pr.th = th;
+            pr.ph = ph;
+            const double cx = xt[1] * xp[2] - xt[2] * xp[1], cy = xt[2] * xp[0] - xt[0] * xp[2],
+                         cz = xt[0] * xp[1] - xt[1] * xp[0];
+            const double cn = std::sqrt(cx * cx + cy * cy + cz * cz);
+            const double nrm[3] = {cx / cn, cy / cn, cz / cn};
+            for (int c = 0; c < 3; ++c) {
+                pr.y[c] = x[c];
+                pr.ny[c] = nrm[c];
+                pr.xt[c] = xt[c];
+                pr.xp[c] = xp[c];
+                pr.nu[c] = (x0[c] - x[c]) / dist;
+            }
+            pr.st = dist;
+            pr.legoff = (long long)legv.size();
+            legv.insert(legv.end(), P.begin(), P.end());
+            legv.insert(legv.end(), dP.begin(), dP.end());
+            pairs.push_back(pr);
+        }
+    }
+    N.npairs = (int)pairs.size();
+    if (!N.npairs) return EHD_OK;
+    // check grids (degree qc) of the drops with pairs
+    std::vector<int> fidx(nd, -1);
+    for (const NearPair& pr : pairs) fidx[pr.j] = 0;
+    std::vector<DropInfo> fd;
+    std::vector<LegTab> fl;
+    std::vector<long long> foff{0};
+    std::vector<int2> frows;
+    std::vector<int> node_drop;
+    std::map<int, int> legid;
+    for (int j = 0; j < nd; ++j) {
+        if (fidx[j] < 0) continue;
+        fidx[j] = (int)fd.size();
+        DropInfo D = ctx->info[j];
+        const int Q = N.qc, nl = nlon_of(Q, ctx->grid_mode);
+        auto it = legid.find(D.p);
+        if (it == legid.end()) {
+            std::vector<double> t, w, P, dP;
+            ehd::gauss_legendre(Q + 1, t, w);
+            ehd::legendre_tables(D.p, t, P, dP);
+            std::vector<double> wq(Q + 1), rs(Q + 1), trig((size_t)nl * (D.p + 1) * 2);
+            for (int i = 0; i <= Q; ++i) {
+                wq[i] = 2.0 * kPi / nl * w[i];
+                rs[i] = 1.0 / std::sqrt((1.0 - t[i]) * (1.0 + t[i]));
+            }
+            for (int l = 0; l < nl; ++l)
+                for (int m = 0; m <= D.p; ++m) {
+                    const double a = 2.0 * kPi * (double)((long)m * l % nl) / nl;
+                    trig[((size_t)l * (D.p + 1) + m) * 2] = std::cos(a);
+                    trig[((size_t)l * (D.p + 1) + m) * 2 + 1] = std::sin(a);
+                }
+            LegTab L{};
+            double* dp;
+            int rc;
+            if ((rc = near_upload(ctx, &dp, P))) return rc;
+            L.P = dp;
+            if ((rc = near_upload(ctx, &dp, dP))) return rc;
+            L.dP = dp;
+            if ((rc = near_upload(ctx, &dp, wq))) return rc;
+            L.wq = dp;
+            if ((rc = near_upload(ctx, &dp, rs))) return rc;
+            L.rsin = dp;
+            if ((rc = near_upload(ctx, &dp, t))) return rc;
+            L.cth = dp;
+            if ((rc = near_upload(ctx, &dp, trig))) return rc;
+            L.trig = dp;
+            L.p = D.p;
+            L.Q = Q;
+            L.nlon = nl;
+            fl.push_back(L);
+            it = legid.emplace(D.p, (int)fl.size() - 1).first;
+        }
+        D.leg_pf = it->second;
+        D.qf = Q;
+        D.nlon_f = nl;
+        D.soff = foff.back();
+        D.ns = (long long)(Q + 1) * nl;
+        for (int i = 0; i <= Q; ++i) frows.push_back(make_int2((int)fd.size(), i));
+        for (long long q = 0; q < D.ns; ++q) node_drop.push_back((int)fd.size());
+        foff.push_back(foff.back() + D.ns);
+        fd.push_back(D);
+    }
+    N.nfd = (int)fd.size();
+    N.nf = foff.back();
+    N.nfrows = (int)frows.size();
+    int rc;
+    if ((rc = near_upload(ctx, &N.d_pairs, pairs)) || (rc = near_upload(ctx, &N.d_legv, legv)) ||
+        (rc = near_upload(ctx, &N.d_fdrops, fd)) || (rc = near_upload(ctx, &N.d_flegs, fl)) ||
+        (rc = near_upload(ctx, &N.d_frows, frows)) || (rc = near_upload(ctx, &N.d_node_drop, node_drop)) ||
+        (rc = near_upload(ctx, &N.d_foff, foff)) || (rc = near_upload(ctx, &N.d_fidx, fidx)))
+        return rc;
+    std::vector<double> z;
+    z.assign((size_t)kRec64 * N.nf, 0.0);
+    if ((rc = near_upload(ctx, &N.d_frec, z))) return rc;
+    z.assign((size_t)9 * N.nf, 0.0);
+    if ((rc = near_upload(ctx, &N.d_fsyn, z))) return rc;
+    z.assign((size_t)9 * ctx->ncoef_total, 0.0);
+    if ((rc = near_upload(ctx, &N.d_selfc, z))) return rc;
+    z.assign((size_t)9 * N.npairs, 0.0);
+    if ((rc = near_upload(ctx, &N.d_lim, z))) return rc;
+    z.assign((size_t)9 * (N.m + 1) * N.npairs, 0.0);
+    if ((rc = near_upload(ctx, &N.d_chk, z))) return rc;
+    // check-grid geometry
+    hipLaunchKernelGGL((k_synth<3, true>), dim3(N.nfrows), dim3(kThreads), 0, ctx->stream, N.d_fdrops, N.d_flegs, 1,
+                       N.d_frows, ctx->d_x, N.d_fsyn, N.nf);
+    hipLaunchKernelGGL(k_fine_geom, dim3((N.nf + 255) / 256), dim3(256), 0, ctx->stream, N.d_fdrops, N.d_flegs,
+                       N.d_node_drop, N.d_fsyn, N.nf, N.d_frec);
+    EHD_HIP(ctx, hipGetLastError());
+    EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return EHD_OK;
+}
+
+// Device work of the nearly singular correction of one evaluation, after
+// the outputs are combined (out: the far part, or the sum).
+static int near_enqueue(ehd_ctx* ctx, const double* fcoef_d, const double* ucoef_d, const double* sigcoef_d,
+                        const RowMap& rows, double* out)
+{
+    ehd_ctx::Near& N = ctx->near;
+    const long long nf = N.nf;
+    double* synf = fcoef_d ? N.d_fsyn : nullptr;
+    double* synu = ucoef_d ? N.d_fsyn + 3 * nf : nullptr;
+    double* syns = sigcoef_d ? N.d_fsyn + 6 * nf : nullptr;
+    if (synf)
+        hipLaunchKernelGGL((k_synth<3, false>), dim3(N.nfrows), dim3(kThreads), 0, ctx->ls, N.d_fdrops, N.d_flegs, 1,
+                           N.d_frows, fcoef_d, synf, nf);
+    if (synu)
+        hipLaunchKernelGGL((k_synth<3, false>), dim3(N.nfrows), dim3(kThreads), 0, ctx->ls, N.d_fdrops, N.d_flegs, 1,
+                           N.d_frows, ucoef_d, synu, nf);
+    if (syns)
+        hipLaunchKernelGGL((k_synth<1, false>), dim3(N.nfrows), dim3(kThreads), 0, ctx->ls, N.d_fdrops, N.d_flegs, 1,
+                           N.d_frows, sigcoef_d, syns, nf);
+    hipLaunchKernelGGL(k_fine_dens, dim3((nf + 255) / 256), dim3(256), 0, ctx->ls, synf, synu, syns, nf, N.d_frec);
+    hipLaunchKernelGGL(k_analyze, dim3(ctx->n_an_items), dim3(kThreads), 0, ctx->ls, ctx->d_info, ctx->d_legs,
+                       ctx->d_an_items, 9, ctx->d_raw, ctx->T, N.d_selfc);
+    const double* uc = ucoef_d ? ucoef_d : fcoef_d;
+    hipLaunchKernelGGL(k_near_limit, dim3(N.npairs), dim3(kThreads), 0, ctx->ls, N.d_pairs, ctx->d_info, N.d_legv,
+                       N.d_selfc, uc ? uc : N.d_selfc, sigcoef_d ? sigcoef_d : N.d_selfc, ctx->d_tn, ctx->T, N.d_lim);
+    hipLaunchKernelGGL(k_near_check, dim3(N.npairs * (N.m + 1)), dim3(kThreads), 0, ctx->ls, N.d_pairs, N.m, N.sc,
+                       N.d_frec, nf, N.d_foff, N.d_fidx, ctx->d_src64, ctx->Spad, ctx->d_info, ctx->d_tx, ctx->d_tn,
+                       ctx->T, N.d_chk);
+    hipLaunchKernelGGL(k_near_apply, dim3((N.npairs + 127) / 128), dim3(128), 0, ctx->ls, N.d_pairs, N.npairs, N.m,
+                       N.sc, N.d_lim, N.d_chk, rows, ctx->T, out);
+    EHD_HIP(ctx, hipGetLastError());
+    return EHD_OK;
 }
 
 extern "C" {
@@ -1854,7 +2376,40 @@ int ehd_update_shape(ehd_ctx* ctx, const double* xcoef_d)
                                 ctx->stream));
     EHD_HIP(ctx, hipMemcpyAsync(ctx->d_info, ctx->info.data(), sizeof(DropInfo) * ctx->info.size(),
                                 hipMemcpyHostToDevice, ctx->stream));
-    return build_geometry(ctx);
+    if ((rc = build_geometry(ctx))) return rc;
+    return near_build(ctx);
+}
+
+int ehd_set_near(ehd_ctx* ctx, double delta, double s_check, int m, int q_check)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ctx->nd) EHD_FAIL(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if (!std::isfinite(delta) || delta < 0.0) EHD_FAIL(ctx, EHD_E_ARG, "delta must be >= 0");
+    if (delta > 0.0) {
+        if (m < 2 || m > kNearMaxM) EHD_FAIL(ctx, EHD_E_ARG, "m must be in [2, %d]", kNearMaxM);
+        if (!(s_check > 0.0) || !std::isfinite(s_check) || delta > s_check * (1.0 + 0.5 * (m - 1)))
+            EHD_FAIL(ctx, EHD_E_ARG, "need s_check > 0 and delta <= s_check (1 + (m-1)/2): the check points "
+                     "must reach past every corrected target");
+        for (int d = 0; d < ctx->nd; ++d)
+            if (q_check < ctx->p[d] || q_check > EHD_MAX_Q_CHECK)
+                EHD_FAIL(ctx, EHD_E_ARG, "q_check must be in [p, %d] for every drop", EHD_MAX_Q_CHECK);
+    }
+    EHD_HIP(ctx, hipSetDevice(ctx->device));
+    EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->drop_graph();
+    ctx->near.on = delta > 0.0;
+    ctx->near.delta = delta;
+    ctx->near.sc = s_check;
+    ctx->near.m = m;
+    ctx->near.qc = q_check;
+    return near_build(ctx);
+}
+
+int ehd_near_pairs(const ehd_ctx* ctx, long long* npairs)
+{
+    if (!ctx || !npairs) return EHD_E_ARG;
+    *npairs = ctx->near.npairs;
+    return ctx->nd ? EHD_OK : EHD_E_STATE;
 }
 
 int ehd_num_targets(const ehd_ctx* ctx, long long* ntargets)
@@ -1936,20 +2491,22 @@ static int enqueue_evaluation(ehd_ctx* ctx, const double* fcoef_d, const double*
     //    through its own pass (x, u) for D while the first pass covers the
     //    other kinds.
     int rc = EHD_OK;
+    // the nearly singular correction of K* needs the single layer's on-surface values
+    const unsigned kself = (ctx->near.npairs && (kinds & EHD_LAP_DLADJ)) ? (kinds | EHD_LAP_SL) : kinds;
     if (needU && (needF || needLap)) {
-        const unsigned k1 = kinds & ~(unsigned)EHD_STOKES_DL;
+        const unsigned k1 = kself & ~(unsigned)EHD_STOKES_DL;
         if (needF && needLap) rc = launch_self<true, false, true>(ctx, fcoef_d, nullptr, sigcoef_d, k1);
         else if (needF) rc = launch_self<true, false, false>(ctx, fcoef_d, nullptr, sigcoef_d, k1);
         else rc = launch_self<false, false, true>(ctx, fcoef_d, nullptr, sigcoef_d, k1);
         if (rc == EHD_OK) rc = launch_self<false, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, EHD_STOKES_DL);
     } else if (needU) {
-        rc = launch_self<false, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
+        rc = launch_self<false, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself);
     } else if (needF && needLap) {
-        rc = launch_self<true, false, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
+        rc = launch_self<true, false, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself);
     } else if (needF) {
-        rc = launch_self<true, false, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
+        rc = launch_self<true, false, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself);
     } else {
-        rc = launch_self<false, false, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kinds);
+        rc = launch_self<false, false, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself);
     }
     if (rc) return rc;
     ctx->mark(2);
@@ -1962,6 +2519,13 @@ static int enqueue_evaluation(ehd_ctx* ctx, const double* fcoef_d, const double*
     hipLaunchKernelGGL(k_combine, dim3((T + 255) / 256), dim3(256), 0, ctx->ls, ctx->d_raw, ctx->d_partial,
                        ctx->nchunk, T, rows, self_out_d, far_out_d);
     EHD_HIP(ctx, hipGetLastError());
+    // 5. nearly singular targets: replace the affected drops' far sums
+    if (ctx->near.npairs) {
+        const double* fc = (needF || (needD && !ucoef_d)) ? fcoef_d : nullptr;
+        const double* uc = needU ? ucoef_d : nullptr;
+        if ((rc = near_enqueue(ctx, fc, uc, needLap ? sigcoef_d : nullptr, rows, far_out_d ? far_out_d : self_out_d)))
+            return rc;
+    }
     ctx->mark(4);
     return EHD_OK;
 }

@@ -7,6 +7,7 @@ if the library is missing or fails to load, the calls raise.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 
 import torch
@@ -23,6 +24,7 @@ GRID_PAPER, GRID_2P = 0, 1
 EOS_CLEAN, EOS_LINEAR, EOS_LANGMUIR = 0, 1, 2
 MAX_P = 48
 MAX_Q = 160
+MAX_Q_CHECK = 400
 
 COMPONENTS = ("Sx", "Sy", "Sz", "Dx", "Dy", "Dz", "SL", "L", "Kstar")
 _KIND_OF_COMP = (STOKES_SL,) * 3 + (STOKES_DL,) * 3 + (LAP_SL, LAP_DL, LAP_DLADJ)
@@ -36,7 +38,8 @@ EXPORTED = ("ehd_create", "ehd_destroy", "ehd_last_error", "ehd_grid_dims", "ehd
             "ehd_solve_surfactant", "ehd_mlp_create", "ehd_mlp_destroy", "ehd_mlp_last_error",
             "ehd_mlp_num_params", "ehd_mlp_get_params", "ehd_mlp_set_params", "ehd_mlp_get_grads",
             "ehd_mlp_forward", "ehd_mlp_backward", "ehd_mlp_mse", "ehd_mlp_adam", "ehd_area_weights",
-            "ehd_update_shape", "ehd_surfactant_terms", "ehd_evolve_step", "ehd_evolve")
+            "ehd_update_shape", "ehd_surfactant_terms", "ehd_evolve_step", "ehd_evolve", "ehd_set_near",
+            "ehd_near_pairs")
 STAGES = ("densities", "self", "far", "combine")
 DEGREE_CLASSES = (16, 24, 32, 48)   # largest p of each self-interaction kernel class
 
@@ -121,6 +124,8 @@ def load(path: str = LIB_PATH):
     lib.ehd_solve_surfactant.argtypes = [vp, dp, vp, C.c_int, C.c_int, C.c_int, C.c_double, vp, ip, dp]
     lib.ehd_explicit_step.argtypes = [vp, C.POINTER(StepParams), vp, vp, vp, vp, ip]
     lib.ehd_area_weights.argtypes = [vp, vp]
+    lib.ehd_set_near.argtypes = [vp, C.c_double, C.c_double, C.c_int, C.c_int]
+    lib.ehd_near_pairs.argtypes = [vp, C.POINTER(C.c_longlong)]
     lib.ehd_update_shape.argtypes = [vp, vp]
     lib.ehd_surfactant_terms.argtypes = [vp, vp, vp, C.c_double, vp, vp]
     lib.ehd_evolve_step.argtypes = [vp, C.POINTER(StepParams), C.c_double, C.c_double, vp, vp, vp,
@@ -371,6 +376,22 @@ class Context:
         self._check(self._lib.ehd_explicit_step(self._h, C.byref(prm), _ptr(gamma), _ptr(en), _ptr(u),
                                                 _ptr(xnew), its))
         return its[0], its[1]
+
+    def set_near(self, delta: float, s_check: float | None = None, m: int = 8, q_check: int | None = None):
+        """Nearly singular correction for targets closer than delta to another
+        drop (ehd_set_near); delta = 0 switches it off.  q_check defaults to
+        10 times the largest p (at most MAX_Q_CHECK), s_check to three
+        check-grid spacings of a unit drop, 3 pi / (q_check + 1)."""
+        if q_check is None:
+            q_check = min(MAX_Q_CHECK, 10 * int(max(self.p)))
+        if s_check is None:
+            s_check = 3.0 * math.pi / (q_check + 1)
+        self._check(self._lib.ehd_set_near(self._h, float(delta), float(s_check), int(m), int(q_check)))
+
+    def near_pairs(self) -> int:
+        n = C.c_longlong()
+        self._check(self._lib.ehd_near_pairs(self._h, C.byref(n)))
+        return n.value
 
     def area_weights(self, w: torch.Tensor):
         """Area quadrature weights at the target nodes (ehd_area_weights)."""

@@ -1,0 +1,127 @@
+"""GPU: the nearly singular correction (Sec. 2.1, interpolation approach)
+against the oracle's line interpolation on two close drops, and against the
+exterior unit-sphere closed forms through the whole evaluation."""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import sph_harm_y
+
+import oracle
+from oracle import near as N
+from paper_1811_10270_amd import workloads as W
+from test_oracle_pins import field, make_susp, sphere_x, tri, y_entry
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1811_10270_amd import ehdbim
+    ehdbim.load()
+    return ehdbim
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def two_spheres(p, gap, r2=1.0, seed=5, q_far=None):
+    """Unit sphere at the origin and a sphere of radius r2 above it along a
+    tilted axis, surfaces `gap` apart; random decaying densities."""
+    axis = np.array([0.3, -0.2, 0.93])
+    axis /= np.linalg.norm(axis)
+    x = np.concatenate([sphere_x(p), sphere_x(p, R=r2, centre=tuple((1.0 + gap + r2) * axis))])
+    rng = np.random.default_rng(seed)
+    nc2 = (p + 1) * (p + 2)
+
+    def dens(nf):
+        out = np.zeros(2 * nf * nc2)
+        for blk in range(2 * nf):
+            for n in range(p + 1):
+                for m in range(n + 1):
+                    k = blk * nc2 + 2 * tri(n, m)
+                    out[k] = rng.standard_normal() / (n + 1) ** 2
+                    if m:
+                        out[k + 1] = rng.standard_normal() / (n + 1) ** 2
+        return out
+    f, u, sg = dens(3), dens(3), dens(1)
+    pa = np.array([p, p], np.int32)
+    qf = 2 * pa if q_far is None else np.array([q_far, q_far], np.int32)
+    return W.Suspension("near", pa, 2 * pa, qf, 0, x, f, sg, u, np.zeros((2, 3)), np.ones(2))
+
+
+def gpu_eval(E, s, near=None):
+    import torch
+    dev = torch.device("cuda", 0)
+    ctx = E.Context(0)
+    ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+    if near:
+        ctx.set_near(*near)
+    npairs = ctx.near_pairs()
+    T = ctx.ntargets
+    out = torch.empty(9, T, dtype=torch.float64, device=dev)
+    ctx.layer_potentials(torch.from_numpy(s.fcoef).to(dev), torch.from_numpy(s.ucoef).to(dev),
+                         torch.from_numpy(s.sigcoef).to(dev), E.ALL_KINDS, E.FAR_FP64, out)
+    x0 = torch.empty(3, T, dtype=torch.float64, device=dev)
+    n0 = torch.empty(3, T, dtype=torch.float64, device=dev)
+    ctx.target_geometry(x0, n0)
+    res = out.cpu().numpy(), x0.cpu().numpy(), n0.cpu().numpy(), npairs
+    ctx.close()
+    return res
+
+
+def test_near_correction_matches_oracle(E):
+    p, gap, delta, m, qc = 8, 0.02, 0.12, 6, 80
+    sc = 3 * math.pi / (qc + 1)
+    s = two_spheres(p, gap)
+    plain, x0, n0, _ = gpu_eval(E, s)
+    corr, _, _, npairs = gpu_eval(E, s, (delta, sc, m, qc))
+    changed = np.flatnonzero(np.abs(corr - plain).max(axis=0) > 0)
+    say("near pairs", npairs, "changed targets", len(changed))
+    assert npairs > 0 and len(changed) > 0
+    td, tn = oracle.all_targets(s)
+    rng = np.random.default_rng(1)
+    sample = rng.choice(changed, size=min(6, len(changed)), replace=False)
+    ref = oracle.self_(s, td[sample], tn[sample]) + oracle.far(s, td[sample], tn[sample])
+    for i, t in enumerate(sample):
+        j = 1 - int(td[t])
+        c, pl, info = N.near_value(s, j, x0[:, t], n0[:, t], sc, m, q_check=qc)
+        assert info["dist"] < delta
+        ref[:, i] += c - pl
+    err = np.abs(corr[:, sample] - ref).max() / np.abs(ref).max()
+    say("near correction vs oracle, rel err", err)
+    assert err < 1e-10
+    far = np.setdiff1d(np.arange(corr.shape[1]), changed)
+    assert np.array_equal(corr[:, far], plain[:, far])          # other targets untouched
+
+
+def test_near_correction_exterior_sphere_closed_form(E):
+    """A unit sphere with sigma = Re Y_31 and a small sphere (radius 0.3,
+    no densities) 0.004 above it: at the small sphere's nodes the evaluation
+    is the unit sphere's exterior field, S_L = Y(d)/(7 r^4), L = 3 Y(d)/(7 r^4).
+    Far sums on degree-5p grids (accurate beyond about 0.15), targets closer
+    than delta = 0.16 corrected with check points on a degree-200 grid."""
+    p, n, m = 12, 3, 1
+    s = two_spheres(p, 0.004, r2=0.3, q_far=5 * p)
+    nc2 = (p + 1) * (p + 2)
+    s.sigcoef[:] = 0.0
+    s.sigcoef[:nc2] = field(p, y_entry(n, m))
+    s.fcoef[:] = 0.0
+    s.ucoef[:] = 0.0
+    plain, x0, _, _ = gpu_eval(E, s)
+    corr, _, _, npairs = gpu_eval(E, s, (0.16, 3 * math.pi / 201, 8, 200))
+    T1 = (p + 1) * (2 * p + 2)
+    pts = x0[:, T1:]                                 # the small sphere's nodes
+    r = np.linalg.norm(pts, axis=0)
+    th, ph = np.arccos(pts[2] / r), np.arctan2(pts[1], pts[0])
+    y = np.real(sph_harm_y(n, m, th, ph))
+    ex = np.stack([y / ((2 * n + 1) * r ** (n + 1)), n * y / ((2 * n + 1) * r ** (n + 1))])
+    e_corr = np.abs(corr[6:8, T1:] - ex).max() / np.abs(ex).max()
+    e_plain = np.abs(plain[6:8, T1:] - ex).max() / np.abs(ex).max()
+    say("closed form: pairs", npairs, "corrected err", e_corr, "plain err", e_plain, "min gap", (r - 1).min())
+    assert npairs > 0
+    assert e_corr < 1e-6 and e_plain > 1e-3
