@@ -210,6 +210,48 @@ def bench_step(args, torch, E, W, dev):
     return 0
 
 
+def bench_near(args, torch, E, W, dev):
+    """Evaluation of two unit spheres (p = 32, q_far = 3p) whose surfaces are
+    args.near_gap apart, all kinds in FP64, with and without the nearly
+    singular correction (targets closer than 3 pi/(q_far + 1), check points
+    on a degree-min(10p, 400) grid from three of its spacings, m = 8)."""
+    s = W.two_drops(32, seed=2, gap=args.near_gap)
+    f = torch.from_numpy(s.fcoef).to(dev)
+    sg = torch.from_numpy(s.sigcoef).to(dev)
+    qf, qc = int(s.q_far[0]), min(E.MAX_Q_CHECK, 10 * 32)
+    delta, sc = 3 * math.pi / (qf + 1), 3 * math.pi / (qc + 1)
+    res = {}
+    for near in (False, True):
+        ctx = E.Context(0)
+        ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+        t0 = time.perf_counter()
+        if near:
+            ctx.set_near(delta, sc, 8, qc)
+        setup = time.perf_counter() - t0
+        out = torch.empty(9, ctx.ntargets, dtype=torch.float64, device=dev)
+        for _ in range(max(args.warmup, 1)):
+            ctx.layer_potentials(f, None, sg, E.ALL_KINDS, E.FAR_FP64, out)
+        ctx.sync()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.layer_potentials(f, None, sg, E.ALL_KINDS, E.FAR_FP64, out)
+        ctx.sync()
+        res[near] = ((time.perf_counter() - t0) / args.steps, ctx.near_pairs(), setup, ctx.ntargets)
+        ctx.close()
+    (t_plain, _, _, T), (t_near, pairs, setup, _) = res[False], res[True]
+    out = {
+        "metric": "layer-potential target evals/sec with the nearly singular correction (FP64)",
+        "value": T / t_near, "unit": "target-evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": max(args.warmup, 1), "ms_per_step": t_near * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "two_drops_p32_gap%g" % args.near_gap, "targets": T, "q_far": qf, "q_check": qc,
+                   "delta": delta, "s_check": sc, "m": 8, "kinds": "S,D,S_L,L,K*"},
+        "near_pairs": pairs, "ms_without_correction": t_plain * 1e3, "setup_ms": setup * 1e3,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_evolve(args, torch, E, W, dev):
     """Steps of Algorithm 1 (ehd_evolve_step: two E_n solves, two velocity
     solves, the implicit surfactant solve, surface terms, midpoint and IMEX
@@ -332,6 +374,10 @@ def main(argv=None):
                     help="time one explicit step of the method (E_n solve, forces, velocity solve, "
                          "position update) on two_drops_p32 with lambda = 2, R = 0.5, Q = 2, uniform "
                          "field E_u = 1, Ca_E = 0.3, clean drops, dt = 0.01")
+    ap.add_argument("--near", action="store_true",
+                    help="time the evaluation of two p = 32 spheres --near-gap apart with and without the "
+                         "nearly singular correction")
+    ap.add_argument("--near-gap", type=float, default=0.01)
     ap.add_argument("--evolve", action="store_true",
                     help="time steps of Algorithm 1 (ehd_evolve_step) on two_drops_p32 with a linear-law "
                          "surfactant, Pe = 10, lambda = 2, R = 0.5, Q = 2, Ca_E = 0.3, E_u = 1, dt = 0.01")
@@ -367,6 +413,8 @@ def main(argv=None):
         return bench_learned(args, torch, E, W, dev)
     if args.evolve:
         return bench_evolve(args, torch, E, W, dev)
+    if args.near:
+        return bench_near(args, torch, E, W, dev)
     if args.step:
         return bench_step(args, torch, E, W, dev)
     if args.solve:

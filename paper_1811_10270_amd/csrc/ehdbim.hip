@@ -1816,6 +1816,9 @@ static int near_build(ehd_ctx* ctx)
                 for (int c = 0; c < 3; ++c) e += (tx[c * T + q] - x0[c]) * (tx[c * T + q] - x0[c]);
                 if (e < bd) { bd = e; best = q; }
             }
+            // the surface is within half a node spacing (about pi rho / (p + 1)
+            // along a parallel, less along a meridian) of its nearest node
+            if (std::sqrt(bd) > N.delta + kPi * rho[j] / (D.p + 1)) continue;
             std::vector<double> tg, wg;
             ehd::gauss_legendre(D.p + 1, tg, wg);
             const long long loc = best - D.toff;
