@@ -195,8 +195,9 @@ int ehd_near_pairs(const ehd_ctx* ctx, long long* npairs);
 
 /* New surface coefficients for the same drops, degrees and grids (e.g. a
  * time step): copies xcoef_d (3 packed fields per drop, as for
- * ehd_set_drops) and recomputes the drop centres and the target and
- * far-source geometry, keeping every table.  Drops a recorded graph.
+ * ehd_set_drops) and recomputes the drop centres, the target and far-source
+ * geometry and, when ehd_set_near is on, the nearly singular pairs, keeping
+ * every table.  Drops a recorded graph.
  * Synchronous. */
 int ehd_update_shape(ehd_ctx* ctx, const double* xcoef_d);
 

@@ -125,3 +125,33 @@ def test_near_correction_exterior_sphere_closed_form(E):
     say("closed form: pairs", npairs, "corrected err", e_corr, "plain err", e_plain, "min gap", (r - 1).min())
     assert npairs > 0
     assert e_corr < 1e-6 and e_plain > 1e-3
+
+
+def test_near_correction_in_graph_mode(E):
+    """The correction's kernels are part of the recorded evaluation: several
+    replays, with eager work and synchronisations between them, each equal
+    the eager result."""
+    import torch
+    p, qc = 8, 80
+    s = two_spheres(p, 0.02)
+    dev = torch.device("cuda", 0)
+    ctx = E.Context(0)
+    ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+    ctx.set_near(0.12, 3 * math.pi / (qc + 1), 6, qc)
+    f, u, sg = (torch.from_numpy(a).to(dev) for a in (s.fcoef, s.ucoef, s.sigcoef))
+    T = ctx.ntargets
+    eager = torch.empty(9, T, dtype=torch.float64, device=dev)
+    ctx.layer_potentials(f, u, sg, E.ALL_KINDS, E.FAR_FP64, eager)
+    ctx.sync()
+    ref = eager.cpu().numpy()
+    ctx.set_graph(True)
+    out = torch.empty(9, T, dtype=torch.float64, device=dev)
+    scratch = torch.randn(512, 512, dtype=torch.float64, device=dev)
+    for _ in range(4):                     # the first call records, the others replay
+        out.fill_(0.0)
+        ctx.layer_potentials(f, u, sg, E.ALL_KINDS, E.FAR_FP64, out)
+        ctx.sync()
+        assert np.array_equal(out.cpu().numpy(), ref)
+        scratch = torch.tanh(scratch @ scratch.T * 1e-3)          # unrelated eager work between replays
+        torch.cuda.synchronize()
+    ctx.close()
