@@ -109,6 +109,8 @@ def bench_solve(args, torch, E, W, dev):
     far_prec = E.FAR_FP32C if args.far_prec == "fp32c" else E.FAR_FP64
     ctx = E.Context(0)
     ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+    if args.overlap:
+        ctx.set_overlap(True)
     nc = ctx.num_coefs()
     T = ctx.ntargets
     f = torch.from_numpy(s.fcoef).to(dev)
@@ -156,7 +158,7 @@ def bench_solve(args, torch, E, W, dev):
         "value": 1.0 / dt, "unit": "solves/s", "n_gpus": 1, "steps": K, "warmup": max(args.warmup, 1),
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if far_prec == E.FAR_FP64 else "f64+f32", "data": "synthetic",
-        "config": {"workload": args.workload, "ndrops": s.ndrops, "p": sorted(set(int(v) for v in s.p)),
+        "config": {"workload": args.workload, "overlap": args.overlap, "ndrops": s.ndrops, "p": sorted(set(int(v) for v in s.p)),
                    "targets": T, "unknowns": nf * nc, "far_prec": "fp64" if far_prec == E.FAR_FP64 else "fp32c",
                    "R" if args.solve == "en" else "lambda": 0.5 if args.solve == "en" else 2.0},
         "iterations": its, "relres": rr, "matvec_ms": mv * 1e3,
@@ -172,6 +174,8 @@ def bench_step(args, torch, E, W, dev):
     far_prec = E.FAR_FP32C if args.far_prec == "fp32c" else E.FAR_FP64
     ctx = E.Context(0)
     ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+    if args.overlap:
+        ctx.set_overlap(True)
     nc = ctx.num_coefs()
     en = torch.zeros(nc, dtype=torch.float64, device=dev)
     u = torch.zeros(3 * nc, dtype=torch.float64, device=dev)
@@ -200,7 +204,7 @@ def bench_step(args, torch, E, W, dev):
         "value": 1.0 / dt, "unit": "steps/s", "n_gpus": 1, "steps": K, "warmup": max(args.warmup, 1),
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if far_prec == E.FAR_FP64 else "f64+f32", "data": "synthetic",
-        "config": {"workload": args.workload, "ndrops": s.ndrops, "p": sorted(set(int(v) for v in s.p)),
+        "config": {"workload": args.workload, "overlap": args.overlap, "ndrops": s.ndrops, "p": sorted(set(int(v) for v in s.p)),
                    "targets": ctx.ntargets, "lambda": 2.0, "R": 0.5, "Q": 2.0, "CaE": 0.3, "E_u": 1.0,
                    "eos": "clean", "dt": 0.01,
                    "far_prec": "fp64" if far_prec == E.FAR_FP64 else "fp32c"},
@@ -224,6 +228,8 @@ def bench_near(args, torch, E, W, dev):
     for near in (False, True):
         ctx = E.Context(0)
         ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+        if args.overlap:
+            ctx.set_overlap(True)
         t0 = time.perf_counter()
         if near:
             ctx.set_near(delta, sc, 8, qc)
@@ -261,6 +267,8 @@ def bench_evolve(args, torch, E, W, dev):
     far_prec = E.FAR_FP32C if args.far_prec == "fp32c" else E.FAR_FP64
     ctx = E.Context(0)
     ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+    if args.overlap:
+        ctx.set_overlap(True)
     nc = ctx.num_coefs()
     rng = np.random.default_rng(7)
     g = np.zeros(nc)
@@ -296,7 +304,7 @@ def bench_evolve(args, torch, E, W, dev):
         "value": 1.0 / dt, "unit": "steps/s", "n_gpus": 1, "steps": K, "warmup": max(args.warmup, 1),
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if far_prec == E.FAR_FP64 else "f64+f32", "data": "synthetic",
-        "config": dict({"workload": args.workload, "ndrops": s.ndrops, "p": sorted(set(int(v) for v in s.p)),
+        "config": dict({"workload": args.workload, "overlap": args.overlap, "ndrops": s.ndrops, "p": sorted(set(int(v) for v in s.p)),
                         "targets": ctx.ntargets,
                         "far_prec": "fp64" if far_prec == E.FAR_FP64 else "fp32c"}, **prm),
         "gmres_iterations": {"E_n": [rep["iters"][0], rep["iters"][2]], "velocity": [rep["iters"][1], rep["iters"][3]],
@@ -374,6 +382,9 @@ def main(argv=None):
                     help="time one explicit step of the method (E_n solve, forces, velocity solve, "
                          "position update) on two_drops_p32 with lambda = 2, R = 0.5, Q = 2, uniform "
                          "field E_u = 1, Ca_E = 0.3, clean drops, dt = 0.01")
+    ap.add_argument("--overlap", action="store_true",
+                    help="far field on a second stream, concurrent with the self-interaction "
+                         "(per-kernel times then include the sharing of the device)")
     ap.add_argument("--near", action="store_true",
                     help="time the evaluation of two p = 32 spheres --near-gap apart with and without the "
                          "nearly singular correction")
@@ -425,6 +436,8 @@ def main(argv=None):
 
     ctx = E.Context(0)
     ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+    if args.overlap:
+        ctx.set_overlap(True)
     T = ctx.ntargets
     tile = {"targets_per_thread": ctx.far_config()[0], "source_chunks": ctx.far_config()[1],
             "autotuned": False}
@@ -501,7 +514,7 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f64+f32" if far_prec == E.FAR_FP32C else "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "ndrops": s.ndrops,
+        "config": {"workload": args.workload, "overlap": args.overlap, "ndrops": s.ndrops,
                    "p": sorted(set(int(x) for x in s.p)), "targets": T,
                    "q_self": "2p", "q_far": "2p", "grid": "paper (2p+2 longitudes)"
                    if s.grid_mode == 0 else "2p longitudes",

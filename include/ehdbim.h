@@ -234,6 +234,14 @@ int ehd_self_class_times(ehd_ctx* ctx, int slot, double* ms);
  * Synchronises the stream. */
 int ehd_set_graph(ehd_ctx* ctx, int enable);
 
+/* Overlap mode (off by default): the far-field sums run on a second stream
+ * of the context, concurrently with the singular self-interaction; results
+ * are bitwise the same.  It pays where the self-interaction alone does not
+ * fill the device (few drops; two p = 32 drops: 10% per evaluation).  Stage
+ * times then read: self as before, far = the part of the far field not
+ * hidden behind the self-interaction.  Drops a recorded graph. */
+int ehd_set_overlap(ehd_ctx* ctx, int enable);
+
 /* Far-field tile shape: targets per thread (1 or 2) and number of source
  * chunks (1..16, at most the number of source tiles) the targets' sums are
  * split into.  ehd_set_drops sets a default; the autotuner (ehd_time_far over

@@ -679,6 +679,7 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     // Rows and columns of a Fourier block that are not rewritten meet zero A
     // entries (padding terms) or feed unused output columns; start from zeros.
     for (int z = threadIdx.x; z < LB * gsz; z += blockDim.x) R[z] = 0.0;
+    __syncthreads();   // every zero is written before any wave stores Legendre sums there
 
     double x0[3], n0v[3];
     for (int c = 0; c < 3; ++c) { x0[c] = tx[c * T + tg]; n0v[c] = tnrm[c * T + tg]; }
@@ -1479,6 +1480,11 @@ struct ehd_ctx {
     } gkey{};
     hipStream_t ls = nullptr;        // stream the current evaluation launches on
     bool capturing = false;
+    // overlap mode: the far field on its own stream, concurrent with the
+    // self-interaction (forked after the densities, joined before combine)
+    bool overlap = false;
+    hipStream_t far_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
     void drop_graph()
     {
@@ -2029,6 +2035,9 @@ void ehd_destroy(ehd_ctx* ctx)
     else (void)hipDeviceSynchronize();
     ctx->drop_graph();
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->far_stream) (void)hipStreamDestroy(ctx->far_stream);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     ctx->free_all();
     ctx->free_events();
     delete ctx;
@@ -2489,6 +2498,17 @@ static int enqueue_evaluation(ehd_ctx* ctx, const double* fcoef_d, const double*
     EHD_HIP(ctx, hipGetLastError());
 
     ctx->mark(1);
+    // overlap mode: fork the far field onto its own stream now
+    if (ctx->overlap) {
+        EHD_HIP(ctx, hipEventRecord(ctx->ev_fork, ctx->ls));
+        EHD_HIP(ctx, hipStreamWaitEvent(ctx->far_stream, ctx->ev_fork, 0));
+        hipStream_t main = ctx->ls;
+        ctx->ls = ctx->far_stream;
+        const int rf = launch_far(ctx, far_prec, kinds, ctx->far_tpt, ctx->nchunk);
+        ctx->ls = main;
+        if (rf) return rf;
+        EHD_HIP(ctx, hipEventRecord(ctx->ev_join, ctx->far_stream));
+    }
     // 2. singular self-interaction.  The kernel holds at most 8 fields (its
     //    Legendre MFMA has 16 columns: field x re/im), so a separate u goes
     //    through its own pass (x, u) for D while the first pass covers the
@@ -2514,8 +2534,9 @@ static int enqueue_evaluation(ehd_ctx* ctx, const double* fcoef_d, const double*
     if (rc) return rc;
     ctx->mark(2);
 
-    // 3. far field
-    if ((rc = launch_far(ctx, far_prec, kinds, ctx->far_tpt, ctx->nchunk))) return rc;
+    // 3. far field (overlap mode: wait for it)
+    if (ctx->overlap) EHD_HIP(ctx, hipStreamWaitEvent(ctx->ls, ctx->ev_join, 0));
+    else if ((rc = launch_far(ctx, far_prec, kinds, ctx->far_tpt, ctx->nchunk))) return rc;
 
     ctx->mark(3);
     // 4. outputs
@@ -2609,6 +2630,21 @@ int ehd_set_graph(ehd_ctx* ctx, int enable)
     if (enable && !ctx->cap_stream)
         EHD_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     ctx->graph_on = enable != 0;
+    return EHD_OK;
+}
+
+int ehd_set_overlap(ehd_ctx* ctx, int enable)
+{
+    if (!ctx) return EHD_E_ARG;
+    EHD_HIP(ctx, hipSetDevice(ctx->device));
+    if (ctx->stream) EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->drop_graph();
+    if (enable && !ctx->far_stream) {
+        EHD_HIP(ctx, hipStreamCreateWithFlags(&ctx->far_stream, hipStreamNonBlocking));
+        EHD_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+        EHD_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+    }
+    ctx->overlap = enable != 0;
     return EHD_OK;
 }
 

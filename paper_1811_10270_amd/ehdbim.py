@@ -39,7 +39,7 @@ EXPORTED = ("ehd_create", "ehd_destroy", "ehd_last_error", "ehd_grid_dims", "ehd
             "ehd_mlp_num_params", "ehd_mlp_get_params", "ehd_mlp_set_params", "ehd_mlp_get_grads",
             "ehd_mlp_forward", "ehd_mlp_backward", "ehd_mlp_mse", "ehd_mlp_adam", "ehd_area_weights",
             "ehd_update_shape", "ehd_surfactant_terms", "ehd_evolve_step", "ehd_evolve", "ehd_set_near",
-            "ehd_near_pairs")
+            "ehd_near_pairs", "ehd_set_overlap")
 STAGES = ("densities", "self", "far", "combine")
 DEGREE_CLASSES = (16, 24, 32, 48)   # largest p of each self-interaction kernel class
 
@@ -124,6 +124,7 @@ def load(path: str = LIB_PATH):
     lib.ehd_solve_surfactant.argtypes = [vp, dp, vp, C.c_int, C.c_int, C.c_int, C.c_double, vp, ip, dp]
     lib.ehd_explicit_step.argtypes = [vp, C.POINTER(StepParams), vp, vp, vp, vp, ip]
     lib.ehd_area_weights.argtypes = [vp, vp]
+    lib.ehd_set_overlap.argtypes = [vp, C.c_int]
     lib.ehd_set_near.argtypes = [vp, C.c_double, C.c_double, C.c_int, C.c_int]
     lib.ehd_near_pairs.argtypes = [vp, C.POINTER(C.c_longlong)]
     lib.ehd_update_shape.argtypes = [vp, vp]
@@ -315,6 +316,10 @@ class Context:
 
     def set_timing(self, nslots: int):
         self._check(self._lib.ehd_set_timing(self._h, nslots))
+
+    def set_overlap(self, enable: bool):
+        """Far field on a second stream, concurrent with the self-interaction (ehd_set_overlap)."""
+        self._check(self._lib.ehd_set_overlap(self._h, 1 if enable else 0))
 
     def set_graph(self, enable: bool):
         self._check(self._lib.ehd_set_graph(self._h, 1 if enable else 0))

@@ -72,6 +72,62 @@ def test_graph_replays_match_eager(E):
     ctx.close()
 
 
+def test_overlap_mode_matches_serial(E):
+    """Far field on its own stream, concurrent with the self-interaction:
+    the same bits as the serial evaluation, eagerly and in graph replays."""
+    import torch
+    for s in (W.subset(W.batched_suspension(seed=3), list(range(10))), W.two_drops(16, seed=4, gap=0.2)):
+        ctx, f, sg, dev = _setup(E, s)
+        T = ctx.ntargets
+        ref = torch.zeros(9, T, dtype=torch.float64, device=dev)
+        ctx.layer_potentials(f, None, sg, E.ALL_KINDS, E.FAR_FP32C, ref)
+        ctx.sync()
+        ctx.set_overlap(True)
+        out = torch.zeros_like(ref)
+        for graph in (False, True):
+            ctx.set_graph(graph)
+            for _ in range(3):
+                out.zero_()
+                ctx.layer_potentials(f, None, sg, E.ALL_KINDS, E.FAR_FP32C, out)
+                ctx.sync()
+                assert torch.equal(out, ref), graph
+                _ = (out * 2.0).sum().item()          # eager work between replays
+        ctx.set_graph(False)
+        ctx.set_overlap(False)
+        ctx.close()
+
+
+def test_overlap_fp64_single_kinds_and_solve(E):
+    """Regression: the FP64 far field running beside the self-interaction
+    slows some of its waves; the self kernel must not depend on its waves'
+    relative timing (every kind alone, FP64 far field, bitwise), and a GMRES
+    solve in overlap mode converges as the serial one does."""
+    import torch
+    s = W.two_drops(32, seed=2)
+    ctx, f, sg, dev = _setup(E, s)
+    T = ctx.ntargets
+    for kinds in (E.LAP_DLADJ, E.LAP_SL, E.LAP_DL, E.STOKES_DL, E.STOKES_SL, E.ALL_KINDS):
+        outs = []
+        for ov in (False, True, True, True):
+            ctx.set_overlap(ov)
+            so = torch.zeros(9, T, dtype=torch.float64, device=dev)
+            fo = torch.zeros_like(so)
+            ctx.layer_potentials(f, None, sg, kinds, E.FAR_FP64, so, fo)
+            ctx.sync()
+            outs.append((so, fo))
+        for so, fo in outs[1:]:
+            assert torch.equal(so, outs[0][0]) and torch.equal(fo, outs[0][1]), kinds
+    res = {}
+    for ov in (False, True):
+        ctx.set_overlap(ov)
+        en = torch.zeros(ctx.num_coefs(), dtype=torch.float64, device=dev)
+        res[ov] = ctx.solve_En(0.5, 1.0, 0.0, en, tol=1e-12) + (en.cpu(),)
+    ctx.set_overlap(False)
+    ctx.close()
+    assert res[True][0] == res[False][0] and res[True][1] <= 1e-12
+    assert torch.equal(res[True][2], res[False][2])
+
+
 def test_far_tile_shapes_agree_and_autotune(E, tmp_path):
     import torch
     from paper_1811_10270_amd import autotune
