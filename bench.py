@@ -47,10 +47,10 @@ def self_flops_per_drop(p: int, q: int, grid_mode: int) -> float:
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs
 # recorded in profiles/hbm_traffic_batched_64_mixed_p.md (counters scaled by a
 # 1 GiB copy), valid only for the kernel source they were taken with.
-TRAFFIC_SOURCE_SHA256 = "9acaabd22c0a2921883b42628c91b9c3f5ed9b23531475b26a24efd0a3a78dc5"
+TRAFFIC_SOURCE_SHA256 = "e3f41e1730161356bba84b1f3fba2975ab0877ba29f166efc63ca5afccd7ebda"
 TRAFFIC_WORKLOAD = "batched_64_mixed_p"
-TRAFFIC_BYTES = {"k_self<48>": 6.536e+08, "k_self<32>": 1.201e+08, "k_self<24>": 2.54e+07,
-                 "k_self<16>": 7.367e+06, "k_far32": 8.02e+08}
+TRAFFIC_BYTES = {"k_self<48>": 6.495e+08, "k_self<32>": 1.201e+08, "k_self<24>": 2.54e+07,
+                 "k_self<16>": 7.369e+06, "k_far32": 8.016e+08}
 
 
 def measured_traffic(kernel: str, workload: str):
