@@ -17,6 +17,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -375,6 +376,28 @@ __global__ void k_geom_sources(const DropInfo* __restrict__ drops, const LegTab*
         src32[(3 + c) * Spad + s] = (float)n[c];
     }
     src64[6 * Spad + s] = L.wq[i] * J;
+}
+
+// (2 rho_d)^2 of each drop, rho_d the largest distance of its far-grid
+// nodes from its centre, into centre[4 d + 3]; one block per drop.
+__global__ __launch_bounds__(kThreads) void k_drop_radius(const DropInfo* __restrict__ drops,
+                                                          const double* __restrict__ src64, long long Spad,
+                                                          double* __restrict__ centre)
+{
+    const DropInfo D = drops[blockIdx.x];
+    double m = 0.0;
+    for (long long s = D.soff + threadIdx.x; s < D.soff + D.ns; s += blockDim.x) {
+        const double dx = src64[s] - D.c[0], dy = src64[Spad + s] - D.c[1], dz = src64[2 * Spad + s] - D.c[2];
+        m = fmax(m, dx * dx + dy * dy + dz * dz);
+    }
+    __shared__ double red[kThreads];
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = kThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) centre[4 * blockIdx.x + 3] = 4.0 * red[0];
 }
 
 // Weighted densities of the far-field sources (both precisions).
@@ -1062,13 +1085,22 @@ __global__ __launch_bounds__(kThreads) void k_far32(const double* __restrict__ t
         bool other = false;   // some target of this thread is not on the tile's drop
         for (int k = 0; k < TPT; ++k) other = other || (sd != myd[k]);
         float ax[TPT], ay[TPT], az[TPT], bx[TPT], by[TPT], bz[TPT], a[TPT][9];
+        const double* cj = dcentre + 4 * sd;            // centre, (2 radius)^2 of the tile's drop
+        bool far_all = true;
         for (int k = 0; k < TPT; ++k) {
-            const double dx = X0[k] - dcentre[3 * sd], dy = Y0[k] - dcentre[3 * sd + 1],
-                         dz = Z0[k] - dcentre[3 * sd + 2];
+            const double dx = X0[k] - cj[0], dy = Y0[k] - cj[1], dz = Z0[k] - cj[2];
             ax[k] = (float)dx; ay[k] = (float)dy; az[k] = (float)dz;
             bx[k] = (float)(dx - ax[k]); by[k] = (float)(dy - ay[k]); bz[k] = (float)(dz - az[k]);
+            far_all = far_all && (tt[k] >= T || dx * dx + dy * dy + dz * dz >= cj[3]);
             for (int c = 0; c < 9; ++c) a[k][c] = 0.0f;
         }
+        // Targets at least two drop radii from the drop's centre have
+        // |d| <= 2 |x0 - x| for every source x: the FP32 head of d alone
+        // then keeps each term's relative error within a few roundings, and
+        // the wave skips the tail (3 of 37 instructions per pair).
+        const bool tail = !__all(far_all);
+        auto pairs = [&](auto with_tail) {
+        constexpr bool TAIL = decltype(with_tail)::value;
         for (int q4 = 0; q4 < (other ? kTile / 4 : 0); ++q4) {
             const float4 X = sm[0][q4], Y = sm[1][q4], Z = sm[2][q4];
             float4 NX, NY, NZ, F0, F1, F2, U0, U1, U2, SG;
@@ -1080,8 +1112,8 @@ __global__ __launch_bounds__(kThreads) void k_far32(const double* __restrict__ t
             for (int j = 0; j < 4; ++j) {
 #pragma unroll
                 for (int k = 0; k < TPT; ++k) {
-                    const float hx = (ax[k] - X[j]) + bx[k], hy = (ay[k] - Y[j]) + by[k],
-                                hz = (az[k] - Z[j]) + bz[k];
+                    float hx = ax[k] - X[j], hy = ay[k] - Y[j], hz = az[k] - Z[j];
+                    if constexpr (TAIL) { hx += bx[k]; hy += by[k]; hz += bz[k]; }
                     const float r2 = fmaf(hx, hx, fmaf(hy, hy, hz * hz));
                     const float ir = __frsqrt_rn(r2), ir2 = ir * ir, ir3 = ir * ir2;
                     float hn = 0.0f;
@@ -1106,6 +1138,9 @@ __global__ __launch_bounds__(kThreads) void k_far32(const double* __restrict__ t
                 }
             }
         }
+        };
+        if (tail) pairs(std::true_type{});
+        else pairs(std::false_type{});
         for (int k = 0; k < TPT; ++k) {
             if (sd == myd[k]) continue;      // own drop: tile not counted
             for (int c = 3; c < 6; ++c) a[k][c] *= -6.0f;
@@ -1452,7 +1487,7 @@ struct ehd_ctx {
     int* d_order = nullptr;          // [T] self work order
     int* d_slot_drop = nullptr;      // [Spad]
     int* d_tile_drop = nullptr;      // [ntiles]
-    double* d_centre = nullptr;      // [3*nd]
+    double* d_centre = nullptr;      // [4*nd]: centre, (2 radius)^2
     double* d_src64 = nullptr;       // [kRec64][Spad]
     float* d_src32 = nullptr;        // [kRec32][Spad]
     double* d_syn = nullptr;         // synthesis scratch [9][max(T,Spad)]
@@ -2095,6 +2130,8 @@ static int build_geometry(ehd_ctx* ctx)
                        ctx->d_info, ctx->d_legs, 1, ctx->d_rows_f, ctx->d_x, ctx->d_syn, vs);
     hipLaunchKernelGGL(k_geom_sources, dim3((S + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_info,
                        ctx->d_legs, ctx->d_slot_drop, ctx->d_syn, vs, S, ctx->d_src64, ctx->d_src32);
+    hipLaunchKernelGGL(k_drop_radius, dim3(ctx->nd), dim3(kThreads), 0, ctx->stream, ctx->d_info, ctx->d_src64, S,
+                       ctx->d_centre);
     EHD_HIP(ctx, hipGetLastError());
     EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return EHD_OK;
@@ -2295,9 +2332,9 @@ int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
                                 ctx->stream));
     if ((rc = read_centres(ctx))) return rc;
     {
-        std::vector<double> cen(3 * ndrops);
+        std::vector<double> cen(4 * ndrops, 0.0);          // radii: build_geometry
         for (int d = 0; d < ndrops; ++d)
-            for (int c = 0; c < 3; ++c) cen[3 * d + c] = ctx->info[d].c[c];
+            for (int c = 0; c < 3; ++c) cen[4 * d + c] = ctx->info[d].c[c];
         if ((rc = upload(ctx, &ctx->d_centre, cen))) return rc;
     }
     if ((rc = upload(ctx, &ctx->d_info, ctx->info))) return rc;
@@ -2381,9 +2418,9 @@ int ehd_update_shape(ehd_ctx* ctx, const double* xcoef_d)
                                     ctx->stream));
     int rc = read_centres(ctx);
     if (rc) return rc;
-    std::vector<double> cen(3 * ctx->nd);
+    std::vector<double> cen(4 * ctx->nd, 0.0);             // radii: build_geometry
     for (int d = 0; d < ctx->nd; ++d)
-        for (int c = 0; c < 3; ++c) cen[3 * d + c] = ctx->info[d].c[c];
+        for (int c = 0; c < 3; ++c) cen[4 * d + c] = ctx->info[d].c[c];
     EHD_HIP(ctx, hipMemcpyAsync(ctx->d_centre, cen.data(), sizeof(double) * cen.size(), hipMemcpyHostToDevice,
                                 ctx->stream));
     EHD_HIP(ctx, hipMemcpyAsync(ctx->d_info, ctx->info.data(), sizeof(DropInfo) * ctx->info.size(),
