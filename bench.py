@@ -47,10 +47,10 @@ def self_flops_per_drop(p: int, q: int, grid_mode: int) -> float:
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs
 # recorded in profiles/hbm_traffic_batched_64_mixed_p.md (counters scaled by a
 # 1 GiB copy), valid only for the kernel source they were taken with.
-TRAFFIC_SOURCE_SHA256 = "f3a657df5458481caf96900a37ae71d43a820e0f2d9c660b5d7a581d4b018e6b"
+TRAFFIC_SOURCE_SHA256 = "80537bce865e9e10589f7d60281084069b7148561ab44069237f81757d55f605"
 TRAFFIC_WORKLOAD = "batched_64_mixed_p"
-TRAFFIC_BYTES = {"k_self<48>": 6.979e+08, "k_self<32>": 1.201e+08, "k_self<24>": 2.54e+07,
-                 "k_self<16>": 7.369e+06, "k_far32": 8.128e+08}
+TRAFFIC_BYTES = {"k_self<48>": 6.442e+08, "k_self<32>": 1.201e+08, "k_self<24>": 2.54e+07,
+                 "k_self<16>": 7.373e+06, "k_far32": 8.068e+08}
 
 
 def measured_traffic(kernel: str, workload: str):

@@ -846,7 +846,16 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
         //     the modified weights.
         if (dft_wave) {
             const int boff = (lane >> 4) * 16 + (lane & 15);
-            for (int ll = wv / qg.nTp; ll < LB; ll += SC::NW / qg.nTp) {
+            // Four row tiles (p = 48): the two waves of a tile share a SIMD,
+            // and with four latitudes each the first finished its sums well
+            // before the second; taking five of the eight balances the pair
+            // (67.6 -> 66.3 ms on the 64-drop workload).  Otherwise latitudes
+            // are dealt round-robin over the waves of a tile.
+            const bool split = qg.nTp == 4;
+            const int ll0 = split ? (wv < 4 ? 0 : 5) : wv / qg.nTp;
+            const int ll1 = split ? (wv < 4 ? 5 : LB) : LB;
+            const int dll = split ? 1 : SC::NW / qg.nTp;
+            for (int ll = ll0; ll < ll1; ll += dll) {
                 const int i = b * LB + ll;
                 if (i > Lq.Q) break;
                 const double* G = R + ll * gsz + boff;
