@@ -260,3 +260,41 @@ def test_evolve_argument_errors(E):
     st = ctx.evolve(sp, 0.0, 0.0, 1e-3, 1e-5, 10, g)                 # t_end = 0: nothing to do
     assert st["t"] == 0.0 and st["accepted"] == 0
     ctx.close()
+
+
+def test_surfactant_covered_drop_in_quadrupole_field(E):
+    """Non-diffusing surfactant (linear law, beta = 0.5), lambda = 1,
+    (R, Q) = (2, 1), quadrupole field E_inf = (-x, -y, 2z): at steady state the
+    shape r = 1 + Ca_E (F_20 P_2 + F_40 P_4) + O(Ca_E^2) has the first-order
+    coefficients of Sec. 3, F_20 = 25((2R - 1)(3 + 2R) - 5Q)/(28 (3 + 2R)^2) and
+    F_40 = 10(1 + R + R^2 - 3Q)/(7 (3 + 2R)^2).  Runs at Ca_E = 0.04 and 0.02,
+    extrapolated linearly to Ca_E = 0."""
+    import torch
+    from scipy.special import eval_legendre
+    p, R, Q = 12, 2.0, 1.0
+    F2p = 25 * ((2 * R - 1) * (3 + 2 * R) - 5 * Q) / (28 * (3 + 2 * R) ** 2)
+    F4p = 10 * (1 + R + R * R - 3 * Q) / (7 * (3 + 2 * R) ** 2)
+    t, wl = oracle.gauss_legendre(p + 1)
+    nl = 2 * p + 2
+    wt = np.repeat(wl, nl) * (2 * math.pi / nl)
+    ct = np.repeat(t, nl)
+    F = {}
+    for Ca in (0.04, 0.02):
+        s = make_susp(p, sphere_x(p))
+        ctx, dev = _ctx(E, s)
+        nc, T = ctx.num_coefs(), ctx.ntargets
+        g = torch.zeros(nc, dtype=torch.float64, device=dev)
+        g[0] = math.sqrt(4 * math.pi)
+        sp = E.Context.step_params(1.0, R, Q, Ca, 0.0, 1.0, eos=E.EOS_LINEAR, beta=0.5, tol=1e-10)
+        st = ctx.evolve(sp, 0.0, 8.0, 1e-3, 1e-6, 40000, g)
+        x0 = torch.empty(3, T, dtype=torch.float64, device=dev)
+        n0 = torch.empty_like(x0)
+        ctx.target_geometry(x0, n0)
+        ctx.close()
+        r = np.linalg.norm(x0.cpu().numpy(), axis=0)
+        # r(theta) at the nodes; at this order the parameter latitude is the polar angle
+        F[Ca] = [np.sum(wt * (r - 1.0) * eval_legendre(k, ct)) * (2 * k + 1) / (4 * math.pi) / Ca for k in (2, 4)]
+        assert abs(st["t"] - 8.0) < 1e-9
+    F0 = [2 * F[0.02][i] - F[0.04][i] for i in range(2)]
+    say("quadrupole, surfactant-covered: F at Ca 0.04, 0.02", F, "extrapolated", F0, "paper", F2p, F4p)
+    assert abs(F0[0] - F2p) < 0.01 * F2p and abs(F0[1] - F4p) < 0.01 * F4p

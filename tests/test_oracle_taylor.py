@@ -52,3 +52,74 @@ def test_taylor_shape_is_stationary_to_first_order(R, Q):
     assert 1.8 < big / small < 2.2                          # |u.n| = O(Ca_E)
     for wrong in (0.0, 2.0 * F):                            # the sphere, twice the deformation
         assert normal_velocity_rms(p, 0.02 * wrong, R, Q, 0.02) > 20.0 * small
+
+
+# ---------------------------------------------------------------------------
+# Quadrupole field (Sec. 3, linear theory, clean drop with viscosity ratio 1):
+# E_inf = E_q (-x, -y, 2z).  The clean-drop coefficients printed there (quoted
+# from another study)
+#   F_20 = 25 (-3 + 3R + 4R^2 - 4Q) / (112 (3 + 2R)^2),
+#   F_40 = 5 (4 + 3R + 4R^2 - 11Q) / (56 (3 + 2R)^2)
+# are 4 times smaller than what this field gives, in both modes and for every
+# (R, Q) tried, with the printed ratio F_40 / F_20.  The surfactant-covered
+# coefficients the paper derives itself (denominators 28 and 7 (3 + 2R)^2)
+# match the method's steady state directly (test_gpu_evolve).  Reading: the
+# quoted clean-drop coefficients are for a field of amplitude 2 E_q, so the
+# shape for this field takes 4 F_20 and 4 F_40.
+# ---------------------------------------------------------------------------
+def quad_f(R, Q):
+    return (25.0 * (-3.0 + 3.0 * R + 4.0 * R * R - 4.0 * Q) / (112.0 * (3.0 + 2.0 * R) ** 2),
+            5.0 * (4.0 + 3.0 * R + 4.0 * R * R - 11.0 * Q) / (56.0 * (3.0 + 2.0 * R) ** 2))
+
+
+def axisym_shape(p, a2, a4):
+    """Coefficients of x = (1 + a2 P_2(cos theta) + a4 P_4(cos theta)) r_hat,
+    by a plain Gauss-Legendre x trapezoid projection onto orthonormal Y_nm
+    (numpy and scipy only; exact for this band-limited field)."""
+    from scipy.special import eval_legendre, sph_harm_y
+    nq = p + 4
+    t, w = np.polynomial.legendre.leggauss(nq)
+    th = np.arccos(t)
+    ph = 2.0 * np.pi * np.arange(2 * nq) / (2 * nq)
+    TH, PH = np.meshgrid(th, ph, indexing="ij")
+    W2 = np.outer(w, np.full(2 * nq, 2.0 * np.pi / (2 * nq)))
+    r = 1.0 + a2 * eval_legendre(2, np.cos(TH)) + a4 * eval_legendre(4, np.cos(TH))
+    comps = [r * np.sin(TH) * np.cos(PH), r * np.sin(TH) * np.sin(PH), r * np.cos(TH)]
+    nc2 = (p + 1) * (p + 2)
+    blk = np.zeros(3 * nc2)
+    for c, g in enumerate(comps):
+        for n in range(p + 1):
+            for m in range(n + 1):
+                v = np.sum(W2 * g * np.conj(sph_harm_y(n, m, TH, PH)))
+                k = c * nc2 + 2 * tri(n, m)
+                blk[k], blk[k + 1] = v.real, (v.imag if m else 0.0)
+    return blk
+
+
+def quad_normal_velocity_rms(p, a2, a4, R, Q, Ca):
+    s = make_susp(p, axisym_shape(p, a2, a4))
+    _, u, _ = G.explicit_step(s, 1.0, R, Q, Ca, 0.0, 1.0, 0.0)
+    _, n0 = oracle.targets(s, *oracle.all_targets(s))
+    un = [oracle.sh_point(p, u, th, ph, nf=3)[0] @ n0[:, i] for i, (_, th, ph) in enumerate(G.node_angles(s))]
+    return math.sqrt(np.mean(np.square(un)))
+
+
+def test_axisym_shape_projection():
+    """The projected shape reproduces the radius 1 + a2 P_2 + a4 P_4."""
+    from scipy.special import eval_legendre
+    p = 6
+    blk = axisym_shape(p, 0.1, -0.05)
+    for th, ph in [(0.3, 0.2), (1.2, 2.0), (2.6, 4.0)]:
+        x = oracle.sh_point(p, blk, th, ph, nf=3)[0]
+        ct = math.cos(th)
+        assert abs(np.linalg.norm(x) - (1 + 0.1 * eval_legendre(2, ct) - 0.05 * eval_legendre(4, ct))) < 1e-13
+
+
+@pytest.mark.parametrize("R,Q", [(2.0, 1.0), (0.5, 2.0)])
+def test_quadrupole_shape_is_stationary_to_first_order(R, Q):
+    p = 6
+    F2, F4 = (4.0 * f for f in quad_f(R, Q))
+    big, small = (quad_normal_velocity_rms(p, Ca * F2, Ca * F4, R, Q, Ca) for Ca in (0.04, 0.02))
+    assert 1.8 < big / small < 2.2                          # |u.n| = O(Ca_E)
+    assert quad_normal_velocity_rms(p, 0.0, 0.0, R, Q, 0.02) > 20.0 * small      # the sphere
+    assert quad_normal_velocity_rms(p, 0.02 * F2, 0.0, R, Q, 0.02) > 5.0 * small  # without the P_4 mode
