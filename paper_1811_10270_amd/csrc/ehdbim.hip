@@ -37,6 +37,7 @@ constexpr int kThreads = 256;
 constexpr int kTile = 256;        // far-field sources per LDS tile
 constexpr int kRec64 = 14;        // x(3) n(3) w(1) wf(3) wu(3) wsig(1)
 constexpr int kNearMaxM = 12;     // nearly singular targets: most check points per line
+constexpr int kNearSplit = 16;    // source chunks per pair in the check-point sums
 constexpr int kRec32 = 13;        // x-c(3) n(3) wf(3) wu(3) wsig(1)
 constexpr int kMaxChunks = 16;    // far field: largest number of source chunks
 
@@ -1365,61 +1366,94 @@ __global__ __launch_bounds__(kThreads) void k_near_limit(const NearPair* __restr
     o[8] = -n0g + (v[8] + 0.5 * v[12]) * n0n;
 }
 
-// Regular-rule sums of one drop at one point, one block per (pair, k):
-// k < m the check points y + s_k nu on the check grid, k = m the target x0
-// on drop j's far-grid records.  out[pair][k][9], scaled by 1/(4 pi).
-__global__ __launch_bounds__(kThreads) void k_near_check(const NearPair* __restrict__ pairs, int m, double sc,
-                                                         const double* __restrict__ frec, long long Nf,
-                                                         const long long* __restrict__ foff,
-                                                         const int* __restrict__ fidx,
+// Kernels of drop j's regular rule at a point p (normal n0 for K*), added to
+// a[9] for one source record (x, n, w f, w u, w sigma).
+__device__ __forceinline__ void near_pair_sum(const double* p, const double* n0, double sx, double sy, double sz,
+                                              double nx, double ny, double nz, double f0, double f1, double f2,
+                                              double u0, double u1, double u2, double sg, double* a)
+{
+    const double hx = p[0] - sx, hy = p[1] - sy, hz = p[2] - sz;
+    const double ir = rsqrt_nr(hx * hx + hy * hy + hz * hz), ir2 = ir * ir, ir3 = ir * ir2;
+    const double hn = hx * nx + hy * ny + hz * nz;
+    const double hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
+    a[0] += f0 * ir + hx * hf;
+    a[1] += f1 * ir + hy * hf;
+    a[2] += f2 * ir + hz * hf;
+    const double tq = -6.0 * (hx * u0 + hy * u1 + hz * u2) * hn * ir3 * ir2;
+    a[3] += tq * hx;
+    a[4] += tq * hy;
+    a[5] += tq * hz;
+    a[6] += sg * ir;
+    a[7] += sg * hn * ir3;
+    a[8] += sg * (hx * n0[0] + hy * n0[1] + hz * n0[2]) * ir3;
+}
+
+// Check-point sums: block (pair, chunk) walks chunk `chunk` of kNearSplit
+// ranges of drop j's check grid in LDS tiles of 256 records; wave k sums at
+// the check point y + s_k nu (k < m).  out[pair][chunk][k][9] (1/(4 pi)
+// applied); the chunks are added in order by k_near_apply.
+__global__ __launch_bounds__(64 * kNearMaxM) void k_near_check(const NearPair* __restrict__ pairs, int m, double sc,
+                                                               const double* __restrict__ frec, long long Nf,
+                                                               const long long* __restrict__ foff,
+                                                               const int* __restrict__ fidx,
+                                                               const double* __restrict__ tnrm, long long T,
+                                                               double* __restrict__ out)
+{
+    constexpr int NR = 13;                               // record rows used: x n (skip w) wf wu wsig
+    __shared__ double tile[NR][kTile];
+    const int pi = blockIdx.x, k = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const NearPair P = pairs[pi];
+    double pt[3], n0[3];
+    for (int c = 0; c < 3; ++c) {
+        n0[c] = tnrm[c * T + P.t];
+        pt[c] = P.y[c] + sc * (1.0 + 0.5 * k) * P.nu[c];
+    }
+    const int fd = fidx[P.j];
+    const long long len = foff[fd + 1] - foff[fd];
+    const long long c0 = foff[fd] + len * blockIdx.y / kNearSplit, c1 = foff[fd] + len * (blockIdx.y + 1) / kNearSplit;
+    double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (long long base = c0; base < c1; base += kTile) {
+        for (int i = threadIdx.x; i < NR * kTile; i += blockDim.x) {
+            const int r = i / kTile, q = i % kTile;
+            const long long s = base + q;
+            const int row = r < 6 ? r : r + 1;
+            // past the chunk: no density, far away
+            tile[r][q] = s < c1 ? frec[row * Nf + s] : (r < 3 ? 1e6 : 0.0);
+        }
+        __syncthreads();
+        for (int q = lane; q < kTile; q += 64)
+            near_pair_sum(pt, n0, tile[0][q], tile[1][q], tile[2][q], tile[3][q], tile[4][q], tile[5][q], tile[6][q],
+                          tile[7][q], tile[8][q], tile[9][q], tile[10][q], tile[11][q], tile[12][q], a);
+        __syncthreads();
+    }
+    for (int c = 0; c < 9; ++c) {
+        const double v = wave_sum(a[c]);
+        if (lane == 0) out[(((long long)pi * kNearSplit + blockIdx.y) * (m + 1) + k) * 9 + c] = v * kInv4Pi;
+    }
+}
+
+// Drop j's regular-rule value at the target x0 on its far-grid records (what
+// the far sum added), one block per pair, into the chunk-0 slot of k = m.
+__global__ __launch_bounds__(kThreads) void k_near_plain(const NearPair* __restrict__ pairs, int m,
                                                          const double* __restrict__ src, long long Spad,
                                                          const DropInfo* __restrict__ drops,
                                                          const double* __restrict__ tx,
                                                          const double* __restrict__ tnrm, long long T,
                                                          double* __restrict__ out)
 {
-    const int pi = blockIdx.x / (m + 1), k = blockIdx.x % (m + 1);
+    const int pi = blockIdx.x;
     const NearPair P = pairs[pi];
-    double x0[3], n0[3];
+    const DropInfo D = drops[P.j];
+    double pt[3], n0[3];
     for (int c = 0; c < 3; ++c) {
+        pt[c] = tx[c * T + P.t];
         n0[c] = tnrm[c * T + P.t];
-        x0[c] = k < m ? P.y[c] + sc * (1.0 + 0.5 * k) * P.nu[c] : tx[c * T + P.t];
-    }
-    const double* rec;
-    long long ld, s0, s1;
-    if (k < m) {
-        const int fd = fidx[P.j];
-        rec = frec;
-        ld = Nf;
-        s0 = foff[fd];
-        s1 = foff[fd + 1];
-    } else {
-        const DropInfo D = drops[P.j];
-        rec = src;
-        ld = Spad;
-        s0 = D.soff;
-        s1 = D.soff + D.ns;
     }
     double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (long long s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
-        const double hx = x0[0] - rec[s], hy = x0[1] - rec[ld + s], hz = x0[2] - rec[2 * ld + s];
-        const double ir = 1.0 / sqrt(hx * hx + hy * hy + hz * hz), ir2 = ir * ir, ir3 = ir * ir2;
-        const double hn = hx * rec[3 * ld + s] + hy * rec[4 * ld + s] + hz * rec[5 * ld + s];
-        const double f0 = rec[7 * ld + s], f1 = rec[8 * ld + s], f2 = rec[9 * ld + s];
-        const double hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
-        a[0] += f0 * ir + hx * hf;
-        a[1] += f1 * ir + hy * hf;
-        a[2] += f2 * ir + hz * hf;
-        const double hu = hx * rec[10 * ld + s] + hy * rec[11 * ld + s] + hz * rec[12 * ld + s];
-        const double tq = -6.0 * hu * hn * ir3 * ir2;
-        a[3] += tq * hx;
-        a[4] += tq * hy;
-        a[5] += tq * hz;
-        const double sg = rec[13 * ld + s];
-        a[6] += sg * ir;
-        a[7] += sg * hn * ir3;
-        a[8] += sg * (hx * n0[0] + hy * n0[1] + hz * n0[2]) * ir3;
-    }
+    for (long long s = D.soff + threadIdx.x; s < D.soff + D.ns; s += blockDim.x)
+        near_pair_sum(pt, n0, src[s], src[Spad + s], src[2 * Spad + s], src[3 * Spad + s], src[4 * Spad + s],
+                      src[5 * Spad + s], src[7 * Spad + s], src[8 * Spad + s], src[9 * Spad + s], src[10 * Spad + s],
+                      src[11 * Spad + s], src[12 * Spad + s], src[13 * Spad + s], a);
     __shared__ double red[kThreads / 64][9];
     for (int c = 0; c < 9; ++c) {
         const double v = wave_sum(a[c]);
@@ -1429,7 +1463,7 @@ __global__ __launch_bounds__(kThreads) void k_near_check(const NearPair* __restr
     if (threadIdx.x < 9) {
         double v = 0.0;
         for (int w = 0; w < kThreads / 64; ++w) v += red[w][threadIdx.x];
-        out[(long long)blockIdx.x * 9 + threadIdx.x] = v * kInv4Pi;
+        out[((long long)pi * kNearSplit * (m + 1) + m) * 9 + threadIdx.x] = v * kInv4Pi;
     }
 }
 
@@ -1452,12 +1486,16 @@ __global__ void k_near_apply(const NearPair* __restrict__ pairs, int npairs, int
             if (i != k) l *= (P.st - nodes[i]) / (nodes[k] - nodes[i]);
         w[k] = l;
     }
-    const double* c0 = chk + (long long)pi * (m + 1) * 9;
+    const double* c0 = chk + (long long)pi * kNearSplit * (m + 1) * 9;
     for (int r = 0; r < rows.n; ++r) {
         const int c = rows.comp[r];
         double v = w[0] * lim[9 * (long long)pi + c];
-        for (int k = 0; k < m; ++k) v += w[k + 1] * c0[k * 9 + c];
-        atomicAdd(out + (long long)r * T + P.t, v - c0[m * 9 + c]);
+        for (int k = 0; k <= m; ++k) {
+            double sk = 0.0;                                     // chunks in order
+            for (int h = 0; h < kNearSplit; ++h) sk += c0[(h * (m + 1) + k) * 9 + c];
+            v += k < m ? w[k + 1] * sk : -sk;
+        }
+        atomicAdd(out + (long long)r * T + P.t, v);
     }
 }
 
@@ -1596,7 +1634,7 @@ struct ehd_ctx {
         double* d_fsyn = nullptr;        // [9][nf]
         double* d_selfc = nullptr;       // [9][ncoef_total] projected self values
         double* d_lim = nullptr;         // [npairs][9]
-        double* d_chk = nullptr;         // [npairs][m+1][9]
+        double* d_chk = nullptr;         // [npairs][kNearSplit][m+1][9]
         void release()
         {
             for (void* a : allocs) (void)hipFree(a);
@@ -2001,7 +2039,7 @@ static int near_build(ehd_ctx* ctx)
     if ((rc = near_upload(ctx, &N.d_selfc, z))) return rc;
     z.assign((size_t)9 * N.npairs, 0.0);
     if ((rc = near_upload(ctx, &N.d_lim, z))) return rc;
-    z.assign((size_t)9 * (N.m + 1) * N.npairs, 0.0);
+    z.assign((size_t)9 * (N.m + 1) * kNearSplit * N.npairs, 0.0);
     if ((rc = near_upload(ctx, &N.d_chk, z))) return rc;
     // check-grid geometry
     hipLaunchKernelGGL((k_synth<3, true>), dim3(N.nfrows), dim3(kThreads), 0, ctx->stream, N.d_fdrops, N.d_flegs, 1,
@@ -2038,9 +2076,10 @@ static int near_enqueue(ehd_ctx* ctx, const double* fcoef_d, const double* ucoef
     const double* uc = ucoef_d ? ucoef_d : fcoef_d;
     hipLaunchKernelGGL(k_near_limit, dim3(N.npairs), dim3(kThreads), 0, ctx->ls, N.d_pairs, ctx->d_info, N.d_legv,
                        N.d_selfc, uc ? uc : N.d_selfc, sigcoef_d ? sigcoef_d : N.d_selfc, ctx->d_tn, ctx->T, N.d_lim);
-    hipLaunchKernelGGL(k_near_check, dim3(N.npairs * (N.m + 1)), dim3(kThreads), 0, ctx->ls, N.d_pairs, N.m, N.sc,
-                       N.d_frec, nf, N.d_foff, N.d_fidx, ctx->d_src64, ctx->Spad, ctx->d_info, ctx->d_tx, ctx->d_tn,
-                       ctx->T, N.d_chk);
+    hipLaunchKernelGGL(k_near_check, dim3(N.npairs, kNearSplit), dim3(64 * N.m), 0, ctx->ls, N.d_pairs, N.m, N.sc,
+                       N.d_frec, nf, N.d_foff, N.d_fidx, ctx->d_tn, ctx->T, N.d_chk);
+    hipLaunchKernelGGL(k_near_plain, dim3(N.npairs), dim3(kThreads), 0, ctx->ls, N.d_pairs, N.m, ctx->d_src64,
+                       ctx->Spad, ctx->d_info, ctx->d_tx, ctx->d_tn, ctx->T, N.d_chk);
     hipLaunchKernelGGL(k_near_apply, dim3((N.npairs + 127) / 128), dim3(128), 0, ctx->ls, N.d_pairs, N.npairs, N.m,
                        N.sc, N.d_lim, N.d_chk, rows, ctx->T, out);
     EHD_HIP(ctx, hipGetLastError());
