@@ -17,6 +17,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <utility>
 #include <vector>
@@ -1635,6 +1636,10 @@ struct ehd_ctx {
         double* d_selfc = nullptr;       // [9][ncoef_total] projected self values
         double* d_lim = nullptr;         // [npairs][9]
         double* d_chk = nullptr;         // [npairs][kNearSplit][m+1][9]
+        // check-grid tables per degree p, kept across shapes for (tab_qc, tab_gm)
+        std::map<int, LegTab> tabs;
+        std::vector<void*> tab_allocs;
+        int tab_qc = -1, tab_gm = -1;
         void release()
         {
             for (void* a : allocs) (void)hipFree(a);
@@ -1642,11 +1647,19 @@ struct ehd_ctx {
             npairs = nfd = nfrows = 0;
             nf = 0;
         }
+        void release_tables()
+        {
+            for (void* a : tab_allocs) (void)hipFree(a);
+            tab_allocs.clear();
+            tabs.clear();
+            tab_qc = tab_gm = -1;
+        }
     } near;
 
     void free_all()
     {
         near.release();
+        near.release_tables();
         near.on = false;
         for (void* a : allocs) (void)hipFree(a);
         allocs.clear();
@@ -1823,23 +1836,91 @@ int ehd_ctx_fail(ehd_ctx* ctx, int code, const char* msg)
 
 // --- nearly singular targets: host set-up ---------------------------------
 template <typename T>
-static int near_upload(ehd_ctx* ctx, T** out, const std::vector<T>& h)
+static int near_upload(ehd_ctx* ctx, T** out, const std::vector<T>& h, std::vector<void*>* owner = nullptr)
 {
     void* p = nullptr;
     EHD_HIP(ctx, hipMalloc(&p, sizeof(T) * std::max<size_t>(h.size(), 1)));
-    ctx->near.allocs.push_back(p);
+    (owner ? owner : &ctx->near.allocs)->push_back(p);
     if (!h.empty())
         EHD_HIP(ctx, hipMemcpyAsync(p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, ctx->stream));
     *out = (T*)p;
     return EHD_OK;
 }
 
-// x, dx/dtheta and dx/dphi of one drop's surface (3 packed fields) at (th, ph).
-static void host_surface_point(int p, const double* xc, double th, double ph, double x[3], double xt[3], double xp[3],
-                               std::vector<double>* Pout = nullptr, std::vector<double>* dPout = nullptr)
+// A zeroed device buffer of n doubles owned by the near set-up.
+static int near_zeros(ehd_ctx* ctx, double** out, size_t n)
 {
-    std::vector<double> P, dP;
-    ehd::legendre_tables(p, std::vector<double>{std::cos(th)}, P, dP);
+    void* p = nullptr;
+    EHD_HIP(ctx, hipMalloc(&p, sizeof(double) * std::max<size_t>(n, 1)));
+    ctx->near.allocs.push_back(p);
+    EHD_HIP(ctx, hipMemsetAsync(p, 0, sizeof(double) * std::max<size_t>(n, 1), ctx->stream));
+    *out = (double*)p;
+    return EHD_OK;
+}
+
+// x, dx/dtheta and dx/dphi of one drop's surface (3 packed fields) at (th, ph).
+// The square-root factors of the orthonormal associated Legendre recurrence
+// in theta (and of its ladder formula for d/dtheta) for one degree, so that a
+// point costs no square roots; values agree bit for bit with the grid tables.
+struct HostLeg {
+    int p = -1;
+    std::vector<double> diag, a, b, up, dn, row, P, dP, tg;
+    explicit HostLeg(int p_) : p(p_)
+    {
+        const int pp = p + 1;
+        diag.assign(pp + 1, 0.0);
+        a.assign(ncoef(pp), 0.0);
+        b.assign(ncoef(pp), 0.0);
+        for (int m = 1; m <= pp; ++m) diag[m] = std::sqrt((2.0 * m + 1.0) / (2.0 * m));
+        for (int m = 0; m <= pp; ++m)
+            for (int n = m + 2; n <= pp; ++n) {
+                a[tri(n, m)] = std::sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m));
+                b[tri(n, m)] = std::sqrt(((n - 1.0) * (n - 1.0) - (double)m * m) / (4.0 * (n - 1.0) * (n - 1.0) - 1.0));
+            }
+        up.assign(ncoef(p), 0.0);
+        dn.assign(ncoef(p), 0.0);
+        for (int n = 0; n <= p; ++n)
+            for (int m = 0; m <= n; ++m) {
+                up[tri(n, m)] = (m + 1 <= n) ? std::sqrt((double)(n - m) * (n + m + 1)) : 0.0;
+                dn[tri(n, m)] = m >= 1 ? std::sqrt((double)(n + m) * (n - m + 1)) : (n >= 1 ? -std::sqrt((double)n * (n + 1)) : 0.0);
+            }
+        row.assign(ncoef(pp), 0.0);
+        P.assign(ncoef(p), 0.0);
+        dP.assign(ncoef(p), 0.0);
+        std::vector<double> w;
+        ehd::gauss_legendre(p + 1, tg, w);
+    }
+    // P and dP/dtheta at cos(theta) = x
+    void eval(double x)
+    {
+        const double s = std::sqrt((1.0 - x) * (1.0 + x));
+        const int pp = p + 1;
+        double dg = 1.0 / std::sqrt(4.0 * kPi);
+        for (int m = 0; m <= pp; ++m) {
+            if (m > 0) dg *= -diag[m] * s;
+            row[tri(m, m)] = dg;
+            if (m + 1 <= pp) row[tri(m + 1, m)] = std::sqrt(2.0 * m + 3.0) * x * dg;
+            for (int n = m + 2; n <= pp; ++n) {
+                const long k = tri(n, m);
+                row[k] = a[k] * (x * row[tri(n - 1, m)] - b[k] * row[tri(n - 2, m)]);
+            }
+        }
+        for (int n = 0; n <= p; ++n)
+            for (int m = 0; m <= n; ++m) {
+                const long k = tri(n, m);
+                P[k] = row[k];
+                const double u = (m + 1 <= n) ? up[k] * row[tri(n, m + 1)] : 0.0;
+                const double d = (m >= 1) ? dn[k] * row[tri(n, m - 1)] : (n >= 1 ? dn[k] * row[tri(n, 1)] : 0.0);
+                dP[k] = 0.5 * (u - d);
+            }
+    }
+};
+
+static void host_surface_point(HostLeg& L, const double* xc, double th, double ph, double x[3], double xt[3], double xp[3])
+{
+    const int p = L.p;
+    L.eval(std::cos(th));
+    const std::vector<double>&P = L.P, &dP = L.dP;
     const long nc = ncoef(p);
     for (int c = 0; c < 3; ++c) x[c] = xt[c] = xp[c] = 0.0;
     for (int m = 0; m <= p; ++m) {
@@ -1855,8 +1936,6 @@ static void host_surface_point(int p, const double* xc, double th, double ph, do
             }
         }
     }
-    if (Pout) *Pout = P;
-    if (dPout) *dPout = dP;
 }
 
 // Near pairs of the current shapes, closest points, check grids.
@@ -1885,78 +1964,108 @@ static int near_build(ehd_ctx* ctx)
             rho[d] = std::max(rho[d], std::sqrt(r2));
         }
     }
+    // chunks of 16 targets dealt round-robin to host threads (near targets
+    // cluster), then the pairs put back in target order
+    struct Part {
+        std::vector<NearPair> pairs;
+        std::vector<double> legv;
+    };
+    const int nth = (int)std::max(1LL, std::min<long long>({16LL, (long long)std::thread::hardware_concurrency(), T / 256}));
+    std::vector<Part> parts(nth);
+    auto search = [&](int w) {
+        Part& R = parts[w];
+        std::map<int, HostLeg> hleg;
+        for (long long t = 0; t < T; ++t) {
+            if ((t / 16) % nth != w) continue;
+            const double x0[3] = {tx[t], tx[T + t], tx[2 * T + t]};
+            for (int j = 0; j < nd; ++j) {
+                if (j == tdrop[t]) continue;
+                const DropInfo& D = ctx->info[j];
+                double d0 = 0.0;
+                for (int c = 0; c < 3; ++c) d0 += (x0[c] - D.c[c]) * (x0[c] - D.c[c]);
+                if (std::sqrt(d0) > 1.2 * rho[j] + N.delta) continue;
+                // nearest grid node of drop j, then damped Gauss-Newton in (theta, phi)
+                const long long n = (long long)(D.p + 1) * D.nlon_p;
+                long long best = D.toff;
+                double bd = 1e300;
+                for (long long q = D.toff; q < D.toff + n; ++q) {
+                    double e = 0.0;
+                    for (int c = 0; c < 3; ++c) e += (tx[c * T + q] - x0[c]) * (tx[c * T + q] - x0[c]);
+                    if (e < bd) { bd = e; best = q; }
+                }
+                // the surface is within half a node spacing (about pi rho / (p + 1)
+                // along a parallel, less along a meridian) of its nearest node
+                if (std::sqrt(bd) > N.delta + kPi * rho[j] / (D.p + 1)) continue;
+                HostLeg& HL = hleg.try_emplace(D.p, D.p).first->second;
+                const std::vector<double>& tg = HL.tg;
+                const long long loc = best - D.toff;
+                double th = std::acos(tg[loc / D.nlon_p]), ph = 2.0 * kPi * (double)(loc % D.nlon_p) / D.nlon_p;
+                const double* xc = xh.data() + 3 * D.coff;
+                double x[3], xt[3], xp[3];
+                for (int it = 0; it < 60; ++it) {
+                    host_surface_point(HL, xc, th, ph, x, xt, xp);
+                    double r[3], A00 = 0, A01 = 0, A11 = 0, g0 = 0, g1 = 0;
+                    for (int c = 0; c < 3; ++c) {
+                        r[c] = x[c] - x0[c];
+                        A00 += xt[c] * xt[c]; A01 += xt[c] * xp[c]; A11 += xp[c] * xp[c];
+                        g0 += xt[c] * r[c]; g1 += xp[c] * r[c];
+                    }
+                    const double mu = 1e-14 * (A00 + A11);
+                    A00 += mu; A11 += mu;
+                    const double det = A00 * A11 - A01 * A01;
+                    const double d_th = -(A11 * g0 - A01 * g1) / det, d_ph = -(A00 * g1 - A01 * g0) / det;
+                    th = std::min(kPi - 1e-9, std::max(1e-9, th + d_th));
+                    ph += d_ph;
+                    if (std::fabs(d_th) + std::fabs(d_ph) < 1e-15) break;
+                }
+                host_surface_point(HL, xc, th, ph, x, xt, xp);
+                const std::vector<double>&P = HL.P, &dP = HL.dP;
+                double dist = 0.0;
+                for (int c = 0; c < 3; ++c) dist += (x0[c] - x[c]) * (x0[c] - x[c]);
+                dist = std::sqrt(dist);
+                if (!(dist < N.delta) || dist < 1e-12) continue;
+                NearPair pr{};
+                pr.t = (int)t;
+                pr.j = j;
+                pr.th = th;
+                pr.ph = ph;
+                const double cx = xt[1] * xp[2] - xt[2] * xp[1], cy = xt[2] * xp[0] - xt[0] * xp[2],
+                             cz = xt[0] * xp[1] - xt[1] * xp[0];
+                const double cn = std::sqrt(cx * cx + cy * cy + cz * cz);
+                const double nrm[3] = {cx / cn, cy / cn, cz / cn};
+                for (int c = 0; c < 3; ++c) {
+                    pr.y[c] = x[c];
+                    pr.ny[c] = nrm[c];
+                    pr.xt[c] = xt[c];
+                    pr.xp[c] = xp[c];
+                    pr.nu[c] = (x0[c] - x[c]) / dist;
+                }
+                pr.st = dist;
+                pr.legoff = (long long)R.legv.size();
+                R.legv.insert(R.legv.end(), P.begin(), P.end());
+                R.legv.insert(R.legv.end(), dP.begin(), dP.end());
+                R.pairs.push_back(pr);
+            }
+        }
+    };
+    std::vector<std::thread> workers;
+    for (int w = 1; w < nth; ++w) workers.emplace_back(search, w);
+    search(0);
+    for (std::thread& th : workers) th.join();
+    std::vector<std::pair<int, int>> order;   // (part, index) by target
+    for (int w = 0; w < nth; ++w)
+        for (int i = 0; i < (int)parts[w].pairs.size(); ++i) order.emplace_back(w, i);
+    std::stable_sort(order.begin(), order.end(), [&](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+        return parts[a.first].pairs[a.second].t < parts[b.first].pairs[b.second].t;
+    });
     std::vector<NearPair> pairs;
     std::vector<double> legv;
-    for (long long t = 0; t < T; ++t) {
-        const double x0[3] = {tx[t], tx[T + t], tx[2 * T + t]};
-        for (int j = 0; j < nd; ++j) {
-            if (j == tdrop[t]) continue;
-            const DropInfo& D = ctx->info[j];
-            double d0 = 0.0;
-            for (int c = 0; c < 3; ++c) d0 += (x0[c] - D.c[c]) * (x0[c] - D.c[c]);
-            if (std::sqrt(d0) > 1.2 * rho[j] + N.delta) continue;
-            // nearest grid node of drop j, then damped Gauss-Newton in (theta, phi)
-            const long long n = (long long)(D.p + 1) * D.nlon_p;
-            long long best = D.toff;
-            double bd = 1e300;
-            for (long long q = D.toff; q < D.toff + n; ++q) {
-                double e = 0.0;
-                for (int c = 0; c < 3; ++c) e += (tx[c * T + q] - x0[c]) * (tx[c * T + q] - x0[c]);
-                if (e < bd) { bd = e; best = q; }
-            }
-            // the surface is within half a node spacing (about pi rho / (p + 1)
-            // along a parallel, less along a meridian) of its nearest node
-            if (std::sqrt(bd) > N.delta + kPi * rho[j] / (D.p + 1)) continue;
-            std::vector<double> tg, wg;
-            ehd::gauss_legendre(D.p + 1, tg, wg);
-            const long long loc = best - D.toff;
-            double th = std::acos(tg[loc / D.nlon_p]), ph = 2.0 * kPi * (double)(loc % D.nlon_p) / D.nlon_p;
-            const double* xc = xh.data() + 3 * D.coff;
-            double x[3], xt[3], xp[3];
-            for (int it = 0; it < 60; ++it) {
-                host_surface_point(D.p, xc, th, ph, x, xt, xp);
-                double r[3], A00 = 0, A01 = 0, A11 = 0, g0 = 0, g1 = 0;
-                for (int c = 0; c < 3; ++c) {
-                    r[c] = x[c] - x0[c];
-                    A00 += xt[c] * xt[c]; A01 += xt[c] * xp[c]; A11 += xp[c] * xp[c];
-                    g0 += xt[c] * r[c]; g1 += xp[c] * r[c];
-                }
-                const double mu = 1e-14 * (A00 + A11);
-                A00 += mu; A11 += mu;
-                const double det = A00 * A11 - A01 * A01;
-                const double d_th = -(A11 * g0 - A01 * g1) / det, d_ph = -(A00 * g1 - A01 * g0) / det;
-                th = std::min(kPi - 1e-9, std::max(1e-9, th + d_th));
-                ph += d_ph;
-                if (std::fabs(d_th) + std::fabs(d_ph) < 1e-15) break;
-            }
-            std::vector<double> P, dP;
-            host_surface_point(D.p, xc, th, ph, x, xt, xp, &P, &dP);
-            double dist = 0.0;
-            for (int c = 0; c < 3; ++c) dist += (x0[c] - x[c]) * (x0[c] - x[c]);
-            dist = std::sqrt(dist);
-            if (!(dist < N.delta) || dist < 1e-12) continue;
-            NearPair pr{};
-            pr.t = (int)t;
-            pr.j = j;
-            pr.th = th;
-            pr.ph = ph;
-            const double cx = xt[1] * xp[2] - xt[2] * xp[1], cy = xt[2] * xp[0] - xt[0] * xp[2],
-                         cz = xt[0] * xp[1] - xt[1] * xp[0];
-            const double cn = std::sqrt(cx * cx + cy * cy + cz * cz);
-            const double nrm[3] = {cx / cn, cy / cn, cz / cn};
-            for (int c = 0; c < 3; ++c) {
-                pr.y[c] = x[c];
-                pr.ny[c] = nrm[c];
-                pr.xt[c] = xt[c];
-                pr.xp[c] = xp[c];
-                pr.nu[c] = (x0[c] - x[c]) / dist;
-            }
-            pr.st = dist;
-            pr.legoff = (long long)legv.size();
-            legv.insert(legv.end(), P.begin(), P.end());
-            legv.insert(legv.end(), dP.begin(), dP.end());
-            pairs.push_back(pr);
-        }
+    for (const std::pair<int, int>& o : order) {
+        NearPair pr = parts[o.first].pairs[o.second];
+        const double* src = parts[o.first].legv.data() + pr.legoff;
+        pr.legoff = (long long)legv.size();
+        legv.insert(legv.end(), src, src + 2 * ncoef(ctx->info[pr.j].p));
+        pairs.push_back(pr);
     }
     N.npairs = (int)pairs.size();
     if (!N.npairs) return EHD_OK;
@@ -1969,12 +2078,21 @@ static int near_build(ehd_ctx* ctx)
     std::vector<int2> frows;
     std::vector<int> node_drop;
     std::map<int, int> legid;
+    if (N.tab_qc != N.qc || N.tab_gm != ctx->grid_mode) {
+        N.release_tables();
+        N.tab_qc = N.qc;
+        N.tab_gm = ctx->grid_mode;
+    }
     for (int j = 0; j < nd; ++j) {
         if (fidx[j] < 0) continue;
         fidx[j] = (int)fd.size();
         DropInfo D = ctx->info[j];
         const int Q = N.qc, nl = nlon_of(Q, ctx->grid_mode);
         auto it = legid.find(D.p);
+        if (it == legid.end() && N.tabs.count(D.p)) {
+            fl.push_back(N.tabs[D.p]);
+            it = legid.emplace(D.p, (int)fl.size() - 1).first;
+        }
         if (it == legid.end()) {
             std::vector<double> t, w, P, dP;
             ehd::gauss_legendre(Q + 1, t, w);
@@ -1993,22 +2111,23 @@ static int near_build(ehd_ctx* ctx)
             LegTab L{};
             double* dp;
             int rc;
-            if ((rc = near_upload(ctx, &dp, P))) return rc;
+            if ((rc = near_upload(ctx, &dp, P, &N.tab_allocs))) return rc;
             L.P = dp;
-            if ((rc = near_upload(ctx, &dp, dP))) return rc;
+            if ((rc = near_upload(ctx, &dp, dP, &N.tab_allocs))) return rc;
             L.dP = dp;
-            if ((rc = near_upload(ctx, &dp, wq))) return rc;
+            if ((rc = near_upload(ctx, &dp, wq, &N.tab_allocs))) return rc;
             L.wq = dp;
-            if ((rc = near_upload(ctx, &dp, rs))) return rc;
+            if ((rc = near_upload(ctx, &dp, rs, &N.tab_allocs))) return rc;
             L.rsin = dp;
-            if ((rc = near_upload(ctx, &dp, t))) return rc;
+            if ((rc = near_upload(ctx, &dp, t, &N.tab_allocs))) return rc;
             L.cth = dp;
-            if ((rc = near_upload(ctx, &dp, trig))) return rc;
+            if ((rc = near_upload(ctx, &dp, trig, &N.tab_allocs))) return rc;
             L.trig = dp;
             L.p = D.p;
             L.Q = Q;
             L.nlon = nl;
             fl.push_back(L);
+            N.tabs[D.p] = L;
             it = legid.emplace(D.p, (int)fl.size() - 1).first;
         }
         D.leg_pf = it->second;
@@ -2030,17 +2149,11 @@ static int near_build(ehd_ctx* ctx)
         (rc = near_upload(ctx, &N.d_frows, frows)) || (rc = near_upload(ctx, &N.d_node_drop, node_drop)) ||
         (rc = near_upload(ctx, &N.d_foff, foff)) || (rc = near_upload(ctx, &N.d_fidx, fidx)))
         return rc;
-    std::vector<double> z;
-    z.assign((size_t)kRec64 * N.nf, 0.0);
-    if ((rc = near_upload(ctx, &N.d_frec, z))) return rc;
-    z.assign((size_t)9 * N.nf, 0.0);
-    if ((rc = near_upload(ctx, &N.d_fsyn, z))) return rc;
-    z.assign((size_t)9 * ctx->ncoef_total, 0.0);
-    if ((rc = near_upload(ctx, &N.d_selfc, z))) return rc;
-    z.assign((size_t)9 * N.npairs, 0.0);
-    if ((rc = near_upload(ctx, &N.d_lim, z))) return rc;
-    z.assign((size_t)9 * (N.m + 1) * kNearSplit * N.npairs, 0.0);
-    if ((rc = near_upload(ctx, &N.d_chk, z))) return rc;
+    if ((rc = near_zeros(ctx, &N.d_frec, (size_t)kRec64 * N.nf)) || (rc = near_zeros(ctx, &N.d_fsyn, (size_t)9 * N.nf)) ||
+        (rc = near_zeros(ctx, &N.d_selfc, (size_t)9 * ctx->ncoef_total)) ||
+        (rc = near_zeros(ctx, &N.d_lim, (size_t)9 * N.npairs)) ||
+        (rc = near_zeros(ctx, &N.d_chk, (size_t)9 * (N.m + 1) * kNearSplit * N.npairs)))
+        return rc;
     // check-grid geometry
     hipLaunchKernelGGL((k_synth<3, true>), dim3(N.nfrows), dim3(kThreads), 0, ctx->stream, N.d_fdrops, N.d_flegs, 1,
                        N.d_frows, ctx->d_x, N.d_fsyn, N.nf);

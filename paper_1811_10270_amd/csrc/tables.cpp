@@ -23,7 +23,8 @@ void gauss_legendre(int n, std::vector<double>& t, std::vector<double>& w)
         double x = std::cos(kPi * (4.0 * i + 3.0) / (4.0 * n + 2.0)) *
                    (1.0 - (n - 1.0) / (8.0 * n * n * n));
         double dpn = 1.0;
-        for (int it = 0; it < 64; ++it) {
+        int fine = 0;   // Newton steps taken once |dx| <= 1e-12: the error after one is about n^2 dx^2
+        for (int it = 0; it < 64 && fine < 2; ++it) {
             double a = 1.0, b = x;  // P_0, P_1
             if (n == 1) { a = 1.0; b = x; }
             for (int k = 1; k < n; ++k) {
@@ -35,7 +36,7 @@ void gauss_legendre(int n, std::vector<double>& t, std::vector<double>& w)
             dpn = n * (pnm1 - x * pn) / (1.0 - x * x);
             double dx = pn / dpn;
             x -= dx;
-            if (std::fabs(dx) <= 1e-17 * (1.0 + std::fabs(x))) break;
+            if (std::fabs(dx) <= 1e-12 * (1.0 + std::fabs(x))) ++fine;
         }
         double a = 1.0, b = x;
         for (int k = 1; k < n; ++k) {
@@ -56,37 +57,42 @@ void legendre_tables(int p, const std::vector<double>& t, std::vector<double>& P
     const long nc = ncoef(p);
     P.assign((size_t)nlat * nc, 0.0);
     dP.assign((size_t)nlat * nc, 0.0);
-    std::vector<double> row(ncoef(p + 1));
+    // values up to degree p+1 in m (needed by the ladder formula for m+1);
+    // the square-root factors do not depend on the point
+    const int pp = p + 1;
+    std::vector<double> row(ncoef(pp)), fd(pp + 1), fs(pp + 1), fa(ncoef(pp)), fb(ncoef(pp)), fu(nc), fn(nc);
+    for (int m = 0; m <= pp; ++m) {
+        fd[m] = m > 0 ? std::sqrt((2.0 * m + 1.0) / (2.0 * m)) : 0.0;
+        fs[m] = std::sqrt(2.0 * m + 3.0);
+        for (int n = m + 2; n <= pp; ++n) {
+            fa[tri(n, m)] = std::sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m));
+            fb[tri(n, m)] = std::sqrt(((n - 1.0) * (n - 1.0) - (double)m * m) / (4.0 * (n - 1.0) * (n - 1.0) - 1.0));
+        }
+    }
+    // ladder: dP/dtheta = 1/2 [ sqrt((n-m)(n+m+1)) P^{m+1} - sqrt((n+m)(n-m+1)) P^{m-1} ],
+    // with P_n^{-1} = -P_n^1.
+    for (int n = 0; n <= p; ++n)
+        for (int m = 0; m <= n; ++m) {
+            fu[tri(n, m)] = (m + 1 <= n) ? std::sqrt((double)(n - m) * (n + m + 1)) : 0.0;
+            fn[tri(n, m)] = m >= 1 ? std::sqrt((double)(n + m) * (n - m + 1)) : (n >= 1 ? -std::sqrt((double)n * (n + 1)) : 0.0);
+        }
     for (int i = 0; i < nlat; ++i) {
         const double x = t[i], s = std::sqrt((1.0 - x) * (1.0 + x));
-        // values up to degree p+1 in m (needed by the ladder formula for m+1)
-        const int pp = p + 1;
         double diag = 1.0 / std::sqrt(4.0 * kPi);
         for (int m = 0; m <= pp; ++m) {
-            if (m > 0) diag *= -std::sqrt((2.0 * m + 1.0) / (2.0 * m)) * s;
+            if (m > 0) diag *= -fd[m] * s;
             row[tri(m, m)] = diag;
-            if (m + 1 <= pp) row[tri(m + 1, m)] = std::sqrt(2.0 * m + 3.0) * x * diag;
-            for (int n = m + 2; n <= pp; ++n) {
-                double a = std::sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m));
-                double b = std::sqrt(((n - 1.0) * (n - 1.0) - (double)m * m) /
-                                     (4.0 * (n - 1.0) * (n - 1.0) - 1.0));
-                row[tri(n, m)] = a * (x * row[tri(n - 1, m)] - b * row[tri(n - 2, m)]);
-            }
+            if (m + 1 <= pp) row[tri(m + 1, m)] = fs[m] * x * diag;
+            for (int n = m + 2; n <= pp; ++n)
+                row[tri(n, m)] = fa[tri(n, m)] * (x * row[tri(n - 1, m)] - fb[tri(n, m)] * row[tri(n - 2, m)]);
         }
         for (int n = 0; n <= p; ++n) {
             for (int m = 0; m <= n; ++m) {
-                P[(size_t)i * nc + tri(n, m)] = row[tri(n, m)];
-                // ladder: dP/dtheta = 1/2 [ sqrt((n-m)(n+m+1)) P^{m+1}
-                //                          - sqrt((n+m)(n-m+1)) P^{m-1} ],
-                // with P_n^{-1} = -P_n^1.
-                double up = (m + 1 <= n) ? std::sqrt((double)(n - m) * (n + m + 1)) * row[tri(n, m + 1)]
-                                         : 0.0;
-                double dn;
-                if (m >= 1)
-                    dn = std::sqrt((double)(n + m) * (n - m + 1)) * row[tri(n, m - 1)];
-                else
-                    dn = (n >= 1) ? -std::sqrt((double)n * (n + 1)) * row[tri(n, 1)] : 0.0;
-                dP[(size_t)i * nc + tri(n, m)] = 0.5 * (up - dn);
+                const long k = tri(n, m);
+                P[(size_t)i * nc + k] = row[k];
+                const double up = (m + 1 <= n) ? fu[k] * row[tri(n, m + 1)] : 0.0;
+                const double dn = m >= 1 ? fn[k] * row[tri(n, m - 1)] : (n >= 1 ? fn[k] * row[tri(n, 1)] : 0.0);
+                dP[(size_t)i * nc + k] = 0.5 * (up - dn);
             }
         }
     }
