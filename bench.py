@@ -47,10 +47,10 @@ def self_flops_per_drop(p: int, q: int, grid_mode: int) -> float:
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs
 # recorded in profiles/hbm_traffic_batched_64_mixed_p.md (counters scaled by a
 # 1 GiB copy), valid only for the kernel source they were taken with.
-TRAFFIC_SOURCE_SHA256 = "80537bce865e9e10589f7d60281084069b7148561ab44069237f81757d55f605"
+TRAFFIC_SOURCE_SHA256 = "b9482830df9d4732690db0211f2aab9dddce20628f43533cdd5c4470eadcda2a"
 TRAFFIC_WORKLOAD = "batched_64_mixed_p"
-TRAFFIC_BYTES = {"k_self<48>": 6.442e+08, "k_self<32>": 1.201e+08, "k_self<24>": 2.54e+07,
-                 "k_self<16>": 7.373e+06, "k_far32": 8.068e+08}
+TRAFFIC_BYTES = {"k_self<48>": 6.359e+08, "k_self<32>": 1.201e+08, "k_self<24>": 2.54e+07,
+                 "k_self<16>": 7.373e+06, "k_far32": 8.102e+08}
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -383,8 +383,10 @@ def main(argv=None):
                          "position update) on two_drops_p32 with lambda = 2, R = 0.5, Q = 2, uniform "
                          "field E_u = 1, Ca_E = 0.3, clean drops, dt = 0.01")
     ap.add_argument("--overlap", action="store_true",
-                    help="far field on a second stream, concurrent with the self-interaction "
-                         "(per-kernel times then include the sharing of the device)")
+                    help="far field partly on a second stream, beside the smaller self-interaction classes "
+                         "(the default for the evaluation; opt-in for --solve/--step/--near/--evolve)")
+    ap.add_argument("--serial", action="store_true",
+                    help="evaluation: self-interaction, then far field, on one stream (every kernel alone)")
     ap.add_argument("--near", action="store_true",
                     help="time the evaluation of two p = 32 spheres --near-gap apart with and without the "
                          "nearly singular correction")
@@ -433,6 +435,7 @@ def main(argv=None):
     s = W.WORKLOADS[args.workload](args.grid_mode)
     far_prec = E.FAR_FP32C if args.far_prec == "fp32c" else E.FAR_FP64
     kinds = E.METRIC_KINDS
+    args.overlap = not args.serial
 
     ctx = E.Context(0)
     ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
@@ -470,7 +473,11 @@ def main(argv=None):
     avg = [sum(st[k] for st in stages) / K for k in range(4)]
     cls_times = [ctx.self_class_times(i) for i in range(K)] if not args.graph else None
 
-    # per-kernel rooflines; the dominant kernel's goes to "roofline"
+    # per-kernel rooflines; the dominant kernel's goes to "roofline".  In
+    # overlap mode the p <= 48 class runs alone; the smaller classes share
+    # the device with the forked far-field part ("shared": their times are
+    # wall times, not theirs alone), and the far field's two launches have
+    # no time of their own.
     self_flops = sum(self_flops_per_drop(int(s.p[d]), int(s.q_self[d]), s.grid_mode)
                      for d in range(s.ndrops))
     far_flops = far_interactions(s) * FAR_FLOPS_PER_INTERACTION
@@ -484,18 +491,23 @@ def main(argv=None):
             if ms > 0 and fl > 0:
                 kernels.append({"kernel": f"k_self<{pmax}> (singular self-interaction, p <= {pmax}, FP64)",
                                 "bound": "alu", "algorithmic_flops": fl, "avg_ms": ms,
-                                "achieved": fl / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS})
+                                "achieved": fl / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS,
+                                "shared": bool(args.overlap and pmax < 48)})
         far_peak = PEAK_FP32_UNPACKED_TFLOPS if far_prec == E.FAR_FP32C else PEAK_FP64_TFLOPS
+        far_ms = None if args.overlap else avg[2]
         kernels.append({"kernel": ("k_far32" if far_prec == E.FAR_FP32C else "k_far64")
                         + " (far-field direct sums)", "bound": "alu", "algorithmic_flops": far_flops,
-                        "avg_ms": avg[2], "achieved": far_flops / (avg[2] * 1e-3) / 1e12, "peak": far_peak})
+                        "avg_ms": far_ms, "achieved": far_flops / (far_ms * 1e-3) / 1e12 if far_ms else None,
+                        "peak": far_peak, "shared": bool(args.overlap)})
         for k in kernels:
             k["unit"] = "TFLOP/s"
-            k["frac"] = k["achieved"] / k["peak"]
-            k["traffic"] = measured_traffic(k["kernel"], args.workload)
+            k["frac"] = k["achieved"] / k["peak"] if k["achieved"] is not None else None
+            # per-launch counter bytes; the far field's two overlap launches have none
+            k["traffic"] = None if (k["shared"] and k["avg_ms"] is None) else measured_traffic(k["kernel"], args.workload)
     roof = None
-    if kernels:
-        dom = max(kernels, key=lambda k: k["avg_ms"])
+    alone = [k for k in kernels if not k["shared"]]
+    if alone:
+        dom = max(alone, key=lambda k: k["avg_ms"])
         roof = {"kernel": dom["kernel"], "bound": dom["bound"], "achieved": dom["achieved"],
                 "peak": dom["peak"], "unit": "TFLOP/s", "frac": dom["frac"], "traffic": dom["traffic"],
                 "algorithmic_flops": dom["algorithmic_flops"], "avg_ms": dom["avg_ms"]}
@@ -522,8 +534,8 @@ def main(argv=None):
                    "far_interactions": far_interactions(s), "far_tile": tile,
                    "graph": bool(args.graph)},
         "stage_ms": dict(zip(E.STAGES, avg)),
-        "self_tflops": self_flops / (avg[1] * 1e-3) / 1e12,
-        "far_tflops": far_flops / (avg[2] * 1e-3) / 1e12,
+        "self_tflops": None if args.overlap else self_flops / (avg[1] * 1e-3) / 1e12,
+        "far_tflops": None if args.overlap else far_flops / (avg[2] * 1e-3) / 1e12,
         "roofline": roof,
         "kernels": kernels,
     }

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <array>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -488,7 +489,11 @@ __host__ __device__ inline QuarterGrid quarter_grid(int p, int nlonq, bool row0)
 
 // Compile-time bounds of one degree class (all p <= PMAX; the rotated grid
 // has at most 8 row tiles of 16 half-period longitudes).
-constexpr int kLatBlock = 8;          // rotated latitudes per Legendre MFMA block
+constexpr int kLatBlock = 8;
+// Overlap mode: share of the far-field work items forked beside the smaller
+// degree classes (the evaluation time is flat from 0.3 to 0.5 on 64 mixed
+// drops and from 0.2 to 0.35 on 256 drops of p = 32).
+constexpr double kOverlapShare = 0.35;          // rotated latitudes per Legendre MFMA block
 
 // Degree columns m = 0..p are dealt to the NW waves in snake order
 // (0,1,..,NW-1, NW-1,..,0, 0,1,..); column m has ceil((p+1-m)/4) k-steps.
@@ -586,9 +591,9 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
 
     const __attribute__((address_space(1))) double* fld[NF];
     for (int c = 0; c < 3; ++c) fld[c] = gmem(xcoef + 3 * D.coff + c * 2 * nc);
-    if (HF) for (int c = 0; c < 3; ++c) fld[FOFF + c] = gmem(fcoef + 3 * D.coff + c * 2 * nc);
-    if (HU) for (int c = 0; c < 3; ++c) fld[UOFF + c] = gmem(ucoef + 3 * D.coff + c * 2 * nc);
-    if (HS) fld[SOFF] = gmem(scoef + D.coff);
+    if constexpr (HF) for (int c = 0; c < 3; ++c) fld[FOFF + c] = gmem(fcoef + 3 * D.coff + c * 2 * nc);
+    if constexpr (HU) for (int c = 0; c < 3; ++c) fld[UOFF + c] = gmem(ucoef + 3 * D.coff + c * 2 * nc);
+    if constexpr (HS) fld[SOFF] = gmem(scoef + D.coff);
 
     // 1. rotation, into LDS (column-major: column m holds n = m..p
     //    contiguously).
@@ -600,7 +605,6 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     //       broadcasts, the rows of A and B coalesced over the lanes), then
     //       overwrites the degree's slots: only this wave reads them.
     static_assert(PMAX < 64, "one lane per order m' of a degree");
-    double* crd = reinterpret_cast<double*>(cr);
     {
         const auto ph = gmem(Lp.trig + (long long)k * (p + 1) * 2);
         for (int it = threadIdx.x; it < nc; it += blockDim.x) {
@@ -964,12 +968,12 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
 // sources read two at a time as double2 broadcasts from each LDS record
 // row), with absolute coordinates and plain FP64 sums.
 template <int TPT, unsigned KM>
-__global__ __launch_bounds__(kThreads) void k_far64(const double* __restrict__ tx,
+__device__ __forceinline__ void far64_block(const double* __restrict__ tx,
                                                     const double* __restrict__ tnrm,
                                                     const int* __restrict__ tdrop, long long T,
                                                     const double* __restrict__ src, long long Spad,
                                                     const int* __restrict__ tile_drop, int ntiles,
-                                                    int tiles_per_chunk, double* __restrict__ partial)
+                                                    int tiles_per_chunk, double* __restrict__ partial, int bx, int by)
 {
     constexpr bool wS = KM & EHD_STOKES_SL, wD = KM & EHD_STOKES_DL;
     constexpr bool wSL = KM & EHD_LAP_SL, wL = KM & EHD_LAP_DL, wK = KM & EHD_LAP_DLADJ;
@@ -980,7 +984,7 @@ __global__ __launch_bounds__(kThreads) void k_far64(const double* __restrict__ t
     int myd[TPT];
     long long tt[TPT];
     for (int q = 0; q < TPT; ++q) {
-        tt[q] = (long long)blockIdx.x * blockDim.x * TPT + q * blockDim.x + threadIdx.x;
+        tt[q] = (long long)bx * blockDim.x * TPT + q * blockDim.x + threadIdx.x;
         const bool valid = tt[q] < T;
         const long long u = valid ? tt[q] : 0;
         x0[q] = tx[u]; y0[q] = tx[T + u]; z0[q] = tx[2 * T + u];
@@ -988,7 +992,7 @@ __global__ __launch_bounds__(kThreads) void k_far64(const double* __restrict__ t
         myd[q] = valid ? tdrop[u] : -1;
         for (int c = 0; c < 9; ++c) acc[q][c] = 0.0;
     }
-    const int t0 = blockIdx.y * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
+    const int t0 = by * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
     for (int tile = t0; tile < t1; ++tile) {
         const long long s = (long long)tile * kTile + threadIdx.x;
         for (int r = 0; r < kRec64; ++r) smd[r * kTile + threadIdx.x] = src[r * Spad + s];
@@ -1050,7 +1054,23 @@ __global__ __launch_bounds__(kThreads) void k_far64(const double* __restrict__ t
     }
     for (int k = 0; k < TPT; ++k)
         if (tt[k] < T)
-            for (int c = 0; c < 9; ++c) partial[((long long)blockIdx.y * 9 + c) * T + tt[k]] = acc[k][c];
+            for (int c = 0; c < 9; ++c) partial[((long long)by * 9 + c) * T + tt[k]] = acc[k][c];
+}
+
+// Work items (target block bx, chunk by) = (vb % nbx, vb / nbx) for vb in
+// [vb0, vb1), dealt to the blocks of the grid in turn: an ordinary launch has
+// one block per item, a persistent one fewer blocks that loop.
+template <int TPT, unsigned KM>
+__global__ __launch_bounds__(kThreads) void k_far64(const double* __restrict__ tx, const double* __restrict__ tnrm,
+                                                    const int* __restrict__ tdrop, long long T,
+                                                    const double* __restrict__ src, long long Spad,
+                                                    const int* __restrict__ tile_drop, int ntiles,
+                                                    int tiles_per_chunk, double* __restrict__ partial, int nbx,
+                                                    int vb0, int vb1)
+{
+    for (int vb = vb0 + (int)blockIdx.x; vb < vb1; vb += (int)gridDim.x)
+        far64_block<TPT, KM>(tx, tnrm, tdrop, T, src, Spad, tile_drop, ntiles, tiles_per_chunk, partial, vb % nbx,
+                             vb / nbx);
 }
 
 // FP32 far field: the kinds KM are a template parameter (no per-interaction
@@ -1061,13 +1081,13 @@ __global__ __launch_bounds__(kThreads) void k_far64(const double* __restrict__ t
 // the tile sums are added with Kahan compensation.  The double-layer
 // factor -6 is applied to the tile sums.
 template <int TPT, unsigned KM>
-__global__ __launch_bounds__(kThreads) void k_far32(const double* __restrict__ tx,
+__device__ __forceinline__ void far32_block(const double* __restrict__ tx,
                                                     const double* __restrict__ tnrm,
                                                     const int* __restrict__ tdrop, long long T,
                                                     const float* __restrict__ src, long long Spad,
                                                     const int* __restrict__ tile_drop,
                                                     const double* __restrict__ dcentre, int ntiles,
-                                                    int tiles_per_chunk, double* __restrict__ partial)
+                                                    int tiles_per_chunk, double* __restrict__ partial, int bx, int by)
 {
     constexpr bool wS = KM & EHD_STOKES_SL, wD = KM & EHD_STOKES_DL;
     constexpr bool wSL = KM & EHD_LAP_SL, wL = KM & EHD_LAP_DL, wK = KM & EHD_LAP_DLADJ;
@@ -1079,7 +1099,7 @@ __global__ __launch_bounds__(kThreads) void k_far32(const double* __restrict__ t
     int myd[TPT];
     long long tt[TPT];
     for (int q = 0; q < TPT; ++q) {
-        tt[q] = (long long)blockIdx.x * blockDim.x * TPT + q * blockDim.x + threadIdx.x;
+        tt[q] = (long long)bx * blockDim.x * TPT + q * blockDim.x + threadIdx.x;
         const bool valid = tt[q] < T;
         const long long u = valid ? tt[q] : 0;
         X0[q] = tx[u]; Y0[q] = tx[T + u]; Z0[q] = tx[2 * T + u];
@@ -1087,7 +1107,7 @@ __global__ __launch_bounds__(kThreads) void k_far32(const double* __restrict__ t
         myd[q] = valid ? tdrop[u] : -1;
         for (int c = 0; c < 9; ++c) { sum[q][c] = 0.0f; cmp[q][c] = 0.0f; }
     }
-    const int t0 = blockIdx.y * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
+    const int t0 = by * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
     for (int tile = t0; tile < t1; ++tile) {
         const long long s = (long long)tile * kTile + threadIdx.x;
         for (int r = 0; r < kRec32; ++r) smf[r * kTile + threadIdx.x] = src[r * Spad + s];
@@ -1167,7 +1187,22 @@ __global__ __launch_bounds__(kThreads) void k_far32(const double* __restrict__ t
     for (int k = 0; k < TPT; ++k)
         if (tt[k] < T)
             for (int c = 0; c < 9; ++c)
-                partial[((long long)blockIdx.y * 9 + c) * T + tt[k]] = (double)sum[k][c] - (double)cmp[k][c];
+                partial[((long long)by * 9 + c) * T + tt[k]] = (double)sum[k][c] - (double)cmp[k][c];
+}
+
+// Work items as for k_far64.
+template <int TPT, unsigned KM>
+__global__ __launch_bounds__(kThreads) void k_far32(const double* __restrict__ tx, const double* __restrict__ tnrm,
+                                                    const int* __restrict__ tdrop, long long T,
+                                                    const float* __restrict__ src, long long Spad,
+                                                    const int* __restrict__ tile_drop,
+                                                    const double* __restrict__ dcentre, int ntiles,
+                                                    int tiles_per_chunk, double* __restrict__ partial, int nbx,
+                                                    int vb0, int vb1)
+{
+    for (int vb = vb0 + (int)blockIdx.x; vb < vb1; vb += (int)gridDim.x)
+        far32_block<TPT, KM>(tx, tnrm, tdrop, T, src, Spad, tile_drop, dcentre, ntiles, tiles_per_chunk, partial,
+                             vb % nbx, vb / nbx);
 }
 
 // Outputs: rows of the requested kinds, scaled far sums added to (or written
@@ -1510,6 +1545,7 @@ struct ehd_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     int max_lds = 65536;
+    int ncu = 256;                       // compute units (looping far-field blocks in overlap mode)
 
     // drops
     int nd = 0, grid_mode = 0;
@@ -1767,26 +1803,28 @@ static int launch_self_class(ehd_ctx* ctx, int cls, const double* f, const doubl
     return EHD_OK;
 }
 
+// The degree classes hi, hi-1, .., lo (3: p <= 48 .. 0: p <= 16), largest first.
 template <bool HF, bool HU, bool HS>
-static int launch_self(ehd_ctx* ctx, const double* f, const double* u, const double* s, unsigned kinds)
+static int launch_self(ehd_ctx* ctx, const double* f, const double* u, const double* s, unsigned kinds, int hi, int lo)
 {
-    int rc = launch_self_class<48, HF, HU, HS>(ctx, 3, f, u, s, kinds);
-    if (!rc) rc = launch_self_class<32, HF, HU, HS>(ctx, 2, f, u, s, kinds);
-    if (!rc) rc = launch_self_class<24, HF, HU, HS>(ctx, 1, f, u, s, kinds);
-    if (!rc) rc = launch_self_class<16, HF, HU, HS>(ctx, 0, f, u, s, kinds);
+    int rc = EHD_OK;
+    if (!rc && hi >= 3 && lo <= 3) rc = launch_self_class<48, HF, HU, HS>(ctx, 3, f, u, s, kinds);
+    if (!rc && hi >= 2 && lo <= 2) rc = launch_self_class<32, HF, HU, HS>(ctx, 2, f, u, s, kinds);
+    if (!rc && hi >= 1 && lo <= 1) rc = launch_self_class<24, HF, HU, HS>(ctx, 1, f, u, s, kinds);
+    if (!rc && hi >= 0 && lo <= 0) rc = launch_self_class<16, HF, HU, HS>(ctx, 0, f, u, s, kinds);
     return rc;
 }
 
 // FP64 far-field launchers, one per (targets per thread, kinds mask).
 using Far64Launch = void (*)(dim3, hipStream_t, const double*, const double*, const int*, long long, const double*,
-                             long long, const int*, int, int, double*);
+                             long long, const int*, int, int, double*, int, int, int);
 template <int TPT, unsigned KM>
 static void launch_far64_km(dim3 grid, hipStream_t st, const double* tx, const double* tn, const int* tdrop,
                             long long T, const double* src, long long S, const int* tile_drop, int ntiles, int tpc,
-                            double* partial)
+                            double* partial, int nbx, int vb0, int vb1)
 {
     hipLaunchKernelGGL((k_far64<TPT, KM>), grid, dim3(kThreads), 0, st, tx, tn, tdrop, T, src, S, tile_drop, ntiles,
-                       tpc, partial);
+                       tpc, partial, nbx, vb0, vb1);
 }
 template <int TPT, std::size_t... I>
 static const std::array<Far64Launch, 32>& far64_table_impl(std::index_sequence<I...>)
@@ -1802,14 +1840,14 @@ static const std::array<Far64Launch, 32>& far64_table()
 
 // FP32 far-field launchers, one per (targets per thread, kinds mask).
 using Far32Launch = void (*)(dim3, hipStream_t, const double*, const double*, const int*, long long, const float*,
-                             long long, const int*, const double*, int, int, double*);
+                             long long, const int*, const double*, int, int, double*, int, int, int);
 template <int TPT, unsigned KM>
 static void launch_far32_km(dim3 grid, hipStream_t st, const double* tx, const double* tn, const int* tdrop,
                             long long T, const float* src, long long S, const int* tile_drop, const double* centre,
-                            int ntiles, int tpc, double* partial)
+                            int ntiles, int tpc, double* partial, int nbx, int vb0, int vb1)
 {
     hipLaunchKernelGGL((k_far32<TPT, KM>), grid, dim3(kThreads), 0, st, tx, tn, tdrop, T, src, S, tile_drop, centre,
-                       ntiles, tpc, partial);
+                       ntiles, tpc, partial, nbx, vb0, vb1);
 }
 template <int TPT, std::size_t... I>
 static const std::array<Far32Launch, 32>& far32_table_impl(std::index_sequence<I...>)
@@ -2219,6 +2257,9 @@ int ehd_create(ehd_ctx** out, int device, void* stream)
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess &&
         lds > 0)
         c->max_lds = lds;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+        c->ncu = ncu;
     *out = c;
     return EHD_OK;
 }
@@ -2641,20 +2682,33 @@ int ehd_num_coefs(const ehd_ctx* ctx, long long* ncoef)
 
 // Far-field launch with the context's tile shape (targets per thread, source
 // chunks) on the context's launch stream.
-static int launch_far(ehd_ctx* ctx, int far_prec, unsigned kinds, int tpt, int nchunk)
+// Number of far-field work items (target block, chunk) of a tile shape.
+static long long far_items(const ehd_ctx* ctx, int tpt, int nchunk)
+{
+    return (ctx->T + (long long)kThreads * tpt - 1) / ((long long)kThreads * tpt) * nchunk;
+}
+
+// Far-field items [vb0, vb1) (vb1 < 0: all), on `blocks` looping blocks
+// (0: one block per item).
+static int launch_far(ehd_ctx* ctx, int far_prec, unsigned kinds, int tpt, int nchunk, long long vb0 = 0,
+                      long long vb1 = -1, long long blocks = 0)
 {
     const long long T = ctx->T, S = ctx->Spad;
     const long long tblocks = (T + (long long)kThreads * tpt - 1) / ((long long)kThreads * tpt);
+    const long long nvb = tblocks * nchunk;
+    if (vb1 < 0) vb1 = nvb;
+    if (nvb > INT_MAX) EHD_FAIL(ctx, EHD_E_SHAPE, "too many far-field work items (%lld)", nvb);
+    if (vb1 <= vb0) return EHD_OK;
     const int tpc = (ctx->ntiles + nchunk - 1) / nchunk;
-    dim3 grid((unsigned)tblocks, (unsigned)nchunk);
+    const dim3 grid((unsigned)(blocks > 0 ? std::min(blocks, vb1 - vb0) : vb1 - vb0));
     if (far_prec == EHD_FAR_FP64) {
         const Far64Launch fn = (tpt == 2 ? far64_table<2>() : far64_table<1>())[kinds & EHD_ALL_KINDS];
         fn(grid, ctx->ls, ctx->d_tx, ctx->d_tn, ctx->d_tdrop, T, ctx->d_src64, S, ctx->d_tile_drop, ctx->ntiles, tpc,
-           ctx->d_partial);
+           ctx->d_partial, (int)tblocks, (int)vb0, (int)vb1);
     } else {
         const Far32Launch fn = (tpt == 2 ? far32_table<2>() : far32_table<1>())[kinds & EHD_ALL_KINDS];
         fn(grid, ctx->ls, ctx->d_tx, ctx->d_tn, ctx->d_tdrop, T, ctx->d_src32, S, ctx->d_tile_drop, ctx->d_centre,
-           ctx->ntiles, tpc, ctx->d_partial);
+           ctx->ntiles, tpc, ctx->d_partial, (int)tblocks, (int)vb0, (int)vb1);
     }
     EHD_HIP(ctx, hipGetLastError());
     return EHD_OK;
@@ -2696,45 +2750,67 @@ static int enqueue_evaluation(ehd_ctx* ctx, const double* fcoef_d, const double*
     EHD_HIP(ctx, hipGetLastError());
 
     ctx->mark(1);
-    // overlap mode: fork the far field onto its own stream now
-    if (ctx->overlap) {
-        EHD_HIP(ctx, hipEventRecord(ctx->ev_fork, ctx->ls));
-        EHD_HIP(ctx, hipStreamWaitEvent(ctx->far_stream, ctx->ev_fork, 0));
-        hipStream_t main = ctx->ls;
-        ctx->ls = ctx->far_stream;
-        const int rf = launch_far(ctx, far_prec, kinds, ctx->far_tpt, ctx->nchunk);
-        ctx->ls = main;
-        if (rf) return rf;
-        EHD_HIP(ctx, hipEventRecord(ctx->ev_join, ctx->far_stream));
-    }
     // 2. singular self-interaction.  The kernel holds at most 8 fields (its
     //    Legendre MFMA has 16 columns: field x re/im), so a separate u goes
     //    through its own pass (x, u) for D while the first pass covers the
     //    other kinds.
-    int rc = EHD_OK;
     // the nearly singular correction of K* needs the single layer's on-surface values
     const unsigned kself = (ctx->near.npairs && (kinds & EHD_LAP_DLADJ)) ? (kinds | EHD_LAP_SL) : kinds;
-    if (needU && (needF || needLap)) {
-        const unsigned k1 = kself & ~(unsigned)EHD_STOKES_DL;
-        if (needF && needLap) rc = launch_self<true, false, true>(ctx, fcoef_d, nullptr, sigcoef_d, k1);
-        else if (needF) rc = launch_self<true, false, false>(ctx, fcoef_d, nullptr, sigcoef_d, k1);
-        else rc = launch_self<false, false, true>(ctx, fcoef_d, nullptr, sigcoef_d, k1);
-        if (rc == EHD_OK) rc = launch_self<false, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, EHD_STOKES_DL);
-    } else if (needU) {
-        rc = launch_self<false, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself);
-    } else if (needF && needLap) {
-        rc = launch_self<true, false, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself);
-    } else if (needF) {
-        rc = launch_self<true, false, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself);
+    auto self_classes = [&](int hi, int lo) {
+        int rc = EHD_OK;
+        if (needU && (needF || needLap)) {
+            const unsigned k1 = kself & ~(unsigned)EHD_STOKES_DL;
+            if (needF && needLap) rc = launch_self<true, false, true>(ctx, fcoef_d, nullptr, sigcoef_d, k1, hi, lo);
+            else if (needF) rc = launch_self<true, false, false>(ctx, fcoef_d, nullptr, sigcoef_d, k1, hi, lo);
+            else rc = launch_self<false, false, true>(ctx, fcoef_d, nullptr, sigcoef_d, k1, hi, lo);
+            if (rc == EHD_OK)
+                rc = launch_self<false, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, EHD_STOKES_DL, hi, lo);
+        } else if (needU) {
+            rc = launch_self<false, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself, hi, lo);
+        } else if (needF && needLap) {
+            rc = launch_self<true, false, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself, hi, lo);
+        } else if (needF) {
+            rc = launch_self<true, false, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself, hi, lo);
+        } else {
+            rc = launch_self<false, false, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself, hi, lo);
+        }
+        return rc;
+    };
+    int rc;
+    if (!ctx->overlap) {
+        if ((rc = self_classes(3, 0))) return rc;
+        ctx->mark(2);
+        // 3. far field
+        if ((rc = launch_far(ctx, far_prec, kinds, ctx->far_tpt, ctx->nchunk))) return rc;
     } else {
-        rc = launch_self<false, false, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself);
+        // Overlap mode.  A far field of at most two work items per compute
+        // unit forks whole, before the self-interaction: its blocks take a
+        // few CUs and the self-interaction the rest.  A larger one would
+        // hold every CU until it drains.  A p <= 48 block takes nearly all
+        // of a CU's LDS and registers, so nothing runs beside it, while the
+        // smaller classes leave room for one far-field block per CU: after
+        // the p <= 48 class the far field forks as one looping block per CU
+        // over the first 35% of its items, beside the smaller classes, and
+        // the rest follows them on this stream as an ordinary launch.
+        // Every item is summed as in the serial order.
+        const long long nvb = far_items(ctx, ctx->far_tpt, ctx->nchunk);
+        const bool whole = nvb <= 2LL * ctx->ncu;
+        const long long split = whole ? nvb : (long long)std::ceil(kOverlapShare * (double)nvb);
+        if (!whole && (rc = self_classes(3, 3))) return rc;
+        EHD_HIP(ctx, hipEventRecord(ctx->ev_fork, ctx->ls));
+        EHD_HIP(ctx, hipStreamWaitEvent(ctx->far_stream, ctx->ev_fork, 0));
+        hipStream_t main = ctx->ls;
+        ctx->ls = ctx->far_stream;
+        rc = launch_far(ctx, far_prec, kinds, ctx->far_tpt, ctx->nchunk, 0, split, whole ? 0 : ctx->ncu);
+        ctx->ls = main;
+        if (rc) return rc;
+        EHD_HIP(ctx, hipEventRecord(ctx->ev_join, ctx->far_stream));
+        if ((rc = self_classes(whole ? 3 : 2, 0))) return rc;
+        ctx->mark(2);
+        // 3. far field: the rest, then the forked part
+        if ((rc = launch_far(ctx, far_prec, kinds, ctx->far_tpt, ctx->nchunk, split, nvb))) return rc;
+        EHD_HIP(ctx, hipStreamWaitEvent(ctx->ls, ctx->ev_join, 0));
     }
-    if (rc) return rc;
-    ctx->mark(2);
-
-    // 3. far field (overlap mode: wait for it)
-    if (ctx->overlap) EHD_HIP(ctx, hipStreamWaitEvent(ctx->ls, ctx->ev_join, 0));
-    else if ((rc = launch_far(ctx, far_prec, kinds, ctx->far_tpt, ctx->nchunk))) return rc;
 
     ctx->mark(3);
     // 4. outputs

@@ -97,6 +97,31 @@ def test_overlap_mode_matches_serial(E):
         ctx.close()
 
 
+def test_overlap_split_over_tile_shapes(E):
+    """Overlap mode splits the far field's (target block, chunk) items into
+    a looping part on the second stream and an ordinary launch: every tile
+    shape, in both precisions, gives the serial evaluation's bits, with and
+    without a p <= 48 class before the fork."""
+    import torch
+    for s in (W.subset(W.batched_suspension(seed=3), list(range(12))), W.two_drops(24, seed=5, gap=0.3)):
+        ctx, f, sg, dev = _setup(E, s)
+        T = ctx.ntargets
+        for prec in (E.FAR_FP32C, E.FAR_FP64):
+            for tpt, nch in ((1, 1), (1, 7), (2, 3), (2, 16)):
+                ctx.set_far_config(tpt, nch)
+                outs = []
+                for ov in (False, True):
+                    ctx.set_overlap(ov)
+                    so = torch.zeros(9, T, dtype=torch.float64, device=dev)
+                    fo = torch.zeros_like(so)
+                    ctx.layer_potentials(f, None, sg, E.ALL_KINDS, prec, so, fo)
+                    ctx.sync()
+                    outs.append((so, fo))
+                assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1]), (prec, tpt, nch)
+        ctx.set_overlap(False)
+        ctx.close()
+
+
 def test_overlap_fp64_single_kinds_and_solve(E):
     """Regression: the FP64 far field running beside the self-interaction
     slows some of its waves; the self kernel must not depend on its waves'
