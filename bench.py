@@ -382,11 +382,9 @@ def main(argv=None):
                     help="time one explicit step of the method (E_n solve, forces, velocity solve, "
                          "position update) on two_drops_p32 with lambda = 2, R = 0.5, Q = 2, uniform "
                          "field E_u = 1, Ca_E = 0.3, clean drops, dt = 0.01")
-    ap.add_argument("--overlap", action="store_true",
-                    help="far field partly on a second stream, beside the smaller self-interaction classes "
-                         "(the default for the evaluation; opt-in for --solve/--step/--near/--evolve)")
     ap.add_argument("--serial", action="store_true",
-                    help="evaluation: self-interaction, then far field, on one stream (every kernel alone)")
+                    help="self-interaction, then far field, on one stream (every kernel alone); by default "
+                         "the far field runs, whole or in part, on a second stream beside the self-interaction")
     ap.add_argument("--near", action="store_true",
                     help="time the evaluation of two p = 32 spheres --near-gap apart with and without the "
                          "nearly singular correction")
@@ -422,6 +420,7 @@ def main(argv=None):
         args.workload = "two_drops_p32" if (args.solve or args.step or args.evolve) else "batched_64_mixed_p"
     if args.far_prec is None:
         args.far_prec = "fp64" if (args.solve or args.step or args.evolve) else "fp32c"
+    args.overlap = not args.serial
     if args.learned:
         return bench_learned(args, torch, E, W, dev)
     if args.evolve:
@@ -435,7 +434,6 @@ def main(argv=None):
     s = W.WORKLOADS[args.workload](args.grid_mode)
     far_prec = E.FAR_FP32C if args.far_prec == "fp32c" else E.FAR_FP64
     kinds = E.METRIC_KINDS
-    args.overlap = not args.serial
 
     ctx = E.Context(0)
     ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
@@ -473,15 +471,20 @@ def main(argv=None):
     avg = [sum(st[k] for st in stages) / K for k in range(4)]
     cls_times = [ctx.self_class_times(i) for i in range(K)] if not args.graph else None
 
-    # per-kernel rooflines; the dominant kernel's goes to "roofline".  In
-    # overlap mode the p <= 48 class runs alone; the smaller classes share
-    # the device with the forked far-field part ("shared": their times are
-    # wall times, not theirs alone), and the far field's two launches have
-    # no time of their own.
+    # per-kernel rooflines; the dominant kernel's goes to "roofline" (none if
+    # every kernel shares the device).  Kernels that run beside the forked
+    # far field are "shared": their times are wall times, not theirs alone;
+    # the far field itself then has no time of its own.
     self_flops = sum(self_flops_per_drop(int(s.p[d]), int(s.q_self[d]), s.grid_mode)
                      for d in range(s.ndrops))
     far_flops = far_interactions(s) * FAR_FLOPS_PER_INTERACTION
     kernels = []
+    # the library's overlap regimes: a far field of at most two work items
+    # per CU forks whole (every class shares the device), a larger one after
+    # the p <= 48 class
+    tpt_, nch_ = ctx.far_config()
+    items = -(-T // (256 * tpt_)) * nch_
+    whole = items <= 2 * torch.cuda.get_device_properties(0).multi_processor_count
     if cls_times is not None:
         for c, pmax in enumerate(E.DEGREE_CLASSES):
             ms = sum(ct[c] for ct in cls_times) / K
@@ -492,7 +495,7 @@ def main(argv=None):
                 kernels.append({"kernel": f"k_self<{pmax}> (singular self-interaction, p <= {pmax}, FP64)",
                                 "bound": "alu", "algorithmic_flops": fl, "avg_ms": ms,
                                 "achieved": fl / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS,
-                                "shared": bool(args.overlap and pmax < 48)})
+                                "shared": bool(args.overlap and (whole or pmax < 48))})
         far_peak = PEAK_FP32_UNPACKED_TFLOPS if far_prec == E.FAR_FP32C else PEAK_FP64_TFLOPS
         far_ms = None if args.overlap else avg[2]
         kernels.append({"kernel": ("k_far32" if far_prec == E.FAR_FP32C else "k_far64")
