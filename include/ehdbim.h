@@ -243,8 +243,9 @@ int ehd_set_graph(ehd_ctx* ctx, int enable);
  * over the first 35% of its items, beside the smaller classes, and the rest
  * is an ordinary launch after them.  Measured: 64 drops of mixed degree
  * 138.2 -> 133.7 ms, 256 drops of p = 32 1023 -> 986 ms, two p = 32 drops
- * 2.10 -> 1.89 ms.  Stage times then read: self = until the last class ends
- * (shared with the forked part), far = the rest.  Drops a recorded graph. */
+ * 2.10 -> 1.89 ms.  A single drop (no far interactions) keeps the serial
+ * order.  Stage times then read: self = until the last class ends (shared
+ * with the forked part), far = the rest.  Drops a recorded graph. */
 int ehd_set_overlap(ehd_ctx* ctx, int enable);
 
 /* Far-field tile shape: targets per thread (1 or 2) and number of source

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -992,8 +993,13 @@ __device__ __forceinline__ void far64_block(const double* __restrict__ tx,
         myd[q] = valid ? tdrop[u] : -1;
         for (int c = 0; c < 9; ++c) acc[q][c] = 0.0;
     }
+    // targets are stored drop by drop: a block whose first and last targets
+    // lie on one drop skips that drop's tiles whole
+    const long long tb0 = (long long)bx * blockDim.x * TPT, tb1 = min(T - 1, tb0 + (long long)blockDim.x * TPT - 1);
+    const int bdrop = tdrop[tb0] == tdrop[tb1] ? tdrop[tb0] : -1;
     const int t0 = by * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
     for (int tile = t0; tile < t1; ++tile) {
+        if (tile_drop[tile] == bdrop) continue;   // uniform over the block
         const long long s = (long long)tile * kTile + threadIdx.x;
         for (int r = 0; r < kRec64; ++r) smd[r * kTile + threadIdx.x] = src[r * Spad + s];
         __syncthreads();
@@ -1107,8 +1113,13 @@ __device__ __forceinline__ void far32_block(const double* __restrict__ tx,
         myd[q] = valid ? tdrop[u] : -1;
         for (int c = 0; c < 9; ++c) { sum[q][c] = 0.0f; cmp[q][c] = 0.0f; }
     }
+    // targets are stored drop by drop: a block whose first and last targets
+    // lie on one drop skips that drop's tiles whole
+    const long long tb0 = (long long)bx * blockDim.x * TPT, tb1 = min(T - 1, tb0 + (long long)blockDim.x * TPT - 1);
+    const int bdrop = tdrop[tb0] == tdrop[tb1] ? tdrop[tb0] : -1;
     const int t0 = by * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
     for (int tile = t0; tile < t1; ++tile) {
+        if (tile_drop[tile] == bdrop) continue;   // uniform over the block
         const long long s = (long long)tile * kTile + threadIdx.x;
         for (int r = 0; r < kRec32; ++r) smf[r * kTile + threadIdx.x] = src[r * Spad + s];
         __syncthreads();
@@ -2086,10 +2097,25 @@ static int near_build(ehd_ctx* ctx)
             }
         }
     };
+    std::atomic<bool> failed{false};
+    auto run = [&](int w) {
+        try {
+            search(w);
+        } catch (...) {   // host allocation: reported below, never across the ABI
+            failed = true;
+        }
+    };
     std::vector<std::thread> workers;
-    for (int w = 1; w < nth; ++w) workers.emplace_back(search, w);
-    search(0);
+    for (int w = 1; w < nth; ++w) {
+        try {
+            workers.emplace_back(run, w);
+        } catch (...) {   // no thread to be had: this one takes the part
+            run(w);
+        }
+    }
+    run(0);
     for (std::thread& th : workers) th.join();
+    if (failed) EHD_FAIL(ctx, EHD_E_NOMEM, "near set-up: host allocation failed");
     std::vector<std::pair<int, int>> order;   // (part, index) by target
     for (int w = 0; w < nth; ++w)
         for (int i = 0; i < (int)parts[w].pairs.size(); ++i) order.emplace_back(w, i);
@@ -2777,7 +2803,7 @@ static int enqueue_evaluation(ehd_ctx* ctx, const double* fcoef_d, const double*
         return rc;
     };
     int rc;
-    if (!ctx->overlap) {
+    if (!ctx->overlap || ctx->nd < 2) {   // one drop: no far interactions, nothing to overlap
         if ((rc = self_classes(3, 0))) return rc;
         ctx->mark(2);
         // 3. far field

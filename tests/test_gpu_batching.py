@@ -76,7 +76,8 @@ def test_overlap_mode_matches_serial(E):
     """Far field on its own stream, concurrent with the self-interaction:
     the same bits as the serial evaluation, eagerly and in graph replays."""
     import torch
-    for s in (W.subset(W.batched_suspension(seed=3), list(range(10))), W.two_drops(16, seed=4, gap=0.2)):
+    for s in (W.subset(W.batched_suspension(seed=3), list(range(10))), W.two_drops(16, seed=4, gap=0.2),
+              W.single_drop(16, seed=1)):
         ctx, f, sg, dev = _setup(E, s)
         T = ctx.ntargets
         ref = torch.zeros(9, T, dtype=torch.float64, device=dev)
