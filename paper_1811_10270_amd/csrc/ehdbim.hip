@@ -490,11 +490,7 @@ __host__ __device__ inline QuarterGrid quarter_grid(int p, int nlonq, bool row0)
 
 // Compile-time bounds of one degree class (all p <= PMAX; the rotated grid
 // has at most 8 row tiles of 16 half-period longitudes).
-constexpr int kLatBlock = 8;
-// Overlap mode: share of the far-field work items forked beside the smaller
-// degree classes (the evaluation time is flat from 0.3 to 0.5 on 64 mixed
-// drops and from 0.2 to 0.35 on 256 drops of p = 32).
-constexpr double kOverlapShare = 0.35;          // rotated latitudes per Legendre MFMA block
+constexpr int kLatBlock = 8;          // rotated latitudes per Legendre MFMA block
 
 // Degree columns m = 0..p are dealt to the NW waves in snake order
 // (0,1,..,NW-1, NW-1,..,0, 0,1,..); column m has ceil((p+1-m)/4) k-steps.
@@ -2740,6 +2736,48 @@ static int launch_far(ehd_ctx* ctx, int far_prec, unsigned kinds, int tpt, int n
     return EHD_OK;
 }
 
+// Algorithmic FP64 work of one drop's singular self-interaction: rotation of
+// 7 fields, Legendre sums of 10 fields, longitude sums of 13 quantities and
+// about 75 flops of kernel per rotated node.
+static double self_work(const DropInfo& D)
+{
+    const double T = (double)(D.p + 1) * D.nlon_p, q1 = D.qs + 1.0;
+    double rot = 0.0;
+    for (int n = 0; n <= D.p; ++n) rot += (n + 1.0) * (2.0 * n + 1.0);
+    rot *= 4.0 * 7.0 * T;
+    const double leg = 4.0 * q1 * (double)ncoef(D.p) * 10.0 * T;
+    const double dft = 2.0 * D.nlon_s * (2.0 * D.p + 1.0) * q1 * 13.0 * T;
+    const double ker = 75.0 * T * q1 * D.nlon_s;
+    return rot + leg + dft + ker;
+}
+
+// Overlap mode: share of the far field's work items forked beside the
+// degree classes below p = 48, the expected time of those classes over that
+// of the far field (each its algorithmic work over the fraction of peak it
+// reaches alone: 0.22, 0.41, 0.56 for the classes, 0.96 for the FP32 far
+// field at 53 flops per interaction), at most one half.  On 64 mixed drops
+// this gives 0.37 and on 256 drops of p = 32 0.26, inside the measured
+// optima (0.3-0.5 and 0.2-0.35).  The FP64 far field needs the same FP64
+// units as the self-interaction, which slows down by about as much as the
+// far work done beside it (256 drops lost 3-8% at shares 0.13 and 0.35):
+// share 0.
+static double overlap_share(const ehd_ctx* ctx, int far_prec)
+{
+    if (far_prec == EHD_FAR_FP64) return 0.0;
+    static const double eff[3] = {0.22, 0.41, 0.56};
+    double small = 0.0, far = 0.0;
+    long long S = 0;
+    for (int d = 0; d < ctx->nd; ++d) S += ctx->info[d].ns;
+    for (int c = 0; c < 3; ++c)
+        for (int d : ctx->cls_drops[c]) small += self_work(ctx->info[d]) / eff[c];
+    for (int d = 0; d < ctx->nd; ++d) {
+        const DropInfo& D = ctx->info[d];
+        far += (double)(D.p + 1) * D.nlon_p * (double)(S - D.ns);
+    }
+    far *= 53.0 / 0.96;
+    return far > 0.0 ? std::min(0.5, small / far) : 0.0;
+}
+
 // The launch sequence of one evaluation, on ctx->ls.
 static int enqueue_evaluation(ehd_ctx* ctx, const double* fcoef_d, const double* ucoef_d,
                               const double* sigcoef_d, unsigned kinds, int far_prec, double* self_out_d,
@@ -2816,12 +2854,13 @@ static int enqueue_evaluation(ehd_ctx* ctx, const double* fcoef_d, const double*
         // of a CU's LDS and registers, so nothing runs beside it, while the
         // smaller classes leave room for one far-field block per CU: after
         // the p <= 48 class the far field forks as one looping block per CU
-        // over the first 35% of its items, beside the smaller classes, and
-        // the rest follows them on this stream as an ordinary launch.
+        // over a first share of its items (overlap_share), beside the
+        // smaller classes, and the rest follows them on this stream as an
+        // ordinary launch.
         // Every item is summed as in the serial order.
         const long long nvb = far_items(ctx, ctx->far_tpt, ctx->nchunk);
         const bool whole = nvb <= 2LL * ctx->ncu;
-        const long long split = whole ? nvb : (long long)std::ceil(kOverlapShare * (double)nvb);
+        const long long split = whole ? nvb : (long long)std::ceil(overlap_share(ctx, far_prec) * (double)nvb);
         if (!whole && (rc = self_classes(3, 3))) return rc;
         EHD_HIP(ctx, hipEventRecord(ctx->ev_fork, ctx->ls));
         EHD_HIP(ctx, hipStreamWaitEvent(ctx->far_stream, ctx->ev_fork, 0));
