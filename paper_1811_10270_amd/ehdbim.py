@@ -468,13 +468,20 @@ class Context:
 
 
 def evaluate(susp, kinds: int = ALL_KINDS, far_prec: int = FAR_FP64, split: bool = True,
-             device: int = 0):
-    """Convenience: one evaluation of a workloads.Suspension on `device`.
-    Returns (self_out, far_out) as CPU float64 tensors [rows][ntargets]."""
+             device: int = 0, overlap: bool = False, autotune: bool = False):
+    """Convenience: one evaluation of a workloads.Suspension on `device`
+    (optionally in overlap mode, with the far-field tile shape from the
+    autotuner, as the benchmark runs it).  Returns (self_out, far_out) as
+    CPU float64 tensors [rows][ntargets]."""
     dev = torch.device("cuda", device)
     ctx = Context(device)
     x = torch.from_numpy(susp.xcoef).to(dev)
     ctx.set_drops(susp.p, susp.q_self, susp.q_far, susp.grid_mode, x)
+    if autotune:
+        from . import autotune as _tune
+        _tune.autotune_far(ctx, susp.p, susp.q_far, susp.grid_mode, far_prec, use_cache=False)
+    if overlap:
+        ctx.set_overlap(True)
     f = torch.from_numpy(susp.fcoef).to(dev)
     s = torch.from_numpy(susp.sigcoef).to(dev)
     u = torch.from_numpy(susp.ucoef).to(dev) if susp.ucoef is not None else None

@@ -40,10 +40,12 @@ def normwise(got, ref):
     return np.abs(got - ref).max(axis=-1) / den
 
 
-def run(E, s, kinds=31, far_prec=0, split=True):
+def run(E, s, kinds=31, far_prec=0, split=True, bench_config=False):
+    """One evaluation; bench_config: overlap mode and the autotuned far-field
+    tile shape, the launch configuration bench.py times."""
     say(f"[gpu] {s.name}: ndrops={s.ndrops} p={sorted(set(s.p.tolist()))} kinds={kinds} "
-        f"far_prec={far_prec} grid_mode={s.grid_mode}")
-    return E.evaluate(s, kinds=kinds, far_prec=far_prec, split=split)
+        f"far_prec={far_prec} grid_mode={s.grid_mode} bench_config={bench_config}")
+    return E.evaluate(s, kinds=kinds, far_prec=far_prec, split=split, overlap=bench_config, autotune=bench_config)
 
 
 def sample(s, per_drop, seed=0):
@@ -218,11 +220,12 @@ def test_argument_errors(E):
 
 
 def test_full_batched_suspension_sampled(E):
-    """The full 64-drop batched suspension, FP64 and FP32 far field, sampled
-    targets against the oracle (self and far separately)."""
+    """The full 64-drop batched suspension, FP64 and FP32 far field, in the
+    benchmark's launch configuration, sampled targets against the oracle
+    (self and far separately)."""
     s = W.batched_suspension(seed=3)
-    so, fo = run(E, s, kinds=31, far_prec=0)
-    _, fo32 = run(E, s, kinds=31, far_prec=1)
+    so, fo = run(E, s, kinds=31, far_prec=0, bench_config=True)
+    _, fo32 = run(E, s, kinds=31, far_prec=1, bench_config=True)
     rng = np.random.default_rng(2)
     td_all, tn_all = oracle.all_targets(s)
     idx = np.sort(rng.choice(len(td_all), size=48, replace=False))
@@ -247,7 +250,7 @@ def test_fp32_far_field_bound_full_size(E, name):
     on sampled targets below and above): normwise error <= 1e-6 per output."""
     s = W.WORKLOADS[name](0)
     _, f64 = run(E, s, kinds=31, far_prec=0)
-    _, f32 = run(E, s, kinds=31, far_prec=1)
+    _, f32 = run(E, s, kinds=31, far_prec=1, bench_config=True)
     err = normwise(f32.numpy(), f64.numpy())
     say(name, "fp32 far normwise err", err)
     assert np.all(err < 1e-6), err
@@ -256,7 +259,7 @@ def test_fp32_far_field_bound_full_size(E, name):
 def test_large_suspension_sampled_parity(E):
     """256 drops at p=32: sampled targets, self and far (FP64) vs the oracle."""
     s = W.large_suspension(seed=5)
-    so, fo = run(E, s, kinds=31, far_prec=0)
+    so, fo = run(E, s, kinds=31, far_prec=0, bench_config=True)
     rng = np.random.default_rng(6)
     td, tn = oracle.all_targets(s)
     idx = np.sort(rng.choice(len(td), size=24, replace=False))
