@@ -176,17 +176,11 @@ int gmres(ehd_ctx* ctx, long long n, const Op& A, const double* b, double* x, in
     DevBuf Vb, wb, hb;
     SOLVE_HIP(hipMalloc(&Vb.p, sizeof(double) * (size_t)(m + 1) * n));
     SOLVE_HIP(hipMalloc(&wb.p, sizeof(double) * (size_t)n));
-    SOLVE_HIP(hipMalloc(&hb.p, sizeof(double) * (size_t)(m + 2)));
+    // hd: first-pass projections [0, m], second-pass [m + 1, 2m + 1], |w|^2 at 2m + 2
+    SOLVE_HIP(hipMalloc(&hb.p, sizeof(double) * (size_t)(2 * m + 3)));
     double* V = Vb.p;
     double* w = wb.p;
     double* hd = hb.p;
-    auto dots = [&](int k, const double* vec, double* host) -> int {
-        hipLaunchKernelGGL(k_dots, dim3(k), dim3(kT), 0, st, V, n, vec, n, hd);
-        SOLVE_HIP(hipGetLastError());
-        SOLVE_HIP(hipMemcpyAsync(host, hd, sizeof(double) * k, hipMemcpyDeviceToHost, st));
-        SOLVE_HIP(hipStreamSynchronize(st));
-        return EHD_OK;
-    };
     auto norm = [&](const double* vec, double* out) -> int {
         hipLaunchKernelGGL(k_dots, dim3(1), dim3(kT), 0, st, vec, n, vec, n, hd);
         SOLVE_HIP(hipGetLastError());
@@ -206,7 +200,7 @@ int gmres(ehd_ctx* ctx, long long n, const Op& A, const double* b, double* x, in
         *relres = 0.0;
         return EHD_OK;
     }
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1), h2(m + 1), y(m);
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1), y(m), hh(2 * m + 3);
     for (;;) {
         // true residual r = b - A x, into V_0
         if ((rc = A(x, w))) return rc;
@@ -224,18 +218,19 @@ int gmres(ehd_ctx* ctx, long long n, const Op& A, const double* b, double* x, in
         for (int j = 0; j < m; ++j) {
             if ((rc = A(V + (size_t)j * n, w))) return rc;
             ++*iters;
-            // CGS2: two passes of h = V^T w, w -= V h
-            if ((rc = dots(j + 1, w, h.data()))) return rc;
-            SOLVE_HIP(hipMemcpyAsync(hd, h.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, st));
+            // CGS2: two passes of h = V^T w, w -= V h, the projections kept
+            // on the device; one copy to the host per step
+            double* const hd2 = hd + (m + 1);
+            hipLaunchKernelGGL(k_dots, dim3(j + 1), dim3(kT), 0, st, V, n, w, n, hd);
             hipLaunchKernelGGL(k_subtract, dim3(nblocks(n)), dim3(kT), 0, st, w, V, n, j + 1, hd, n);
+            hipLaunchKernelGGL(k_dots, dim3(j + 1), dim3(kT), 0, st, V, n, w, n, hd2);
+            hipLaunchKernelGGL(k_subtract, dim3(nblocks(n)), dim3(kT), 0, st, w, V, n, j + 1, hd2, n);
+            hipLaunchKernelGGL(k_dots, dim3(1), dim3(kT), 0, st, w, n, w, n, hd + 2 * m + 2);
             SOLVE_HIP(hipGetLastError());
-            if ((rc = dots(j + 1, w, h2.data()))) return rc;
-            SOLVE_HIP(hipMemcpyAsync(hd, h2.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, st));
-            hipLaunchKernelGGL(k_subtract, dim3(nblocks(n)), dim3(kT), 0, st, w, V, n, j + 1, hd, n);
-            SOLVE_HIP(hipGetLastError());
-            double hn;
-            if ((rc = norm(w, &hn))) return rc;
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i] + h2[i];
+            SOLVE_HIP(hipMemcpyAsync(hh.data(), hd, sizeof(double) * (size_t)(2 * m + 3), hipMemcpyDeviceToHost, st));
+            SOLVE_HIP(hipStreamSynchronize(st));
+            const double hn = std::sqrt(hh[2 * m + 2]);
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[m + 1 + i];
             H[(size_t)(j + 1) * m + j] = hn;
             // previous Givens rotations, then a new one zeroing H[j+1][j]
             for (int i = 0; i < j; ++i) {
