@@ -1432,46 +1432,59 @@ __device__ __forceinline__ void near_pair_sum(const double* p, const double* n0,
 }
 
 // Check-point sums: block (pair, chunk) walks chunk `chunk` of kNearSplit
-// ranges of drop j's check grid in LDS tiles of 256 records; wave k sums at
-// the check point y + s_k nu (k < m).  out[pair][chunk][k][9] (1/(4 pi)
-// applied); the chunks are added in order by k_near_apply.
-__global__ __launch_bounds__(64 * kNearMaxM) void k_near_check(const NearPair* __restrict__ pairs, int m, double sc,
-                                                               const double* __restrict__ frec, long long Nf,
-                                                               const long long* __restrict__ foff,
-                                                               const int* __restrict__ fidx,
-                                                               const double* __restrict__ tnrm, long long T,
-                                                               double* __restrict__ out)
+// ranges of drop j's check grid; each thread takes every kThreads-th record
+// straight from memory (coalesced) and adds its kernels at four check points
+// y + s_k nu at a time, so that one read of a record serves four points.
+// out[pair][chunk][k][9] (1/(4 pi) applied); the chunks are added in order
+// by k_near_apply.
+__global__ __launch_bounds__(kThreads) void k_near_check(const NearPair* __restrict__ pairs, int m, double sc,
+                                                         const double* __restrict__ frec, long long Nf,
+                                                         const long long* __restrict__ foff,
+                                                         const int* __restrict__ fidx,
+                                                         const double* __restrict__ tnrm, long long T,
+                                                         double* __restrict__ out)
 {
-    constexpr int NR = 13;                               // record rows used: x n (skip w) wf wu wsig
-    __shared__ double tile[NR][kTile];
-    const int pi = blockIdx.x, k = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    constexpr int G = 4;                                  // check points per pass over the records
+    __shared__ double red[kThreads / 64][G * 9];
+    const int pi = blockIdx.x, lane = threadIdx.x & 63;
     const NearPair P = pairs[pi];
-    double pt[3], n0[3];
-    for (int c = 0; c < 3; ++c) {
-        n0[c] = tnrm[c * T + P.t];
-        pt[c] = P.y[c] + sc * (1.0 + 0.5 * k) * P.nu[c];
-    }
+    double n0[3];
+    for (int c = 0; c < 3; ++c) n0[c] = tnrm[c * T + P.t];
     const int fd = fidx[P.j];
     const long long len = foff[fd + 1] - foff[fd];
     const long long c0 = foff[fd] + len * blockIdx.y / kNearSplit, c1 = foff[fd] + len * (blockIdx.y + 1) / kNearSplit;
-    double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (long long base = c0; base < c1; base += kTile) {
-        for (int i = threadIdx.x; i < NR * kTile; i += blockDim.x) {
-            const int r = i / kTile, q = i % kTile;
-            const long long s = base + q;
-            const int row = r < 6 ? r : r + 1;
-            // past the chunk: no density, far away
-            tile[r][q] = s < c1 ? frec[row * Nf + s] : (r < 3 ? 1e6 : 0.0);
+    for (int k0 = 0; k0 < m; k0 += G) {
+        double pt[G][3], a[G][9];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            for (int c = 0; c < 3; ++c) pt[g][c] = P.y[c] + sc * (1.0 + 0.5 * (k0 + g)) * P.nu[c];
+            for (int c = 0; c < 9; ++c) a[g][c] = 0.0;
         }
+        // record rows: x 0-2, n 3-5, (w 6), w f 7-9, w u 10-12, w sigma 13
+        for (long long s = c0 + threadIdx.x; s < c1; s += kThreads) {
+            const double sx = frec[s], sy = frec[Nf + s], sz = frec[2 * Nf + s];
+            const double nx = frec[3 * Nf + s], ny = frec[4 * Nf + s], nz = frec[5 * Nf + s];
+            const double f0 = frec[7 * Nf + s], f1 = frec[8 * Nf + s], f2 = frec[9 * Nf + s];
+            const double u0 = frec[10 * Nf + s], u1 = frec[11 * Nf + s], u2 = frec[12 * Nf + s];
+            const double sg = frec[13 * Nf + s];
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                near_pair_sum(pt[g], n0, sx, sy, sz, nx, ny, nz, f0, f1, f2, u0, u1, u2, sg, a[g]);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            for (int c = 0; c < 9; ++c) {
+                const double v = wave_sum(a[g][c]);
+                if (lane == 0) red[threadIdx.x >> 6][g * 9 + c] = v;
+            }
         __syncthreads();
-        for (int q = lane; q < kTile; q += 64)
-            near_pair_sum(pt, n0, tile[0][q], tile[1][q], tile[2][q], tile[3][q], tile[4][q], tile[5][q], tile[6][q],
-                          tile[7][q], tile[8][q], tile[9][q], tile[10][q], tile[11][q], tile[12][q], a);
-        __syncthreads();
-    }
-    for (int c = 0; c < 9; ++c) {
-        const double v = wave_sum(a[c]);
-        if (lane == 0) out[(((long long)pi * kNearSplit + blockIdx.y) * (m + 1) + k) * 9 + c] = v * kInv4Pi;
+        if (threadIdx.x < G * 9 && k0 + threadIdx.x / 9 < m) {
+            double v = 0.0;
+            for (int w = 0; w < kThreads / 64; ++w) v += red[w][threadIdx.x];
+            const int k = k0 + threadIdx.x / 9, c = threadIdx.x % 9;
+            out[(((long long)pi * kNearSplit + blockIdx.y) * (m + 1) + k) * 9 + c] = v * kInv4Pi;
+        }
+        __syncthreads();   // red is rewritten by the next pass
     }
 }
 
@@ -1510,14 +1523,25 @@ __global__ __launch_bounds__(kThreads) void k_near_plain(const NearPair* __restr
     }
 }
 
-// Lagrange interpolation and the correction of the output rows, one thread
-// per pair (pairs sharing a target add atomically).
-__global__ void k_near_apply(const NearPair* __restrict__ pairs, int npairs, int m, double sc,
-                             const double* __restrict__ lim, const double* __restrict__ chk, RowMap rows,
-                             long long T, double* __restrict__ out)
+// Lagrange interpolation and the correction of the output rows, one block
+// per pair: thread (k, c) adds the chunks of check point k (k = m: the plain
+// value at the target) in order, then thread r combines row r's values in
+// order of k (pairs sharing a target add atomically).
+__global__ __launch_bounds__(128) void k_near_apply(const NearPair* __restrict__ pairs, int m, double sc,
+                                                    const double* __restrict__ lim, const double* __restrict__ chk,
+                                                    RowMap rows, long long T, double* __restrict__ out)
 {
-    const int pi = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pi >= npairs) return;
+    __shared__ double sk[(kNearMaxM + 1) * 9];
+    const int pi = blockIdx.x;
+    const double* c0 = chk + (long long)pi * kNearSplit * (m + 1) * 9;
+    for (int i = threadIdx.x; i < (m + 1) * 9; i += blockDim.x) {
+        const int k = i / 9, c = i % 9;
+        double v = 0.0;
+        for (int h = 0; h < kNearSplit; ++h) v += c0[(h * (m + 1) + k) * 9 + c];
+        sk[i] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x >= rows.n) return;
     const NearPair P = pairs[pi];
     double nodes[kNearMaxM + 1];
     nodes[0] = 0.0;
@@ -1529,17 +1553,10 @@ __global__ void k_near_apply(const NearPair* __restrict__ pairs, int npairs, int
             if (i != k) l *= (P.st - nodes[i]) / (nodes[k] - nodes[i]);
         w[k] = l;
     }
-    const double* c0 = chk + (long long)pi * kNearSplit * (m + 1) * 9;
-    for (int r = 0; r < rows.n; ++r) {
-        const int c = rows.comp[r];
-        double v = w[0] * lim[9 * (long long)pi + c];
-        for (int k = 0; k <= m; ++k) {
-            double sk = 0.0;                                     // chunks in order
-            for (int h = 0; h < kNearSplit; ++h) sk += c0[(h * (m + 1) + k) * 9 + c];
-            v += k < m ? w[k + 1] * sk : -sk;
-        }
-        atomicAdd(out + (long long)r * T + P.t, v);
-    }
+    const int r = threadIdx.x, c = rows.comp[r];
+    double v = w[0] * lim[9 * (long long)pi + c];
+    for (int k = 0; k <= m; ++k) v += k < m ? w[k + 1] * sk[k * 9 + c] : -sk[k * 9 + c];
+    atomicAdd(out + (long long)r * T + P.t, v);
 }
 
 }  // namespace
@@ -2249,12 +2266,12 @@ static int near_enqueue(ehd_ctx* ctx, const double* fcoef_d, const double* ucoef
     const double* uc = ucoef_d ? ucoef_d : fcoef_d;
     hipLaunchKernelGGL(k_near_limit, dim3(N.npairs), dim3(kThreads), 0, ctx->ls, N.d_pairs, ctx->d_info, N.d_legv,
                        N.d_selfc, uc ? uc : N.d_selfc, sigcoef_d ? sigcoef_d : N.d_selfc, ctx->d_tn, ctx->T, N.d_lim);
-    hipLaunchKernelGGL(k_near_check, dim3(N.npairs, kNearSplit), dim3(64 * N.m), 0, ctx->ls, N.d_pairs, N.m, N.sc,
+    hipLaunchKernelGGL(k_near_check, dim3(N.npairs, kNearSplit), dim3(kThreads), 0, ctx->ls, N.d_pairs, N.m, N.sc,
                        N.d_frec, nf, N.d_foff, N.d_fidx, ctx->d_tn, ctx->T, N.d_chk);
     hipLaunchKernelGGL(k_near_plain, dim3(N.npairs), dim3(kThreads), 0, ctx->ls, N.d_pairs, N.m, ctx->d_src64,
                        ctx->Spad, ctx->d_info, ctx->d_tx, ctx->d_tn, ctx->T, N.d_chk);
-    hipLaunchKernelGGL(k_near_apply, dim3((N.npairs + 127) / 128), dim3(128), 0, ctx->ls, N.d_pairs, N.npairs, N.m,
-                       N.sc, N.d_lim, N.d_chk, rows, ctx->T, out);
+    hipLaunchKernelGGL(k_near_apply, dim3(N.npairs), dim3(128), 0, ctx->ls, N.d_pairs, N.m, N.sc, N.d_lim, N.d_chk,
+                       rows, ctx->T, out);
     EHD_HIP(ctx, hipGetLastError());
     return EHD_OK;
 }
