@@ -47,10 +47,10 @@ def self_flops_per_drop(p: int, q: int, grid_mode: int) -> float:
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs
 # recorded in profiles/hbm_traffic_batched_64_mixed_p.md (counters scaled by a
 # 1 GiB copy), valid only for the kernel source they were taken with.
-TRAFFIC_SOURCE_SHA256 = "9b5502ca200799ba281bfbd31221cf311bcc4d6052285616a7110679c4830b08"
+TRAFFIC_SOURCE_SHA256 = "887b1e57ab7d9434bccd1a7fee6f1ff2714cd657475887ecba0e57c4b3863b22"
 TRAFFIC_WORKLOAD = "batched_64_mixed_p"
-TRAFFIC_BYTES = {"k_self<48>": 6.381e+08, "k_self<32>": 1.201e+08, "k_self<24>": 2.54e+07,
-                 "k_self<16>": 7.373e+06, "k_far32": 7.981e+08}
+TRAFFIC_BYTES = {"k_self<48>": 6.394e+08, "k_self<32>": 1.201e+08, "k_self<24>": 2.54e+07,
+                 "k_self<16>": 7.373e+06, "k_far32": 7.989e+08}
 
 
 def measured_traffic(kernel: str, workload: str):
