@@ -155,3 +155,34 @@ def test_near_correction_in_graph_mode(E):
         scratch = torch.tanh(scratch @ scratch.T * 1e-3)          # unrelated eager work between replays
         torch.cuda.synchronize()
     ctx.close()
+
+
+def test_near_correction_in_overlap_mode(E):
+    """With the far field beside the self-interaction (the benchmark's
+    default), the corrected outputs equal the serial ones bit for bit, in
+    both far-field precisions, eagerly and in graph replays."""
+    import torch
+    p, qc = 8, 80
+    s = two_spheres(p, 0.02)
+    dev = torch.device("cuda", 0)
+    ctx = E.Context(0)
+    ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+    ctx.set_near(0.12, 3 * math.pi / (qc + 1), 6, qc)
+    assert ctx.near_pairs() > 0
+    f, u, sg = (torch.from_numpy(a).to(dev) for a in (s.fcoef, s.ucoef, s.sigcoef))
+    T = ctx.ntargets
+    for prec in (E.FAR_FP64, E.FAR_FP32C):
+        ref = torch.empty(9, T, dtype=torch.float64, device=dev)
+        ctx.layer_potentials(f, u, sg, E.ALL_KINDS, prec, ref)
+        ctx.sync()
+        ctx.set_overlap(True)
+        for graph in (False, True):
+            ctx.set_graph(graph)
+            for _ in range(2):
+                out = torch.full_like(ref, 7.0)
+                ctx.layer_potentials(f, u, sg, E.ALL_KINDS, prec, out)
+                ctx.sync()
+                assert torch.equal(out, ref), (prec, graph)
+        ctx.set_graph(False)
+        ctx.set_overlap(False)
+    ctx.close()
