@@ -753,7 +753,9 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     };
 
     const int m_first = wv <= p ? wv : p + 1;
-    constexpr int PF = 6;                                 // Legendre fragments per prefetch batch
+    // Legendre fragments per prefetch batch (measured best per class:
+    // 5 for p <= 48, 3 for p <= 32, 2 below; 6 for all cost p <= 32 6%)
+    constexpr int PF = PMAX == 48 ? 5 : PMAX == 32 ? 3 : 2;
     constexpr int NBATCH = (SC::KW + PF - 1) / PF;
     for (int b = 0; b < nblk; ++b) {
         // 3a. Legendre sums on MFMA: per degree column of this wave, a chain
