@@ -534,6 +534,8 @@ struct SelfClass {
     // row 0 of the longitude sums may be taken apart (pays at q = 2p for
     // p = 16 and 32: one tile less; elsewhere the tile count is unchanged)
     static constexpr bool ROW0 = PMAX == 16 || PMAX == 32;
+    // rotation loop unroll (measured: 2 for p <= 24, 4 above)
+    static constexpr int RU = PMAX <= 24 ? 2 : 4;
 };
 
 // Legendre k-steps per wave of the degree class of p (table stride per wave).
@@ -630,7 +632,7 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
 #pragma unroll
             for (int f = 0; f < NF; ++f) { are[f] = 0.0; aim[f] = 0.0; }
             const double2* zn = cr + column_start(p, 0) + n;   // z_n0 of field 0; z_nm at + column_start(p, m) - m
-#pragma unroll 4
+#pragma unroll SC::RU
             for (int m = 0; m <= n; ++m) {
                 const double a = An[m * (n + 1)], b = Bn[m * (n + 1)];
                 const int zo = column_start(p, m) - m;
