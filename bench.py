@@ -47,10 +47,10 @@ def self_flops_per_drop(p: int, q: int, grid_mode: int) -> float:
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs
 # recorded in profiles/hbm_traffic_batched_64_mixed_p.md (counters scaled by a
 # 1 GiB copy), valid only for the kernel source they were taken with.
-TRAFFIC_SOURCE_SHA256 = "02092e9359d2c54dc77d1d3c41a2317fefec01bd8012c693723b49c913e6aec4"
+TRAFFIC_SOURCE_SHA256 = "4647d00ccf0c4d100f64afeb9ea8e37e22121ddc95bb82654628be165c9caef3"
 TRAFFIC_WORKLOAD = "batched_64_mixed_p"
-TRAFFIC_BYTES = {"k_self<48>": 6.517e+08, "k_self<32>": 1.201e+08, "k_self<24>": 2.54e+07,
-                 "k_self<16>": 7.373e+06, "k_far32": 7.953e+08}
+TRAFFIC_BYTES = {"k_self<48>": 6.527e+08, "k_self<32>": 1.201e+08, "k_self<24>": 2.54e+07,
+                 "k_self<16>": 7.373e+06, "k_far32": 7.964e+08}
 
 
 def measured_traffic(kernel: str, workload: str):

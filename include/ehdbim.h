@@ -242,10 +242,10 @@ int ehd_set_graph(ehd_ctx* ctx, int enable);
  * blocks leave no room beside them) as one looping block per compute unit
  * over a first share of its items, beside the smaller classes, and the rest
  * is an ordinary launch after them.  The share is the expected time of the
- * smaller classes over that of the far field (0.37 on 64 drops of mixed
- * degree, 0.26 on 256 drops of p = 32) for the FP32 far field, and 0 for
+ * smaller classes over that of the far field (0.34 on 64 drops of mixed
+ * degree, 0.24 on 256 drops of p = 32) for the FP32 far field, and 0 for
  * the FP64 one, which slows the self-interaction as much as it gains.
- * Measured: 64 drops 138.5 -> 133.4 ms, 256 drops of p = 32 1023 -> 1000 ms,
+ * Measured: 64 drops 136.2 -> 131.9 ms, 256 drops of p = 32 about 4% less,
  * two p = 32 drops 2.10 -> 1.90 ms (FP64 far field 2.25 -> 1.96 ms).  A
  * single drop (no far interactions) keeps the serial order.  Stage times
  * then read: self = until the last class ends (shared with the forked

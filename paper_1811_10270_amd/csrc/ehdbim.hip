@@ -2775,9 +2775,9 @@ static double self_work(const DropInfo& D)
 // Overlap mode: share of the far field's work items forked beside the
 // degree classes below p = 48, the expected time of those classes over that
 // of the far field (each its algorithmic work over the fraction of peak it
-// reaches alone: 0.22, 0.41, 0.56 for the classes, 0.96 for the FP32 far
+// reaches alone: 0.24, 0.44, 0.60 for the classes, 0.96 for the FP32 far
 // field at 53 flops per interaction), at most one half.  On 64 mixed drops
-// this gives 0.37 and on 256 drops of p = 32 0.26, inside the measured
+// this gives 0.34 and on 256 drops of p = 32 0.24, inside the measured
 // optima (0.3-0.5 and 0.2-0.35).  The FP64 far field needs the same FP64
 // units as the self-interaction, which slows down by about as much as the
 // far work done beside it (256 drops lost 3-8% at shares 0.13 and 0.35):
@@ -2785,7 +2785,7 @@ static double self_work(const DropInfo& D)
 static double overlap_share(const ehd_ctx* ctx, int far_prec)
 {
     if (far_prec == EHD_FAR_FP64) return 0.0;
-    static const double eff[3] = {0.22, 0.41, 0.56};
+    static const double eff[3] = {0.24, 0.44, 0.60};
     double small = 0.0, far = 0.0;
     long long S = 0;
     for (int d = 0; d < ctx->nd; ++d) S += ctx->info[d].ns;
