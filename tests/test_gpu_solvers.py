@@ -84,6 +84,32 @@ def test_velocity_two_drops_matches_oracle(E, lam):
     assert rr <= 1e-13 and err < TOL
 
 
+@pytest.mark.parametrize("R", [0.5, 3.0])
+def test_En_spheroid_closed_form(E, R):
+    """ehd_solve_En on a prolate spheroid (1, 1, 1.2) at p = 12 against the
+    ellipsoid's closed form E_n = R E n_z / (1 + (R - 1) L_z), node values
+    and normals from the library."""
+    import torch
+    from test_oracle_galerkin import depolarisation
+    p, axes = 12, (1.0, 1.0, 1.2)
+    s = make_susp(p, sphere_x(p, axes=axes))
+    ctx, dev = _ctx(E, s)
+    en = torch.zeros(ctx.num_coefs(), dtype=torch.float64, device=dev)
+    it, rr = ctx.solve_En(R, 1.0, 0.0, en, tol=1e-13)
+    T = ctx.ntargets
+    vals = torch.zeros(1, T, dtype=torch.float64, device=dev)
+    x = torch.zeros(3, T, dtype=torch.float64, device=dev)
+    n = torch.zeros_like(x)
+    ctx.synthesize(1, en, vals)
+    ctx.target_geometry(x, n)
+    ctx.sync()
+    exact = R * n[2].cpu().numpy() / (1.0 + (R - 1.0) * depolarisation(axes, 2))
+    err = np.abs(vals[0].cpu().numpy() - exact).max()
+    ctx.close()
+    say("spheroid E_n R", R, "iters", it, "relres", rr, "err vs closed form", err)
+    assert rr <= 1e-13 and err < 1e-9, err
+
+
 def test_sphere_closed_forms(E):
     p = 8
     s = make_susp(p, sphere_x(p), q_self=16)

@@ -6,7 +6,9 @@ and the systems have closed-form solutions:
   * quadrupole field: E_n = 10 R E_q P_2(cos theta) / (2R+3)
     (K*[Y_nm] = Y_nm / (2(2n+1)) on the unit sphere);
   * constant force density e: u = (2/3) e for every viscosity ratio
-    (S[e] = (4/3) e and D[e] = e on the unit sphere).
+    (S[e] = (4/3) e and D[e] = e on the unit sphere);
+  * an ellipsoid in a uniform field along a principal axis has a uniform
+    interior field E / (1 + (R - 1) L) with L its depolarisation factor.
 With R = 1 or lambda = 1 the systems reduce to projections, which pins the
 right-hand sides on a deformed drop.
 """
@@ -28,6 +30,59 @@ def test_En_unit_sphere_uniform_field(R):
     expect = np.zeros_like(en)
     expect[2 * tri(1, 0)] = 3 * R / (R + 2) * math.sqrt(4 * math.pi / 3)
     assert np.abs(en - expect).max() < 1e-12
+
+
+def depolarisation(axes, i):
+    """Depolarisation factor of the ellipsoid with semi-axes `axes` along
+    axis i: (abc/2) times the integral over s > 0 of
+    1 / ((s + a_i^2) sqrt((s + a^2)(s + b^2)(s + c^2))); 1/3 on a sphere."""
+    from scipy.integrate import quad
+    a, b, c = axes
+
+    def f(t):
+        return 1.0 / ((t + axes[i] ** 2) * math.sqrt((t + a * a) * (t + b * b) * (t + c * c)))
+    return 0.5 * a * b * c * quad(f, 0.0, np.inf, epsabs=1e-14, epsrel=1e-13, limit=200)[0]
+
+
+def ellipsoid_En_error(axes, p, R, L=None):
+    """Largest node error of the Galerkin E_n on the ellipsoid `axes` in a
+    uniform field along z against the textbook solution: the interior field
+    is uniform, E / (1 + (R - 1) L_z), so E_n = R E n_z / (1 + (R - 1) L_z)."""
+    import oracle
+    s = make_susp(p, sphere_x(p, axes=axes))
+    en = G.solve_En_dense(s, R, 1.0, 0.0)
+    td, tn = oracle.all_targets(s)
+    _, n = oracle.targets(s, td, tn)
+    Lz = depolarisation(axes, 2) if L is None else L
+    return np.abs(G._node_values(s, en, 1)[:, 0] - R * n[2] / (1.0 + (R - 1.0) * Lz)).max()
+
+
+def test_depolarisation_factors():
+    assert abs(depolarisation((1.0, 1.0, 1.0), 2) - 1.0 / 3.0) < 1e-13
+    axes = (1.15, 0.9, 1.0)
+    assert abs(sum(depolarisation(axes, i) for i in range(3)) - 1.0) < 1e-12
+    # prolate spheroid along z, eccentricity e: L_z = (1 - e^2)/e^3 (atanh e - e)
+    e = math.sqrt(1.0 - 1.0 / 1.2 ** 2)
+    assert abs(depolarisation((1.0, 1.0, 1.2), 2) - (1 - e * e) / e ** 3 * (math.atanh(e) - e)) < 1e-12
+
+
+@pytest.mark.parametrize("R", [0.5, 3.0])
+def test_En_prolate_spheroid_uniform_field(R):
+    """A spheroid (the surface is exactly degree 1; only n_z is not band-
+    limited): the Galerkin E_n at the nodes within 1e-7 of the ellipsoid's
+    closed form at p = 8, while the sphere's factor 1/3 misses by 1e-2."""
+    axes = (1.0, 1.0, 1.2)
+    err = ellipsoid_En_error(axes, 8, R)
+    assert err < 1e-7, err
+    assert ellipsoid_En_error(axes, 8, R, L=1.0 / 3.0) > 1e-2
+
+
+def test_En_triaxial_ellipsoid_converges():
+    """A triaxial ellipsoid: the error against the closed form falls about
+    tenfold per two degrees (spectral convergence to the exact solution)."""
+    axes = (1.15, 0.9, 1.0)
+    e6, e8 = ellipsoid_En_error(axes, 6, 3.0), ellipsoid_En_error(axes, 8, 3.0)
+    assert e8 < 1e-4 and e8 < e6 / 5, (e6, e8)
 
 
 @pytest.mark.parametrize("R", [0.25, 4.0])
