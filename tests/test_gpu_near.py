@@ -186,3 +186,40 @@ def test_near_correction_in_overlap_mode(E):
         ctx.set_graph(False)
         ctx.set_overlap(False)
     ctx.close()
+
+
+def test_time_step_with_the_correction(E):
+    """Algorithm 1 with the correction on: every shape of the step (the
+    half-step one included) gets its own pairs, the corrected step differs
+    from the plain one by a small amount, and overlap mode gives the same
+    bits as the serial order."""
+    import torch
+    p, qc = 8, 80
+    s = two_spheres(p, 0.02)
+    dev = torch.device("cuda", 0)
+    sp = E.Context.step_params(2.0, 0.5, 2.0, 0.3, 1.0, 0.0, tol=1e-12)
+    gamma = torch.from_numpy(np.ascontiguousarray(s.sigcoef)).to(dev)
+    res = {}
+    for near in (False, True):
+        for ov in (False, True):
+            ctx = E.Context(0)
+            ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+            if near:
+                ctx.set_near(0.12, 3 * math.pi / (qc + 1), 6, qc)
+                assert ctx.near_pairs() > 0
+            ctx.set_overlap(ov)
+            nc = ctx.num_coefs()
+            xn = torch.empty(3 * nc, dtype=torch.float64, device=dev)
+            gn = torch.empty(nc, dtype=torch.float64, device=dev)
+            rep = ctx.evolve_step(sp, 0.1, 0.01, gamma, xn, gn)
+            if near:
+                assert ctx.near_pairs() > 0          # the context is back at x^n, pairs rebuilt
+            res[(near, ov)] = (xn.cpu().numpy(), gn.cpu().numpy(), rep["iters"])
+            ctx.close()
+    for near in (False, True):
+        assert np.array_equal(res[(near, False)][0], res[(near, True)][0]), near
+        assert np.array_equal(res[(near, False)][1], res[(near, True)][1]), near
+    d = np.abs(res[(True, False)][0] - res[(False, False)][0]).max()
+    print("corrected vs plain step: max coefficient difference", d, "iterations", res[(True, False)][2],
+          res[(False, False)][2], flush=True)
+    assert 0.0 < d < 1e-2, d
