@@ -187,7 +187,10 @@ int ehd_area_weights(ehd_ctx* ctx, double* w_d);
  * The regular rule on a degree-q grid of a drop of radius a is accurate
  * beyond about 3 pi a / q: delta should exceed that distance for q_far
  * (targets farther out keep the plain sums) and s_check for q_check.
- * Synchronous. */
+ * Synchronous.  The closest-point search runs on up to 16 host threads of
+ * the calling process (joined before the call returns); the check-grid
+ * tables are kept while q_check and the grid mode stay the same.  A host
+ * allocation failure returns EHD_E_NOMEM. */
 int ehd_set_near(ehd_ctx* ctx, double delta, double s_check, int m, int q_check);
 
 /* Number of (target, drop) pairs the nearly singular correction treats. */
