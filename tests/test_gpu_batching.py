@@ -123,6 +123,32 @@ def test_overlap_split_over_tile_shapes(E):
         ctx.close()
 
 
+def test_overlap_with_separate_u(E):
+    """A separate double-layer density takes a second self-interaction pass
+    per degree class; in overlap mode both passes of the p <= 48 class run
+    before the fork and both passes of the others after it.  Same bits as
+    the serial order, every kind set that needs u, both precisions."""
+    import torch
+    s = W.with_separate_u(W.subset(W.batched_suspension(seed=3), list(range(12))))
+    ctx, f, sg, dev = _setup(E, s)
+    u = torch.from_numpy(s.ucoef).to(dev)
+    T = ctx.ntargets
+    for prec in (E.FAR_FP32C, E.FAR_FP64):
+        for kinds in (E.ALL_KINDS, E.STOKES_DL, E.STOKES_DL | E.LAP_SL, E.STOKES_SL | E.STOKES_DL):
+            outs = []
+            for ov in (False, True):
+                ctx.set_overlap(ov)
+                rows = len(E.rows_for_kinds(kinds))
+                so = torch.zeros(rows, T, dtype=torch.float64, device=dev)
+                fo = torch.zeros_like(so)
+                ctx.layer_potentials(f, u, sg, kinds, prec, so, fo)
+                ctx.sync()
+                outs.append((so, fo))
+            assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1]), (prec, kinds)
+    ctx.set_overlap(False)
+    ctx.close()
+
+
 def test_overlap_fp64_single_kinds_and_solve(E):
     """Regression: the FP64 far field running beside the self-interaction
     slows some of its waves; the self kernel must not depend on its waves'
