@@ -139,6 +139,31 @@ def test_self_tiny_degrees(E, p):
     assert np.all(err < FP64_TOL), err
 
 
+@pytest.mark.parametrize("q", [48, 127])
+def test_self_max_degree_and_grid_extremes(E, q):
+    """p = 48, the largest degree, on the smallest (q = p: two row tiles of
+    longitude sums) and the largest (q = 127, 256 longitudes: eight row
+    tiles, one per wave) rotated grids; sampled targets, both poles'
+    neighbourhoods included.  One degree more is refused."""
+    import torch
+    s = W.single_drop(48, seed=3)
+    s.q_self[:] = q
+    s.q_far[:] = q
+    if q == 127:
+        ctx = E.Context(0)
+        with pytest.raises(E.EhdError) as ei:
+            ctx.set_drops(s.p, s.q_self + 1, s.q_far, s.grid_mode,
+                          torch.from_numpy(s.xcoef).to(torch.device("cuda", 0)))
+        assert ei.value.code == E.EHD_E_SHAPE
+        ctx.close()
+    so, _ = run(E, s)
+    idx, td, tn = sample(s, 6, seed=4)
+    ref = oracle.self_(s, td, tn)
+    err = normwise(so.numpy()[:, idx], ref)
+    say(f"self p48 q{q} err", err)
+    assert np.all(err < FP64_TOL), err
+
+
 def test_far_fp64_two_drops(E):
     """Two p=12 spheres at gap 0.1, far grid q = 3p (near-contact pair)."""
     s = W.two_drops(12, seed=2, q_far_mult=3)
