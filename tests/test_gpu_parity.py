@@ -164,6 +164,21 @@ def test_self_max_degree_and_grid_extremes(E, q):
     assert np.all(err < FP64_TOL), err
 
 
+def test_far_largest_grid(E):
+    """The far field on the largest source grid (q_far = 160, 51,842 nodes
+    per drop) at every target of two p = 8 drops: FP64 against the oracle,
+    the compensated FP32 sums within their bound."""
+    s = W.two_drops(8, seed=6, gap=0.2)
+    s.q_far[:] = 160
+    _, fo = run(E, s, far_prec=0)
+    _, fo32 = run(E, s, far_prec=1)
+    td, tn = oracle.all_targets(s)
+    ref = oracle.far(s, td, tn)
+    err, err32 = normwise(fo.numpy(), ref), normwise(fo32.numpy(), ref)
+    say("far q_far 160 err fp64", err, "fp32", err32)
+    assert np.all(err < FP64_TOL) and np.all(err32 < FP32_FAR_BOUND), (err, err32)
+
+
 def test_far_fp64_two_drops(E):
     """Two p=12 spheres at gap 0.1, far grid q = 3p (near-contact pair)."""
     s = W.two_drops(12, seed=2, q_far_mult=3)
