@@ -235,6 +235,9 @@ def test_argument_errors(E):
     ctx = E.Context(0)
     dev = torch.device("cuda", 0)
     x = torch.zeros(3 * 20, dtype=torch.float64, device=dev)
+    with pytest.raises(E.EhdError) as ei:        # no drops
+        ctx.set_drops([], [], [], 0, x)
+    assert ei.value.code == E.EHD_E_ARG
     with pytest.raises(E.EhdError) as ei:
         ctx.set_drops([0], [4], [4], 0, x)
     assert ei.value.code == E.EHD_E_SHAPE
