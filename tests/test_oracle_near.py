@@ -1,6 +1,7 @@
 """Accuracy of the upsampled direct sums near another drop (the regular rule
 of eq. reg_quadrature on a degree-q grid; Sec. 2.1 replaces it by line
-interpolation for nearly singular targets, which is not built).  Against the
+interpolation for nearly singular targets, pinned below and built on the
+device as an option of the library).  Against the
 exterior unit-sphere closed forms S_L[Y_nm](x0) = Y_nm(d)/((2n+1)|x0|^{n+1})
 and L[Y_nm](x0) = n Y_nm(d)/((2n+1)|x0|^{n+1}), d = x0/|x0|: with q = 3p
 (p = 32) the sums hold 1e-7 at a gap of 0.1 (the two-drop workload) and fail
@@ -37,7 +38,8 @@ def test_upsampled_sums_near_a_drop(nm):
 
 # ---------------------------------------------------------------------------
 # Line interpolation for nearly singular targets (the oracle's reading of
-# Sec. 2.1's interpolation approach; not built on the device)
+# Sec. 2.1's interpolation approach; the device path is checked against it
+# in the GPU tests of the nearly singular correction)
 # ---------------------------------------------------------------------------
 def test_line_interpolation_laplace_near_the_unit_sphere():
     """S_L, L and K* (target normal radial) of sigma = Re Y_31 at 0.05, 0.01

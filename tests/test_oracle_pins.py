@@ -323,6 +323,9 @@ def test_exterior_sphere_laplace(ora, nm):
         y = real_y(n, m, th, ph)
         np.testing.assert_allclose(out[6], y / ((2 * n + 1) * d ** (n + 1)), atol=1e-13)
         np.testing.assert_allclose(out[7], n * y / ((2 * n + 1) * d ** (n + 1)), atol=1e-13)
+        # adjoint double layer with the radial target normal n0 = x0/|x0|:
+        # K*[s](x0) = -n0 . grad_x0 S_L[s](x0) = -d/dd of the exterior S_L
+        np.testing.assert_allclose(out[8], (n + 1) * y / ((2 * n + 1) * d ** (n + 2)), atol=1e-13)
 
 
 def test_exterior_sphere_stokeslet_translating_sphere(ora):
