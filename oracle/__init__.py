@@ -52,6 +52,13 @@ def _load():
                                    _dp, _dp, _dp]
     lib.ora_geom_point.restype = None
     lib.ora_num_threads.restype = C.c_int
+    lib.ora_set_threads.argtypes = [C.c_int]
+    lib.ora_set_threads.restype = None
+    lib.ora_far_sources.argtypes = [C.c_int, _ip, _ip, C.c_int, _dp, _dp, _dp, _dp]
+    lib.ora_far_sources.restype = C.c_void_p
+    lib.ora_far_eval.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _ip, _dp]
+    lib.ora_far_free.argtypes = [C.c_void_p]
+    lib.ora_far_free.restype = None
     _lib = lib
     return lib
 
@@ -78,6 +85,11 @@ def nlon_of(P: int, grid_mode: int) -> int:
 
 def num_threads() -> int:
     return int(_load().ora_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of later oracle calls."""
+    _load().ora_set_threads(int(n))
 
 
 def gauss_legendre(n: int):
@@ -182,6 +194,36 @@ def far_points(s, x0: np.ndarray, n0: np.ndarray, exclude=None):
                     _d(u) if u is not None else None, _d(sg), nt, _d(x0), _d(n0), _i(ex),
                     _d(out))
     return out.reshape(9, nt)
+
+
+class FarSources:
+    """The regular-rule source records of every drop, built once
+    (``ora_far_sources``) and summed at points by ``eval``; ``far_points``
+    does both in one call."""
+
+    def __init__(self, s):
+        p, x, f, u, sg = _susp_args(s)
+        qf = _i32(s.q_far)
+        self._keep = (p, qf, x, f, u, sg)
+        self.h = _load().ora_far_sources(s.ndrops, _i(p), _i(qf), s.grid_mode, _d(x), _d(f),
+                                         _d(u) if u is not None else None, _d(sg))
+
+    def eval(self, x0, n0, exclude=None):
+        x0 = _f64(x0)
+        n0 = _f64(n0)
+        nt = x0.shape[1]
+        ex = _i32(exclude if exclude is not None else -np.ones(nt))
+        out = np.zeros(9 * nt)
+        _load().ora_far_eval(self.h, nt, _d(x0), _d(n0), _i(ex), _d(out))
+        return out.reshape(9, nt)
+
+    def close(self):
+        if self.h:
+            _load().ora_far_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 def far(s, tgt_drop, tgt_node):

@@ -332,10 +332,18 @@ int ora_targets(int nd, const int* p, int grid_mode, const double* xcoef, int nt
 /* Far field: for each target point (x0, n0) sum the regular quadrature
  * (eq. reg_quadrature) over the degree-qfar grid of every drop except
  * tgt_exclude[i] (-1: none).  Sources are built once by point evaluation.   */
-int ora_far(int nd, const int* p, const int* qfar, int grid_mode, const double* xcoef,
-            const double* fcoef, const double* ucoef, const double* sigcoef, int nt,
-            const double* x0 /*[3][nt]*/, const double* n0 /*[3][nt]*/,
-            const int* tgt_exclude, double* out /*[9][nt]*/)
+/* Source records of the regular rule (eq. reg_quadrature) on every drop's
+ * degree-qfar grid: x(3) n(3) f(3) u(3) sigma(1) weight(1) per node.  The
+ * returned block holds the node offsets of the drops (nd + 1 longs) and then
+ * the records; ora_far_free releases it.                                    */
+typedef struct {
+    int nd;
+    long* soff;
+    double* src;
+} far_src_t;
+
+void* ora_far_sources(int nd, const int* p, const int* qfar, int grid_mode, const double* xcoef,
+                      const double* fcoef, const double* ucoef, const double* sigcoef)
 {
     drops_t D;
     drops_init(&D, nd, p);
@@ -381,6 +389,33 @@ int ora_far(int nd, const int* p, const int* qfar, int grid_mode, const double* 
         (void)nc;
         free(tt); free(ww);
     }
+    free(D.off);
+    far_src_t* h = (far_src_t*)malloc(sizeof(far_src_t));
+    h->nd = nd;
+    h->soff = soff;
+    h->src = src;
+    return h;
+}
+
+void ora_far_free(void* handle)
+{
+    far_src_t* h = (far_src_t*)handle;
+    if (!h) return;
+    free(h->src);
+    free(h->soff);
+    free(h);
+}
+
+/* Far-field sums at arbitrary points x0 with target normals n0: every
+ * drop's records except the drop tgt_exclude[it] (NULL: none), natural
+ * order, times 1/(4 pi).                                                    */
+int ora_far_eval(const void* handle, int nt, const double* x0 /*[3][nt]*/, const double* n0 /*[3][nt]*/,
+                 const int* tgt_exclude, double* out /*[9][nt]*/)
+{
+    const far_src_t* h = (const far_src_t*)handle;
+    const int nd = h->nd;
+    const long* soff = h->soff;
+    const double* src = h->src;
 #pragma omp parallel for schedule(dynamic, 8)
     for (int it = 0; it < nt; ++it) {
         double acc[NCOMP] = {0};
@@ -396,10 +431,18 @@ int ora_far(int nd, const int* p, const int* qfar, int grid_mode, const double* 
         }
         for (int c = 0; c < NCOMP; ++c) out[c * nt + it] = acc[c] / (4.0 * ORA_PI);
     }
-    free(src);
-    free(soff);
-    free(D.off);
     return 0;
+}
+
+int ora_far(int nd, const int* p, const int* qfar, int grid_mode, const double* xcoef,
+            const double* fcoef, const double* ucoef, const double* sigcoef, int nt,
+            const double* x0 /*[3][nt]*/, const double* n0 /*[3][nt]*/,
+            const int* tgt_exclude, double* out /*[9][nt]*/)
+{
+    void* h = ora_far_sources(nd, p, qfar, grid_mode, xcoef, fcoef, ucoef, sigcoef);
+    int rc = ora_far_eval(h, nt, x0, n0, tgt_exclude, out);
+    ora_far_free(h);
+    return rc;
 }
 
 /* Sum_{n=0}^{N} P_n(t) by the Legendre recurrence. */
@@ -651,5 +694,15 @@ int ora_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Number of OpenMP threads of later calls (n >= 1). */
+void ora_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }
