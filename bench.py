@@ -2,11 +2,16 @@
 
 One step = one call of ehd_layer_potentials over the whole workload: the
 singular self-interaction of every target (FP64, rotated-pole rule) plus the
-far-field direct sums over every other drop (FP32 with compensated
-accumulation by default), the four potentials of the metric (S, D, S_L, L:
-8 values per target).  Inputs are resident in HBM before the timed region.
+far-field direct sums over every other drop, the four potentials of the
+metric (S, D, S_L, L: 8 values per target).  Inputs are resident in HBM
+before the timed region.
 
-Prints one JSON line.
+Default: the 256-drop suspension at p = 32 (q = 2p), timed twice: all in
+FP64 (the paper's precision; this is `value`) and with the FP32 compensated
+far field (the `fp32_far` object, with its measured error per output against
+the FP64 path at every target and against the FP64 oracle on 16 drops).
+
+Prints one JSON line (progress goes to stderr).
 """
 from __future__ import annotations
 
@@ -30,12 +35,16 @@ FAR_FLOPS_PER_INTERACTION = 53   # S 18, D 19, S_L 2, L 3, xh/r^2/powers 11 (K* 
 SELF_KERNEL_FLOPS_PER_NODE = 75
 
 
+def _nlon(P: int, grid_mode: int) -> int:
+    return 2 * P + 2 if grid_mode == 0 else 2 * P
+
+
 def self_flops_per_drop(p: int, q: int, grid_mode: int) -> float:
-    """Algorithmic FP64 work of the singular self-interaction of one drop:
-    rotation of 7 fields, Legendre sums (7 fields + 3 theta derivatives),
-    longitude sums of 13 grid quantities, kernel evaluation per rotated node."""
-    nlon_p = 2 * p + 2 if grid_mode == 0 else 2 * p
-    nlon_q = 2 * q + 2 if grid_mode == 0 else 2 * q
+    """Dense algorithmic FP64 work of the singular self-interaction of one
+    drop (the scope table's count): complex rotation of 7 fields, Legendre
+    sums (7 fields + 3 theta derivatives), longitude sums of 13 grid
+    quantities as a dense DFT, kernel evaluation per rotated node."""
+    nlon_p, nlon_q = _nlon(p, grid_mode), _nlon(q, grid_mode)
     T = (p + 1) * nlon_p
     rot = 4 * 7 * T * sum((n + 1) * (2 * n + 1) for n in range(p + 1))
     leg = 4 * (q + 1) * ((p + 1) * (p + 2) // 2) * 10 * T
@@ -44,22 +53,45 @@ def self_flops_per_drop(p: int, q: int, grid_mode: int) -> float:
     return float(rot + leg + dft + ker)
 
 
-# HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs
-# recorded in profiles/hbm_traffic_batched_64_mixed_p.md (counters scaled by a
-# 1 GiB copy), valid only for the kernel source they were taken with.
-TRAFFIC_SOURCE_SHA256 = "4647d00ccf0c4d100f64afeb9ea8e37e22121ddc95bb82654628be165c9caef3"
-TRAFFIC_WORKLOAD = "batched_64_mixed_p"
-TRAFFIC_BYTES = {"k_self<48>": 6.527e+08, "k_self<32>": 1.201e+08, "k_self<24>": 2.54e+07,
-                 "k_self<16>": 7.373e+06, "k_far32": 7.964e+08}
+def self_exec_flops_per_drop(p: int, q: int, grid_mode: int) -> float:
+    """FP64 work of the singular self-interaction as the kernel's route does
+    it (no padding counted):
+      rotation, real form: per field and degree n, the phase e^{i m phi_t}
+        (6 flops per m) and two real (n+1) x (n+1) products (4 (n+1)^2);
+      Legendre sums: as in the dense count;
+      longitude sums, quarter-period split: per latitude and quantity,
+        rows l = 0..floor(H/2) (H = nlon_q / 2) of 2p+1 terms, 2 flops each,
+        plus 12 flops per row to form the four images;
+      kernel: 75 flops per rotated node."""
+    nlon_p, nlon_q = _nlon(p, grid_mode), _nlon(q, grid_mode)
+    T = (p + 1) * nlon_p
+    rot = 7 * T * sum(4 * (n + 1) ** 2 + 6 * (n + 1) for n in range(p + 1))
+    leg = 4 * (q + 1) * ((p + 1) * (p + 2) // 2) * 10 * T
+    rows = nlon_q // 4 + 1
+    dft = 13 * (q + 1) * T * rows * (2 * (2 * p + 1) + 12)
+    ker = SELF_KERNEL_FLOPS_PER_NODE * T * (q + 1) * nlon_q
+    return float(rot + leg + dft + ker)
 
 
-def measured_traffic(kernel: str, workload: str):
+# HBM bytes per launch of each (workload, far precision, kernel) from the
+# rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs summarised in profiles/
+# (counters scaled by what they read for a plain device copy of known size),
+# valid only for the kernel source they were taken with.
+TRAFFIC_SOURCE_SHA256 = ""
+TRAFFIC_BYTES = {}   # (workload, "fp64" | "fp32c", kernel name) -> bytes per launch
+
+
+def kernel_source_sha256() -> str:
     import hashlib
     path = os.path.join(ROOT, "paper_1811_10270_amd", "csrc", "ehdbim.hip")
     with open(path, "rb") as fh:
-        if hashlib.sha256(fh.read()).hexdigest() != TRAFFIC_SOURCE_SHA256 or workload != TRAFFIC_WORKLOAD:
-            return None
-    return TRAFFIC_BYTES.get(kernel.split(" ")[0])
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str, far_prec: int):
+    if kernel_source_sha256() != TRAFFIC_SOURCE_SHA256:
+        return None
+    return TRAFFIC_BYTES.get((workload, "fp64" if far_prec == 0 else "fp32c", kernel.split(" ")[0]))
 
 
 def far_interactions(s) -> float:
@@ -78,27 +110,314 @@ def far_interactions(s) -> float:
     return tot
 
 
-def cpu_baseline(s, nsample: int, seed: int = 0):
-    """The oracle timed on a bounded random sample of the workload's targets:
-    self (singular rule) + far (all other drops) for each sampled target."""
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(s, nsample: int, seed: int = 0, one_core_targets: int = 4):
+    """The oracle as it stands, timed on the host on a bounded sample of the
+    workload: the singular self-interaction of `nsample` random targets, the
+    far-field source records of every drop (built once per evaluation) and
+    the far sums at the same targets.  The rate is that of a whole
+    evaluation, extrapolated per target from the sample: T / (T (t_self +
+    t_far) + t_sources).  The one-core rate takes one_core_targets of the
+    same targets (evenly spaced in the sample) and the source records of two
+    drops, scaled to all drops by their nodes x coefficients."""
     import numpy as np
     import oracle
     td, tn = oracle.all_targets(s)
+    T = len(td)
     rng = np.random.default_rng(seed)
-    idx = np.sort(rng.choice(len(td), size=min(nsample, len(td)), replace=False))
+    idx = np.sort(rng.choice(T, size=min(nsample, T), replace=False))
+    nthr = oracle.num_threads()
+
+    from paper_1811_10270_amd.workloads import subset as W_subset
     t0 = time.perf_counter()
-    oracle.self_(s, td[idx], tn[idx])
-    t1 = time.perf_counter()
-    oracle.far(s, td[idx], tn[idx])
-    t2 = time.perf_counter()
+    far_all = oracle.FarSources(s)
+    t_src = time.perf_counter() - t0
+
+    def timed(threads, sel, src_drops=None):
+        """Per-target self and far times on `threads` threads, and the time
+        to build the source records of src_drops (None: skipped)."""
+        oracle.set_threads(threads)
+        try:
+            t0 = time.perf_counter()
+            oracle.self_(s, td[sel], tn[sel])
+            t1 = time.perf_counter()
+            t_sub = 0.0
+            if src_drops is not None:
+                fs = oracle.FarSources(W_subset(s, src_drops))
+                t_sub = time.perf_counter() - t1
+                fs.close()
+            x0, n0 = oracle.targets(s, td[sel], tn[sel])
+            t3 = time.perf_counter()
+            far_all.eval(x0, n0, td[sel])
+            t4 = time.perf_counter()
+        finally:
+            oracle.set_threads(nthr)
+        return (t1 - t0) / len(sel), t_sub, (t4 - t3) / len(sel)
+
+    t_self, _, t_far = timed(nthr, idx)
+    rate = T / (T * (t_self + t_far) + t_src)
+    # one core: a few targets, and the source records of two drops scaled
+    # to all drops by nodes x coefficients
+    sub = [0, s.ndrops - 1] if s.ndrops > 1 else [0]
+    cost = [(int(s.q_far[d]) + 1) * (2 * int(s.q_far[d]) + 2) * (int(s.p[d]) + 1) * (int(s.p[d]) + 2)
+            for d in range(s.ndrops)]
+    pick = idx[np.linspace(0, len(idx) - 1, min(one_core_targets, len(idx))).astype(int)]
+    s1_self, s1_src_sub, s1_far = timed(1, pick, sub)
+    s1_src = s1_src_sub * sum(cost) / sum(cost[d] for d in sub)
+    rate1 = T / (T * (s1_self + s1_far) + s1_src)
+    far_all.close()
     return {
-        "value": len(idx) / (t2 - t0),
+        "value": rate,
         "unit": "target-evals/s",
-        "cores": oracle.num_threads(),
+        "cores": nthr,
         "kind": "oracle",
-        "sample": f"{len(idx)} random targets of {len(td)} (seed {seed}), self + far over all "
-                  f"{s.ndrops} drops, FP64; self {t1 - t0:.1f} s, far {t2 - t1:.1f} s",
+        "cpu_model": cpu_model(),
+        "host_cpus": os.cpu_count(),
+        "sample": f"{len(idx)} random targets of {T} (seed {seed}) of the same workload, self + far over all "
+                  f"{s.ndrops} drops, FP64, {nthr} threads: self {t_self * 1e3:.1f} ms and far "
+                  f"{t_far * 1e3:.2f} ms per target, far source records {t_src:.1f} s per evaluation; "
+                  f"rate extrapolated to all {T} targets",
+        "one_core": {"value": rate1, "unit": "target-evals/s", "cores": 1,
+                     "sample": f"{len(pick)} of the same targets (evenly spaced): self "
+                               f"{s1_self:.2f} s and far {s1_far * 1e3:.1f} ms per target; source records of "
+                               f"drops {sub} ({s1_src_sub:.2f} s) scaled to all drops ({s1_src:.1f} s)"},
     }
+
+
+COMP_NAMES = ("S_x", "S_y", "S_z", "D_x", "D_y", "D_z", "S_L", "L", "K*")
+GOLDEN_FAR = {"large_256_p32": os.path.join(ROOT, "tests", "golden", "large_256_p32_far16.npz")}
+
+
+def input_checksums(s):
+    """Sums and weighted sums of the input coefficients (as stored with the
+    oracle's values, to detect a change of the generator's draws)."""
+    import numpy as np
+    out = []
+    for a in (s.xcoef, s.fcoef, s.sigcoef):
+        w = np.arange(1, a.size + 1, dtype=np.float64) / a.size
+        out += [float(a.sum()), float((a * w).sum())]
+    return np.array(out)
+
+
+def normwise(got, ref):
+    """Per output row: max |got - ref| / max |ref| over the targets."""
+    import numpy as np
+    den = np.abs(ref).max(axis=-1)
+    den = np.where(den == 0, 1.0, den)
+    return np.abs(got - ref).max(axis=-1) / den
+
+
+def time_evaluation(args, torch, E, ctx, s, far_prec, kinds, f, sig, out):
+    """Warm-up, then args.steps timed evaluations with HIP-event stage and
+    class times; per-kernel work and rates; the far part of one more
+    (untimed, split) evaluation for the error report."""
+    K = args.steps
+    tile = {"targets_per_thread": ctx.far_config()[0], "source_chunks": ctx.far_config()[1], "autotuned": False}
+    if not args.no_autotune:
+        from paper_1811_10270_amd import autotune
+        tpt, nch, timings, cached = autotune.autotune_far(ctx, s.p, s.q_far, s.grid_mode, far_prec, kinds=kinds)
+        tile = {"targets_per_thread": tpt, "source_chunks": nch, "autotuned": True, "from_cache": cached,
+                "timings_ms": timings}
+    log("far tile", tile)
+    ctx.set_graph(bool(args.graph))
+    for _ in range(args.warmup):
+        ctx.layer_potentials(f, None, sig, kinds, far_prec, out)
+    ctx.sync()
+    torch.cuda.synchronize()
+    ctx.set_timing(K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        ctx.layer_potentials(f, None, sig, kinds, far_prec, out)
+    ctx.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"far_prec {far_prec}: {K} steps in {dt:.3f} s")
+    timing_pass = "timed region"
+    if args.graph:
+        # a replayed graph records no per-kernel events: time the same
+        # launch sequence once more without the graph
+        ctx.set_graph(False)
+        ctx.set_timing(K)
+        for _ in range(K):
+            ctx.layer_potentials(f, None, sig, kinds, far_prec, out)
+        ctx.sync()
+        timing_pass = "separate pass of the same launches without the graph"
+    stages = [ctx.stage_times(i) for i in range(K)]
+    avg = [sum(st[k] for st in stages) / K for k in range(4)]
+    cls_times = [ctx.self_class_times(i) for i in range(K)]
+
+    T = ctx.ntargets
+    overlap = bool(args.overlap and s.ndrops > 1)
+    tpt_, nch_ = ctx.far_config()
+    items = -(-T // (256 * tpt_)) * nch_
+    whole = items <= 2 * torch.cuda.get_device_properties(0).multi_processor_count
+    kernels = []
+    for c, pmax in enumerate(E.DEGREE_CLASSES):
+        ms = sum(ct[c] for ct in cls_times) / K
+        lo = E.DEGREE_CLASSES[c - 1] if c else 0
+        sel = [d for d in range(s.ndrops) if lo < int(s.p[d]) <= pmax]
+        fl = sum(self_exec_flops_per_drop(int(s.p[d]), int(s.q_self[d]), s.grid_mode) for d in sel)
+        dense = sum(self_flops_per_drop(int(s.p[d]), int(s.q_self[d]), s.grid_mode) for d in sel)
+        if ms > 0 and fl > 0:
+            # shared: a forked far-field share runs beside the class
+            shared = overlap and (whole or (pmax < 48 and far_prec == E.FAR_FP32C))
+            kernels.append({"kernel": f"k_self<{pmax}> (singular self-interaction, p <= {pmax}, FP64)",
+                            "bound": "alu", "algorithmic_flops": fl, "dense_flops": dense, "avg_ms": ms,
+                            "achieved": fl / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS, "shared": shared})
+    far_flops = far_interactions(s) * FAR_FLOPS_PER_INTERACTION
+    # the far field runs alone in the timed region unless a share of it is
+    # forked beside the self-interaction (the FP32 far field in overlap mode)
+    far_alone = (not overlap) or (far_prec == E.FAR_FP64 and not whole)
+    name = "k_far32" if far_prec == E.FAR_FP32C else "k_far64"
+    far_ms = avg[2] if far_alone else None
+    far_src = timing_pass
+    if far_ms is None and far_flops > 0:
+        # time the far kernel alone with HIP events (ehd_time_far), same tile
+        far_ms = ctx.time_far(far_prec, tpt_, nch_, reps=3, kinds=kinds)
+        far_src = "launched alone (ehd_time_far, 3 launches)"
+    if far_flops > 0:
+        peak = PEAK_FP32_VECTOR_TFLOPS if far_prec == E.FAR_FP32C else PEAK_FP64_TFLOPS
+        ach = far_flops / (far_ms * 1e-3) / 1e12
+        k = {"kernel": name + " (far-field direct sums)", "bound": "alu", "algorithmic_flops": far_flops,
+             "avg_ms": far_ms, "achieved": ach, "peak": peak, "shared": not far_alone, "timed": far_src}
+        if far_prec == E.FAR_FP32C:
+            k["peak_unpacked"] = PEAK_FP32_UNPACKED_TFLOPS
+            k["frac_unpacked"] = ach / PEAK_FP32_UNPACKED_TFLOPS
+        kernels.append(k)
+    for k in kernels:
+        k["unit"] = "TFLOP/s"
+        k["frac"] = k["achieved"] / k["peak"]
+        k["traffic"] = measured_traffic(k["kernel"], args.workload, far_prec) if not k["shared"] else None
+    roof = None
+    alone = [k for k in kernels if not k["shared"]]
+    if alone:
+        dom = max(alone, key=lambda k: k["avg_ms"])
+        roof = {key: dom[key] for key in ("kernel", "bound", "achieved", "peak", "unit", "frac", "traffic",
+                                          "algorithmic_flops", "avg_ms")}
+        for key in ("dense_flops", "peak_unpacked", "frac_unpacked"):
+            if key in dom:
+                roof[key] = dom[key]
+        roof["per_unit"] = ("53 flops per target-source interaction" if dom["kernel"].startswith("k_far")
+                            else "executed self-interaction flops per drop (rotation, Legendre, quarter-period "
+                                 "longitude sums, 75 per rotated node)")
+    ctx.set_timing(0)
+    # far part of one split evaluation (errors)
+    so = torch.empty_like(out)
+    fo = torch.empty_like(out)
+    ctx.layer_potentials(f, None, sig, kinds, far_prec, so, fo)
+    ctx.sync()
+    return {"dt": dt, "ms_per_step": dt / K * 1e3, "value": T * K / dt, "stage_ms": dict(zip(E.STAGES, avg)),
+            "kernels": kernels, "roofline": roof, "far_tile": tile, "far": fo.cpu().numpy(),
+            "kernel_times": timing_pass}
+
+
+def bench_eval(args, torch, E, W, dev):
+    """The layer-potential evaluation (the metric)."""
+    import numpy as np
+    s = W.WORKLOADS[args.workload](args.grid_mode)
+    kinds = E.METRIC_KINDS
+    rows = E.rows_for_kinds(kinds)
+    precs = {"both": [E.FAR_FP64, E.FAR_FP32C], "fp64": [E.FAR_FP64], "fp32c": [E.FAR_FP32C]}[args.far_prec]
+    log(f"workload {args.workload}: {s.ndrops} drops, far precisions {precs}")
+    ctx = E.Context(0)
+    ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+    if args.overlap:
+        ctx.set_overlap(True)
+    T = ctx.ntargets
+    f = torch.from_numpy(s.fcoef).to(dev)
+    sig = torch.from_numpy(s.sigcoef).to(dev)
+    out = torch.empty(len(rows), T, dtype=torch.float64, device=dev)
+    runs = {prec: time_evaluation(args, torch, E, ctx, s, prec, kinds, f, sig, out) for prec in precs}
+    ctx.close()
+
+    golden = None
+    path = GOLDEN_FAR.get(args.workload)
+    if path and os.path.exists(path) and s.grid_mode == 0:
+        g = np.load(path)
+        if np.allclose(g["checksums"], input_checksums(s), rtol=1e-14, atol=0):
+            golden = g
+
+    def errors(run):
+        e = {}
+        if E.FAR_FP64 in runs and run is not runs[E.FAR_FP64]:
+            err = normwise(run["far"], runs[E.FAR_FP64]["far"])
+            e["vs_fp64_path_all_targets"] = {COMP_NAMES[c]: float(v) for c, v in zip(rows, err)}
+        if golden is not None:
+            idx = golden["far_idx"]
+            err = normwise(run["far"][:, idx], golden["far"][list(rows)])
+            e["vs_oracle_16_drops"] = {COMP_NAMES[c]: float(v) for c, v in zip(rows, err)}
+            e["oracle_targets"] = int(len(idx))
+        return e
+
+    def q_desc(qs):
+        ratio = {int(q) / int(p) for p, q in zip(s.p, qs)}
+        return f"{ratio.pop():g}p" if len(ratio) == 1 else sorted({(int(p), int(q)) for p, q in zip(s.p, qs)})
+
+    main_prec = precs[0]
+    r = runs[main_prec]
+    res = {
+        "metric": "layer-potential target evals/sec (singular+far) FP64 vs FP32 at stated rel err",
+        "value": r["value"],
+        "unit": "target-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_prec == E.FAR_FP64 else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "overlap": bool(args.overlap and s.ndrops > 1), "ndrops": s.ndrops,
+                   "p": sorted(set(int(x) for x in s.p)), "targets": T,
+                   "q_self": q_desc(s.q_self), "q_far": q_desc(s.q_far),
+                   "grid": "paper (2p+2 longitudes)" if s.grid_mode == 0 else "2p longitudes",
+                   "kinds": "S,D,S_L,L", "far_prec": "fp64" if main_prec == E.FAR_FP64 else "fp32c",
+                   "far_interactions": far_interactions(s), "far_tile": r["far_tile"],
+                   "graph": bool(args.graph)},
+        "stage_ms": r["stage_ms"],
+        "roofline": r["roofline"],
+        "kernels": r["kernels"],
+        "kernel_times": r["kernel_times"],
+    }
+    if golden is not None or len(runs) > 1:
+        res["far_error"] = errors(r)
+    if len(runs) > 1:
+        r32 = runs[E.FAR_FP32C]
+        res["fp32_far"] = {"value": r32["value"], "unit": "target-evals/s", "ms_per_step": r32["ms_per_step"],
+                           "dtype": "f64+f32", "far_tile": r32["far_tile"], "stage_ms": r32["stage_ms"],
+                           "roofline": r32["roofline"], "kernels": r32["kernels"],
+                           "far_error": errors(r32),
+                           "error_bound_stated": 1e-6}
+    if args.copy_probe > 0:
+        n = args.copy_probe * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        res["copy_probe_bytes"] = {"read": n * 8, "written": n * 8}
+        del a, b
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        res["cpu_baseline"] = cpu_baseline(s, args.cpu_sample)
+    print(json.dumps(res), flush=True)
+    return 0
 
 
 def bench_solve(args, torch, E, W, dev):
@@ -364,15 +683,20 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=None,
                     choices=["batched_64_mixed_p", "large_256_p32", "two_drops_p32",
-                             "single_drop_p16"])
-    ap.add_argument("--far-prec", default=None, choices=["fp32c", "fp64"],
-                    help="far-field precision (default: fp32c for the evaluation, fp64 for --solve)")
+                             "single_drop_p16"],
+                    help="default: large_256_p32 for the evaluation, two_drops_p32 for --solve, --step, "
+                         "--evolve")
+    ap.add_argument("--far-prec", default=None, choices=["fp32c", "fp64", "both"],
+                    help="far-field precision (default: both for the evaluation, FP64 giving `value` and "
+                         "the FP32 compensated far field the `fp32_far` object; fp64 for --solve)")
     ap.add_argument("--grid-mode", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=320)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--graph", action="store_true",
-                    help="replay the evaluation as a recorded HIP graph (stage times then hold "
-                         "the whole evaluation in the first stage)")
+    ap.add_argument("--graph", action="store_true", default=None,
+                    help="replay the evaluation as a recorded HIP graph (default for "
+                         "batched_64_mixed_p; per-kernel times then come from a second pass of the "
+                         "same launches without the graph)")
+    ap.add_argument("--no-graph", dest="graph", action="store_false")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--solve", choices=["en", "velocity"], default=None,
                     help="time the Galerkin GMRES solve (E_n with R = 0.5, E_u = 1; velocity with "
@@ -416,10 +740,15 @@ def main(argv=None):
         print(json.dumps({"error": "no GPU available"}))
         return 1
     dev = torch.device("cuda", 0)
+    other = args.solve or args.step or args.evolve
     if args.workload is None:
-        args.workload = "two_drops_p32" if (args.solve or args.step or args.evolve) else "batched_64_mixed_p"
+        args.workload = "two_drops_p32" if other else "large_256_p32"
     if args.far_prec is None:
-        args.far_prec = "fp64" if (args.solve or args.step or args.evolve) else "fp32c"
+        args.far_prec = "fp64" if other else "both"
+    if args.far_prec == "both" and other:
+        args.far_prec = "fp64"
+    if args.graph is None:
+        args.graph = args.workload == "batched_64_mixed_p"
     args.overlap = not args.serial
     if args.learned:
         return bench_learned(args, torch, E, W, dev)
@@ -431,134 +760,7 @@ def main(argv=None):
         return bench_step(args, torch, E, W, dev)
     if args.solve:
         return bench_solve(args, torch, E, W, dev)
-    s = W.WORKLOADS[args.workload](args.grid_mode)
-    far_prec = E.FAR_FP32C if args.far_prec == "fp32c" else E.FAR_FP64
-    kinds = E.METRIC_KINDS
-
-    ctx = E.Context(0)
-    ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
-    if args.overlap:
-        ctx.set_overlap(True)
-    T = ctx.ntargets
-    tile = {"targets_per_thread": ctx.far_config()[0], "source_chunks": ctx.far_config()[1],
-            "autotuned": False}
-    if not args.no_autotune:
-        from paper_1811_10270_amd import autotune
-        tpt, nch, timings, cached = autotune.autotune_far(ctx, s.p, s.q_far, s.grid_mode, far_prec)
-        tile = {"targets_per_thread": tpt, "source_chunks": nch, "autotuned": True,
-                "from_cache": cached}
-    if args.graph:
-        ctx.set_graph(True)
-    f = torch.from_numpy(s.fcoef).to(dev)
-    sig = torch.from_numpy(s.sigcoef).to(dev)
-    out = torch.empty(len(E.rows_for_kinds(kinds)), T, dtype=torch.float64, device=dev)
-    for _ in range(args.warmup):
-        ctx.layer_potentials(f, None, sig, kinds, far_prec, out)
-    ctx.sync()
-    torch.cuda.synchronize()
-
-    K = args.steps
-    ctx.set_timing(K)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(K):
-        ctx.layer_potentials(f, None, sig, kinds, far_prec, out)
-    ctx.sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dt = t1 - t0
-    stages = [ctx.stage_times(i) for i in range(K)]
-    avg = [sum(st[k] for st in stages) / K for k in range(4)]
-    cls_times = [ctx.self_class_times(i) for i in range(K)] if not args.graph else None
-
-    # per-kernel rooflines; the dominant kernel's goes to "roofline" (none if
-    # every kernel shares the device).  Kernels that run beside the forked
-    # far field are "shared": their times are wall times, not theirs alone;
-    # the far field itself then has no time of its own.
-    self_flops = sum(self_flops_per_drop(int(s.p[d]), int(s.q_self[d]), s.grid_mode)
-                     for d in range(s.ndrops))
-    far_flops = far_interactions(s) * FAR_FLOPS_PER_INTERACTION
-    kernels = []
-    # the library's overlap regimes: a far field of at most two work items
-    # per CU forks whole (every class shares the device), a larger one after
-    # the p <= 48 class
-    tpt_, nch_ = ctx.far_config()
-    items = -(-T // (256 * tpt_)) * nch_
-    whole = items <= 2 * torch.cuda.get_device_properties(0).multi_processor_count
-    if s.ndrops < 2:
-        args.overlap = False   # the library keeps the serial order for one drop
-    if cls_times is not None:
-        for c, pmax in enumerate(E.DEGREE_CLASSES):
-            ms = sum(ct[c] for ct in cls_times) / K
-            lo = E.DEGREE_CLASSES[c - 1] if c else 0
-            fl = sum(self_flops_per_drop(int(s.p[d]), int(s.q_self[d]), s.grid_mode)
-                     for d in range(s.ndrops) if lo < int(s.p[d]) <= pmax)
-            if ms > 0 and fl > 0:
-                kernels.append({"kernel": f"k_self<{pmax}> (singular self-interaction, p <= {pmax}, FP64)",
-                                "bound": "alu", "algorithmic_flops": fl, "avg_ms": ms,
-                                "achieved": fl / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS,
-                                "shared": bool(args.overlap and (whole or pmax < 48))})
-        far_peak = PEAK_FP32_UNPACKED_TFLOPS if far_prec == E.FAR_FP32C else PEAK_FP64_TFLOPS
-        far_ms = None if args.overlap else avg[2]
-        kernels.append({"kernel": ("k_far32" if far_prec == E.FAR_FP32C else "k_far64")
-                        + " (far-field direct sums)", "bound": "alu", "algorithmic_flops": far_flops,
-                        "avg_ms": far_ms, "achieved": far_flops / (far_ms * 1e-3) / 1e12 if far_ms else None,
-                        "peak": far_peak, "shared": bool(args.overlap)})
-        for k in kernels:
-            k["unit"] = "TFLOP/s"
-            k["frac"] = k["achieved"] / k["peak"] if k["achieved"] is not None else None
-            # per-launch counter bytes; the far field's two overlap launches have none
-            k["traffic"] = None if (k["shared"] and k["avg_ms"] is None) else measured_traffic(k["kernel"], args.workload)
-    roof = None
-    alone = [k for k in kernels if not k["shared"]]
-    if alone:
-        dom = max(alone, key=lambda k: k["avg_ms"])
-        roof = {"kernel": dom["kernel"], "bound": dom["bound"], "achieved": dom["achieved"],
-                "peak": dom["peak"], "unit": "TFLOP/s", "frac": dom["frac"], "traffic": dom["traffic"],
-                "algorithmic_flops": dom["algorithmic_flops"], "avg_ms": dom["avg_ms"]}
-
-    res = {
-        "metric": "layer-potential target evals/sec (singular+far) FP64 self + "
-                  + ("FP32 far" if far_prec == E.FAR_FP32C else "FP64 far"),
-        "value": T * K / dt,
-        "unit": "target-evals/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": dt / K * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64+f32" if far_prec == E.FAR_FP32C else "f64",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "overlap": args.overlap, "ndrops": s.ndrops,
-                   "p": sorted(set(int(x) for x in s.p)), "targets": T,
-                   "q_self": "2p", "q_far": "2p", "grid": "paper (2p+2 longitudes)"
-                   if s.grid_mode == 0 else "2p longitudes",
-                   "kinds": "S,D,S_L,L", "far_prec": args.far_prec,
-                   "far_interactions": far_interactions(s), "far_tile": tile,
-                   "graph": bool(args.graph)},
-        "stage_ms": dict(zip(E.STAGES, avg)),
-        "self_tflops": None if args.overlap else self_flops / (avg[1] * 1e-3) / 1e12,
-        "far_tflops": None if args.overlap else far_flops / (avg[2] * 1e-3) / 1e12,
-        "roofline": roof,
-        "kernels": kernels,
-    }
-    ctx.close()
-    if args.copy_probe > 0:
-        n = args.copy_probe * (1 << 20) // 8
-        a = torch.ones(n, dtype=torch.float64, device=dev)
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        res["copy_probe_bytes"] = {"read": n * 8, "written": n * 8}
-        del a, b
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(s, args.cpu_sample)
-    print(json.dumps(res), flush=True)
-    return 0
-
+    return bench_eval(args, torch, E, W, dev)
 
 if __name__ == "__main__":
     sys.exit(main())

@@ -262,11 +262,13 @@ int ehd_set_overlap(ehd_ctx* ctx, int enable);
 int ehd_set_far_config(ehd_ctx* ctx, int targets_per_thread, int nchunk);
 int ehd_get_far_config(const ehd_ctx* ctx, int* targets_per_thread, int* nchunk);
 
-/* Autotuner support: mean milliseconds of `reps` launches of the far-field
- * kernel of precision far_prec with the given tile shape, on the current
- * source records, timed with HIP events (all kinds).  Overwrites the far
- * field's partial sums (not the caller's outputs).  Synchronous. */
-int ehd_time_far(ehd_ctx* ctx, int far_prec, int targets_per_thread, int nchunk, int reps, double* ms);
+/* Autotuner support: mean milliseconds of `reps` launches (after one
+ * warm-up launch) of the far-field kernel of precision far_prec for the
+ * kinds mask `kinds` (as for ehd_layer_potentials) with the given tile
+ * shape, on the current source records, timed with HIP events.  Overwrites
+ * the far field's partial sums (not the caller's outputs).  Synchronous. */
+int ehd_time_far(ehd_ctx* ctx, int far_prec, unsigned kinds, int targets_per_thread, int nchunk, int reps,
+                 double* ms);
 
 /* Galerkin solvers (Sec. 2, eq. galerkin_En and eq. BIM_galerkin) by
  * restarted GMRES in FP64 on the device.  Each iteration is one

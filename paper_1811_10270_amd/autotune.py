@@ -1,20 +1,28 @@
 """Far-field tile-shape autotuner.
 
 Times every candidate shape (targets per thread x number of source chunks)
-of the far-field kernel on the context's own workload with HIP events
-(ehd_time_far), keeps the fastest in the context, and caches the choice in a
-JSON file keyed by device architecture, workload signature and precision.
+of the far-field kernel on the context's own workload, for the kinds the
+caller evaluates, with HIP events (ehd_time_far: the kernel launched alone;
+the share that overlap mode forks beside the self-interaction uses the same
+shape).  Each shape is timed `reps` times (once when a launch takes longer
+than LONG_MS) and ranked by its median.  The
+fastest is kept in the context and cached in a JSON file keyed by device
+architecture, library build, workload signature, kinds and precision, so a
+rebuilt library never reuses a stale choice.
 """
 from __future__ import annotations
 
 import hashlib
 import json
 import os
+import statistics
 
 import torch
 
 TPT_CANDIDATES = (1, 2)
 CHUNK_CANDIDATES = (1, 4, 16)
+LONG_MS = 100.0
+_LIB_HASH = {}
 
 
 def default_cache_path() -> str:
@@ -22,12 +30,26 @@ def default_cache_path() -> str:
                           os.path.join(os.path.expanduser("~"), ".cache", "ehdbim_tune.json"))
 
 
-def signature(ctx, p, q_far, grid_mode: int, far_prec: int) -> str:
+def library_hash() -> str:
+    """Content hash of the loaded HIP library (the build the timings are for)."""
+    from . import ehdbim
+    path = ehdbim.LIB_PATH
+    if path not in _LIB_HASH:
+        h = hashlib.sha1()
+        with open(path, "rb") as fh:
+            for chunk in iter(lambda: fh.read(1 << 20), b""):
+                h.update(chunk)
+        _LIB_HASH[path] = h.hexdigest()[:16]
+    return _LIB_HASH[path]
+
+
+def signature(ctx, p, q_far, grid_mode: int, far_prec: int, kinds: int) -> str:
     prop = torch.cuda.get_device_properties(ctx.device)
     arch = getattr(prop, "gcnArchName", prop.name)
     h = hashlib.sha1()
     h.update(repr((list(map(int, p)), list(map(int, q_far)), int(grid_mode))).encode())
-    return f"{arch}|{prop.multi_processor_count}|T{ctx.ntargets}|{h.hexdigest()[:16]}|prec{far_prec}"
+    return (f"{arch}|{prop.multi_processor_count}|lib{library_hash()}|T{ctx.ntargets}|{h.hexdigest()[:16]}"
+            f"|prec{far_prec}|kinds{kinds}")
 
 
 def _load(path):
@@ -38,12 +60,12 @@ def _load(path):
         return {}
 
 
-def autotune_far(ctx, p, q_far, grid_mode: int, far_prec: int, reps: int = 1,
+def autotune_far(ctx, p, q_far, grid_mode: int, far_prec: int, kinds: int = 31, reps: int = 3,
                  cache_path: str | None = None, use_cache: bool = True):
-    """Pick and set the fastest far-field tile shape; returns
-    (targets_per_thread, nchunk, {shape: ms}, from_cache)."""
+    """Pick and set the fastest far-field tile shape for `kinds`; returns
+    (targets_per_thread, nchunk, {shape: median ms}, from_cache)."""
     path = cache_path or default_cache_path()
-    key = signature(ctx, p, q_far, grid_mode, far_prec)
+    key = signature(ctx, p, q_far, grid_mode, far_prec, kinds)
     cache = _load(path) if use_cache else {}
     if key in cache:
         tpt, nch = cache[key]["best"]
@@ -53,10 +75,13 @@ def autotune_far(ctx, p, q_far, grid_mode: int, far_prec: int, reps: int = 1,
     for tpt in TPT_CANDIDATES:
         for nch in CHUNK_CANDIDATES:
             try:
-                ms = ctx.time_far(far_prec, tpt, nch, reps)
+                ms = [ctx.time_far(far_prec, tpt, nch, 1, kinds=kinds)]
+                # long launches (hundreds of ms) vary little: one timing
+                while len(ms) < reps and ms[0] < LONG_MS:
+                    ms.append(ctx.time_far(far_prec, tpt, nch, 1, kinds=kinds))
             except RuntimeError:
                 continue      # shape not valid for this workload (e.g. more chunks than tiles)
-            timings[f"{tpt}x{nch}"] = ms
+            timings[f"{tpt}x{nch}"] = statistics.median(ms)
     best = min(timings, key=timings.get)
     tpt, nch = (int(v) for v in best.split("x"))
     ctx.set_far_config(tpt, nch)

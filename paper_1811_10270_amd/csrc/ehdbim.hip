@@ -1533,7 +1533,7 @@ __global__ __launch_bounds__(kThreads) void k_near_plain(const NearPair* __restr
 // order of k (pairs sharing a target add atomically).
 __global__ __launch_bounds__(128) void k_near_apply(const NearPair* __restrict__ pairs, int m, double sc,
                                                     const double* __restrict__ lim, const double* __restrict__ chk,
-                                                    RowMap rows, long long T, double* __restrict__ out)
+                                                    RowMap rows, double* __restrict__ corr)
 {
     __shared__ double sk[(kNearMaxM + 1) * 9];
     const int pi = blockIdx.x;
@@ -1560,7 +1560,22 @@ __global__ __launch_bounds__(128) void k_near_apply(const NearPair* __restrict__
     const int r = threadIdx.x, c = rows.comp[r];
     double v = w[0] * lim[9 * (long long)pi + c];
     for (int k = 0; k <= m; ++k) v += k < m ? w[k + 1] * sk[k * 9 + c] : -sk[k * 9 + c];
-    atomicAdd(out + (long long)r * T + P.t, v);
+    corr[9 * (long long)pi + r] = v;
+}
+
+// Adds each corrected target's pair corrections to its output rows: one
+// thread per (target, row), the target's pairs (consecutive: pairs are kept
+// in target order) summed in their stored order, so the result does not
+// depend on scheduling.
+__global__ void k_near_gather(const int* __restrict__ tstart, const int* __restrict__ tlist, int ntgt,
+                              const double* __restrict__ corr, RowMap rows, long long T, double* __restrict__ out)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)ntgt * rows.n) return;
+    const int u = (int)(i / rows.n), r = (int)(i % rows.n);
+    double v = 0.0;
+    for (int pi = tstart[u]; pi < tstart[u + 1]; ++pi) v += corr[9 * (long long)pi + r];
+    out[(long long)r * T + tlist[u]] += v;
 }
 
 }  // namespace
@@ -1699,6 +1714,10 @@ struct ehd_ctx {
         double* d_fsyn = nullptr;        // [9][nf]
         double* d_selfc = nullptr;       // [9][ncoef_total] projected self values
         double* d_lim = nullptr;         // [npairs][9]
+        double* d_corr = nullptr;        // [npairs][9] each pair's correction of the output rows
+        int ntgt = 0;                    // targets with at least one pair
+        int* d_tlist = nullptr;          // [ntgt] those targets, increasing
+        int* d_tstart = nullptr;         // [ntgt + 1] first pair of each (pairs are in target order)
         double* d_chk = nullptr;         // [npairs][kNearSplit][m+1][9]
         // check-grid tables per degree p, kept across shapes for (tab_qc, tab_gm)
         std::map<int, LegTab> tabs;
@@ -1708,7 +1727,7 @@ struct ehd_ctx {
         {
             for (void* a : allocs) (void)hipFree(a);
             allocs.clear();
-            npairs = nfd = nfrows = 0;
+            npairs = nfd = nfrows = ntgt = 0;
             nf = 0;
         }
         void release_tables()
@@ -2150,6 +2169,15 @@ static int near_build(ehd_ctx* ctx)
     }
     N.npairs = (int)pairs.size();
     if (!N.npairs) return EHD_OK;
+    // the corrected targets and the first of each one's (consecutive) pairs
+    std::vector<int> tlist, tstart;
+    for (int i = 0; i < N.npairs; ++i)
+        if (i == 0 || pairs[i].t != pairs[i - 1].t) {
+            tlist.push_back(pairs[i].t);
+            tstart.push_back(i);
+        }
+    tstart.push_back(N.npairs);
+    N.ntgt = (int)tlist.size();
     // check grids (degree qc) of the drops with pairs
     std::vector<int> fidx(nd, -1);
     for (const NearPair& pr : pairs) fidx[pr.j] = 0;
@@ -2228,11 +2256,13 @@ static int near_build(ehd_ctx* ctx)
     if ((rc = near_upload(ctx, &N.d_pairs, pairs)) || (rc = near_upload(ctx, &N.d_legv, legv)) ||
         (rc = near_upload(ctx, &N.d_fdrops, fd)) || (rc = near_upload(ctx, &N.d_flegs, fl)) ||
         (rc = near_upload(ctx, &N.d_frows, frows)) || (rc = near_upload(ctx, &N.d_node_drop, node_drop)) ||
-        (rc = near_upload(ctx, &N.d_foff, foff)) || (rc = near_upload(ctx, &N.d_fidx, fidx)))
+        (rc = near_upload(ctx, &N.d_foff, foff)) || (rc = near_upload(ctx, &N.d_fidx, fidx)) ||
+        (rc = near_upload(ctx, &N.d_tlist, tlist)) || (rc = near_upload(ctx, &N.d_tstart, tstart)))
         return rc;
     if ((rc = near_zeros(ctx, &N.d_frec, (size_t)kRec64 * N.nf)) || (rc = near_zeros(ctx, &N.d_fsyn, (size_t)9 * N.nf)) ||
         (rc = near_zeros(ctx, &N.d_selfc, (size_t)9 * ctx->ncoef_total)) ||
         (rc = near_zeros(ctx, &N.d_lim, (size_t)9 * N.npairs)) ||
+        (rc = near_zeros(ctx, &N.d_corr, (size_t)9 * N.npairs)) ||
         (rc = near_zeros(ctx, &N.d_chk, (size_t)9 * (N.m + 1) * kNearSplit * N.npairs)))
         return rc;
     // check-grid geometry
@@ -2275,7 +2305,10 @@ static int near_enqueue(ehd_ctx* ctx, const double* fcoef_d, const double* ucoef
     hipLaunchKernelGGL(k_near_plain, dim3(N.npairs), dim3(kThreads), 0, ctx->ls, N.d_pairs, N.m, ctx->d_src64,
                        ctx->Spad, ctx->d_info, ctx->d_tx, ctx->d_tn, ctx->T, N.d_chk);
     hipLaunchKernelGGL(k_near_apply, dim3(N.npairs), dim3(128), 0, ctx->ls, N.d_pairs, N.m, N.sc, N.d_lim, N.d_chk,
-                       rows, ctx->T, out);
+                       rows, N.d_corr);
+    const long long ng = (long long)N.ntgt * rows.n;
+    hipLaunchKernelGGL(k_near_gather, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, ctx->ls, N.d_tstart,
+                       N.d_tlist, N.ntgt, N.d_corr, rows, ctx->T, out);
     EHD_HIP(ctx, hipGetLastError());
     return EHD_OK;
 }
@@ -3029,12 +3062,14 @@ int ehd_get_far_config(const ehd_ctx* ctx, int* targets_per_thread, int* nchunk)
     return ctx->nd ? EHD_OK : EHD_E_STATE;
 }
 
-int ehd_time_far(ehd_ctx* ctx, int far_prec, int targets_per_thread, int nchunk, int reps, double* ms)
+int ehd_time_far(ehd_ctx* ctx, int far_prec, unsigned kinds, int targets_per_thread, int nchunk, int reps,
+                 double* ms)
 {
     if (!ctx) return EHD_E_ARG;
     if (!ctx->nd) EHD_FAIL(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
     if (!ms || reps < 1 || reps > 1000 || (far_prec != EHD_FAR_FP64 && far_prec != EHD_FAR_FP32C))
         EHD_FAIL(ctx, EHD_E_ARG, "invalid arguments");
+    if (kinds == 0 || (kinds & ~(unsigned)EHD_ALL_KINDS)) EHD_FAIL(ctx, EHD_E_ARG, "invalid kinds mask 0x%x", kinds);
     if ((targets_per_thread != 1 && targets_per_thread != 2) || nchunk < 1 || nchunk > kMaxChunks ||
         nchunk > ctx->ntiles)
         EHD_FAIL(ctx, EHD_E_ARG, "invalid tile shape");
@@ -3043,10 +3078,10 @@ int ehd_time_far(ehd_ctx* ctx, int far_prec, int targets_per_thread, int nchunk,
     EHD_HIP(ctx, hipEventCreate(&e0));
     EHD_HIP(ctx, hipEventCreate(&e1));
     ctx->ls = ctx->stream;
-    int rc = launch_far(ctx, far_prec, EHD_ALL_KINDS, targets_per_thread, nchunk);  // warm-up
+    int rc = launch_far(ctx, far_prec, kinds, targets_per_thread, nchunk);  // warm-up
     if (!rc) {
         (void)hipEventRecord(e0, ctx->stream);
-        for (int r = 0; r < reps && !rc; ++r) rc = launch_far(ctx, far_prec, EHD_ALL_KINDS, targets_per_thread, nchunk);
+        for (int r = 0; r < reps && !rc; ++r) rc = launch_far(ctx, far_prec, kinds, targets_per_thread, nchunk);
         (void)hipEventRecord(e1, ctx->stream);
         (void)hipEventSynchronize(e1);
         float t = 0.0f;

@@ -102,7 +102,7 @@ def load(path: str = LIB_PATH):
     lib.ehd_set_graph.argtypes = [vp, C.c_int]
     lib.ehd_set_far_config.argtypes = [vp, C.c_int, C.c_int]
     lib.ehd_get_far_config.argtypes = [vp, ip, ip]
-    lib.ehd_time_far.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, dp]
+    lib.ehd_time_far.argtypes = [vp, C.c_int, C.c_uint, C.c_int, C.c_int, C.c_int, dp]
     lib.ehd_num_coefs.argtypes = [vp, C.POINTER(C.c_longlong)]
     lib.ehd_surface.argtypes = [vp, C.c_int, vp, vp, vp, vp]
     lib.ehd_drop_coefs.argtypes = [vp, vp]
@@ -332,9 +332,10 @@ class Context:
         self._check(self._lib.ehd_get_far_config(self._h, C.byref(a), C.byref(b)))
         return a.value, b.value
 
-    def time_far(self, far_prec: int, targets_per_thread: int, nchunk: int, reps: int = 3) -> float:
+    def time_far(self, far_prec: int, targets_per_thread: int, nchunk: int, reps: int = 3,
+                 kinds: int = ALL_KINDS) -> float:
         ms = C.c_double()
-        self._check(self._lib.ehd_time_far(self._h, far_prec, targets_per_thread, nchunk, reps,
+        self._check(self._lib.ehd_time_far(self._h, far_prec, kinds, targets_per_thread, nchunk, reps,
                                            C.byref(ms)))
         return ms.value
 
@@ -479,7 +480,7 @@ def evaluate(susp, kinds: int = ALL_KINDS, far_prec: int = FAR_FP64, split: bool
     ctx.set_drops(susp.p, susp.q_self, susp.q_far, susp.grid_mode, x)
     if autotune:
         from . import autotune as _tune
-        _tune.autotune_far(ctx, susp.p, susp.q_far, susp.grid_mode, far_prec, use_cache=False)
+        _tune.autotune_far(ctx, susp.p, susp.q_far, susp.grid_mode, far_prec, kinds=kinds, use_cache=False)
     if overlap:
         ctx.set_overlap(True)
     f = torch.from_numpy(susp.fcoef).to(dev)

@@ -56,13 +56,27 @@ def test_far_interactions_of_the_workloads():
     assert bench.FAR_FLOPS_PER_INTERACTION == 18 + 19 + 2 + 3 + 11
 
 
+def test_self_exec_flops_by_hand():
+    # p = 1, q = 2 on the paper's grid: T = 8 targets, rotated grid 3 x 6
+    T, nlq = 8, 6
+    rot = 7 * T * ((4 * 1 + 6 * 1) + (4 * 4 + 6 * 2))      # real-form rotation + phases, n = 0, 1
+    leg = 4 * 3 * 3 * 10 * T
+    dft = 13 * 3 * T * (nlq // 4 + 1) * (2 * 3 + 12)        # quarter-period rows 0..1, 2p+1 = 3 terms
+    ker = bench.SELF_KERNEL_FLOPS_PER_NODE * T * 3 * nlq
+    assert bench.self_exec_flops_per_drop(1, 2, 0) == rot + leg + dft + ker
+    # the executed count is below the dense one: a quarter of the longitude
+    # sums and about half of the rotation
+    for p in (16, 32, 48):
+        r = bench.self_exec_flops_per_drop(p, 2 * p, 0) / bench.self_flops_per_drop(p, 2 * p, 0)
+        assert 0.3 < r < 0.45, (p, r)
+
+
 def test_traffic_lookup_is_tied_to_source_and_workload():
-    assert bench.measured_traffic("k_self<48> (x)", "large_256_p32") is None
-    got = bench.measured_traffic("k_self<48> (x)", bench.TRAFFIC_WORKLOAD)
-    import hashlib
-    with open(os.path.join(ROOT, "paper_1811_10270_amd", "csrc", "ehdbim.hip"), "rb") as fh:
-        same = hashlib.sha256(fh.read()).hexdigest() == bench.TRAFFIC_SOURCE_SHA256
-    assert (got == bench.TRAFFIC_BYTES["k_self<48>"]) if same else got is None
+    assert bench.measured_traffic("k_far64 (x)", "no_such_workload", 0) is None
+    same = bench.kernel_source_sha256() == bench.TRAFFIC_SOURCE_SHA256
+    for (wl, prec, kern), v in bench.TRAFFIC_BYTES.items():
+        got = bench.measured_traffic(kern + " (x)", wl, 0 if prec == "fp64" else 1)
+        assert (got == v) if same else got is None
 
 
 @pytest.mark.gpu
@@ -77,9 +91,11 @@ def test_json_line_fields():
         assert k in b, k
     assert b["n_gpus"] == 1 and b["steps"] == 2 and b["warmup"] == 1 and b["value"] > 0
     assert b["config"]["workload"] == "single_drop_p16" and b["vs_baseline"] is None
+    assert b["dtype"] == "f64" and b["config"]["q_self"] == "2p" and "fp32_far" in b
     roof = b["roofline"]
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in roof, k
     assert roof["unit"] == "TFLOP/s" and abs(roof["frac"] - roof["achieved"] / roof["peak"]) < 1e-12
     cb = b["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0 and "8 random targets" in cb["sample"]
+    assert cb["one_core"]["cores"] == 1 and cb["one_core"]["value"] > 0 and cb["cpu_model"]

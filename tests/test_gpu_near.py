@@ -223,3 +223,72 @@ def test_time_step_with_the_correction(E):
     print("corrected vs plain step: max coefficient difference", d, "iterations", res[(True, False)][2],
           res[(False, False)][2], flush=True)
     assert 0.0 < d < 1e-2, d
+
+
+def three_spheres(p, gap, seed=6):
+    """Three unit spheres at the corners of a triangle in the plane z = 0
+    (surfaces `gap` apart), turned so that a node of the first sphere's grid
+    lies on the bisector between the other two: targets near two drops."""
+    d = 2.0 + gap
+    a1, a2 = math.radians(-10.0), math.radians(50.0)
+    centres = [(0.0, 0.0, 0.0), (d * math.cos(a1), d * math.sin(a1), 0.0), (d * math.cos(a2), d * math.sin(a2), 0.0)]
+    x = np.concatenate([sphere_x(p, centre=c) for c in centres])
+    rng = np.random.default_rng(seed)
+    nc2 = (p + 1) * (p + 2)
+
+    def dens(nf):
+        out = np.zeros(3 * nf * nc2)
+        for blk in range(3 * nf):
+            for n in range(p + 1):
+                for m in range(n + 1):
+                    k = blk * nc2 + 2 * tri(n, m)
+                    out[k] = rng.standard_normal() / (n + 1) ** 2
+                    if m:
+                        out[k + 1] = rng.standard_normal() / (n + 1) ** 2
+        return out
+    f, u, sg = dens(3), dens(3), dens(1)
+    pa = np.array([p, p, p], np.int32)
+    return W.Suspension("near3", pa, 2 * pa, 2 * pa, 0, x, f, sg, u, np.array(centres), np.ones(3))
+
+
+def test_near_correction_deterministic_with_two_pairs_per_target(E):
+    """Targets closer than delta to two other drops get both corrections
+    added in a fixed order: eager serial, overlap mode and graph replays give
+    the same bits, in both far-field precisions, call after call."""
+    import torch
+    p, qc, delta = 8, 80, 0.35
+    s = three_spheres(p, 0.02)
+    dev = torch.device("cuda", 0)
+    ctx = E.Context(0)
+    ctx.set_drops(s.p, s.q_self, s.q_far, s.grid_mode, torch.from_numpy(s.xcoef).to(dev))
+    ctx.set_near(delta, 3 * math.pi / (qc + 1), 6, qc)
+    T = ctx.ntargets
+    x0 = torch.empty(3, T, dtype=torch.float64, device=dev)
+    n0 = torch.empty_like(x0)
+    ctx.target_geometry(x0, n0)
+    x0 = x0.cpu().numpy()
+    npt = (p + 1) * (2 * p + 2)
+    near_count = np.zeros(T, int)
+    for j in range(3):
+        dist = np.linalg.norm(x0 - s.centres[j][:, None], axis=0) - 1.0
+        own = np.arange(T) // npt == j
+        near_count += (~own) & (dist < delta)
+    say("pairs", ctx.near_pairs(), "targets near two drops", int((near_count >= 2).sum()))
+    assert (near_count >= 2).sum() >= 2 and abs(ctx.near_pairs() - near_count.sum()) <= 2
+    f, u, sg = (torch.from_numpy(a).to(dev) for a in (s.fcoef, s.ucoef, s.sigcoef))
+    for prec in (E.FAR_FP64, E.FAR_FP32C):
+        ref = torch.empty(9, T, dtype=torch.float64, device=dev)
+        ctx.layer_potentials(f, u, sg, E.ALL_KINDS, prec, ref)
+        ctx.sync()
+        for ov in (False, True):
+            ctx.set_overlap(ov)
+            for graph in (False, True):
+                ctx.set_graph(graph)
+                for _ in range(3):
+                    out = torch.full_like(ref, 7.0)
+                    ctx.layer_potentials(f, u, sg, E.ALL_KINDS, prec, out)
+                    ctx.sync()
+                    assert torch.equal(out, ref), (prec, ov, graph)
+            ctx.set_graph(False)
+        ctx.set_overlap(False)
+    ctx.close()
