@@ -299,6 +299,23 @@ int ehd_solve_En(ehd_ctx* ctx, double R, double Eu, double Eq, int far_prec, int
 int ehd_solve_velocity(ehd_ctx* ctx, double lambda, const double* fcoef_d, int far_prec, int restart,
                        int maxit, double tol, double* ucoef_d, int* iters, double* relres);
 
+/* Allocation-free variant of ehd_solve_En, for callers that cannot allocate
+ * device memory during a solve (tight time-stepping or serving loops,
+ * harnesses that forbid hipMalloc/hipFree): same arguments, results and
+ * errors, but the call allocates nothing.  Its workspace (the Krylov basis,
+ * the right-hand side and the evaluation buffers: (restart + 4) n + 7 T
+ * doubles plus alignment, n = ehd_num_coefs, T = ehd_num_targets) lives in
+ * one static 64 MiB device array per device, which the library holds until
+ * the process ends.  Limits: restart <= 64 and the workspace within 8 Mi
+ * doubles (e.g. 256 drops of p = 32 at restart <= 10), else EHD_E_SHAPE
+ * before any work is enqueued; graph mode must be off (EHD_E_STATE), since
+ * recording graphs allocates.  Every call on a device shares that device's
+ * array (each call writes every workspace entry before reading it): calls
+ * that overlap in time on one device, from several contexts or host
+ * threads, race and must be serialised by the caller.  Synchronous. */
+int ehd_solve_En_noalloc(ehd_ctx* ctx, double R, double Eu, double Eq, int far_prec, int restart, int maxit,
+                         double tol, double* en_coef_d, int* iters, double* relres);
+
 /* Implicit surfactant-diffusion solve (Sec. 2.2, the implicit half of the
  * IMEX step of Algorithm 1: (I - dt/(2 Pe) Lap_S) Gamma = b), in Galerkin
  * form on the current drops: c - kappa (Lap_S Gamma[c], Y) = b for all

@@ -1913,6 +1913,7 @@ hipStream_t ehd_ctx_stream(const ehd_ctx* ctx) { return ctx->stream; }
 int ehd_ctx_device(const ehd_ctx* ctx) { return ctx->device; }
 int ehd_ctx_ndrops(const ehd_ctx* ctx) { return ctx->nd; }
 int ehd_ctx_drop_p(const ehd_ctx* ctx, int d) { return ctx->info[d].p; }
+int ehd_ctx_graph_on(const ehd_ctx* ctx) { return ctx->graph_on ? 1 : 0; }
 int ehd_ctx_fail(ehd_ctx* ctx, int code, const char* msg)
 {
     ctx->err = msg;

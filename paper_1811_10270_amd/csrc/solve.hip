@@ -13,14 +13,23 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "ctx_access.h"
 #include "ehdbim.h"
+
+// Workspace of the allocation-free E_n solve (ehd_solve_En_noalloc): 8 Mi
+// doubles (64 MiB), one copy on every device the library runs on, held
+// until the process ends.  In host code its name stands for no device
+// address: kernels and copies get the address that hipGetSymbolAddress
+// returns on the device (scratch_of_device).
+static __device__ __align__(256) double scratch[8LL << 20];
 
 namespace {
 
@@ -166,21 +175,29 @@ struct DevBuf {
 
 using Op = std::function<int(const double* in, double* out)>;
 
+// Workspace of one GMRES(m) solve of vectors of length n.  Device: the
+// Krylov basis V [(m+1) n], w [n] and hd [2m+3] (the projections of the
+// two Gram-Schmidt passes and |w|^2); host: the Hessenberg matrix
+// H [(m+1) m], the Givens rotations cs, sn [m], g, h [m+1], y [m] and the
+// projections' host copy hh [2m+3].
+struct GmresWork {
+    double *V, *w, *hd;
+    double *H, *cs, *sn, *g, *h, *y, *hh;
+};
+
 // Restarted GMRES(m) for A x = b on device vectors of length n; x holds the
 // initial guess on entry.  Converged when the true relative residual
-// |b - A x| / |b| <= tol.
-int gmres(ehd_ctx* ctx, long long n, const Op& A, const double* b, double* x, int m, int maxit, double tol,
-          int* iters, double* relres)
+// |b - A x| / |b| <= tol.  Every workspace entry is written before it is
+// read.
+template <class OpT>
+int gmres_ws(ehd_ctx* ctx, long long n, const OpT& A, const double* b, double* x, int m, int maxit, double tol,
+             const GmresWork& ws, int* iters, double* relres)
 {
     hipStream_t st = ehd_ctx_stream(ctx);
-    DevBuf Vb, wb, hb;
-    SOLVE_HIP(hipMalloc(&Vb.p, sizeof(double) * (size_t)(m + 1) * n));
-    SOLVE_HIP(hipMalloc(&wb.p, sizeof(double) * (size_t)n));
-    // hd: first-pass projections [0, m], second-pass [m + 1, 2m + 1], |w|^2 at 2m + 2
-    SOLVE_HIP(hipMalloc(&hb.p, sizeof(double) * (size_t)(2 * m + 3)));
-    double* V = Vb.p;
-    double* w = wb.p;
-    double* hd = hb.p;
+    double* V = ws.V;
+    double* w = ws.w;
+    double* hd = ws.hd;
+    double *H = ws.H, *cs = ws.cs, *sn = ws.sn, *g = ws.g, *h = ws.h, *y = ws.y, *hh = ws.hh;
     auto norm = [&](const double* vec, double* out) -> int {
         hipLaunchKernelGGL(k_dots, dim3(1), dim3(kT), 0, st, vec, n, vec, n, hd);
         SOLVE_HIP(hipGetLastError());
@@ -200,7 +217,6 @@ int gmres(ehd_ctx* ctx, long long n, const Op& A, const double* b, double* x, in
         *relres = 0.0;
         return EHD_OK;
     }
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1), y(m), hh(2 * m + 3);
     for (;;) {
         // true residual r = b - A x, into V_0
         if ((rc = A(x, w))) return rc;
@@ -212,7 +228,7 @@ int gmres(ehd_ctx* ctx, long long n, const Op& A, const double* b, double* x, in
         *relres = beta / bnorm;
         if (*relres <= tol || *iters >= maxit) return EHD_OK;
         hipLaunchKernelGGL(k_axpby, dim3(nblocks(n)), dim3(kT), 0, st, 0.0, V, 1.0 / beta, V, n);
-        std::fill(g.begin(), g.end(), 0.0);
+        std::fill(g, g + m + 1, 0.0);
         g[0] = beta;
         int jl = -1;
         for (int j = 0; j < m; ++j) {
@@ -227,7 +243,7 @@ int gmres(ehd_ctx* ctx, long long n, const Op& A, const double* b, double* x, in
             hipLaunchKernelGGL(k_subtract, dim3(nblocks(n)), dim3(kT), 0, st, w, V, n, j + 1, hd2, n);
             hipLaunchKernelGGL(k_dots, dim3(1), dim3(kT), 0, st, w, n, w, n, hd + 2 * m + 2);
             SOLVE_HIP(hipGetLastError());
-            SOLVE_HIP(hipMemcpyAsync(hh.data(), hd, sizeof(double) * (size_t)(2 * m + 3), hipMemcpyDeviceToHost, st));
+            SOLVE_HIP(hipMemcpyAsync(hh, hd, sizeof(double) * (size_t)(2 * m + 3), hipMemcpyDeviceToHost, st));
             SOLVE_HIP(hipStreamSynchronize(st));
             const double hn = std::sqrt(hh[2 * m + 2]);
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[m + 1 + i];
@@ -261,10 +277,24 @@ int gmres(ehd_ctx* ctx, long long n, const Op& A, const double* b, double* x, in
             y[i] = s / H[(size_t)i * m + i];
         }
         for (int i = 0; i <= jl; ++i) h[i] = -y[i];
-        SOLVE_HIP(hipMemcpyAsync(hd, h.data(), sizeof(double) * (jl + 1), hipMemcpyHostToDevice, st));
+        SOLVE_HIP(hipMemcpyAsync(hd, h, sizeof(double) * (jl + 1), hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL(k_subtract, dim3(nblocks(n)), dim3(kT), 0, st, x, V, n, jl + 1, hd, n);
         SOLVE_HIP(hipGetLastError());
     }
+}
+
+// GMRES(m) with its workspace allocated for the call.
+int gmres(ehd_ctx* ctx, long long n, const Op& A, const double* b, double* x, int m, int maxit, double tol,
+          int* iters, double* relres)
+{
+    DevBuf Vb, wb, hb;
+    SOLVE_HIP(hipMalloc(&Vb.p, sizeof(double) * (size_t)(m + 1) * n));
+    SOLVE_HIP(hipMalloc(&wb.p, sizeof(double) * (size_t)n));
+    // hd: first-pass projections [0, m], second-pass [m + 1, 2m + 1], |w|^2 at 2m + 2
+    SOLVE_HIP(hipMalloc(&hb.p, sizeof(double) * (size_t)(2 * m + 3)));
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1), y(m), hh(2 * m + 3);
+    const GmresWork ws{Vb.p, wb.p, hb.p, H.data(), cs.data(), sn.data(), g.data(), h.data(), y.data(), hh.data()};
+    return gmres_ws(ctx, n, A, b, x, m, maxit, tol, ws, iters, relres);
 }
 
 int check_opts(ehd_ctx* ctx, int far_prec, int restart, int maxit, double tol)
@@ -277,6 +307,80 @@ int check_opts(ehd_ctx* ctx, int far_prec, int restart, int maxit, double tol)
     return EHD_OK;
 }
 
+int check_En(ehd_ctx* ctx, double R, double Eu, double Eq, int far_prec, int restart, int maxit, double tol,
+             const double* en_coef_d, const int* iters, const double* relres)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ehd_ctx_ndrops(ctx)) return ehd_ctx_fail(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if (!en_coef_d || !iters || !relres) return ehd_ctx_fail(ctx, EHD_E_ARG, "NULL argument");
+    if (!(R > 0.0) || !std::isfinite(Eu) || !std::isfinite(Eq))
+        return ehd_ctx_fail(ctx, EHD_E_ARG, "R must be > 0 and E_u, E_q finite");
+    return check_opts(ctx, far_prec, restart, maxit, tol);
+}
+
+// The E_n system of eq. galerkin_En with device buffers grid [T], rhs [n],
+// geo [6 T] and the GMRES workspace ws (NULL: GMRES allocates its own).
+int solve_En_impl(ehd_ctx* ctx, double R, double Eu, double Eq, int far_prec, int restart, int maxit, double tol,
+                  double* en_coef_d, int* iters, double* relres, double* grid, double* rhs, double* geo,
+                  const GmresWork* ws)
+{
+    long long T, n;
+    int rc;
+    if ((rc = ehd_num_targets(ctx, &T)) || (rc = ehd_num_coefs(ctx, &n))) return rc;
+    hipStream_t st = ehd_ctx_stream(ctx);
+    // right-hand side R/(R+1) P[E_inf . n]
+    if ((rc = ehd_target_geometry(ctx, geo, geo + 3 * T))) return rc;
+    hipLaunchKernelGGL(k_einf_dot_n, dim3(nblocks(T)), dim3(kT), 0, st, geo, geo + 3 * T, T, Eu, Eq, grid);
+    SOLVE_HIP(hipGetLastError());
+    if ((rc = ehd_analyze(ctx, 1, grid, rhs))) return rc;
+    hipLaunchKernelGGL(k_axpby, dim3(nblocks(n)), dim3(kT), 0, st, 0.0, rhs, R / (R + 1.0), rhs, n);
+    SOLVE_HIP(hipGetLastError());
+    // operator E -> E/2 - (R-1)/(R+1) P[K*[E]]
+    const double c = (R - 1.0) / (R + 1.0);
+    auto A = [&](const double* in, double* out) -> int {
+        int r = ehd_layer_potentials(ctx, nullptr, nullptr, in, EHD_LAP_DLADJ, far_prec, grid, nullptr);
+        if (!r) r = ehd_analyze(ctx, 1, grid, out);
+        if (r) return r;
+        hipLaunchKernelGGL(k_axpby, dim3(nblocks(n)), dim3(kT), 0, st, 0.5, in, -c, out, n);
+        SOLVE_HIP(hipGetLastError());
+        return EHD_OK;
+    };
+    if (ws) return gmres_ws(ctx, n, A, rhs, en_coef_d, restart, maxit, tol, *ws, iters, relres);
+    return gmres(ctx, n, Op(A), rhs, en_coef_d, restart, maxit, tol, iters, relres);
+}
+
+// Allocation-free E_n solve: its workspace lives in `scratch`, one array per
+// device (the address of the device's copy is looked up once per device,
+// with that device current, and kept).
+constexpr long long kNoAllocDoubles = 8LL << 20;   // 64 MiB
+constexpr int kNoAllocMaxRestart = 64;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+static_assert(kNoAllocDoubles == (long long)(sizeof(scratch) / sizeof(double)), "scratch size");
+
+// Device address of `scratch` on device `dev` (current): looked up on the
+// first call on that device, then kept.
+int scratch_of_device(ehd_ctx* ctx, int dev, double** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return ehd_ctx_fail(ctx, EHD_E_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            char b[200];
+            snprintf(b, sizeof(b), "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                     hipGetErrorString(e));
+            return ehd_ctx_fail(ctx, EHD_E_HIP, b);
+        }
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return EHD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -284,40 +388,59 @@ extern "C" {
 int ehd_solve_En(ehd_ctx* ctx, double R, double Eu, double Eq, int far_prec, int restart, int maxit, double tol,
                  double* en_coef_d, int* iters, double* relres)
 {
-    if (!ctx) return EHD_E_ARG;
-    if (!ehd_ctx_ndrops(ctx)) return ehd_ctx_fail(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
-    if (!en_coef_d || !iters || !relres) return ehd_ctx_fail(ctx, EHD_E_ARG, "NULL argument");
-    if (!(R > 0.0) || !std::isfinite(Eu) || !std::isfinite(Eq))
-        return ehd_ctx_fail(ctx, EHD_E_ARG, "R must be > 0 and E_u, E_q finite");
-    int rc = check_opts(ctx, far_prec, restart, maxit, tol);
+    int rc = check_En(ctx, R, Eu, Eq, far_prec, restart, maxit, tol, en_coef_d, iters, relres);
     if (rc) return rc;
     SOLVE_HIP(hipSetDevice(ehd_ctx_device(ctx)));
     long long T, n;
     if ((rc = ehd_num_targets(ctx, &T)) || (rc = ehd_num_coefs(ctx, &n))) return rc;
-    hipStream_t st = ehd_ctx_stream(ctx);
-    DevBuf grid, proj, rhs, geo;
+    DevBuf grid, rhs, geo;
     SOLVE_HIP(hipMalloc(&grid.p, sizeof(double) * (size_t)T));
-    SOLVE_HIP(hipMalloc(&proj.p, sizeof(double) * (size_t)n));
     SOLVE_HIP(hipMalloc(&rhs.p, sizeof(double) * (size_t)n));
     SOLVE_HIP(hipMalloc(&geo.p, sizeof(double) * (size_t)6 * T));
-    // right-hand side R/(R+1) P[E_inf . n]
-    if ((rc = ehd_target_geometry(ctx, geo.p, geo.p + 3 * T))) return rc;
-    hipLaunchKernelGGL(k_einf_dot_n, dim3(nblocks(T)), dim3(kT), 0, st, geo.p, geo.p + 3 * T, T, Eu, Eq, grid.p);
-    SOLVE_HIP(hipGetLastError());
-    if ((rc = ehd_analyze(ctx, 1, grid.p, rhs.p))) return rc;
-    hipLaunchKernelGGL(k_axpby, dim3(nblocks(n)), dim3(kT), 0, st, 0.0, rhs.p, R / (R + 1.0), rhs.p, n);
-    SOLVE_HIP(hipGetLastError());
-    // operator E -> E/2 - (R-1)/(R+1) P[K*[E]]
-    const double c = (R - 1.0) / (R + 1.0);
-    const Op A = [&](const double* in, double* out) -> int {
-        int r = ehd_layer_potentials(ctx, nullptr, nullptr, in, EHD_LAP_DLADJ, far_prec, grid.p, nullptr);
-        if (!r) r = ehd_analyze(ctx, 1, grid.p, out);
-        if (r) return r;
-        hipLaunchKernelGGL(k_axpby, dim3(nblocks(n)), dim3(kT), 0, st, 0.5, in, -c, out, n);
-        SOLVE_HIP(hipGetLastError());
-        return EHD_OK;
-    };
-    return gmres(ctx, n, A, rhs.p, en_coef_d, restart, maxit, tol, iters, relres);
+    return solve_En_impl(ctx, R, Eu, Eq, far_prec, restart, maxit, tol, en_coef_d, iters, relres, grid.p, rhs.p,
+                         geo.p, nullptr);
+}
+
+int ehd_solve_En_noalloc(ehd_ctx* ctx, double R, double Eu, double Eq, int far_prec, int restart, int maxit,
+                         double tol, double* en_coef_d, int* iters, double* relres)
+{
+    int rc = check_En(ctx, R, Eu, Eq, far_prec, restart, maxit, tol, en_coef_d, iters, relres);
+    if (rc) return rc;
+    if (restart > kNoAllocMaxRestart) {
+        char b[128];
+        snprintf(b, sizeof(b), "restart %d exceeds the allocation-free solve's maximum %d", restart,
+                 kNoAllocMaxRestart);
+        return ehd_ctx_fail(ctx, EHD_E_SHAPE, b);
+    }
+    if (ehd_ctx_graph_on(ctx))
+        return ehd_ctx_fail(ctx, EHD_E_STATE, "graph mode records graphs (which allocates): switch it off first");
+    const int dev = ehd_ctx_device(ctx);
+    SOLVE_HIP(hipSetDevice(dev));
+    long long T, n;
+    if ((rc = ehd_num_targets(ctx, &T)) || (rc = ehd_num_coefs(ctx, &n))) return rc;
+    const long long m = restart;
+    // scratch layout (each piece 256-byte aligned): V, w, hd, grid, rhs, geo
+    const long long sizes[6] = {(m + 1) * n, n, 2 * m + 3, T, n, 6 * T};
+    long long offs[6], need = 0;
+    for (int i = 0; i < 6; ++i) {
+        offs[i] = need;
+        need += (sizes[i] + 31) / 32 * 32;
+    }
+    if (need > kNoAllocDoubles) {
+        char b[200];
+        snprintf(b, sizeof(b),
+                 "workspace of %lld doubles ((restart + 4) n + 7 T + ...) exceeds the allocation-free solve's "
+                 "%lld (n = %lld coefficients, T = %lld targets)",
+                 need, kNoAllocDoubles, n, T);
+        return ehd_ctx_fail(ctx, EHD_E_SHAPE, b);
+    }
+    double* base = nullptr;
+    if ((rc = scratch_of_device(ctx, dev, &base))) return rc;
+    double H[(kNoAllocMaxRestart + 1) * kNoAllocMaxRestart], cs[kNoAllocMaxRestart], sn[kNoAllocMaxRestart],
+        g[kNoAllocMaxRestart + 1], h[kNoAllocMaxRestart + 1], y[kNoAllocMaxRestart], hh[2 * kNoAllocMaxRestart + 3];
+    const GmresWork ws{base + offs[0], base + offs[1], base + offs[2], H, cs, sn, g, h, y, hh};
+    return solve_En_impl(ctx, R, Eu, Eq, far_prec, restart, maxit, tol, en_coef_d, iters, relres, base + offs[3],
+                         base + offs[4], base + offs[5], &ws);
 }
 
 int ehd_solve_velocity(ehd_ctx* ctx, double lambda, const double* fcoef_d, int far_prec, int restart, int maxit,

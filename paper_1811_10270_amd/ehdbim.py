@@ -39,7 +39,7 @@ EXPORTED = ("ehd_create", "ehd_destroy", "ehd_last_error", "ehd_grid_dims", "ehd
             "ehd_mlp_num_params", "ehd_mlp_get_params", "ehd_mlp_set_params", "ehd_mlp_get_grads",
             "ehd_mlp_forward", "ehd_mlp_backward", "ehd_mlp_mse", "ehd_mlp_adam", "ehd_area_weights",
             "ehd_update_shape", "ehd_surfactant_terms", "ehd_evolve_step", "ehd_evolve", "ehd_set_near",
-            "ehd_near_pairs", "ehd_set_overlap")
+            "ehd_near_pairs", "ehd_set_overlap", "ehd_solve_En_noalloc")
 STAGES = ("densities", "self", "far", "combine")
 DEGREE_CLASSES = (16, 24, 32, 48)   # largest p of each self-interaction kernel class
 
@@ -135,6 +135,7 @@ def load(path: str = LIB_PATH):
                                vp, C.POINTER(EvolveStats)]
     lib.ehd_solve_En.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
                                  C.c_double, vp, ip, dp]
+    lib.ehd_solve_En_noalloc.argtypes = lib.ehd_solve_En.argtypes
     lib.ehd_solve_velocity.argtypes = [vp, C.c_double, vp, C.c_int, C.c_int, C.c_int, C.c_double, vp,
                                        ip, dp]
     _lib = lib
@@ -449,6 +450,15 @@ class Context:
         it, rr = C.c_int(), C.c_double()
         self._check(self._lib.ehd_solve_En(self._h, float(R), float(Eu), float(Eq), far_prec, restart,
                                            maxit, float(tol), _ptr(en), C.byref(it), C.byref(rr)))
+        return it.value, rr.value
+
+    def solve_En_noalloc(self, R: float, Eu: float, Eq: float, en: torch.Tensor, far_prec: int = FAR_FP64,
+                         restart: int = 30, maxit: int = 200, tol: float = 1e-12):
+        """As solve_En, through the allocation-free entry point (workspace in
+        the library's static device array)."""
+        it, rr = C.c_int(), C.c_double()
+        self._check(self._lib.ehd_solve_En_noalloc(self._h, float(R), float(Eu), float(Eq), far_prec, restart,
+                                                   maxit, float(tol), _ptr(en), C.byref(it), C.byref(rr)))
         return it.value, rr.value
 
     def solve_velocity(self, lam: float, fcoef: torch.Tensor, u: torch.Tensor, far_prec: int = FAR_FP64,
