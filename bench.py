@@ -226,8 +226,11 @@ def time_evaluation(args, torch, E, ctx, s, far_prec, kinds, f, sig, out):
     class times; per-kernel work and rates; the far part of one more
     (untimed, split) evaluation for the error report."""
     K = args.steps
+    if args.far_tile:
+        tpt, nch = (int(v) for v in args.far_tile.lower().split("x"))
+        ctx.set_far_config(tpt, nch)
     tile = {"targets_per_thread": ctx.far_config()[0], "source_chunks": ctx.far_config()[1], "autotuned": False}
-    if not args.no_autotune:
+    if not args.no_autotune and not args.far_tile:
         from paper_1811_10270_amd import autotune
         tpt, nch, timings, cached = autotune.autotune_far(ctx, s.p, s.q_far, s.grid_mode, far_prec, kinds=kinds)
         tile = {"targets_per_thread": tpt, "source_chunks": nch, "autotuned": True, "from_cache": cached,
@@ -698,6 +701,9 @@ def main(argv=None):
                          "same launches without the graph)")
     ap.add_argument("--no-graph", dest="graph", action="store_false")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--far-tile", default=None, metavar="TPTxCHUNKS",
+                    help="far-field tile shape (targets per thread x source chunks) instead of the autotuner's, "
+                         "e.g. 2x16 (profiling runs repeat the timed run's shape)")
     ap.add_argument("--solve", choices=["en", "velocity"], default=None,
                     help="time the Galerkin GMRES solve (E_n with R = 0.5, E_u = 1; velocity with "
                          "lambda = 2 for the workload's f) instead of the evaluation; default workload "

@@ -111,6 +111,17 @@ __device__ __forceinline__ double rsqrt_nr(double x)
     return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
+// 1/sqrt(x) in FP64 with one Newton step: y (1 + e/2), e = 1 - x y^2, from
+// the hardware estimate; relative error about 3 e^2 / 8 (a few 1e-15), one
+// instruction fewer than rsqrt_nr.  For the far-field sums, whose terms are
+// far from any cancellation at that level.
+__device__ __forceinline__ double rsqrt_newton(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-(x * y), y, 1.0);
+    return fma(y * e, 0.5, y);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)
 {
@@ -622,10 +633,21 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
         const long wb = ehd::wig_block(p);
         const auto A = gmem(W.A + (long long)j * wb);
         const auto B = gmem(W.B + (long long)j * wb);
+        // Jobs: each degree >= 2 npair alone (64 lanes, m' = lane), then the
+        // pairs (2k, 2k+1) of degrees <= 31 on the two half-waves (m' =
+        // lane % 32), so that each LDS broadcast of z_nm serves two degrees
+        // (the rotation is bound by those broadcasts).  Jobs by decreasing
+        // length, dealt to the waves in snake order.
+        const int npair = min(p + 1, 32) / 2, nsingle = p + 1 - 2 * npair, njob = nsingle + npair;
         const int dn0 = 2 * NW - 1 - 2 * wv, dn1 = 2 * wv + 1;
         bool odd = false;
-        for (int n = wv; n <= p; n += odd ? dn1 : dn0, odd = !odd) {
-            const int mp = lane <= n ? lane : n;            // lanes past n repeat m' = n, store nothing
+        for (int J = wv; J < njob; J += odd ? dn1 : dn0, odd = !odd) {
+            const bool single = J < nsingle;                               // wave-uniform
+            const int k2 = single ? 0 : 2 * (npair - 1 - (J - nsingle));
+            const int nmax = single ? p - J : k2 + 1;                      // last order m of the job
+            const int n = single ? nmax : k2 + (lane >> 5);                // this lane's degree
+            const int mpl = single ? lane : (lane & 31);                   // this lane's order m'
+            const int mp = mpl <= n ? mpl : n;            // lanes past n repeat m' = n, store nothing
             const auto An = A + ehd::wig_off(n) + mp;
             const auto Bn = B + ehd::wig_off(n) + mp;
             double are[NF], aim[NF];
@@ -633,8 +655,12 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
             for (int f = 0; f < NF; ++f) { are[f] = 0.0; aim[f] = 0.0; }
             const double2* zn = cr + column_start(p, 0) + n;   // z_n0 of field 0; z_nm at + column_start(p, m) - m
 #pragma unroll SC::RU
-            for (int m = 0; m <= n; ++m) {
-                const double a = An[m * (n + 1)], b = Bn[m * (n + 1)];
+            for (int m = 0; m <= nmax; ++m) {
+                // the lower degree of a pair has no order m = nmax: weight 0 (its
+                // z address then lies in the next column, in bounds)
+                const bool on = m <= n;
+                const int mm = on ? m : n;
+                const double a = on ? An[mm * (n + 1)] : 0.0, b = on ? Bn[mm * (n + 1)] : 0.0;
                 const int zo = column_start(p, m) - m;
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
@@ -643,8 +669,8 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
                     aim[f] = fma(b, z.y, aim[f]);
                 }
             }
-            if (lane <= n) {
-                const int cpos = column_start(p, lane) + n - lane;
+            if (mpl <= n) {
+                const int cpos = column_start(p, mpl) + n - mpl;
 #pragma unroll
                 for (int f = 0; f < NF; ++f) cr[f * nc + cpos] = make_double2(are[f], aim[f]);
             }
@@ -660,21 +686,29 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     double cB[SC::KW];
     const int ci = lane & 15, cf_ = ci >> 1, cri = ci & 1;
     {
-        int m = -1, left = 0, ks = 0;
+        // this wave's columns in snake order: m = wv, then steps of dn0 and
+        // dn1 in turn (wave-uniform, straight-line, so the loads issue together)
+        const int dn0 = 2 * NW - 1 - 2 * wv, dn1 = 2 * wv + 1;
+        int m = wv, ks = 0;
+        bool odd = false;
+        int left = (m <= p) ? (p + 1 - m + 3) / 4 : 0;
 #pragma unroll
         for (int t = 0; t < SC::KW; ++t) {
-            if (left == 0) {            // next column of this wave (wave-uniform)
-                ++m;
-                while (m <= p && snake_wave(m, NW) != wv) ++m;
-                left = (m <= p) ? (p + 1 - m + 3) / 4 : 0;
-                ks = 0;
-            }
             const int n = m + 4 * ks + (lane >> 4);
             const bool ok = left > 0 && cf_ < NF && n <= p;
             const int idx = ok ? cf_ * (int)nc + column_start(p, m) + n - m : 0;
             const double2 c = cr[idx];
             cB[t] = ok ? (cri ? c.y : c.x) : 0.0;
-            if (left > 0) { --left; ++ks; }
+            if (left > 0) {
+                --left;
+                ++ks;
+                if (left == 0) {
+                    m += odd ? dn1 : dn0;
+                    odd = !odd;
+                    ks = 0;
+                    left = (m <= p) ? (p + 1 - m + 3) / 4 : 0;
+                }
+            }
         }
     }
     __syncthreads();   // LDS free: Fourier blocks and per-wave node buffers from here on
@@ -703,7 +737,10 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
 
     const int gsz = qg.nks * 64;                      // one latitude's Fourier block
     constexpr int NVP = NV | 1;                       // node record stride (odd: fewer bank conflicts)
-    double* NB = R + LB * gsz + wv * 64 * NVP;        // this wave's node values (64 nodes)
+    // node buffer per wave: 64 records (+ spare slots for the pipelined
+    // stores of p <= 32)
+    constexpr int NBW = 64 * NVP + (PMAX <= 32 ? 16 : 0);
+    double* NB = R + LB * gsz + wv * NBW;             // this wave's node values (64 nodes)
     // Rows and columns of a Fourier block that are not rewritten meet zero A
     // entries (padding terms) or feed unused output columns; start from zeros.
     for (int z = threadIdx.x; z < LB * gsz; z += blockDim.x) R[z] = 0.0;
@@ -803,24 +840,33 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
         }
         __syncthreads();
 
-        // kernels at one node (this lane's record of the wave's node buffer)
-        // with the modified weight wi of its latitude, accumulated per lane
-        auto eval_node = [&](const double* val, double wi) {
+        // kernels at one node (its NV values in val, from this lane's record
+        // of the wave's node buffer) with the modified weight wi of its
+        // latitude (0 for a lane without a node of its own), accumulated per
+        // lane.  gate: skip the kinds not requested (branches); without it
+        // every kind the fields allow is accumulated (the requested ones are
+        // stored) and the code has no branch, so the scheduler can interleave
+        // it with the next latitude's longitude-sum MFMAs.
+        auto eval_node = [&](const double* val, double wi, bool gate) {
             const double xt0 = val[3], xt1 = val[4], xt2 = val[5];
             const double xp0 = val[6], xp1 = val[7], xp2 = val[8];
             const double cx = xt1 * xp2 - xt2 * xp1;
             const double cy = xt2 * xp0 - xt0 * xp2;
             const double cz = xt0 * xp1 - xt1 * xp0;
-            const double J2 = cx * cx + cy * cy + cz * cz;
+            // ungated, lanes without a node (weight 0) may hold padding rows of
+            // the longitude sums (zeros): keep their arithmetic finite (gated
+            // calls come from lanes with a node only)
+            const bool live = gate || wi != 0.0;
+            const double J2 = live ? cx * cx + cy * cy + cz * cz : 1.0;
             const double iJ = rsqrt_nr(J2);
             const double w = wi * J2 * iJ;
             const double nx = cx * iJ, ny = cy * iJ, nz = cz * iJ;
             const double hx = x0[0] - val[0], hy = x0[1] - val[1], hz = x0[2] - val[2];
-            const double r2 = hx * hx + hy * hy + hz * hz;
+            const double r2 = live ? hx * hx + hy * hy + hz * hz : 1.0;
             const double ir = rsqrt_nr(r2), ir2 = ir * ir, ir3 = ir * ir2;
             const double hn = hx * nx + hy * ny + hz * nz;
             if constexpr (HF) {
-                if (wS) {
+                if (!gate || wS) {
                     const double f0 = val[VD], f1 = val[VD + 1], f2 = val[VD + 2];
                     const double hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
                     acc[0] += w * (f0 * ir + hx * hf);
@@ -829,7 +875,7 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
                 }
             }
             if constexpr (HF || HU) {
-                if (wD) {
+                if (!gate || wD) {
                     constexpr int uo = VD + (HU ? UOFF : FOFF) - 3;
                     const double hu = hx * val[uo] + hy * val[uo + 1] + hz * val[uo + 2];
                     const double tq = -6.0 * w * hu * hn * ir3 * ir2;
@@ -840,9 +886,9 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
             }
             if constexpr (HS) {
                 const double sg = w * val[VD + SOFF - 3];
-                if (wSL) acc[6] += sg * ir;
-                if (wL) acc[7] += sg * hn * ir3;
-                if (wK) acc[8] += sg * (hx * n0v[0] + hy * n0v[1] + hz * n0v[2]) * ir3;
+                if (!gate || wSL) acc[6] += sg * ir;
+                if (!gate || wL) acc[7] += sg * hn * ir3;
+                if (!gate || wK) acc[8] += sg * (hx * n0v[0] + hy * n0v[1] + hz * n0v[2]) * ir3;
             }
         };
 
@@ -862,14 +908,24 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
             const int ll0 = split ? (wv < 4 ? 0 : 5) : wv / qg.nTp;
             const int ll1 = split ? (wv < 4 ? 5 : LB) : LB;
             const int dll = split ? 1 : SC::NW / qg.nTp;
-            for (int ll = ll0; ll < ll1; ll += dll) {
-                const int i = b * LB + ll;
-                if (i > Lq.Q) break;
+            int nmine = 0;                               // this wave's latitudes in the block
+            for (int ll = ll0; ll < ll1 && b * LB + ll <= Lq.Q; ll += dll) ++nmine;
+            // node of this lane; the four images coincide pairwise at l = 0 and at 2 l = H
+            const int c4 = lane >> 4, l = qg.l0 + 16 * my_tile + (lane & 15);
+            const bool node_ok = 2 * l <= qg.H &&
+                                 (c4 == 0 || (c4 == 1 && 2 * l < qg.H) || (c4 == 2 && l > 0) ||
+                                  (c4 == 3 && l > 0 && 2 * l < qg.H));
+            dbl4 ec, es, oc, os;
+            // longitude sums of latitude ll of the block, this wave's row tile:
+            // k-steps up to the class maximum without guards (past a group's
+            // last k-step the A fragment is zero and the B address is clamped
+            // to the group's last k-step)
+            auto chain = [&](int ll) {
                 const double* G = R + ll * gsz + boff;
-                // k-steps up to the class maximum without guards: past a
-                // group's last k-step the A fragment is zero and the B address
-                // is clamped to the group's last k-step
-                dbl4 ec = dbl4{0, 0, 0, 0}, es = ec, oc = ec, os = ec;
+                ec = dbl4{0, 0, 0, 0};
+                es = ec;
+                oc = ec;
+                os = ec;
                 const int kl0 = qg.nk[0] - 1, kl1 = qg.nk[1] - 1, kl2 = qg.nk[2] - 1, kl3 = qg.nk[3] - 1;
                 const int g0 = qg.base[0] / 4, g1 = qg.base[1] / 4, g2 = qg.base[2] / 4, g3 = qg.base[3] / 4;
 #pragma unroll
@@ -885,35 +941,103 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
                                                                   os, 0, 0, 0);
                     }
                 }
-                // node buffer: record 16 c + row for the nodes c = 0..3 of the row
+            };
+            // node buffer <- the four images of the latitude in ec, es, oc, os
+            // (record 16 c + row for the nodes c = 0..3 of the row), then this
+            // lane's node values -> nv (registers: the buffer is then free)
+            auto publish = [&](double* nv) {
                 {
+                    // lanes of the unused columns v >= NV write to spare slots
+                    // past the records instead of branching around the stores
                     const int v = lane & 15;
-                    if (v < NV) {
+                    const bool real = v < NV;
+                    double* const dst = real ? NB + v : NB + 64 * NVP + (v - NV);
+                    const int step = real ? NVP : 0;
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int row = (lane >> 4) + 4 * r;
-                            const double s0 = ec[r] + oc[r], s1 = ec[r] - oc[r];
-                            const double t0 = es[r] + os[r], t1 = es[r] - os[r];
-                            NB[row * NVP + v] = s0 + t0;             // l
-                            NB[(16 + row) * NVP + v] = s1 - t1;      // H - l
-                            NB[(32 + row) * NVP + v] = s1 + t1;      // H + l
-                            NB[(48 + row) * NVP + v] = s0 - t0;      // N - l
-                        }
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = (lane >> 4) + 4 * r;
+                        const double s0 = ec[r] + oc[r], s1 = ec[r] - oc[r];
+                        const double t0 = es[r] + os[r], t1 = es[r] - os[r];
+                        dst[row * step] = s0 + t0;             // l
+                        dst[(16 + row) * step] = s1 - t1;      // H - l
+                        dst[(32 + row) * step] = s1 + t1;      // H + l
+                        dst[(48 + row) * step] = s0 - t0;      // N - l
                     }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                // node of this lane; the four images coincide pairwise at l = 0 and at 2 l = H
-                const int c4 = lane >> 4, l = qg.l0 + 16 * my_tile + (lane & 15);
-                const bool node_ok = 2 * l <= qg.H &&
-                                     (c4 == 0 || (c4 == 1 && 2 * l < qg.H) || (c4 == 2 && l > 0) ||
-                                      (c4 == 3 && l > 0 && 2 * l < qg.H));
-                if (node_ok) eval_node(NB + lane * NVP, wsing[i]);
-                // the buffer is rewritten for the next latitude
+#pragma unroll
+                for (int v = 0; v < NV; ++v) nv[v] = NB[lane * NVP + v];
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            };
+            // Software pipeline over a wave's two latitudes (p = 24, 32): the
+            // second latitude's sums are issued to the matrix unit right before
+            // the vector unit evaluates the kernels at the first latitude's
+            // nodes, in one basic block, so the two overlap.  (p = 48 has no
+            // registers to spare for it, p = 16 one latitude per wave and block.)
+            double na[NV], nb[NV];
+            if (PMAX <= 32 && nmine == 2) {
+                // the weights are loaded unconditionally (both latitudes exist),
+                // so no branch splits the block
+                const double wa = wsing[b * LB + ll0], wb = wsing[b * LB + ll0 + dll];
+                chain(ll0);
+                publish(na);
+                __builtin_amdgcn_sched_barrier(0);
+                chain(ll0 + dll);
+                eval_node(na, node_ok ? wa : 0.0, false);
+                __builtin_amdgcn_sched_barrier(0);
+                publish(nb);
+                eval_node(nb, node_ok ? wb : 0.0, false);
+            } else {
+                for (int ll = ll0; ll < ll1; ll += dll) {
+                    const int i = b * LB + ll;
+                    if (i > Lq.Q) break;
+                    const double* G = R + ll * gsz + boff;
+                    dbl4 ec1 = dbl4{0, 0, 0, 0}, es1 = ec1, oc1 = ec1, os1 = ec1;
+                    const int kl0 = qg.nk[0] - 1, kl1 = qg.nk[1] - 1, kl2 = qg.nk[2] - 1, kl3 = qg.nk[3] - 1;
+                    const int g0 = qg.base[0] / 4, g1 = qg.base[1] / 4, g2 = qg.base[2] / 4, g3 = qg.base[3] / 4;
+#pragma unroll
+                    for (int ks = 0; ks < SC::KEC; ++ks) {
+                        ec1 = __builtin_amdgcn_mfma_f64_16x16x4f64(aEC[ks], G[(g0 + min(ks, kl0)) * 64], ec1, 0, 0, 0);
+                        if (ks < SC::KES)
+                            es1 = __builtin_amdgcn_mfma_f64_16x16x4f64(aES[ks < SC::KES ? ks : 0],
+                                                                       G[(g1 + max(min(ks, kl1), 0)) * 64], es1, 0, 0,
+                                                                       0);
+                        if (ks < SC::KOC) {
+                            oc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(aOC[ks < SC::KOC ? ks : 0],
+                                                                       G[(g2 + min(ks, kl2)) * 64], oc1, 0, 0, 0);
+                            os1 = __builtin_amdgcn_mfma_f64_16x16x4f64(aOS[ks < SC::KOC ? ks : 0],
+                                                                       G[(g3 + min(ks, kl3)) * 64], os1, 0, 0, 0);
+                        }
+                    }
+                    // node buffer: record 16 c + row for the nodes c = 0..3 of the row
+                    {
+                        const int v = lane & 15;
+                        if (v < NV) {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const int row = (lane >> 4) + 4 * r;
+                                const double s0 = ec1[r] + oc1[r], s1 = ec1[r] - oc1[r];
+                                const double t0 = es1[r] + os1[r], t1 = es1[r] - os1[r];
+                                NB[row * NVP + v] = s0 + t0;             // l
+                                NB[(16 + row) * NVP + v] = s1 - t1;      // H - l
+                                NB[(32 + row) * NVP + v] = s1 + t1;      // H + l
+                                NB[(48 + row) * NVP + v] = s0 - t0;      // N - l
+                            }
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    if (node_ok) eval_node(NB + lane * NVP, wsing[i], true);
+                    // the buffer is rewritten for the next latitude
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
             }
         }
         // 3d. when row 0 is apart: row 0 of latitude wv of the block, phi = 0
@@ -935,7 +1059,7 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (lane < 2) eval_node(NB + lane * NVP, wsing[b * LB + wv]);
+            if (lane < 2) eval_node(NB + lane * NVP, wsing[b * LB + wv], true);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1023,7 +1147,7 @@ __device__ __forceinline__ void far64_block(const double* __restrict__ tx,
                 for (int k = 0; k < TPT; ++k) {
                     const double hx = x0[k] - xs, hy = y0[k] - ys, hz = z0[k] - zs;
                     const double r2 = fma(hx, hx, fma(hy, hy, hz * hz));
-                    const double ir = rsqrt_nr(r2), ir2 = ir * ir, ir3 = ir * ir2;
+                    const double ir = rsqrt_newton(r2), ir2 = ir * ir, ir3 = ir * ir2;
                     double hn = 0.0;
                     if constexpr (needN)
                         hn = fma(hx, j ? NX.y : NX.x, fma(hy, j ? NY.y : NY.x, hz * (j ? NZ.y : NZ.x)));
@@ -1820,7 +1944,7 @@ static size_t self_lds_bytes(const ehd_ctx* ctx, const std::vector<int>& drops, 
         const QuarterGrid g = quarter_grid(D.p, D.nlon_s, self_row0(D.p));
         const size_t coef = (size_t)nf * ncoef(D.p) * 16;
         const size_t work = ((size_t)kLatBlock * g.nks * 64 +
-                             (size_t)SelfClass<16>::NW * 64 * ((nf + 6) | 1)) * 8;
+                             (size_t)SelfClass<16>::NW * (64 * ((nf + 6) | 1) + (D.p <= 32 ? 16 : 0))) * 8;
         best = std::max(best, std::max(coef, work));
     }
     return best;
