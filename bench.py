@@ -657,6 +657,17 @@ def bench_learned(args, torch, E, W, dev):
     te = L.solve_all(L.draw(args.steps, p, seed=2, kind=kind))
     g = L.predict(m, te)
     r = L.compare(te, g, tol=1e-10)
+    # mean iterations per decade of kappa = dt / (2 Pe)
+    by_kappa = {}
+    for lo in (5e-7, 5e-6, 5e-5):
+        sel = (te.kappa >= lo) & (te.kappa < 10 * lo)
+        if sel.any():
+            by_kappa[f"[{lo:g}, {10 * lo:g})"] = {
+                "solves": int(sel.sum()), "plain": float(r["iters_plain"][sel].mean()),
+                "precond_rhs": float(r["iters_precond"][sel].mean()),
+                "learned": float(r["iters_learned"][sel].mean()),
+                "relres_median_precond_rhs": float(np.median(r["precond_relres"][sel])),
+                "relres_median_learned": float(np.median(r["guess_relres"][sel]))}
     res = {
         "metric": "GMRES iterations to 1e-10 true residual, implicit surfactant solve, learned initial guess",
         "value": float(r["iters_learned"].mean()), "unit": "iterations", "n_gpus": 1, "steps": args.steps,
@@ -671,6 +682,7 @@ def bench_learned(args, torch, E, W, dev):
         "relres_median": {"precond_rhs": float(np.median(r["precond_relres"])),
                           "learned": float(np.median(r["guess_relres"]))},
         "guess_used_frac": float(r["guess_used"].mean()),
+        "by_kappa": by_kappa,
         "train_loss": [float(m.history[0]), float(m.history[-1])],
         "active_outputs": int((m.gain > 0.5).sum()), "outputs": int(m.gain.size),
         "generate_s": t1 - t0, "train_s": t2 - t1,

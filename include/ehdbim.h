@@ -331,6 +331,30 @@ int ehd_solve_En_noalloc(ehd_ctx* ctx, double R, double Eu, double Eq, int far_p
 int ehd_solve_surfactant(ehd_ctx* ctx, const double* kappa_h, const double* rhs_d, int precond, int restart,
                          int maxit, double tol, double* gamma_d, int* iters, double* relres);
 
+/* Initial guess of the surfactant solve (Sec. 2.2: the preconditioned
+ * implicit half-step, with a learned correction).  Per drop d, with
+ * M = diag(1 + kappa_d n(n+1)) the preconditioner of ehd_solve_surfactant
+ * and |b_d| the Euclidean norm of the drop's packed right-hand side:
+ *   guess_d = M^{-1} b_d + kappa_d |b_d| gain (y_d std + mean)   (y_d != NULL)
+ *   guess_d = M^{-1} b_d                                           (y_d == NULL)
+ * elementwise over the drop's packed coefficients.  y_d: FP32 [ndrops][ny]
+ * device buffer (a network's standardised outputs), ny = (p+1)(p+2) for
+ * every drop; ymean_d, ystd_d, gain_d: FP64 [ny] device buffers (the
+ * output de-standardisation and a per-coefficient shrinkage).  kappa_h
+ * [ndrops] >= 0 (host); rhs_d, guess_d: 1 packed field.  Synchronous. */
+int ehd_surfactant_guess(ehd_ctx* ctx, const double* kappa_h, const double* rhs_d, const float* y_d, int ny,
+                         const double* ymean_d, const double* ystd_d, const double* gain_d, double* guess_d);
+
+/* Inputs of the learned-guess network for the current drops (all of one
+ * degree p, nc = (p+1)(p+2)): per drop, FP32 feat_d[d][4 nc + 1] =
+ * standardised [x (the drop's 3 packed surface fields with their degree-0
+ * terms set to 0), b / |b|, log10 kappa], each entry (v - mean_d[k]) /
+ * std_d[k] (FP64 [4 nc + 1] device buffers; mean 0 and std 1 give the raw
+ * inputs).  kappa_h [ndrops] > 0 (host), rhs_d: 1 packed field.
+ * Synchronous. */
+int ehd_learned_features(ehd_ctx* ctx, const double* kappa_h, const double* rhs_d, const double* mean_d,
+                         const double* std_d, float* feat_d);
+
 /* Copy of the current drops' surface coefficients (3 packed fields, as
  * passed to ehd_set_drops) into xcoef_d. */
 int ehd_drop_coefs(ehd_ctx* ctx, double* xcoef_d);

@@ -101,6 +101,76 @@ __global__ void k_einf_dot_n(const double* __restrict__ x0, const double* __rest
     g[t] = -Eq * x * n0[t] - Eq * y * n0[T + t] + (Eu + 2.0 * Eq * z) * n0[2 * T + t];
 }
 
+// Degree n of the packed entry k (complex index k / 2 = n(n+1)/2 + m).
+__device__ __forceinline__ int packed_degree(int k)
+{
+    const int c = k >> 1;
+    int n = (int)((sqrt(8.0 * c + 1.0) - 1.0) * 0.5);
+    while ((n + 1) * (n + 2) / 2 <= c) ++n;
+    while (n * (n + 1) / 2 > c) --n;
+    return n;
+}
+
+// Euclidean norm of the block's ne doubles at v (block reduction, fixed order).
+__device__ double block_norm(const double* __restrict__ v, int ne)
+{
+    __shared__ double sh[kT];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < ne; k += kT) s = fma(v[k], v[k], s);
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = kT / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double r = sqrt(sh[0]);
+    __syncthreads();
+    return r;
+}
+
+// Initial guess of drop blockIdx.x (ne packed doubles from off[d]):
+//   M^{-1} b + kappa |b| gain (y std + mean)        (y != NULL)
+//   M^{-1} b                                          (y == NULL)
+// with M = diag(1 + kappa n(n+1)) and y the network's (FP32) output.
+__global__ __launch_bounds__(kT) void k_guess(const long long* __restrict__ off, const double* __restrict__ kappa,
+                                              const double* __restrict__ b, const float* __restrict__ y, int ny,
+                                              const double* __restrict__ ymean, const double* __restrict__ ystd,
+                                              const double* __restrict__ gain, double* __restrict__ guess)
+{
+    const int d = blockIdx.x;
+    const long long o = off[d];
+    const int ne = (int)(off[d + 1] - o);
+    const double kd = kappa[d];
+    const double bn = y ? block_norm(b + o, ne) : 0.0;
+    for (int k = threadIdx.x; k < ne; k += kT) {
+        const int n = packed_degree(k);
+        double g = b[o + k] / (1.0 + kd * n * (n + 1.0));
+        if (y) g += kd * bn * gain[k] * ((double)y[(long long)d * ny + k] * ystd[k] + ymean[k]);
+        guess[o + k] = g;
+    }
+}
+
+// Network inputs of drop blockIdx.x (all drops of degree p, nc = (p+1)(p+2)):
+// [x without its degree-0 terms (3 nc), b / |b| (nc), log10 kappa], each
+// entry standardised, (v - mean) / std, and stored as FP32.
+__global__ __launch_bounds__(kT) void k_features(int nc, const double* __restrict__ xcoef,
+                                                 const double* __restrict__ kappa, const double* __restrict__ b,
+                                                 const double* __restrict__ mean, const double* __restrict__ stdv,
+                                                 float* __restrict__ feat)
+{
+    const int d = blockIdx.x, nf = 4 * nc + 1;
+    const double* bd = b + (long long)d * nc;
+    const double* xd = xcoef + (long long)d * 3 * nc;
+    const double bn = block_norm(bd, nc);
+    for (int k = threadIdx.x; k < nf; k += kT) {
+        double v;
+        if (k < 3 * nc) v = (k % nc) < 2 ? 0.0 : xd[k];     // degree 0 (translation) drops out
+        else if (k < 4 * nc) v = bd[k - 3 * nc] / bn;
+        else v = log10(kappa[d]);
+        feat[(long long)d * nf + k] = (float)((v - mean[k]) / stdv[k]);
+    }
+}
+
 unsigned nblocks(long long n) { return (unsigned)((n + kT - 1) / kT); }
 
 // Interface force density of the velocity equation at the target nodes
@@ -607,6 +677,67 @@ int ehd_solve_surfactant(ehd_ctx* ctx, const double* kappa_h, const double* rhs_
     SOLVE_HIP(hipGetLastError());
     if ((rc = gmres(ctx, n, A, rhs_d, gamma_d, restart, maxit, tol, iters, relres))) return rc;
     hipLaunchKernelGGL(k_mul, dim3(nblocks(n)), dim3(kT), 0, st, di.p, gamma_d, gamma_d, n);
+    SOLVE_HIP(hipGetLastError());
+    SOLVE_HIP(hipStreamSynchronize(st));
+    return EHD_OK;
+}
+
+int ehd_surfactant_guess(ehd_ctx* ctx, const double* kappa_h, const double* rhs_d, const float* y_d, int ny,
+                         const double* ymean_d, const double* ystd_d, const double* gain_d, double* guess_d)
+{
+    if (!ctx) return EHD_E_ARG;
+    const int nd = ehd_ctx_ndrops(ctx);
+    if (!nd) return ehd_ctx_fail(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if (!kappa_h || !rhs_d || !guess_d) return ehd_ctx_fail(ctx, EHD_E_ARG, "NULL argument");
+    if (y_d && (!ymean_d || !ystd_d || !gain_d)) return ehd_ctx_fail(ctx, EHD_E_ARG, "NULL network scaling");
+    std::vector<long long> off((size_t)nd + 1, 0);
+    std::vector<double> kv((size_t)nd);
+    for (int d = 0; d < nd; ++d) {
+        const int p = ehd_ctx_drop_p(ctx, d);
+        if (!(kappa_h[d] >= 0.0) || !std::isfinite(kappa_h[d]))
+            return ehd_ctx_fail(ctx, EHD_E_ARG, "kappa must be >= 0 for every drop");
+        if (y_d && ny != (p + 1) * (p + 2))
+            return ehd_ctx_fail(ctx, EHD_E_SHAPE, "ny must be (p+1)(p+2) for every drop");
+        off[d + 1] = off[d] + (long long)(p + 1) * (p + 2);
+        kv[d] = kappa_h[d];
+    }
+    SOLVE_HIP(hipSetDevice(ehd_ctx_device(ctx)));
+    hipStream_t st = ehd_ctx_stream(ctx);
+    DevBuf offb, kb;
+    SOLVE_HIP(hipMalloc(&offb.p, sizeof(long long) * off.size()));
+    SOLVE_HIP(hipMalloc(&kb.p, sizeof(double) * kv.size()));
+    SOLVE_HIP(hipMemcpyAsync(offb.p, off.data(), sizeof(long long) * off.size(), hipMemcpyHostToDevice, st));
+    SOLVE_HIP(hipMemcpyAsync(kb.p, kv.data(), sizeof(double) * kv.size(), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_guess, dim3(nd), dim3(kT), 0, st, reinterpret_cast<const long long*>(offb.p), kb.p, rhs_d,
+                       y_d, ny, ymean_d, ystd_d, gain_d, guess_d);
+    SOLVE_HIP(hipGetLastError());
+    SOLVE_HIP(hipStreamSynchronize(st));
+    return EHD_OK;
+}
+
+int ehd_learned_features(ehd_ctx* ctx, const double* kappa_h, const double* rhs_d, const double* mean_d,
+                         const double* std_d, float* feat_d)
+{
+    if (!ctx) return EHD_E_ARG;
+    const int nd = ehd_ctx_ndrops(ctx);
+    if (!nd) return ehd_ctx_fail(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if (!kappa_h || !rhs_d || !mean_d || !std_d || !feat_d) return ehd_ctx_fail(ctx, EHD_E_ARG, "NULL argument");
+    const int p = ehd_ctx_drop_p(ctx, 0);
+    for (int d = 0; d < nd; ++d) {
+        if (ehd_ctx_drop_p(ctx, d) != p) return ehd_ctx_fail(ctx, EHD_E_SHAPE, "every drop must have the same p");
+        if (!(kappa_h[d] > 0.0) || !std::isfinite(kappa_h[d]))
+            return ehd_ctx_fail(ctx, EHD_E_ARG, "kappa must be > 0 for every drop");
+    }
+    const int nc = (p + 1) * (p + 2);
+    SOLVE_HIP(hipSetDevice(ehd_ctx_device(ctx)));
+    hipStream_t st = ehd_ctx_stream(ctx);
+    DevBuf x, kb;
+    SOLVE_HIP(hipMalloc(&x.p, sizeof(double) * (size_t)3 * nc * nd));
+    SOLVE_HIP(hipMalloc(&kb.p, sizeof(double) * (size_t)nd));
+    int rc = ehd_drop_coefs(ctx, x.p);
+    if (rc) return rc;
+    SOLVE_HIP(hipMemcpyAsync(kb.p, kappa_h, sizeof(double) * nd, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_features, dim3(nd), dim3(kT), 0, st, nc, x.p, kb.p, rhs_d, mean_d, std_d, feat_d);
     SOLVE_HIP(hipGetLastError());
     SOLVE_HIP(hipStreamSynchronize(st));
     return EHD_OK;

@@ -39,7 +39,8 @@ EXPORTED = ("ehd_create", "ehd_destroy", "ehd_last_error", "ehd_grid_dims", "ehd
             "ehd_mlp_num_params", "ehd_mlp_get_params", "ehd_mlp_set_params", "ehd_mlp_get_grads",
             "ehd_mlp_forward", "ehd_mlp_backward", "ehd_mlp_mse", "ehd_mlp_adam", "ehd_area_weights",
             "ehd_update_shape", "ehd_surfactant_terms", "ehd_evolve_step", "ehd_evolve", "ehd_set_near",
-            "ehd_near_pairs", "ehd_set_overlap", "ehd_solve_En_noalloc")
+            "ehd_near_pairs", "ehd_set_overlap", "ehd_solve_En_noalloc", "ehd_surfactant_guess",
+            "ehd_learned_features")
 STAGES = ("densities", "self", "far", "combine")
 DEGREE_CLASSES = (16, 24, 32, 48)   # largest p of each self-interaction kernel class
 
@@ -136,6 +137,8 @@ def load(path: str = LIB_PATH):
     lib.ehd_solve_En.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
                                  C.c_double, vp, ip, dp]
     lib.ehd_solve_En_noalloc.argtypes = lib.ehd_solve_En.argtypes
+    lib.ehd_surfactant_guess.argtypes = [vp, dp, vp, vp, C.c_int, vp, vp, vp, vp]
+    lib.ehd_learned_features.argtypes = [vp, dp, vp, vp, vp, vp]
     lib.ehd_solve_velocity.argtypes = [vp, C.c_double, vp, C.c_int, C.c_int, C.c_int, C.c_double, vp,
                                        ip, dp]
     _lib = lib
@@ -460,6 +463,28 @@ class Context:
         self._check(self._lib.ehd_solve_En_noalloc(self._h, float(R), float(Eu), float(Eq), far_prec, restart,
                                                    maxit, float(tol), _ptr(en), C.byref(it), C.byref(rr)))
         return it.value, rr.value
+
+    def surfactant_guess(self, kappa, rhs: torch.Tensor, guess: torch.Tensor, y: torch.Tensor | None = None,
+                         ymean: torch.Tensor | None = None, ystd: torch.Tensor | None = None,
+                         gain: torch.Tensor | None = None):
+        """guess = M^{-1} rhs (+ kappa |rhs| gain (y ystd + ymean) per drop when
+        y, the network's FP32 outputs [ndrops][ny], is given)."""
+        import numpy as np
+        k = np.broadcast_to(np.asarray(kappa, np.float64), (len(self.p),)).copy()
+        ny = int(y.shape[1]) if y is not None else 0
+        self._check(self._lib.ehd_surfactant_guess(
+            self._h, k.ctypes.data_as(C.POINTER(C.c_double)), _ptr(rhs),
+            _fptr(y) if y is not None else None, ny,
+            _ptr(ymean) if y is not None else None, _ptr(ystd) if y is not None else None,
+            _ptr(gain) if y is not None else None, _ptr(guess)))
+
+    def learned_features(self, kappa, rhs: torch.Tensor, mean: torch.Tensor, std: torch.Tensor,
+                         feat: torch.Tensor):
+        """FP32 network inputs [ndrops][4 nc + 1], standardised with mean, std."""
+        import numpy as np
+        k = np.broadcast_to(np.asarray(kappa, np.float64), (len(self.p),)).copy()
+        self._check(self._lib.ehd_learned_features(self._h, k.ctypes.data_as(C.POINTER(C.c_double)), _ptr(rhs),
+                                                   _ptr(mean), _ptr(std), _fptr(feat)))
 
     def solve_velocity(self, lam: float, fcoef: torch.Tensor, u: torch.Tensor, far_prec: int = FAR_FP64,
                        restart: int = 30, maxit: int = 200, tol: float = 1e-12):

@@ -241,3 +241,33 @@ def test_self_class_times(E):
             assert (ms[c] > 0) == (pm in present), (pm, ms)
         assert sum(ms) <= st[1] * 1.02 + 0.05
     ctx.close()
+
+
+def test_bench_graph_configuration_batched(E):
+    """The benchmark's configuration of the 64-drop mixed-degree workload:
+    overlap mode, the far-field tile the autotuner picks for the metric's
+    kinds, and the evaluation recorded as one HIP graph and replayed.  Every
+    replay, with eager work and synchronisations between them, gives the
+    eager result bit for bit, in both far-field precisions."""
+    import torch
+    from paper_1811_10270_amd import autotune
+    s = W.batched_suspension(seed=3)
+    ctx, f, sg, dev = _setup(E, s)
+    ctx.set_overlap(True)
+    out = torch.zeros(8, ctx.ntargets, dtype=torch.float64, device=dev)
+    for prec in (E.FAR_FP32C, E.FAR_FP64):
+        autotune.autotune_far(ctx, s.p, s.q_far, s.grid_mode, prec, kinds=E.METRIC_KINDS, use_cache=False)
+        ctx.set_graph(False)
+        ctx.layer_potentials(f, None, sg, E.METRIC_KINDS, prec, out)
+        ctx.sync()
+        ref = out.clone()
+        ctx.set_graph(True)
+        for rep in range(3):
+            out.fill_(7.0)
+            ctx.layer_potentials(f, None, sg, E.METRIC_KINDS, prec, out)
+            ctx.sync()
+            assert torch.equal(out, ref), (prec, rep)
+            _ = (out * 2.0).sum().item()          # eager work between replays
+            torch.cuda.synchronize()
+        ctx.set_graph(False)
+    ctx.close()
