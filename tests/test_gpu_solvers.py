@@ -273,3 +273,32 @@ def test_surfactant_preconditioner_exact_on_sphere(E):
     it, rr = ctx.solve_surfactant(0.2, torch.from_numpy(b).to(dev), g, precond=True, tol=1e-12)
     ctx.close()
     assert it <= 1 and rr < 1e-12, (it, rr)
+
+
+def test_two_drop_workload_solves_against_stored_oracle_solutions(E):
+    """The two-drop workload at full size (two p = 32 spheres 0.1 apart,
+    q_self = 64, q_far = 96): the GPU's GMRES solutions of the E_n system
+    (eq. galerkin_En, R = 0.5, E_u = 1) and of the velocity system
+    (eq. BIM_galerkin, lambda = 2, the workload's f) against the solutions
+    of the same systems by GMRES over the oracle's operators, stored by
+    tests/golden/make_golden.py (oracle residuals about 2e-14)."""
+    import os
+    import sys
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    sys.path.insert(0, gold)
+    try:
+        from make_golden import input_checksums
+    finally:
+        sys.path.pop(0)
+    s = W.two_drops(32, seed=2)
+    g = np.load(os.path.join(gold, "two_drops_p32_solves.npz"))
+    np.testing.assert_allclose(g["checksums"], input_checksums(s), rtol=1e-14, atol=0)
+    R, Eu, Eq, lam = (float(v) for v in g["params"])
+    say("[gpu] two_drops_p32: E_n and velocity solves, tol 1e-13")
+    en, it, rr = gpu_En(E, s, R, Eu, Eq)
+    u, itu, rru = gpu_velocity(E, s, lam, s.fcoef)
+    e_en, e_u = rel(en, g["en"]), rel(u, g["u"])
+    say("E_n iterations", it, "relres", rr, "rel err", e_en, "| velocity iterations", itu, "relres", rru,
+        "rel err", e_u)
+    assert rr <= 1e-13 and rru <= 1e-13
+    assert e_en < TOL and e_u < TOL, (e_en, e_u)
