@@ -227,7 +227,9 @@ def time_evaluation(args, torch, E, ctx, s, far_prec, kinds, f, sig, out):
     (untimed, split) evaluation for the error report."""
     K = args.steps
     if args.far_tile:
-        tpt, nch = (int(v) for v in args.far_tile.lower().split("x"))
+        shapes = args.far_tile.lower().split(",")
+        shape = shapes[1] if far_prec == E.FAR_FP32C and len(shapes) > 1 else shapes[0]
+        tpt, nch = (int(v) for v in shape.split("x"))
         ctx.set_far_config(tpt, nch)
     tile = {"targets_per_thread": ctx.far_config()[0], "source_chunks": ctx.far_config()[1], "autotuned": False}
     if not args.no_autotune and not args.far_tile:
@@ -713,9 +715,10 @@ def main(argv=None):
                          "same launches without the graph)")
     ap.add_argument("--no-graph", dest="graph", action="store_false")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--far-tile", default=None, metavar="TPTxCHUNKS",
+    ap.add_argument("--far-tile", default=None, metavar="TPTxCHUNKS[,TPTxCHUNKS]",
                     help="far-field tile shape (targets per thread x source chunks) instead of the autotuner's, "
-                         "e.g. 2x16 (profiling runs repeat the timed run's shape)")
+                         "e.g. 2x16; a second shape after a comma is the FP32 path's when both precisions "
+                         "run (profiling runs repeat the timed run's shapes)")
     ap.add_argument("--solve", choices=["en", "velocity"], default=None,
                     help="time the Galerkin GMRES solve (E_n with R = 0.5, E_u = 1; velocity with "
                          "lambda = 2 for the workload's f) instead of the evaluation; default workload "

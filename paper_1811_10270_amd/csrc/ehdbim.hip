@@ -1771,6 +1771,10 @@ struct ehd_ctx {
     bool overlap = false;
     hipStream_t far_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // registers per lane (rounded to the allocation granule) and static LDS
+    // bytes of each kernel as built, queried once per kernel
+    struct KernRes { int vgpr, lds; };
+    std::map<const void*, KernRes> kres;
 
     void drop_graph()
     {
@@ -1974,16 +1978,31 @@ static int launch_self_class(ehd_ctx* ctx, int cls, const double* f, const doubl
     return EHD_OK;
 }
 
-// The degree classes hi, hi-1, .., lo (3: p <= 48 .. 0: p <= 16), largest first.
+// The degree classes in the mask (bit 3: p <= 48 .. bit 0: p <= 16), largest first.
 template <bool HF, bool HU, bool HS>
-static int launch_self(ehd_ctx* ctx, const double* f, const double* u, const double* s, unsigned kinds, int hi, int lo)
+static int launch_self(ehd_ctx* ctx, const double* f, const double* u, const double* s, unsigned kinds, unsigned cm)
 {
     int rc = EHD_OK;
-    if (!rc && hi >= 3 && lo <= 3) rc = launch_self_class<48, HF, HU, HS>(ctx, 3, f, u, s, kinds);
-    if (!rc && hi >= 2 && lo <= 2) rc = launch_self_class<32, HF, HU, HS>(ctx, 2, f, u, s, kinds);
-    if (!rc && hi >= 1 && lo <= 1) rc = launch_self_class<24, HF, HU, HS>(ctx, 1, f, u, s, kinds);
-    if (!rc && hi >= 0 && lo <= 0) rc = launch_self_class<16, HF, HU, HS>(ctx, 0, f, u, s, kinds);
+    if (!rc && (cm & 8u)) rc = launch_self_class<48, HF, HU, HS>(ctx, 3, f, u, s, kinds);
+    if (!rc && (cm & 4u)) rc = launch_self_class<32, HF, HU, HS>(ctx, 2, f, u, s, kinds);
+    if (!rc && (cm & 2u)) rc = launch_self_class<24, HF, HU, HS>(ctx, 1, f, u, s, kinds);
+    if (!rc && (cm & 1u)) rc = launch_self_class<16, HF, HU, HS>(ctx, 0, f, u, s, kinds);
     return rc;
+}
+
+// The self-interaction kernel of degree class PMAX for the fields it holds.
+template <int PMAX>
+static const void* self_kernel(bool HF, bool HU, bool HS)
+{
+    if (HU) return (const void*)k_self<PMAX, false, true, false>;
+    if (HF && HS) return (const void*)k_self<PMAX, true, false, true>;
+    if (HF) return (const void*)k_self<PMAX, true, false, false>;
+    return (const void*)k_self<PMAX, false, false, true>;
+}
+static const void* self_kernel_of_class(int cls, bool HF, bool HU, bool HS)
+{
+    return cls == 0 ? self_kernel<16>(HF, HU, HS) : cls == 1 ? self_kernel<24>(HF, HU, HS)
+           : cls == 2 ? self_kernel<32>(HF, HU, HS) : self_kernel<48>(HF, HU, HS);
 }
 
 // FP64 far-field launchers, one per (targets per thread, kinds mask).
@@ -2030,6 +2049,18 @@ template <int TPT>
 static const std::array<Far32Launch, 32>& far32_table()
 {
     return far32_table_impl<TPT>(std::make_index_sequence<32>{});
+}
+// The FP32 far-field kernels themselves (resource queries).
+template <int TPT, std::size_t... I>
+static const std::array<const void*, 32>& far32_kernels_impl(std::index_sequence<I...>)
+{
+    static const std::array<const void*, 32> t{{(const void*)k_far32<TPT, (unsigned)I>...}};
+    return t;
+}
+static const void* far32_kernel(int tpt, unsigned kinds)
+{
+    return (tpt == 2 ? far32_kernels_impl<2>(std::make_index_sequence<32>{})
+                     : far32_kernels_impl<1>(std::make_index_sequence<32>{}))[kinds & EHD_ALL_KINDS];
 }
 
 // Accessors for the solvers (ctx_access.h).
@@ -2930,25 +2961,72 @@ static double self_work(const DropInfo& D)
     return rot + leg + dft + ker;
 }
 
-// Overlap mode: share of the far field's work items forked beside the
-// degree classes below p = 48, the expected time of those classes over that
-// of the far field (each its algorithmic work over the fraction of peak it
-// reaches alone: 0.24, 0.44, 0.60 for the classes, 0.96 for the FP32 far
-// field at 53 flops per interaction), at most one half.  On 64 mixed drops
-// this gives 0.34 and on 256 drops of p = 32 0.24, inside the measured
-// optima (0.3-0.5 and 0.2-0.35).  The FP64 far field needs the same FP64
-// units as the self-interaction, which slows down by about as much as the
-// far work done beside it (256 drops lost 3-8% at shares 0.13 and 0.35):
-// share 0.
-static double overlap_share(const ehd_ctx* ctx, int far_prec)
+// Registers per lane (rounded up to the allocation granule of 8) and static
+// LDS bytes of a kernel as built; a kernel the runtime cannot describe fits
+// beside nothing.
+static ehd_ctx::KernRes kernel_res(ehd_ctx* ctx, const void* fn)
 {
-    if (far_prec == EHD_FAR_FP64) return 0.0;
-    static const double eff[3] = {0.24, 0.44, 0.60};
+    auto it = ctx->kres.find(fn);
+    if (it != ctx->kres.end()) return it->second;
+    ehd_ctx::KernRes r{512, 1 << 30};
+    hipFuncAttributes a{};
+    if (hipFuncGetAttributes(&a, fn) == hipSuccess) r = {(a.numRegs + 7) / 8 * 8, (int)a.sharedSizeBytes};
+    else (void)hipGetLastError();
+    ctx->kres.emplace(fn, r);
+    return r;
+}
+
+// Overlap mode: the degree classes below p = 48 whose blocks leave room on a
+// compute unit for one looping FP32 far-field block: each SIMD holds the
+// block's two waves of the self-interaction and one far-field wave in its
+// 512 registers per lane, and the LDS of both blocks fits the CU's.  A
+// class without that room would have its CUs taken by the far-field blocks
+// and slow down several times over, so it runs before the fork.  Every
+// kernel the evaluation launches for the class must fit.
+static unsigned classes_beside_far(ehd_ctx* ctx, int far_prec, unsigned kinds, bool needF, bool needU, bool needLap)
+{
+    if (far_prec == EHD_FAR_FP64) return 0u;
+    struct V { bool hf, hu, hs; };
+    V v[2];
+    int nv = 0;
+    if (needU && (needF || needLap)) { v[nv++] = {needF, false, needLap}; v[nv++] = {false, true, false}; }
+    else if (needU) v[nv++] = {false, true, false};
+    else v[nv++] = {needF, false, needLap};
+    const ehd_ctx::KernRes fr = kernel_res(ctx, far32_kernel(ctx->far_tpt, kinds));
+    constexpr int self_waves = SelfClass<16>::NT / 256, far_waves = kThreads / 256;   // per SIMD
+    unsigned m = 0;
+    for (int c = 0; c < 3; ++c) {
+        if (ctx->cls_drops[c].empty()) continue;
+        bool fits = true;
+        for (int i = 0; i < nv; ++i) {
+            const ehd_ctx::KernRes sr = kernel_res(ctx, self_kernel_of_class(c, v[i].hf, v[i].hu, v[i].hs));
+            const int nf = 3 + (v[i].hf ? 3 : 0) + (v[i].hu ? 3 : 0) + (v[i].hs ? 1 : 0);
+            const size_t lds = self_lds_bytes(ctx, ctx->cls_drops[c], nf) + (size_t)sr.lds + (size_t)fr.lds;
+            fits = fits && self_waves * sr.vgpr + far_waves * fr.vgpr <= 512 && lds <= (size_t)ctx->max_lds;
+        }
+        if (fits) m |= 1u << c;
+    }
+    return m;
+}
+
+// Overlap mode: share of the far field's work items forked beside the
+// degree classes in `beside`, the expected time of those classes over that
+// of the far field (each its algorithmic work over the fraction of peak it
+// reaches alone: 0.25, 0.48, 0.65 for the classes, 0.96 for the FP32 far
+// field at 53 flops per interaction), at most one half.  The FP64 far field
+// needs the same FP64 units as the self-interaction, which slows down by
+// about as much as the far work done beside it (256 drops lost 3-8% at
+// shares 0.13 and 0.35): share 0.
+static double overlap_share(const ehd_ctx* ctx, int far_prec, unsigned beside)
+{
+    if (far_prec == EHD_FAR_FP64 || !beside) return 0.0;
+    static const double eff[3] = {0.25, 0.48, 0.65};
     double small = 0.0, far = 0.0;
     long long S = 0;
     for (int d = 0; d < ctx->nd; ++d) S += ctx->info[d].ns;
     for (int c = 0; c < 3; ++c)
-        for (int d : ctx->cls_drops[c]) small += self_work(ctx->info[d]) / eff[c];
+        if (beside & (1u << c))
+            for (int d : ctx->cls_drops[c]) small += self_work(ctx->info[d]) / eff[c];
     for (int d = 0; d < ctx->nd; ++d) {
         const DropInfo& D = ctx->info[d];
         far += (double)(D.p + 1) * D.nlon_p * (double)(S - D.ns);
@@ -2999,48 +3077,54 @@ static int enqueue_evaluation(ehd_ctx* ctx, const double* fcoef_d, const double*
     //    other kinds.
     // the nearly singular correction of K* needs the single layer's on-surface values
     const unsigned kself = (ctx->near.npairs && (kinds & EHD_LAP_DLADJ)) ? (kinds | EHD_LAP_SL) : kinds;
-    auto self_classes = [&](int hi, int lo) {
+    auto self_classes = [&](unsigned cm) {
         int rc = EHD_OK;
         if (needU && (needF || needLap)) {
             const unsigned k1 = kself & ~(unsigned)EHD_STOKES_DL;
-            if (needF && needLap) rc = launch_self<true, false, true>(ctx, fcoef_d, nullptr, sigcoef_d, k1, hi, lo);
-            else if (needF) rc = launch_self<true, false, false>(ctx, fcoef_d, nullptr, sigcoef_d, k1, hi, lo);
-            else rc = launch_self<false, false, true>(ctx, fcoef_d, nullptr, sigcoef_d, k1, hi, lo);
+            if (needF && needLap) rc = launch_self<true, false, true>(ctx, fcoef_d, nullptr, sigcoef_d, k1, cm);
+            else if (needF) rc = launch_self<true, false, false>(ctx, fcoef_d, nullptr, sigcoef_d, k1, cm);
+            else rc = launch_self<false, false, true>(ctx, fcoef_d, nullptr, sigcoef_d, k1, cm);
             if (rc == EHD_OK)
-                rc = launch_self<false, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, EHD_STOKES_DL, hi, lo);
+                rc = launch_self<false, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, EHD_STOKES_DL, cm);
         } else if (needU) {
-            rc = launch_self<false, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself, hi, lo);
+            rc = launch_self<false, true, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself, cm);
         } else if (needF && needLap) {
-            rc = launch_self<true, false, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself, hi, lo);
+            rc = launch_self<true, false, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself, cm);
         } else if (needF) {
-            rc = launch_self<true, false, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself, hi, lo);
+            rc = launch_self<true, false, false>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself, cm);
         } else {
-            rc = launch_self<false, false, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself, hi, lo);
+            rc = launch_self<false, false, true>(ctx, fcoef_d, ucoef_d, sigcoef_d, kself, cm);
         }
         return rc;
     };
+    // Overlap mode.  A far field of at most two work items per compute unit
+    // forks whole, before the self-interaction: its blocks take a few CUs
+    // and the self-interaction the rest.  A larger one would hold every CU
+    // until it drains, so it forks as one looping block per CU over a first
+    // share of its items (overlap_share) beside the degree classes that
+    // leave room for such a block (classes_beside_far); the other classes
+    // run before the fork, and the rest of the far field follows on this
+    // stream as an ordinary launch.  Every item is summed as in the serial
+    // order.
+    const long long nvb = far_items(ctx, ctx->far_tpt, ctx->nchunk);
+    const bool whole = ctx->overlap && ctx->nd >= 2 && nvb <= 2LL * ctx->ncu;
+    unsigned beside = 0;
+    long long split = 0;
+    if (whole) {
+        beside = 0xFu;
+        split = nvb;
+    } else if (ctx->overlap && ctx->nd >= 2) {   // one drop: no far interactions, nothing to overlap
+        beside = classes_beside_far(ctx, far_prec, kinds, needF, needU, needLap);
+        split = (long long)std::ceil(overlap_share(ctx, far_prec, beside) * (double)nvb);
+    }
     int rc;
-    if (!ctx->overlap || ctx->nd < 2) {   // one drop: no far interactions, nothing to overlap
-        if ((rc = self_classes(3, 0))) return rc;
+    if (split == 0) {
+        if ((rc = self_classes(0xFu))) return rc;
         ctx->mark(2);
         // 3. far field
         if ((rc = launch_far(ctx, far_prec, kinds, ctx->far_tpt, ctx->nchunk))) return rc;
     } else {
-        // Overlap mode.  A far field of at most two work items per compute
-        // unit forks whole, before the self-interaction: its blocks take a
-        // few CUs and the self-interaction the rest.  A larger one would
-        // hold every CU until it drains.  A p <= 48 block takes nearly all
-        // of a CU's LDS and registers, so nothing runs beside it, while the
-        // smaller classes leave room for one far-field block per CU: after
-        // the p <= 48 class the far field forks as one looping block per CU
-        // over a first share of its items (overlap_share), beside the
-        // smaller classes, and the rest follows them on this stream as an
-        // ordinary launch.
-        // Every item is summed as in the serial order.
-        const long long nvb = far_items(ctx, ctx->far_tpt, ctx->nchunk);
-        const bool whole = nvb <= 2LL * ctx->ncu;
-        const long long split = whole ? nvb : (long long)std::ceil(overlap_share(ctx, far_prec) * (double)nvb);
-        if (!whole && (rc = self_classes(3, 3))) return rc;
+        if (!whole && (rc = self_classes(0xFu & ~beside))) return rc;
         EHD_HIP(ctx, hipEventRecord(ctx->ev_fork, ctx->ls));
         EHD_HIP(ctx, hipStreamWaitEvent(ctx->far_stream, ctx->ev_fork, 0));
         hipStream_t main = ctx->ls;
@@ -3049,7 +3133,7 @@ static int enqueue_evaluation(ehd_ctx* ctx, const double* fcoef_d, const double*
         ctx->ls = main;
         if (rc) return rc;
         EHD_HIP(ctx, hipEventRecord(ctx->ev_join, ctx->far_stream));
-        if ((rc = self_classes(whole ? 3 : 2, 0))) return rc;
+        if ((rc = self_classes(beside))) return rc;
         ctx->mark(2);
         // 3. far field: the rest, then the forked part
         if ((rc = launch_far(ctx, far_prec, kinds, ctx->far_tpt, ctx->nchunk, split, nvb))) return rc;
