@@ -1148,9 +1148,10 @@ __device__ __forceinline__ void far64_block(const double* __restrict__ tx,
                     const double hx = x0[k] - xs, hy = y0[k] - ys, hz = z0[k] - zs;
                     const double r2 = fma(hx, hx, fma(hy, hy, hz * hz));
                     const double ir = rsqrt_newton(r2), ir2 = ir * ir, ir3 = ir * ir2;
-                    double hn = 0.0;
+                    // both double layers carry (h.n) / r^3
+                    double hn3 = 0.0;
                     if constexpr (needN)
-                        hn = fma(hx, j ? NX.y : NX.x, fma(hy, j ? NY.y : NY.x, hz * (j ? NZ.y : NZ.x)));
+                        hn3 = fma(hx, j ? NX.y : NX.x, fma(hy, j ? NY.y : NY.x, hz * (j ? NZ.y : NZ.x))) * ir3;
                     if constexpr (wS) {
                         const double f0 = j ? F0.y : F0.x, f1 = j ? F1.y : F1.x, f2 = j ? F2.y : F2.x;
                         const double hf = fma(hx, f0, fma(hy, f1, hz * f2)) * ir3;
@@ -1161,7 +1162,7 @@ __device__ __forceinline__ void far64_block(const double* __restrict__ tx,
                     if constexpr (wD) {
                         const double hu =
                             fma(hx, j ? U0.y : U0.x, fma(hy, j ? U1.y : U1.x, hz * (j ? U2.y : U2.x)));
-                        const double tq = (hu * hn) * (ir3 * ir2);
+                        const double tq = (hu * ir2) * hn3;
                         a[k][3] = fma(tq, hx, a[k][3]);
                         a[k][4] = fma(tq, hy, a[k][4]);
                         a[k][5] = fma(tq, hz, a[k][5]);
@@ -1169,7 +1170,7 @@ __device__ __forceinline__ void far64_block(const double* __restrict__ tx,
                     if constexpr (needSig) {
                         const double sg = j ? SG.y : SG.x;
                         if constexpr (wSL) a[k][6] = fma(sg, ir, a[k][6]);
-                        if constexpr (wL) a[k][7] = fma(sg * hn, ir3, a[k][7]);
+                        if constexpr (wL) a[k][7] = fma(sg, hn3, a[k][7]);
                         if constexpr (wK)
                             a[k][8] = fma(sg * fma(hx, n0x[k], fma(hy, n0y[k], hz * n0z[k])), ir3, a[k][8]);
                     }
@@ -1263,7 +1264,7 @@ __device__ __forceinline__ void far32_block(const double* __restrict__ tx,
         // Targets at least two drop radii from the drop's centre have
         // |d| <= 2 |x0 - x| for every source x: the FP32 head of d alone
         // then keeps each term's relative error within a few roundings, and
-        // the wave skips the tail (3 of 37 instructions per pair).
+        // the wave skips the tail (3 of 36 instructions per pair).
         const bool tail = !__all(far_all);
         auto pairs = [&](auto with_tail) {
         constexpr bool TAIL = decltype(with_tail)::value;
@@ -1282,8 +1283,8 @@ __device__ __forceinline__ void far32_block(const double* __restrict__ tx,
                     if constexpr (TAIL) { hx += bx[k]; hy += by[k]; hz += bz[k]; }
                     const float r2 = fmaf(hx, hx, fmaf(hy, hy, hz * hz));
                     const float ir = __frsqrt_rn(r2), ir2 = ir * ir, ir3 = ir * ir2;
-                    float hn = 0.0f;
-                    if constexpr (needN) hn = fmaf(hx, NX[j], fmaf(hy, NY[j], hz * NZ[j]));
+                    float hn3 = 0.0f;   // (h.n) / r^3, shared by both double layers
+                    if constexpr (needN) hn3 = fmaf(hx, NX[j], fmaf(hy, NY[j], hz * NZ[j])) * ir3;
                     if constexpr (wS) {
                         const float hf = fmaf(hx, F0[j], fmaf(hy, F1[j], hz * F2[j])) * ir3;
                         a[k][0] = fmaf(hx, hf, fmaf(F0[j], ir, a[k][0]));
@@ -1292,13 +1293,13 @@ __device__ __forceinline__ void far32_block(const double* __restrict__ tx,
                     }
                     if constexpr (wD) {
                         const float hu = fmaf(hx, U0[j], fmaf(hy, U1[j], hz * U2[j]));
-                        const float tq = (hu * hn) * (ir3 * ir2);
+                        const float tq = (hu * ir2) * hn3;
                         a[k][3] = fmaf(tq, hx, a[k][3]);
                         a[k][4] = fmaf(tq, hy, a[k][4]);
                         a[k][5] = fmaf(tq, hz, a[k][5]);
                     }
                     if constexpr (wSL) a[k][6] = fmaf(SG[j], ir, a[k][6]);
-                    if constexpr (wL) a[k][7] = fmaf(SG[j] * hn, ir3, a[k][7]);
+                    if constexpr (wL) a[k][7] = fmaf(SG[j], hn3, a[k][7]);
                     if constexpr (wK)
                         a[k][8] = fmaf(SG[j] * fmaf(hx, n0x[k], fmaf(hy, n0y[k], hz * n0z[k])), ir3, a[k][8]);
                 }
