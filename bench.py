@@ -267,10 +267,10 @@ def time_evaluation(args, torch, E, ctx, s, far_prec, kinds, f, sig, out):
     cls_times = [ctx.self_class_times(i) for i in range(K)]
 
     T = ctx.ntargets
-    overlap = bool(args.overlap and s.ndrops > 1)
     tpt_, nch_ = ctx.far_config()
-    items = -(-T // (256 * tpt_)) * nch_
-    whole = items <= 2 * torch.cuda.get_device_properties(0).multi_processor_count
+    # the library's overlap plan: classes beside a forked far-field share
+    beside, forked = ctx.overlap_plan(kinds, far_prec) if args.overlap else (0, 0)
+    overlap = forked > 0
     kernels = []
     for c, pmax in enumerate(E.DEGREE_CLASSES):
         ms = sum(ct[c] for ct in cls_times) / K
@@ -280,14 +280,14 @@ def time_evaluation(args, torch, E, ctx, s, far_prec, kinds, f, sig, out):
         dense = sum(self_flops_per_drop(int(s.p[d]), int(s.q_self[d]), s.grid_mode) for d in sel)
         if ms > 0 and fl > 0:
             # shared: a forked far-field share runs beside the class
-            shared = overlap and (whole or (pmax < 48 and far_prec == E.FAR_FP32C))
+            shared = overlap and bool(beside >> c & 1)
             kernels.append({"kernel": f"k_self<{pmax}> (singular self-interaction, p <= {pmax}, FP64)",
                             "bound": "alu", "algorithmic_flops": fl, "dense_flops": dense, "avg_ms": ms,
                             "achieved": fl / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS, "shared": shared})
     far_flops = far_interactions(s) * FAR_FLOPS_PER_INTERACTION
     # the far field runs alone in the timed region unless a share of it is
-    # forked beside the self-interaction (the FP32 far field in overlap mode)
-    far_alone = (not overlap) or (far_prec == E.FAR_FP64 and not whole)
+    # forked beside the self-interaction
+    far_alone = not overlap
     name = "k_far32" if far_prec == E.FAR_FP32C else "k_far64"
     far_ms = avg[2] if far_alone else None
     far_src = timing_pass
@@ -328,7 +328,9 @@ def time_evaluation(args, torch, E, ctx, s, far_prec, kinds, f, sig, out):
     ctx.sync()
     return {"dt": dt, "ms_per_step": dt / K * 1e3, "value": T * K / dt, "stage_ms": dict(zip(E.STAGES, avg)),
             "kernels": kernels, "roofline": roof, "far_tile": tile, "far": fo.cpu().numpy(),
-            "kernel_times": timing_pass}
+            "kernel_times": timing_pass,
+            "overlap_plan": {"classes_beside_far": [p for c, p in enumerate(E.DEGREE_CLASSES) if beside >> c & 1],
+                             "far_items_forked": forked}}
 
 
 def bench_eval(args, torch, E, W, dev):
@@ -394,7 +396,7 @@ def bench_eval(args, torch, E, W, dev):
                    "grid": "paper (2p+2 longitudes)" if s.grid_mode == 0 else "2p longitudes",
                    "kinds": "S,D,S_L,L", "far_prec": "fp64" if main_prec == E.FAR_FP64 else "fp32c",
                    "far_interactions": far_interactions(s), "far_tile": r["far_tile"],
-                   "graph": bool(args.graph)},
+                   "overlap_plan": r["overlap_plan"], "graph": bool(args.graph)},
         "stage_ms": r["stage_ms"],
         "roofline": r["roofline"],
         "kernels": r["kernels"],
@@ -405,7 +407,8 @@ def bench_eval(args, torch, E, W, dev):
     if len(runs) > 1:
         r32 = runs[E.FAR_FP32C]
         res["fp32_far"] = {"value": r32["value"], "unit": "target-evals/s", "ms_per_step": r32["ms_per_step"],
-                           "dtype": "f64+f32", "far_tile": r32["far_tile"], "stage_ms": r32["stage_ms"],
+                           "dtype": "f64+f32", "far_tile": r32["far_tile"], "overlap_plan": r32["overlap_plan"],
+                           "stage_ms": r32["stage_ms"],
                            "roofline": r32["roofline"], "kernels": r32["kernels"],
                            "far_error": errors(r32),
                            "error_bound_stated": 1e-6}

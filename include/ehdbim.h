@@ -241,19 +241,30 @@ int ehd_set_graph(ehd_ctx* ctx, int enable);
  * on a second stream of the context, concurrently with the singular
  * self-interaction; results are bitwise the same.  A far field of at most
  * two (target block, chunk) work items per compute unit forks whole before
- * the self-interaction.  A larger one forks after the p <= 48 class (whose
- * blocks leave no room beside them) as one looping block per compute unit
- * over a first share of its items, beside the smaller classes, and the rest
- * is an ordinary launch after them.  The share is the expected time of the
- * smaller classes over that of the far field (0.34 on 64 drops of mixed
- * degree, 0.24 on 256 drops of p = 32) for the FP32 far field, and 0 for
- * the FP64 one, which slows the self-interaction as much as it gains.
- * Measured: 64 drops 136.2 -> 131.9 ms, 256 drops of p = 32 about 4% less,
- * two p = 32 drops 2.10 -> 1.90 ms (FP64 far field 2.25 -> 1.96 ms).  A
- * single drop (no far interactions) keeps the serial order.  Stage times
+ * the self-interaction.  A larger one forks as one looping block per
+ * compute unit over a first share of its items beside the degree classes
+ * whose kernels leave room on a compute unit for one such block (registers
+ * of two self-interaction waves and one far-field wave per SIMD within 512
+ * per lane, LDS of both blocks within the CU's, as the runtime reports them
+ * for the kernels built); the other classes run before the fork and the
+ * rest of the far field is an ordinary launch after them.  The share is
+ * the expected time of those classes over that of the far field for the
+ * FP32 far field, and 0 for the FP64 one, which needs the same FP64 units
+ * and slows the self-interaction as much as it gains; with share 0 the
+ * evaluation keeps the serial order (ehd_overlap_plan reports the plan).
+ * A single drop (no far interactions) keeps the serial order.  Stage times
  * then read: self = until the last class ends (shared with the forked
  * part), far = the rest.  Drops a recorded graph. */
 int ehd_set_overlap(ehd_ctx* ctx, int enable);
+
+/* The overlap plan an evaluation with these kinds (EHD_* mask), far
+ * precision (EHD_FAR_*) and double-layer density (with_u != 0: a separate
+ * u, as ehd_layer_potentials with ucoef) would follow now: *beside = the
+ * degree classes (bit 0: p <= 16 .. bit 3: p <= 48) that run beside the
+ * forked far-field share, *forked = the far-field work items forked (0:
+ * serial order, as always outside overlap mode).  Host query only; errors:
+ * EHD_E_ARG (null pointer, bad mask or precision), EHD_E_STATE (no drops). */
+int ehd_overlap_plan(ehd_ctx* ctx, unsigned kinds, int far_prec, int with_u, unsigned* beside, long long* forked);
 
 /* Far-field tile shape: targets per thread (1 or 2) and number of source
  * chunks (1..16, at most the number of source tiles) the targets' sums are

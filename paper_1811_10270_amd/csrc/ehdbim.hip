@@ -3036,6 +3036,37 @@ static double overlap_share(const ehd_ctx* ctx, int far_prec, unsigned beside)
     return far > 0.0 ? std::min(0.5, small / far) : 0.0;
 }
 
+// Overlap mode.  A far field of at most two work items per compute unit
+// forks whole, before the self-interaction: its blocks take a few CUs and
+// the self-interaction the rest.  A larger one would hold every CU until it
+// drains, so it forks as one looping block per CU over a first share of its
+// items (overlap_share) beside the degree classes that leave room for such
+// a block (classes_beside_far); the other classes run before the fork, and
+// the rest of the far field follows on the main stream as an ordinary
+// launch.  Every item is summed as in the serial order.  split = the number
+// of items forked (0: serial order).
+struct OverlapPlan {
+    long long nvb = 0, split = 0;
+    unsigned beside = 0;
+    bool whole = false;
+};
+static OverlapPlan overlap_plan(ehd_ctx* ctx, int far_prec, unsigned kinds, bool needF, bool needU, bool needLap)
+{
+    OverlapPlan pl;
+    pl.nvb = far_items(ctx, ctx->far_tpt, ctx->nchunk);
+    if (!ctx->overlap || ctx->nd < 2) return pl;   // one drop: no far interactions, nothing to overlap
+    pl.whole = pl.nvb <= 2LL * ctx->ncu;
+    if (pl.whole) {
+        pl.beside = 0xFu;
+        pl.split = pl.nvb;
+    } else {
+        pl.beside = classes_beside_far(ctx, far_prec, kinds, needF, needU, needLap);
+        pl.split = (long long)std::ceil(overlap_share(ctx, far_prec, pl.beside) * (double)pl.nvb);
+        if (pl.split == 0) pl.beside = 0;
+    }
+    return pl;
+}
+
 // The launch sequence of one evaluation, on ctx->ls.
 static int enqueue_evaluation(ehd_ctx* ctx, const double* fcoef_d, const double* ucoef_d,
                               const double* sigcoef_d, unsigned kinds, int far_prec, double* self_out_d,
@@ -3098,26 +3129,10 @@ static int enqueue_evaluation(ehd_ctx* ctx, const double* fcoef_d, const double*
         }
         return rc;
     };
-    // Overlap mode.  A far field of at most two work items per compute unit
-    // forks whole, before the self-interaction: its blocks take a few CUs
-    // and the self-interaction the rest.  A larger one would hold every CU
-    // until it drains, so it forks as one looping block per CU over a first
-    // share of its items (overlap_share) beside the degree classes that
-    // leave room for such a block (classes_beside_far); the other classes
-    // run before the fork, and the rest of the far field follows on this
-    // stream as an ordinary launch.  Every item is summed as in the serial
-    // order.
-    const long long nvb = far_items(ctx, ctx->far_tpt, ctx->nchunk);
-    const bool whole = ctx->overlap && ctx->nd >= 2 && nvb <= 2LL * ctx->ncu;
-    unsigned beside = 0;
-    long long split = 0;
-    if (whole) {
-        beside = 0xFu;
-        split = nvb;
-    } else if (ctx->overlap && ctx->nd >= 2) {   // one drop: no far interactions, nothing to overlap
-        beside = classes_beside_far(ctx, far_prec, kinds, needF, needU, needLap);
-        split = (long long)std::ceil(overlap_share(ctx, far_prec, beside) * (double)nvb);
-    }
+    const OverlapPlan pl = overlap_plan(ctx, far_prec, kinds, needF, needU, needLap);
+    const long long nvb = pl.nvb, split = pl.split;
+    const bool whole = pl.whole;
+    const unsigned beside = pl.beside;
     int rc;
     if (split == 0) {
         if ((rc = self_classes(0xFu))) return rc;
@@ -3248,6 +3263,21 @@ int ehd_set_overlap(ehd_ctx* ctx, int enable)
         EHD_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
     }
     ctx->overlap = enable != 0;
+    return EHD_OK;
+}
+
+int ehd_overlap_plan(ehd_ctx* ctx, unsigned kinds, int far_prec, int with_u, unsigned* beside, long long* forked)
+{
+    if (!ctx || !beside || !forked) return EHD_E_ARG;
+    if (!ctx->nd) EHD_FAIL(ctx, EHD_E_STATE, "no drops set");
+    if (far_prec != EHD_FAR_FP64 && far_prec != EHD_FAR_FP32C) EHD_FAIL(ctx, EHD_E_ARG, "unknown far precision");
+    if (!(kinds & EHD_ALL_KINDS) || (kinds & ~(unsigned)EHD_ALL_KINDS)) EHD_FAIL(ctx, EHD_E_ARG, "bad kinds mask");
+    EHD_HIP(ctx, hipSetDevice(ctx->device));
+    const bool needS = kinds & EHD_STOKES_SL, needD = kinds & EHD_STOKES_DL;
+    const bool needLap = kinds & (EHD_LAP_SL | EHD_LAP_DL | EHD_LAP_DLADJ);
+    const OverlapPlan pl = overlap_plan(ctx, far_prec, kinds, needS || (needD && !with_u), needD && with_u, needLap);
+    *beside = pl.split ? pl.beside : 0u;
+    *forked = pl.split;
     return EHD_OK;
 }
 

@@ -39,7 +39,7 @@ EXPORTED = ("ehd_create", "ehd_destroy", "ehd_last_error", "ehd_grid_dims", "ehd
             "ehd_mlp_num_params", "ehd_mlp_get_params", "ehd_mlp_set_params", "ehd_mlp_get_grads",
             "ehd_mlp_forward", "ehd_mlp_backward", "ehd_mlp_mse", "ehd_mlp_adam", "ehd_area_weights",
             "ehd_update_shape", "ehd_surfactant_terms", "ehd_evolve_step", "ehd_evolve", "ehd_set_near",
-            "ehd_near_pairs", "ehd_set_overlap", "ehd_solve_En_noalloc", "ehd_surfactant_guess",
+            "ehd_near_pairs", "ehd_set_overlap", "ehd_overlap_plan", "ehd_solve_En_noalloc", "ehd_surfactant_guess",
             "ehd_learned_features")
 STAGES = ("densities", "self", "far", "combine")
 DEGREE_CLASSES = (16, 24, 32, 48)   # largest p of each self-interaction kernel class
@@ -126,6 +126,7 @@ def load(path: str = LIB_PATH):
     lib.ehd_explicit_step.argtypes = [vp, C.POINTER(StepParams), vp, vp, vp, vp, ip]
     lib.ehd_area_weights.argtypes = [vp, vp]
     lib.ehd_set_overlap.argtypes = [vp, C.c_int]
+    lib.ehd_overlap_plan.argtypes = [vp, C.c_uint, C.c_int, C.c_int, C.POINTER(C.c_uint), C.POINTER(C.c_longlong)]
     lib.ehd_set_near.argtypes = [vp, C.c_double, C.c_double, C.c_int, C.c_int]
     lib.ehd_near_pairs.argtypes = [vp, C.POINTER(C.c_longlong)]
     lib.ehd_update_shape.argtypes = [vp, vp]
@@ -324,6 +325,13 @@ class Context:
     def set_overlap(self, enable: bool):
         """Far field on a second stream, concurrent with the self-interaction (ehd_set_overlap)."""
         self._check(self._lib.ehd_set_overlap(self._h, 1 if enable else 0))
+
+    def overlap_plan(self, kinds: int, far_prec: int, with_u: bool = False):
+        """(classes beside the forked far-field share as a bit mask, forked
+        far-field work items) of an evaluation now (ehd_overlap_plan)."""
+        m, n = C.c_uint(0), C.c_longlong(0)
+        self._check(self._lib.ehd_overlap_plan(self._h, kinds, far_prec, 1 if with_u else 0, C.byref(m), C.byref(n)))
+        return int(m.value), int(n.value)
 
     def set_graph(self, enable: bool):
         self._check(self._lib.ehd_set_graph(self._h, 1 if enable else 0))

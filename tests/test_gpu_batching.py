@@ -271,3 +271,46 @@ def test_bench_graph_configuration_batched(E):
             torch.cuda.synchronize()
         ctx.set_graph(False)
     ctx.close()
+
+
+def test_overlap_plan(E):
+    """The overlap plan the library reports: serial order outside overlap
+    mode, for one drop and for the FP64 far field of a large workload; a
+    tiny far field forks whole; the FP32 far field of the 64-drop workload
+    never forks beside the p <= 48 class, forks exactly when some class
+    runs beside it, and the evaluation it plans gives the serial bits."""
+    import torch
+    big = W.batched_suspension(seed=3)
+    ctx, f, sg, dev = _setup(E, big)
+    assert ctx.overlap_plan(E.ALL_KINDS, E.FAR_FP32C) == (0, 0)
+    ctx.set_overlap(True)
+    assert ctx.overlap_plan(E.METRIC_KINDS, E.FAR_FP64) == (0, 0)
+    present = 0
+    for c, pmax in enumerate(E.DEGREE_CLASSES):
+        lo = E.DEGREE_CLASSES[c - 1] if c else 0
+        present |= int(any(lo < int(p) <= pmax for p in big.p)) << c
+    for kinds, with_u in ((E.METRIC_KINDS, False), (E.ALL_KINDS, True), (E.LAP_SL, False)):
+        beside, forked = ctx.overlap_plan(kinds, E.FAR_FP32C, with_u)
+        assert not beside & 8 and beside & ~present == 0, (kinds, beside)
+        assert (forked > 0) == (beside != 0), (kinds, beside, forked)
+    T = ctx.ntargets
+    outs = []
+    for ov in (False, True):
+        ctx.set_overlap(ov)
+        so = torch.zeros(8, T, dtype=torch.float64, device=dev)
+        fo = torch.zeros_like(so)
+        ctx.layer_potentials(f, None, sg, E.METRIC_KINDS, E.FAR_FP32C, so, fo)
+        ctx.sync()
+        outs.append((so, fo))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    ctx.set_overlap(False)
+    ctx.close()
+    for s, whole in ((W.single_drop(16, seed=1), False), (W.two_drops(16, seed=4, gap=0.2), True)):
+        ctx, f, sg, dev = _setup(E, s)
+        ctx.set_overlap(True)
+        ctx.set_far_config(2, 1)
+        for prec in (E.FAR_FP32C, E.FAR_FP64):
+            beside, forked = ctx.overlap_plan(E.METRIC_KINDS, prec)
+            assert (forked > 0) == whole and (beside != 0) == whole, (s.ndrops, prec, beside, forked)
+        ctx.set_overlap(False)
+        ctx.close()
