@@ -99,3 +99,14 @@ def test_json_line_fields():
     cb = b["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0 and "8 random targets" in cb["sample"]
     assert cb["one_core"]["cores"] == 1 and cb["one_core"]["value"] > 0 and cb["cpu_model"]
+
+
+def test_kernel_hash_covers_the_device_code():
+    """The traffic table is keyed to the device code only: the hash stops at
+    the one host-side banner of the library source."""
+    path = os.path.join(ROOT, "paper_1811_10270_amd", "csrc", "ehdbim.hip")
+    text = open(path, "rb").read()
+    assert text.count(b"\n// Host side\n") == 1
+    import hashlib
+    cut = text.find(b"\n// Host side\n")
+    assert bench.kernel_source_sha256() == hashlib.sha256(text[:cut]).hexdigest()
