@@ -3057,7 +3057,8 @@ static OverlapPlan overlap_plan(ehd_ctx* ctx, int far_prec, unsigned kinds, bool
     if (!ctx->overlap || ctx->nd < 2) return pl;   // one drop: no far interactions, nothing to overlap
     pl.whole = pl.nvb <= 2LL * ctx->ncu;
     if (pl.whole) {
-        pl.beside = 0xFu;
+        for (int c = 0; c < 4; ++c)
+            if (!ctx->cls_drops[c].empty()) pl.beside |= 1u << c;
         pl.split = pl.nvb;
     } else {
         pl.beside = classes_beside_far(ctx, far_prec, kinds, needF, needU, needLap);
@@ -3132,7 +3133,7 @@ static int enqueue_evaluation(ehd_ctx* ctx, const double* fcoef_d, const double*
     const OverlapPlan pl = overlap_plan(ctx, far_prec, kinds, needF, needU, needLap);
     const long long nvb = pl.nvb, split = pl.split;
     const bool whole = pl.whole;
-    const unsigned beside = pl.beside;
+    const unsigned beside = whole ? 0xFu : pl.beside;
     int rc;
     if (split == 0) {
         if ((rc = self_classes(0xFu))) return rc;
