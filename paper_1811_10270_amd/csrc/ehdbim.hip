@@ -111,15 +111,16 @@ __device__ __forceinline__ double rsqrt_nr(double x)
     return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
-// 1/sqrt(x) in FP64 with one Newton step: y (1 + e/2), e = 1 - x y^2, from
-// the hardware estimate; relative error about 3 e^2 / 8 (a few 1e-15), one
-// instruction fewer than rsqrt_nr.  For the far-field sums, whose terms are
-// far from any cancellation at that level.
-__device__ __forceinline__ double rsqrt_newton(double x)
+// 2/sqrt(x) in FP64 with one Newton step from the hardware estimate y:
+// y (3 - x y^2), relative error about 3 e^2 / 8 with e = 1 - x y^2 (a few
+// 1e-15).  Twice the reciprocal square root spares the step's halving (three
+// instructions instead of four); the far-field sums take the powers of two
+// out once per tile.  For those sums, whose terms are far from any
+// cancellation at that level.
+__device__ __forceinline__ double rsqrt2_newton(double x)
 {
     const double y = __builtin_amdgcn_rsq(x);
-    const double e = fma(-(x * y), y, 1.0);
-    return fma(y * e, 0.5, y);
+    return y * fma(-(x * y), y, 3.0);
 }
 
 template <typename T>
@@ -1091,7 +1092,11 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
 // ---------------------------------------------------------------------------
 // FP64 far field: as the FP32 kernel below (kinds a template parameter,
 // sources read two at a time as double2 broadcasts from each LDS record
-// row), with absolute coordinates and plain FP64 sums.
+// row), with absolute coordinates and plain FP64 sums.  The pair terms use
+// 2/r and its powers (rsqrt2_newton); each output's power of two, and the
+// double layer's -6, multiply the tile sums, and the Stokes single layer
+// keeps its f/r and r^-3 parts in separate tile sums (2 and 8 times the
+// terms).
 template <int TPT, unsigned KM>
 __device__ __forceinline__ void far64_block(const double* __restrict__ tx,
                                                     const double* __restrict__ tnrm,
@@ -1130,9 +1135,11 @@ __device__ __forceinline__ void far64_block(const double* __restrict__ tx,
         const int sd = tile_drop[tile];
         bool other = false;   // some target of this thread is not on the tile's drop
         for (int k = 0; k < TPT; ++k) other = other || (sd != myd[k]);
-        double a[TPT][9];
-        for (int k = 0; k < TPT; ++k)
+        double a[TPT][9], b[TPT][3];
+        for (int k = 0; k < TPT; ++k) {
             for (int c = 0; c < 9; ++c) a[k][c] = 0.0;
+            for (int c = 0; c < 3; ++c) b[k][c] = 0.0;
+        }
         for (int q2 = 0; q2 < (other ? kTile / 2 : 0); ++q2) {
             const double2 X = sm[0][q2], Y = sm[1][q2], Z = sm[2][q2];
             double2 NX, NY, NZ, F0, F1, F2, U0, U1, U2, SG;
@@ -1147,7 +1154,8 @@ __device__ __forceinline__ void far64_block(const double* __restrict__ tx,
                 for (int k = 0; k < TPT; ++k) {
                     const double hx = x0[k] - xs, hy = y0[k] - ys, hz = z0[k] - zs;
                     const double r2 = fma(hx, hx, fma(hy, hy, hz * hz));
-                    const double ir = rsqrt_newton(r2), ir2 = ir * ir, ir3 = ir * ir2;
+                    // 2/r, 4/r^2, 8/r^3
+                    const double ir = rsqrt2_newton(r2), ir2 = ir * ir, ir3 = ir * ir2;
                     // both double layers carry (h.n) / r^3
                     double hn3 = 0.0;
                     if constexpr (needN)
@@ -1155,9 +1163,12 @@ __device__ __forceinline__ void far64_block(const double* __restrict__ tx,
                     if constexpr (wS) {
                         const double f0 = j ? F0.y : F0.x, f1 = j ? F1.y : F1.x, f2 = j ? F2.y : F2.x;
                         const double hf = fma(hx, f0, fma(hy, f1, hz * f2)) * ir3;
-                        a[k][0] = fma(hx, hf, fma(f0, ir, a[k][0]));
-                        a[k][1] = fma(hy, hf, fma(f1, ir, a[k][1]));
-                        a[k][2] = fma(hz, hf, fma(f2, ir, a[k][2]));
+                        a[k][0] = fma(f0, ir, a[k][0]);
+                        a[k][1] = fma(f1, ir, a[k][1]);
+                        a[k][2] = fma(f2, ir, a[k][2]);
+                        b[k][0] = fma(hx, hf, b[k][0]);
+                        b[k][1] = fma(hy, hf, b[k][1]);
+                        b[k][2] = fma(hz, hf, b[k][2]);
                     }
                     if constexpr (wD) {
                         const double hu =
@@ -1179,7 +1190,12 @@ __device__ __forceinline__ void far64_block(const double* __restrict__ tx,
         }
         for (int k = 0; k < TPT; ++k) {
             if (sd == myd[k]) continue;      // own drop: tile not counted
-            for (int c = 0; c < 9; ++c) acc[k][c] += (c >= 3 && c < 6) ? -6.0 * a[k][c] : a[k][c];
+            // powers of two of 2/r: S 2 and 8, D 32 (with its -6), S_L 2, L and K* 8
+            for (int c = 0; c < 3; ++c) acc[k][c] += fma(0.125, b[k][c], 0.5 * a[k][c]);
+            for (int c = 3; c < 6; ++c) acc[k][c] += -0.1875 * a[k][c];
+            acc[k][6] += 0.5 * a[k][6];
+            acc[k][7] += 0.125 * a[k][7];
+            acc[k][8] += 0.125 * a[k][8];
         }
         __syncthreads();
     }
