@@ -441,12 +441,13 @@ __global__ void k_src_dens(const double* __restrict__ synf, const double* __rest
 // Singular self-interaction, one block per target (paper Sec. 2.1,
 // eq. mod_weights and the rotation of the target to the north pole).
 //   1. rotated coefficients c'_{nm'} = sum_m d^n_{m m'}(theta_t) e^{i m phi_t} c_nm
-//      of every field, in the real form of tables.h, into LDS;
-//   2. for each latitude i of the rotated degree-q grid:
+//      of every field, in the real form of tables.h, into LDS (vector ALU),
+//      then into registers as the B operand of step 2a;
+//   2. for each block of 8 latitudes t_i of the rotated degree-q grid:
 //      a. Legendre sums G_f(m) = sum_n Pbar_n^m(t_i) c'_f(n,m) (and the theta
-//         derivative table for x) on the vector ALU, written as real
-//         Fourier coefficients (cos / sin of m phi) of every grid quantity
-//         (x, x_theta, x_phi / sin theta, densities) into LDS;
+//         derivative table for x) as FP64 MFMA chains over the degrees n,
+//         written as real Fourier coefficients (cos / sin of m phi) of every
+//         grid quantity (x, x_theta, x_phi / sin theta, densities) into LDS;
 //      b. longitude sums as FP64 MFMA products: the four nodes phi_l,
 //         pi - phi_l, pi + phi_l and 2 pi - phi_l share the four partial
 //         sums over (even m, odd m) x (cos, sin) terms, so four GEMMs of a
