@@ -363,6 +363,16 @@ def bench_eval(args, torch, E, W, dev):
     f = torch.from_numpy(s.fcoef).to(dev)
     sig = torch.from_numpy(s.sigcoef).to(dev)
     out = torch.empty(len(rows), T, dtype=torch.float64, device=dev)
+    # the self-interaction's Legendre prefetch batch per degree class (one
+    # choice for both far-field precisions: the self-interaction is the same)
+    self_tile = {str(pm): ctx.self_config(c) for c, pm in enumerate(E.DEGREE_CLASSES)}
+    self_tile = {"prefetch": self_tile, "autotuned": False}
+    if not args.no_autotune:
+        from paper_1811_10270_amd import autotune
+        best, timings, cached = autotune.autotune_self(ctx, s.p, s.q_self, s.grid_mode, f, sig)
+        self_tile = {"prefetch": {str(k): v for k, v in best.items()}, "autotuned": True, "from_cache": cached,
+                     "timings_ms": {str(k): v for k, v in timings.items()}}
+    log("self prefetch", self_tile)
     runs = {prec: time_evaluation(args, torch, E, ctx, s, prec, kinds, f, sig, out) for prec in precs}
     ctx.close()
 
@@ -410,7 +420,7 @@ def bench_eval(args, torch, E, W, dev):
                    "grid": "paper (2p+2 longitudes)" if s.grid_mode == 0 else "2p longitudes",
                    "kinds": "S,D,S_L,L", "far_prec": "fp64" if main_prec == E.FAR_FP64 else "fp32c",
                    "far_interactions": far_interactions(s), "far_tile": r["far_tile"],
-                   "overlap_plan": r["overlap_plan"], "graph": bool(args.graph)},
+                   "overlap_plan": r["overlap_plan"], "self_tile": self_tile, "graph": bool(args.graph)},
         "stage_ms": r["stage_ms"],
         "roofline": r["roofline"],
         "kernels": r["kernels"],

@@ -281,6 +281,27 @@ int ehd_get_far_config(const ehd_ctx* ctx, int* targets_per_thread, int* nchunk)
 int ehd_time_far(ehd_ctx* ctx, int far_prec, unsigned kinds, int targets_per_thread, int nchunk, int reps,
                  double* ms);
 
+/* Self-interaction tuning (the per-target singular rule of Sec. 2.1,
+ * eq. mod_weights, batched by degree class).  The class kernels stream the
+ * Legendre tables of the rotated grid in prefetch batches; each class is
+ * built with three batch sizes for the field set x, f, sigma (the kinds S, D,
+ * S_L, L with u = f, and the E_n and velocity solves' field sets use the
+ * default).  ehd_self_config_candidates (host only, no device needed) lists
+ * them for class cls (0: p <= 16, 1: p <= 24, 2: p <= 32, 3: p <= 48), the
+ * default first: *n = 3, pf[3].  ehd_set_self_config selects one for a class
+ * of the context (0: the default; another value: EHD_E_ARG) and drops a
+ * recorded graph when it changes; results are bitwise the same for every
+ * choice (only the load schedule differs).  ehd_get_self_config returns the
+ * batch in effect.  ehd_time_self: mean milliseconds of `reps` launches
+ * (after one warm-up) of class cls with batch pf (restored afterwards) on the
+ * kinds S, D, S_L, L from the device coefficients fcoef_d and sigcoef_d
+ * (layout of ehd_layer_potentials), HIP events, synchronous; 0 for a class
+ * without drops.  Overwrites the self-interaction's internal sums only. */
+int ehd_self_config_candidates(int cls, int* pf, int* n);
+int ehd_set_self_config(ehd_ctx* ctx, int cls, int pf);
+int ehd_get_self_config(const ehd_ctx* ctx, int cls, int* pf);
+int ehd_time_self(ehd_ctx* ctx, int cls, int pf, const double* fcoef_d, const double* sigcoef_d, int reps, double* ms);
+
 /* Galerkin solvers (Sec. 2, eq. galerkin_En and eq. BIM_galerkin) by
  * restarted GMRES in FP64 on the device.  Each iteration is one
  * ehd_layer_potentials call (far field in far_prec) and one ehd_analyze.

@@ -1,4 +1,4 @@
-"""Far-field tile-shape autotuner.
+"""Far-field tile-shape and self-interaction prefetch autotuners.
 
 Times every candidate shape (targets per thread x number of source chunks)
 of the far-field kernel on the context's own workload, for the kinds the
@@ -9,6 +9,11 @@ than LONG_MS) and ranked by its median.  The
 fastest is kept in the context and cached in a JSON file keyed by device
 architecture, library build, workload signature, kinds and precision, so a
 rebuilt library never reuses a stale choice.
+
+The self-interaction autotuner does the same for the Legendre prefetch
+batch of each degree class present (ehd_time_self over the batches the
+library builds for the class), keyed by device, library build, class and the
+(p, q_self) mix of the class's drops.
 """
 from __future__ import annotations
 
@@ -96,3 +101,55 @@ def autotune_far(ctx, p, q_far, grid_mode: int, far_prec: int, kinds: int = 31, 
         except OSError:
             pass
     return tpt, nch, timings, False
+
+
+def self_signature(ctx, cls: int, pq, grid_mode: int) -> str:
+    prop = torch.cuda.get_device_properties(ctx.device)
+    arch = getattr(prop, "gcnArchName", prop.name)
+    return (f"{arch}|{prop.multi_processor_count}|lib{library_hash()}|self{cls}|"
+            f"{sorted(set(pq))}|grid{int(grid_mode)}")
+
+
+def autotune_self(ctx, p, q_self, grid_mode: int, fcoef, sigcoef, reps: int = 3,
+                  cache_path: str | None = None, use_cache: bool = True):
+    """Pick and set the fastest Legendre prefetch batch of every degree class
+    that has drops; returns ({class pmax: batch}, {class pmax: {batch: median
+    ms}}, from_cache) (from_cache: every class came from the cache)."""
+    from . import ehdbim
+    path = cache_path or default_cache_path()
+    cache = _load(path) if use_cache else {}
+    best, timings, cached, new = {}, {}, True, {}
+    lo = 0
+    for cls, pmax in enumerate(ehdbim.DEGREE_CLASSES):
+        pq = [(int(a), int(b)) for a, b in zip(p, q_self) if lo < int(a) <= pmax]
+        lo = pmax
+        if not pq:
+            continue
+        key = self_signature(ctx, cls, pq, grid_mode)
+        if key in cache:
+            pf = int(cache[key]["best"])
+            ctx.set_self_config(cls, pf)
+            best[pmax], timings[pmax] = pf, cache[key]["timings"]
+            continue
+        cached = False
+        t = {}
+        for pf in ehdbim.self_config_candidates(cls):
+            ms = [ctx.time_self(cls, pf, fcoef, sigcoef, 1)]
+            while len(ms) < reps and ms[0] < LONG_MS:
+                ms.append(ctx.time_self(cls, pf, fcoef, sigcoef, 1))
+            t[str(pf)] = statistics.median(ms)
+        pf = int(min(t, key=t.get))
+        ctx.set_self_config(cls, pf)
+        best[pmax], timings[pmax] = pf, t
+        new[key] = {"best": pf, "timings": t}
+    if use_cache and new:
+        cache = _load(path)
+        cache.update(new)
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            with open(path + ".tmp", "w") as fh:
+                json.dump(cache, fh, indent=1)
+            os.replace(path + ".tmp", path)
+        except OSError:
+            pass
+    return best, timings, cached and bool(best)

@@ -549,6 +549,12 @@ struct SelfClass {
     static constexpr bool ROW0 = PMAX == 16 || PMAX == 32;
     // rotation loop unroll (measured: 2 for p <= 24, 4 above)
     static constexpr int RU = PMAX <= 24 ? 2 : 4;
+    // Legendre A fragments per prefetch batch: the default (measured best:
+    // 5 for p <= 48, 3 for p <= 32, 2 below) and the two others built for the
+    // field set x, f, sigma, among which the self-interaction autotuner picks
+    static constexpr int PF = PMAX == 48 ? 5 : PMAX == 32 ? 3 : 2;
+    static constexpr int PF_ALT0 = PMAX == 48 ? 3 : PMAX == 32 ? 2 : 3;
+    static constexpr int PF_ALT1 = PMAX == 48 ? 6 : PMAX == 32 ? 5 : 4;
 };
 
 // Legendre k-steps per wave of the degree class of p (table stride per wave).
@@ -562,7 +568,7 @@ static inline bool self_row0(int p)
     return p <= 16 ? SelfClass<16>::ROW0 : p <= 24 ? SelfClass<24>::ROW0 : p <= 32 ? SelfClass<32>::ROW0 : SelfClass<48>::ROW0;
 }
 
-template <int PMAX, bool HF, bool HU, bool HS>
+template <int PMAX, bool HF, bool HU, bool HS, int PFT = 0>
 __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     const DropInfo* __restrict__ drops, const LegTab* __restrict__ legs,
     const WigTab* __restrict__ wigs, const int* __restrict__ order, const int* __restrict__ tdrop,
@@ -794,9 +800,8 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     };
 
     const int m_first = wv <= p ? wv : p + 1;
-    // Legendre fragments per prefetch batch (measured best per class:
-    // 5 for p <= 48, 3 for p <= 32, 2 below; 6 for all cost p <= 32 6%)
-    constexpr int PF = PMAX == 48 ? 5 : PMAX == 32 ? 3 : 2;
+    // Legendre fragments per prefetch batch (PFT, else the class default)
+    constexpr int PF = PFT > 0 ? PFT : SC::PF;
     constexpr int NBATCH = (SC::KW + PF - 1) / PF;
     for (int b = 0; b < nblk; ++b) {
         // 3a. Legendre sums on MFMA: per degree column of this wave, a chain
@@ -1765,6 +1770,7 @@ struct ehd_ctx {
     double* d_partial = nullptr;     // [kMaxChunks][9][T]
     int nchunk = 1;                  // far field: source chunks (grid y)
     int far_tpt = 1;                 // far field: targets per thread
+    int self_pf[4] = {0, 0, 0, 0};   // self-interaction: Legendre prefetch batch per degree class (0: default)
 
     // graph mode: the launch sequence of ehd_layer_potentials recorded once
     // per argument set and replayed
@@ -1972,6 +1978,22 @@ static size_t self_lds_bytes(const ehd_ctx* ctx, const std::vector<int>& drops, 
     return best;
 }
 
+// The self-interaction kernel of degree class PMAX for a field set and a
+// Legendre prefetch batch (pf 0: the class default; other batches are built
+// for the field set x, f, sigma only).
+template <int PMAX, bool HF, bool HU, bool HS>
+static const void* self_kernel_pf(int pf)
+{
+    using SC = SelfClass<PMAX>;
+    if constexpr (HF && !HU && HS) {
+        if (pf == SC::PF_ALT0) return (const void*)k_self<PMAX, HF, HU, HS, SC::PF_ALT0>;
+        if (pf == SC::PF_ALT1) return (const void*)k_self<PMAX, HF, HU, HS, SC::PF_ALT1>;
+    }
+    return (const void*)k_self<PMAX, HF, HU, HS>;
+}
+
+// Launch of one degree class's self-interaction with the context's prefetch
+// batch for the class (ehd_set_self_config), over the targets of the class.
 template <int PMAX, bool HF, bool HU, bool HS>
 static int launch_self_class(ehd_ctx* ctx, int cls, const double* f, const double* u, const double* s,
                              unsigned kinds)
@@ -1983,15 +2005,21 @@ static int launch_self_class(ehd_ctx* ctx, int cls, const double* f, const doubl
     const size_t lds_static = (size_t)SelfClass<PMAX>::NW * 9 * 8;   // reduction scratch
     if (lds + lds_static > (size_t)ctx->max_lds)
         EHD_FAIL(ctx, EHD_E_SHAPE, "self-interaction needs %zu bytes of LDS (limit %d)", lds, ctx->max_lds);
-    if (lds > 65536)
-        EHD_HIP(ctx, hipFuncSetAttribute((const void*)k_self<PMAX, HF, HU, HS>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const void* fn = self_kernel_pf<PMAX, HF, HU, HS>(ctx->self_pf[cls]);
+    if (lds > 65536) EHD_HIP(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     ctx->mark_class(cls, 0);
-    hipLaunchKernelGGL((k_self<PMAX, HF, HU, HS>), dim3((unsigned)count), dim3(SelfClass<PMAX>::NT), lds,
-                       ctx->ls,
-                       ctx->d_info, ctx->d_legs, ctx->d_wigs, ctx->d_order + ctx->cls_off[cls], ctx->d_tdrop,
-                       ctx->d_x, f, u, s, ctx->d_tx, ctx->d_tn, ctx->T, kinds, ctx->d_raw);
-    EHD_HIP(ctx, hipGetLastError());
+    const DropInfo* a0 = ctx->d_info;
+    const LegTab* a1 = ctx->d_legs;
+    const WigTab* a2 = ctx->d_wigs;
+    const int* a3 = ctx->d_order + ctx->cls_off[cls];
+    const int* a4 = ctx->d_tdrop;
+    const double* a5 = ctx->d_x;
+    const double *a9 = ctx->d_tx, *a10 = ctx->d_tn;
+    long long a11 = ctx->T;
+    double* a13 = ctx->d_raw;
+    void* args[] = {(void*)&a0, (void*)&a1, (void*)&a2, (void*)&a3, (void*)&a4, (void*)&a5, (void*)&f, (void*)&u,
+                    (void*)&s, (void*)&a9, (void*)&a10, (void*)&a11, (void*)&kinds, (void*)&a13};
+    EHD_HIP(ctx, hipLaunchKernel(fn, dim3((unsigned)count), dim3(SelfClass<PMAX>::NT), args, lds, ctx->ls));
     ctx->mark_class(cls, 1);
     return EHD_OK;
 }
@@ -2008,19 +2036,20 @@ static int launch_self(ehd_ctx* ctx, const double* f, const double* u, const dou
     return rc;
 }
 
-// The self-interaction kernel of degree class PMAX for the fields it holds.
+// The self-interaction kernel of degree class PMAX for the fields it holds
+// and a prefetch batch.
 template <int PMAX>
-static const void* self_kernel(bool HF, bool HU, bool HS)
+static const void* self_kernel(bool HF, bool HU, bool HS, int pf)
 {
-    if (HU) return (const void*)k_self<PMAX, false, true, false>;
-    if (HF && HS) return (const void*)k_self<PMAX, true, false, true>;
-    if (HF) return (const void*)k_self<PMAX, true, false, false>;
-    return (const void*)k_self<PMAX, false, false, true>;
+    if (HU) return self_kernel_pf<PMAX, false, true, false>(pf);
+    if (HF && HS) return self_kernel_pf<PMAX, true, false, true>(pf);
+    if (HF) return self_kernel_pf<PMAX, true, false, false>(pf);
+    return self_kernel_pf<PMAX, false, false, true>(pf);
 }
-static const void* self_kernel_of_class(int cls, bool HF, bool HU, bool HS)
+static const void* self_kernel_of_class(int cls, bool HF, bool HU, bool HS, int pf)
 {
-    return cls == 0 ? self_kernel<16>(HF, HU, HS) : cls == 1 ? self_kernel<24>(HF, HU, HS)
-           : cls == 2 ? self_kernel<32>(HF, HU, HS) : self_kernel<48>(HF, HU, HS);
+    return cls == 0 ? self_kernel<16>(HF, HU, HS, pf) : cls == 1 ? self_kernel<24>(HF, HU, HS, pf)
+           : cls == 2 ? self_kernel<32>(HF, HU, HS, pf) : self_kernel<48>(HF, HU, HS, pf);
 }
 
 // FP64 far-field launchers, one per (targets per thread, kinds mask).
@@ -3017,7 +3046,8 @@ static unsigned classes_beside_far(ehd_ctx* ctx, int far_prec, unsigned kinds, b
         if (ctx->cls_drops[c].empty()) continue;
         bool fits = true;
         for (int i = 0; i < nv; ++i) {
-            const ehd_ctx::KernRes sr = kernel_res(ctx, self_kernel_of_class(c, v[i].hf, v[i].hu, v[i].hs));
+            const ehd_ctx::KernRes sr =
+                kernel_res(ctx, self_kernel_of_class(c, v[i].hf, v[i].hu, v[i].hs, ctx->self_pf[c]));
             const int nf = 3 + (v[i].hf ? 3 : 0) + (v[i].hu ? 3 : 0) + (v[i].hs ? 1 : 0);
             const size_t lds = self_lds_bytes(ctx, ctx->cls_drops[c], nf) + (size_t)sr.lds + (size_t)fr.lds;
             fits = fits && self_waves * sr.vgpr + far_waves * fr.vgpr <= 512 && lds <= (size_t)ctx->max_lds;
@@ -3349,6 +3379,87 @@ int ehd_time_far(ehd_ctx* ctx, int far_prec, unsigned kinds, int targets_per_thr
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
+}
+
+// Self-interaction prefetch batches built per degree class: the default
+// first, then the two alternatives (field set x, f, sigma only).
+static void self_pf_candidates(int cls, int* pf)
+{
+    switch (cls) {
+    case 0: pf[0] = SelfClass<16>::PF; pf[1] = SelfClass<16>::PF_ALT0; pf[2] = SelfClass<16>::PF_ALT1; break;
+    case 1: pf[0] = SelfClass<24>::PF; pf[1] = SelfClass<24>::PF_ALT0; pf[2] = SelfClass<24>::PF_ALT1; break;
+    case 2: pf[0] = SelfClass<32>::PF; pf[1] = SelfClass<32>::PF_ALT0; pf[2] = SelfClass<32>::PF_ALT1; break;
+    default: pf[0] = SelfClass<48>::PF; pf[1] = SelfClass<48>::PF_ALT0; pf[2] = SelfClass<48>::PF_ALT1; break;
+    }
+}
+
+int ehd_self_config_candidates(int cls, int* pf, int* n)
+{
+    if (cls < 0 || cls > 3 || !pf || !n) return EHD_E_ARG;
+    self_pf_candidates(cls, pf);
+    *n = 3;
+    return EHD_OK;
+}
+
+int ehd_set_self_config(ehd_ctx* ctx, int cls, int pf)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (cls < 0 || cls > 3) EHD_FAIL(ctx, EHD_E_ARG, "degree class must be 0..3");
+    int c[3];
+    self_pf_candidates(cls, c);
+    if (pf != 0 && pf != c[0] && pf != c[1] && pf != c[2])
+        EHD_FAIL(ctx, EHD_E_ARG, "prefetch batch %d is not built for class %d (0, %d, %d or %d)", pf, cls, c[0], c[1],
+                 c[2]);
+    const int eff = pf == c[0] ? 0 : pf;
+    if (ctx->self_pf[cls] != eff) {
+        if (ctx->stream) EHD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        ctx->drop_graph();
+        ctx->self_pf[cls] = eff;
+    }
+    return EHD_OK;
+}
+
+int ehd_get_self_config(const ehd_ctx* ctx, int cls, int* pf)
+{
+    if (!ctx || cls < 0 || cls > 3 || !pf) return EHD_E_ARG;
+    int c[3];
+    self_pf_candidates(cls, c);
+    *pf = ctx->self_pf[cls] ? ctx->self_pf[cls] : c[0];
+    return EHD_OK;
+}
+
+int ehd_time_self(ehd_ctx* ctx, int cls, int pf, const double* fcoef_d, const double* sigcoef_d, int reps, double* ms)
+{
+    if (!ctx) return EHD_E_ARG;
+    if (!ctx->nd) EHD_FAIL(ctx, EHD_E_STATE, "ehd_set_drops has not been called");
+    if (!ms || !fcoef_d || !sigcoef_d || reps < 1 || reps > 1000) EHD_FAIL(ctx, EHD_E_ARG, "invalid arguments");
+    if (cls < 0 || cls > 3) EHD_FAIL(ctx, EHD_E_ARG, "degree class must be 0..3");
+    const int keep = ctx->self_pf[cls];
+    int rc = ehd_set_self_config(ctx, cls, pf);
+    if (rc) return rc;
+    *ms = 0.0;
+    if (ctx->cls_off[cls + 1] == ctx->cls_off[cls]) return ehd_set_self_config(ctx, cls, keep);
+    EHD_HIP(ctx, hipSetDevice(ctx->device));
+    hipEvent_t e0, e1;
+    EHD_HIP(ctx, hipEventCreate(&e0));
+    EHD_HIP(ctx, hipEventCreate(&e1));
+    ctx->ls = ctx->stream;
+    const unsigned kinds = EHD_STOKES_SL | EHD_STOKES_DL | EHD_LAP_SL | EHD_LAP_DL;
+    const unsigned cm = 1u << cls;
+    rc = launch_self<true, false, true>(ctx, fcoef_d, nullptr, sigcoef_d, kinds, cm);   // warm-up
+    if (!rc) {
+        (void)hipEventRecord(e0, ctx->stream);
+        for (int r = 0; r < reps && !rc; ++r) rc = launch_self<true, false, true>(ctx, fcoef_d, nullptr, sigcoef_d, kinds, cm);
+        (void)hipEventRecord(e1, ctx->stream);
+        (void)hipEventSynchronize(e1);
+        float t = 0.0f;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        *ms = t / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const int rc2 = ehd_set_self_config(ctx, cls, keep == 0 ? 0 : keep);
+    return rc ? rc : rc2;
 }
 
 int ehd_surface(ehd_ctx* ctx, int ng, const double* gcoef_d, double* H_d, double* grad_d, double* lap_d)

@@ -39,7 +39,7 @@ EXPORTED = ("ehd_create", "ehd_destroy", "ehd_last_error", "ehd_grid_dims", "ehd
             "ehd_mlp_num_params", "ehd_mlp_get_params", "ehd_mlp_set_params", "ehd_mlp_get_grads",
             "ehd_mlp_forward", "ehd_mlp_backward", "ehd_mlp_mse", "ehd_mlp_adam", "ehd_area_weights",
             "ehd_update_shape", "ehd_surfactant_terms", "ehd_evolve_step", "ehd_evolve", "ehd_set_near",
-            "ehd_near_pairs", "ehd_set_overlap", "ehd_overlap_plan", "ehd_solve_En_noalloc", "ehd_surfactant_guess",
+            "ehd_near_pairs", "ehd_set_overlap", "ehd_overlap_plan", "ehd_self_config_candidates", "ehd_set_self_config", "ehd_get_self_config", "ehd_time_self", "ehd_solve_En_noalloc", "ehd_surfactant_guess",
             "ehd_learned_features")
 STAGES = ("densities", "self", "far", "combine")
 DEGREE_CLASSES = (16, 24, 32, 48)   # largest p of each self-interaction kernel class
@@ -71,6 +71,16 @@ class EhdError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"ehdbim error {code}: {msg}")
         self.code = code
+
+
+def self_config_candidates(cls: int):
+    """Prefetch batches built for self-interaction class cls, the default
+    first (host only)."""
+    lib = load()
+    pf, n = (C.c_int * 3)(), C.c_int()
+    if lib.ehd_self_config_candidates(cls, pf, C.byref(n)) != 0:
+        raise ValueError(f"invalid degree class {cls}")
+    return [pf[i] for i in range(n.value)]
 
 
 def load(path: str = LIB_PATH):
@@ -127,6 +137,10 @@ def load(path: str = LIB_PATH):
     lib.ehd_area_weights.argtypes = [vp, vp]
     lib.ehd_set_overlap.argtypes = [vp, C.c_int]
     lib.ehd_overlap_plan.argtypes = [vp, C.c_uint, C.c_int, C.c_int, C.POINTER(C.c_uint), C.POINTER(C.c_longlong)]
+    lib.ehd_self_config_candidates.argtypes = [C.c_int, ip, ip]
+    lib.ehd_set_self_config.argtypes = [vp, C.c_int, C.c_int]
+    lib.ehd_get_self_config.argtypes = [vp, C.c_int, ip]
+    lib.ehd_time_self.argtypes = [vp, C.c_int, C.c_int, vp, vp, C.c_int, dp]
     lib.ehd_set_near.argtypes = [vp, C.c_double, C.c_double, C.c_int, C.c_int]
     lib.ehd_near_pairs.argtypes = [vp, C.POINTER(C.c_longlong)]
     lib.ehd_update_shape.argtypes = [vp, vp]
@@ -325,6 +339,23 @@ class Context:
     def set_overlap(self, enable: bool):
         """Far field on a second stream, concurrent with the self-interaction (ehd_set_overlap)."""
         self._check(self._lib.ehd_set_overlap(self._h, 1 if enable else 0))
+
+    def set_self_config(self, cls: int, pf: int):
+        """Legendre prefetch batch of degree class cls (0: the default; see
+        self_config_candidates)."""
+        self._check(self._lib.ehd_set_self_config(self._h, cls, pf))
+
+    def self_config(self, cls: int) -> int:
+        pf = C.c_int()
+        self._check(self._lib.ehd_get_self_config(self._h, cls, C.byref(pf)))
+        return pf.value
+
+    def time_self(self, cls: int, pf: int, fcoef, sigcoef, reps: int = 3) -> float:
+        """Milliseconds of one launch of class cls with prefetch batch pf
+        (kinds S, D, S_L, L from fcoef and sigcoef)."""
+        ms = C.c_double()
+        self._check(self._lib.ehd_time_self(self._h, cls, pf, _ptr(fcoef), _ptr(sigcoef), reps, C.byref(ms)))
+        return ms.value
 
     def overlap_plan(self, kinds: int, far_prec: int, with_u: bool = False):
         """(classes beside the forked far-field share as a bit mask, forked

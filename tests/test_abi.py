@@ -79,6 +79,19 @@ def test_wigner_d_orthogonal_at_high_degree(lib, n):
         assert err < 1e-12, (n, beta, err)
 
 
+def test_self_prefetch_candidates(lib):
+    """Three Legendre prefetch batches per degree class, the default first,
+    distinct; bad classes are refused (host only)."""
+    for cls in range(4):
+        c = E.self_config_candidates(cls)
+        assert len(c) == 3 and len(set(c)) == 3 and all(1 <= v <= 8 for v in c)
+    assert E.self_config_candidates(2)[0] == 3 and E.self_config_candidates(3)[0] == 5
+    import ctypes
+    pf, n = (ctypes.c_int * 3)(), ctypes.c_int()
+    assert lib.ehd_self_config_candidates(4, pf, ctypes.byref(n)) == E.EHD_E_ARG
+    assert lib.ehd_self_config_candidates(-1, pf, ctypes.byref(n)) == E.EHD_E_ARG
+
+
 def test_rows_for_kinds():
     assert E.rows_for_kinds(E.ALL_KINDS) == list(range(9))
     assert E.rows_for_kinds(E.METRIC_KINDS) == list(range(8))

@@ -314,3 +314,55 @@ def test_overlap_plan(E):
             assert (forked > 0) == whole and beside == (1 if whole else 0), (s.ndrops, prec, beside, forked)
         ctx.set_overlap(False)
         ctx.close()
+
+
+def test_self_prefetch_autotuner(E, tmp_path):
+    """Every Legendre prefetch batch built for a degree class gives the same
+    bits (only the load schedule differs); ehd_time_self times a class; the
+    autotuner picks one of the candidates per class present, sets it, and a
+    second call takes it from its cache; a batch not built is refused."""
+    import torch
+    from paper_1811_10270_amd import autotune
+    s = W.subset(W.batched_suspension(seed=3), list(range(12)))
+    ctx, f, sg, dev = _setup(E, s)
+    T = ctx.ntargets
+    present = [c for c, pm in enumerate(E.DEGREE_CLASSES)
+               if any((E.DEGREE_CLASSES[c - 1] if c else 0) < int(p) <= pm for p in s.p)]
+    assert len(present) >= 3
+    ref = torch.zeros(8, T, dtype=torch.float64, device=dev)
+    ctx.layer_potentials(f, None, sg, E.METRIC_KINDS, E.FAR_FP64, ref)
+    ctx.sync()
+    for c in present:
+        for pf in E.self_config_candidates(c):
+            ctx.set_self_config(c, pf)
+            assert ctx.self_config(c) == pf
+            out = torch.zeros_like(ref)
+            ctx.layer_potentials(f, None, sg, E.METRIC_KINDS, E.FAR_FP64, out)
+            ctx.sync()
+            assert torch.equal(out, ref), (c, pf)
+            assert ctx.time_self(c, pf, f, sg, 1) > 0.0
+        ctx.set_self_config(c, 0)
+    with pytest.raises(RuntimeError):
+        ctx.set_self_config(present[0], 7)
+    cache = str(tmp_path / "tune.json")
+    best, timings, cached = autotune.autotune_self(ctx, s.p, s.q_self, s.grid_mode, f, sg, cache_path=cache)
+    assert not cached and sorted(best) == sorted(E.DEGREE_CLASSES[c] for c in present)
+    for c in present:
+        pm = E.DEGREE_CLASSES[c]
+        assert best[pm] in E.self_config_candidates(c) and ctx.self_config(c) == best[pm]
+        assert min(timings[pm], key=timings[pm].get) == str(best[pm])
+    ctx2, f2, sg2, _ = _setup(E, s)
+    best2, _, cached2 = autotune.autotune_self(ctx2, s.p, s.q_self, s.grid_mode, f2, sg2, cache_path=cache)
+    assert cached2 and best2 == best
+    # overlap mode and graph replays with the tuned batches: the same bits
+    ctx.set_overlap(True)
+    ctx.set_graph(True)
+    for _ in range(2):
+        out = torch.zeros_like(ref)
+        ctx.layer_potentials(f, None, sg, E.METRIC_KINDS, E.FAR_FP64, out)
+        ctx.sync()
+        assert torch.equal(out, ref)
+    ctx.set_graph(False)
+    ctx.set_overlap(False)
+    ctx.close()
+    ctx2.close()
