@@ -77,16 +77,16 @@ def self_exec_flops_per_drop(p: int, q: int, grid_mode: int) -> float:
 # rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs summarised in profiles/
 # (counters scaled by what they read for a plain device copy of known size),
 # valid only for the kernel source they were taken with.
-TRAFFIC_SOURCE_SHA256 = "05218e51baf5012af806e561692d3b5f5d1264d7aef813698a5179fe21240360"
+TRAFFIC_SOURCE_SHA256 = "76e6423ab2da538f571263d6ec2dd72a68bb0fd8857d7e893a9dbc3a59eefb09"
 TRAFFIC_BYTES = {   # (workload, "fp64" | "fp32c", kernel name) -> bytes per launch of all its items
-    ("large_256_p32", "fp64", "k_far64"): 1.916e10,
+    ("large_256_p32", "fp64", "k_far64"): 1.180e10,
     ("large_256_p32", "fp64", "k_self<32>"): 1.815e9,
-    ("large_256_p32", "fp32c", "k_far32"): 1.157e10,
+    ("large_256_p32", "fp32c", "k_far32"): 1.231e10,
     ("large_256_p32", "fp32c", "k_self<32>"): 1.815e9,
-    ("batched_64_mixed_p", "fp64", "k_far64"): 2.204e9,
-    ("batched_64_mixed_p", "fp32c", "k_far32"): 4.691e8,
+    ("batched_64_mixed_p", "fp64", "k_far64"): 1.751e9,
+    ("batched_64_mixed_p", "fp32c", "k_far32"): 4.712e8,
 }
-for _pmax, _b in ((48, 6.515e8), (32, 1.201e8), (24, 2.542e7), (16, 7.375e6)):
+for _pmax, _b in ((48, 6.030e8), (32, 1.201e8), (24, 2.541e7), (16, 7.375e6)):
     for _prec in ("fp64", "fp32c"):
         TRAFFIC_BYTES[("batched_64_mixed_p", _prec, f"k_self<{_pmax}>")] = _b
 
