@@ -235,7 +235,7 @@ def normwise(got, ref):
     return np.abs(got - ref).max(axis=-1) / den
 
 
-def time_evaluation(args, torch, E, ctx, s, far_prec, kinds, f, sig, out):
+def time_evaluation(args, torch, E, ctx, s, far_prec, kinds, f, sig, out, u=None):
     """Warm-up, then args.steps timed evaluations with HIP-event stage and
     class times; per-kernel work and rates; the far part of one more
     (untimed, split) evaluation for the error report."""
@@ -254,14 +254,14 @@ def time_evaluation(args, torch, E, ctx, s, far_prec, kinds, f, sig, out):
     log("far tile", tile)
     ctx.set_graph(bool(args.graph))
     for _ in range(args.warmup):
-        ctx.layer_potentials(f, None, sig, kinds, far_prec, out)
+        ctx.layer_potentials(f, u, sig, kinds, far_prec, out)
     ctx.sync()
     torch.cuda.synchronize()
     ctx.set_timing(K)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(K):
-        ctx.layer_potentials(f, None, sig, kinds, far_prec, out)
+        ctx.layer_potentials(f, u, sig, kinds, far_prec, out)
     ctx.sync()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -273,7 +273,7 @@ def time_evaluation(args, torch, E, ctx, s, far_prec, kinds, f, sig, out):
         ctx.set_graph(False)
         ctx.set_timing(K)
         for _ in range(K):
-            ctx.layer_potentials(f, None, sig, kinds, far_prec, out)
+            ctx.layer_potentials(f, u, sig, kinds, far_prec, out)
         ctx.sync()
         timing_pass = "separate pass of the same launches without the graph"
     stages = [ctx.stage_times(i) for i in range(K)]
@@ -298,6 +298,11 @@ def time_evaluation(args, torch, E, ctx, s, far_prec, kinds, f, sig, out):
             kernels.append({"kernel": f"k_self<{pmax}> (singular self-interaction, p <= {pmax}, FP64)",
                             "bound": "alu", "algorithmic_flops": fl, "dense_flops": dense, "avg_ms": ms,
                             "achieved": fl / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS, "shared": shared})
+    if u is not None:
+        # a separate u takes a second self-interaction pass per class (x, u),
+        # whose class events overwrite the first pass's: the self stage time
+        # holds both, the class rows would not
+        kernels = []
     far_flops = far_interactions(s) * FAR_FLOPS_PER_INTERACTION
     # the far field runs alone in the timed region unless a share of it is
     # forked beside the self-interaction
@@ -338,7 +343,7 @@ def time_evaluation(args, torch, E, ctx, s, far_prec, kinds, f, sig, out):
     # far part of one split evaluation (errors)
     so = torch.empty_like(out)
     fo = torch.empty_like(out)
-    ctx.layer_potentials(f, None, sig, kinds, far_prec, so, fo)
+    ctx.layer_potentials(f, u, sig, kinds, far_prec, so, fo)
     ctx.sync()
     return {"dt": dt, "ms_per_step": dt / K * 1e3, "value": T * K / dt, "stage_ms": dict(zip(E.STAGES, avg)),
             "kernels": kernels, "roofline": roof, "far_tile": tile, "far": fo.cpu().numpy(),
@@ -351,6 +356,8 @@ def bench_eval(args, torch, E, W, dev):
     """The layer-potential evaluation (the metric)."""
     import numpy as np
     s = W.WORKLOADS[args.workload](args.grid_mode)
+    if args.separate_u:
+        s = W.with_separate_u(s)
     kinds = E.METRIC_KINDS
     rows = E.rows_for_kinds(kinds)
     precs = {"both": [E.FAR_FP64, E.FAR_FP32C], "fp64": [E.FAR_FP64], "fp32c": [E.FAR_FP32C]}[args.far_prec]
@@ -362,6 +369,7 @@ def bench_eval(args, torch, E, W, dev):
     T = ctx.ntargets
     f = torch.from_numpy(s.fcoef).to(dev)
     sig = torch.from_numpy(s.sigcoef).to(dev)
+    u = torch.from_numpy(s.ucoef).to(dev) if args.separate_u else None
     out = torch.empty(len(rows), T, dtype=torch.float64, device=dev)
     # the self-interaction's Legendre prefetch batch per degree class (one
     # choice for both far-field precisions: the self-interaction is the same)
@@ -373,12 +381,13 @@ def bench_eval(args, torch, E, W, dev):
         self_tile = {"prefetch": {str(k): v for k, v in best.items()}, "autotuned": True, "from_cache": cached,
                      "timings_ms": {str(k): v for k, v in timings.items()}}
     log("self prefetch", self_tile)
-    runs = {prec: time_evaluation(args, torch, E, ctx, s, prec, kinds, f, sig, out) for prec in precs}
+    runs = {prec: time_evaluation(args, torch, E, ctx, s, prec, kinds, f, sig, out, u) for prec in precs}
     ctx.close()
 
     golden = None
     path = GOLDEN_FAR.get(args.workload)
-    if path and os.path.exists(path) and s.grid_mode == 0:
+    # the stored oracle far field is for D on f (no separate u)
+    if path and os.path.exists(path) and s.grid_mode == 0 and not args.separate_u:
         g = np.load(path)
         if np.allclose(g["checksums"], input_checksums(s), rtol=1e-14, atol=0):
             golden = g
@@ -418,7 +427,8 @@ def bench_eval(args, torch, E, W, dev):
                    "p": sorted(set(int(x) for x in s.p)), "targets": T,
                    "q_self": q_desc(s.q_self), "q_far": q_desc(s.q_far),
                    "grid": "paper (2p+2 longitudes)" if s.grid_mode == 0 else "2p longitudes",
-                   "kinds": "S,D,S_L,L", "far_prec": "fp64" if main_prec == E.FAR_FP64 else "fp32c",
+                   "kinds": "S,D,S_L,L", "double_layer_density": "separate u" if args.separate_u else "f",
+                   "far_prec": "fp64" if main_prec == E.FAR_FP64 else "fp32c",
                    "far_interactions": far_interactions(s), "far_tile": r["far_tile"],
                    "overlap_plan": r["overlap_plan"], "self_tile": self_tile, "graph": bool(args.graph)},
         "stage_ms": r["stage_ms"],
@@ -736,6 +746,9 @@ def main(argv=None):
     ap.add_argument("--grid-mode", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=320)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--separate-u", action="store_true",
+                    help="the double layer takes its own density u instead of f (a second self-interaction pass "
+                         "per degree class; the far field reads u's records either way)")
     ap.add_argument("--graph", action="store_true", default=None,
                     help="replay the evaluation as a recorded HIP graph (default for "
                          "batched_64_mixed_p; per-kernel times then come from a second pass of the "
