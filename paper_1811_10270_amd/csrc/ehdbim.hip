@@ -803,6 +803,15 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     // Legendre fragments per prefetch batch (PFT, else the class default)
     constexpr int PF = PFT > 0 ? PFT : SC::PF;
     constexpr int NBATCH = (SC::KW + PF - 1) / PF;
+    // first prefetch batch of the next latitude block: block 0's here, each
+    // later one loaded at the end of the block before, so that its latency
+    // hides behind that block's longitude sums
+    double avn[PF];
+    {
+        const auto lf0 = gmem(Lq.lfrag + (long long)wv * SC::KW * 64 + lane);
+#pragma unroll
+        for (int u = 0; u < PF; ++u) avn[u] = (u < SC::KW) ? lf0[(long long)u * 64] : 0.0;
+    }
     for (int b = 0; b < nblk; ++b) {
         // 3a. Legendre sums on MFMA: per degree column of this wave, a chain
         //     over n of (Pbar; dPbar at 8 latitudes) x (rotated coefficients).
@@ -813,7 +822,7 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
             const auto lf = gmem(Lq.lfrag + ((long long)b * NW + wv) * SC::KW * 64 + lane);
             double av[2][PF];
 #pragma unroll
-            for (int u = 0; u < PF; ++u) av[0][u] = (u < SC::KW) ? lf[(long long)u * 64] : 0.0;
+            for (int u = 0; u < PF; ++u) av[0][u] = avn[u];
             int m = m_first, left = (m <= p) ? (p + 1 - m + 3) / 4 : 0;
             bool odd_step = (m_first / NW) & 1;
             dbl4 a = dbl4{0, 0, 0, 0};
@@ -843,6 +852,11 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
                         }
                     }
                 }
+            }
+            if (b + 1 < nblk) {
+                const auto lfn = lf + (long long)NW * SC::KW * 64;   // block b + 1, this wave
+#pragma unroll
+                for (int u = 0; u < PF; ++u) avn[u] = (u < SC::KW) ? lfn[(long long)u * 64] : 0.0;
             }
         }
         __syncthreads();
