@@ -130,6 +130,36 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
+// A double moved between lanes by a DPP pattern (both halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes, valid in every lane: within each row of 16 by DPP
+// (swaps within quads, then the half-row and row mirrors; vector ALU, no
+// LDS), then the four row sums read from lanes 0, 16, 32, 48.
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+    v += dpp_f64<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(v);   // row_half_mirror
+    v += dpp_f64<0x140>(v);   // row_mirror
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    double r[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, 16 * k);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), 16 * k);
+        r[k] = __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+    }
+    return (r[0] + r[1]) + (r[2] + r[3]);
+}
+
 // ---------------------------------------------------------------------------
 // Synthesis of K packed fields on a grid (own p-grid or far q-grid), one
 // block per (drop, latitude).  Legendre sums per m into LDS, then the
@@ -1088,7 +1118,7 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
         __syncthreads();  // Fourier blocks consumed before the next block's Legendre sums
     }
     for (int c = 0; c < 9; ++c) {
-        const double sv = wave_sum(acc[c]);
+        const double sv = wave_sum_dpp(acc[c]);
         if (lane == 0) red[wv][c] = sv;
     }
     __syncthreads();
