@@ -833,6 +833,69 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     // Legendre fragments per prefetch batch (PFT, else the class default)
     constexpr int PF = PFT > 0 ? PFT : SC::PF;
     constexpr int NBATCH = (SC::KW + PF - 1) / PF;
+    // kernels at one node (its NV values in val, from this lane's record
+    // of the wave's node buffer) with the modified weight wi of its
+    // latitude (0 for a lane without a node of its own), accumulated per
+    // lane.  gate: skip the kinds not requested (branches); without it
+    // every kind the fields allow is accumulated (the requested ones are
+    // stored) and the code has no branch, so the scheduler can interleave
+    // it with the next latitude's longitude-sum MFMAs.
+    auto eval_node = [&](const double* val, double wi, bool gate) {
+        const double xt0 = val[3], xt1 = val[4], xt2 = val[5];
+        const double xp0 = val[6], xp1 = val[7], xp2 = val[8];
+        const double cx = xt1 * xp2 - xt2 * xp1;
+        const double cy = xt2 * xp0 - xt0 * xp2;
+        const double cz = xt0 * xp1 - xt1 * xp0;
+        // ungated, lanes without a node (weight 0) may hold padding rows of
+        // the longitude sums (zeros): keep their arithmetic finite (gated
+        // calls come from lanes with a node only)
+        const bool live = gate || wi != 0.0;
+        const double J2 = live ? cx * cx + cy * cy + cz * cz : 1.0;
+        const double iJ = rsqrt_nr(J2);
+        const double w = wi * J2 * iJ;
+        const double nx = cx * iJ, ny = cy * iJ, nz = cz * iJ;
+        const double hx = x0[0] - val[0], hy = x0[1] - val[1], hz = x0[2] - val[2];
+        const double r2 = live ? hx * hx + hy * hy + hz * hz : 1.0;
+        const double ir = rsqrt_nr(r2), ir2 = ir * ir, ir3 = ir * ir2;
+        const double hn = hx * nx + hy * ny + hz * nz;
+        if constexpr (HF) {
+            if (!gate || wS) {
+                const double f0 = val[VD], f1 = val[VD + 1], f2 = val[VD + 2];
+                const double hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
+                acc[0] += w * (f0 * ir + hx * hf);
+                acc[1] += w * (f1 * ir + hy * hf);
+                acc[2] += w * (f2 * ir + hz * hf);
+            }
+        }
+        if constexpr (HF || HU) {
+            if (!gate || wD) {
+                constexpr int uo = VD + (HU ? UOFF : FOFF) - 3;
+                const double hu = hx * val[uo] + hy * val[uo + 1] + hz * val[uo + 2];
+                const double tq = -6.0 * w * hu * hn * ir3 * ir2;
+                acc[3] += tq * hx;
+                acc[4] += tq * hy;
+                acc[5] += tq * hz;
+            }
+        }
+        if constexpr (HS) {
+            const double sg = w * val[VD + SOFF - 3];
+            if (!gate || wSL) acc[6] += sg * ir;
+            if (!gate || wL) acc[7] += sg * hn * ir3;
+            if (!gate || wK) acc[8] += sg * (hx * n0v[0] + hy * n0v[1] + hz * n0v[2]) * ir3;
+        }
+    };
+
+    // Row 0 of the longitude sums (when taken apart): each wave stores the two
+    // nodes (phi = 0, pi) of its latitude in the block's row-0 records, and
+    // after the block's last barrier one wave evaluates all sixteen in
+    // sixteen lanes (during the next block's Legendre sums), instead of two
+    // lanes in each of the eight waves.
+    double* const RZ = R + LB * gsz + NW * NBW;
+    auto row0_eval = [&](int bb) {
+        const int i = bb * LB + (lane >> 1);
+        if (lane < 2 * LB && i <= Lq.Q) eval_node(RZ + lane * NVP, wsing[i], true);
+    };
+
     // first prefetch batch of the next latitude block: block 0's here, each
     // later one loaded at the end of the block before, so that its latency
     // hides behind that block's longitude sums
@@ -843,6 +906,7 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
         for (int u = 0; u < PF; ++u) avn[u] = (u < SC::KW) ? lf0[(long long)u * 64] : 0.0;
     }
     for (int b = 0; b < nblk; ++b) {
+        if (SC::ROW0 && qg.l0 == 1 && b > 0 && wv == ((b - 1) & (NW - 1))) row0_eval(b - 1);
         // 3a. Legendre sums on MFMA: per degree column of this wave, a chain
         //     over n of (Pbar; dPbar at 8 latitudes) x (rotated coefficients).
         //     This wave's A fragments are contiguous in the table (zero past
@@ -890,58 +954,6 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
             }
         }
         __syncthreads();
-
-        // kernels at one node (its NV values in val, from this lane's record
-        // of the wave's node buffer) with the modified weight wi of its
-        // latitude (0 for a lane without a node of its own), accumulated per
-        // lane.  gate: skip the kinds not requested (branches); without it
-        // every kind the fields allow is accumulated (the requested ones are
-        // stored) and the code has no branch, so the scheduler can interleave
-        // it with the next latitude's longitude-sum MFMAs.
-        auto eval_node = [&](const double* val, double wi, bool gate) {
-            const double xt0 = val[3], xt1 = val[4], xt2 = val[5];
-            const double xp0 = val[6], xp1 = val[7], xp2 = val[8];
-            const double cx = xt1 * xp2 - xt2 * xp1;
-            const double cy = xt2 * xp0 - xt0 * xp2;
-            const double cz = xt0 * xp1 - xt1 * xp0;
-            // ungated, lanes without a node (weight 0) may hold padding rows of
-            // the longitude sums (zeros): keep their arithmetic finite (gated
-            // calls come from lanes with a node only)
-            const bool live = gate || wi != 0.0;
-            const double J2 = live ? cx * cx + cy * cy + cz * cz : 1.0;
-            const double iJ = rsqrt_nr(J2);
-            const double w = wi * J2 * iJ;
-            const double nx = cx * iJ, ny = cy * iJ, nz = cz * iJ;
-            const double hx = x0[0] - val[0], hy = x0[1] - val[1], hz = x0[2] - val[2];
-            const double r2 = live ? hx * hx + hy * hy + hz * hz : 1.0;
-            const double ir = rsqrt_nr(r2), ir2 = ir * ir, ir3 = ir * ir2;
-            const double hn = hx * nx + hy * ny + hz * nz;
-            if constexpr (HF) {
-                if (!gate || wS) {
-                    const double f0 = val[VD], f1 = val[VD + 1], f2 = val[VD + 2];
-                    const double hf = (hx * f0 + hy * f1 + hz * f2) * ir3;
-                    acc[0] += w * (f0 * ir + hx * hf);
-                    acc[1] += w * (f1 * ir + hy * hf);
-                    acc[2] += w * (f2 * ir + hz * hf);
-                }
-            }
-            if constexpr (HF || HU) {
-                if (!gate || wD) {
-                    constexpr int uo = VD + (HU ? UOFF : FOFF) - 3;
-                    const double hu = hx * val[uo] + hy * val[uo + 1] + hz * val[uo + 2];
-                    const double tq = -6.0 * w * hu * hn * ir3 * ir2;
-                    acc[3] += tq * hx;
-                    acc[4] += tq * hy;
-                    acc[5] += tq * hz;
-                }
-            }
-            if constexpr (HS) {
-                const double sg = w * val[VD + SOFF - 3];
-                if (!gate || wSL) acc[6] += sg * ir;
-                if (!gate || wL) acc[7] += sg * hn * ir3;
-                if (!gate || wK) acc[8] += sg * (hx * n0v[0] + hy * n0v[1] + hz * n0v[2]) * ir3;
-            }
-        };
 
         // 3b/3c. per latitude of the block owned by this wave: longitude
         //     sums of its row tile on MFMA (four term-group chains), node
@@ -1094,7 +1106,7 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
         // 3d. when row 0 is apart: row 0 of latitude wv of the block, phi = 0
         //     and pi take EC + OC and EC - OC, the sums of the cos rows of even
         //     and odd m; lane (column v, part) sums every fourth row, shuffles
-        //     add the parts.
+        //     add the parts; the two records go to the row-0 area.
         if (SC::ROW0 && qg.l0 == 1 && b * LB + wv <= Lq.Q) {
             const double* G = R + wv * gsz + (lane & 15);
             const int part = lane >> 4;
@@ -1106,17 +1118,11 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
             ocs += __shfl_xor(ocs, 16);
             ocs += __shfl_xor(ocs, 32);
             const int v = lane & 15;
-            if (part < 2 && v < NV) NB[part * NVP + v] = part ? ecs - ocs : ecs + ocs;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (lane < 2) eval_node(NB + lane * NVP, wsing[b * LB + wv], true);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (part < 2 && v < NV) RZ[(2 * wv + part) * NVP + v] = part ? ecs - ocs : ecs + ocs;
         }
         __syncthreads();  // Fourier blocks consumed before the next block's Legendre sums
     }
+    if (SC::ROW0 && qg.l0 == 1 && nblk > 0 && wv == ((nblk - 1) & (NW - 1))) row0_eval(nblk - 1);
     for (int c = 0; c < 9; ++c) {
         const double sv = wave_sum_dpp(acc[c]);
         if (lane == 0) red[wv][c] = sv;
@@ -2016,7 +2022,8 @@ static size_t self_lds_bytes(const ehd_ctx* ctx, const std::vector<int>& drops, 
         const QuarterGrid g = quarter_grid(D.p, D.nlon_s, self_row0(D.p));
         const size_t coef = (size_t)nf * ncoef(D.p) * 16;
         const size_t work = ((size_t)kLatBlock * g.nks * 64 +
-                             (size_t)SelfClass<16>::NW * (64 * ((nf + 6) | 1) + (D.p <= 32 ? 16 : 0))) * 8;
+                             (size_t)SelfClass<16>::NW * (64 * ((nf + 6) | 1) + (D.p <= 32 ? 16 : 0)) +
+                             (self_row0(D.p) ? (size_t)2 * kLatBlock * ((nf + 6) | 1) : 0)) * 8;
         best = std::max(best, std::max(coef, work));
     }
     return best;
