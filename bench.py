@@ -77,16 +77,16 @@ def self_exec_flops_per_drop(p: int, q: int, grid_mode: int) -> float:
 # rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs summarised in profiles/
 # (counters scaled by what they read for a plain device copy of known size),
 # valid only for the kernel source they were taken with.
-TRAFFIC_SOURCE_SHA256 = "b0075ab8a5efcf38c851ab21d52358f551739fe24ba7b24a4cb8a8b7864d0ca7"
+TRAFFIC_SOURCE_SHA256 = "41759e0100b8e850b2f134d3c7932f066ec74cd307439e1e6547e46f7621199f"
 TRAFFIC_BYTES = {   # (workload, "fp64" | "fp32c", kernel name) -> bytes per launch of all its items
-    ("large_256_p32", "fp64", "k_far64"): 1.185e10,
+    ("large_256_p32", "fp64", "k_far64"): 1.191e10,
     ("large_256_p32", "fp64", "k_self<32>"): 1.815e9,
-    ("large_256_p32", "fp32c", "k_far32"): 1.157e10,
+    ("large_256_p32", "fp32c", "k_far32"): 1.161e10,
     ("large_256_p32", "fp32c", "k_self<32>"): 1.815e9,
-    ("batched_64_mixed_p", "fp64", "k_far64"): 1.765e9,
+    ("batched_64_mixed_p", "fp64", "k_far64"): 1.771e9,
     ("batched_64_mixed_p", "fp32c", "k_far32"): 4.689e8,
 }
-for _pmax, _b in ((48, 6.369e8), (32, 1.201e8), (24, 2.543e7), (16, 7.385e6)):
+for _pmax, _b in ((48, 6.407e8), (32, 1.202e8), (24, 2.543e7), (16, 7.392e6)):
     for _prec in ("fp64", "fp32c"):
         TRAFFIC_BYTES[("batched_64_mixed_p", _prec, f"k_self<{_pmax}>")] = _b
 
