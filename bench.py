@@ -77,7 +77,7 @@ def self_exec_flops_per_drop(p: int, q: int, grid_mode: int) -> float:
 # rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs summarised in profiles/
 # (counters scaled by what they read for a plain device copy of known size),
 # valid only for the kernel source they were taken with.
-TRAFFIC_SOURCE_SHA256 = "41759e0100b8e850b2f134d3c7932f066ec74cd307439e1e6547e46f7621199f"
+TRAFFIC_SOURCE_SHA256 = "def99c4dfd0b7dbc7d253684ce8ef98cf33829d8e13223e6158e5a31967e9df4"
 TRAFFIC_BYTES = {   # (workload, "fp64" | "fp32c", kernel name) -> bytes per launch of all its items
     ("large_256_p32", "fp64", "k_far64"): 1.191e10,
     ("large_256_p32", "fp64", "k_self<32>"): 1.815e9,

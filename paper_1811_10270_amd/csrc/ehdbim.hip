@@ -833,8 +833,8 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     // Legendre fragments per prefetch batch (PFT, else the class default)
     constexpr int PF = PFT > 0 ? PFT : SC::PF;
     constexpr int NBATCH = (SC::KW + PF - 1) / PF;
-    // kernels at one node (its NV values in val, from this lane's record
-    // of the wave's node buffer) with the modified weight wi of its
+    // kernels at one node (its NV values in val: this lane's record of the
+    // wave's node buffer or of the row-0 records) with the modified weight wi of its
     // latitude (0 for a lane without a node of its own), accumulated per
     // lane.  gate: skip the kinds not requested (branches); without it
     // every kind the fields allow is accumulated (the requested ones are
