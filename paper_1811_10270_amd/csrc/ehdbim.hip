@@ -643,6 +643,29 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
     if constexpr (HU) for (int c = 0; c < 3; ++c) fld[UOFF + c] = gmem(ucoef + 3 * D.coff + c * 2 * nc);
     if constexpr (HS) fld[SOFF] = gmem(scoef + D.coff);
 
+    // register-resident A operand of the longitude sums of this wave's row
+    // tile (rows l = 16 tile .. 16 tile + 15): cos/sin(m phi_l) of the four
+    // term groups.  Waves w, w + nTp, .. share tile w % nTp and split the
+    // latitudes of a block.  Loaded here, before the rotation, whose time
+    // hides their latency.
+    const int my_tile = wv % qg.nTp;
+    const bool dft_wave = my_tile < qg.nT;
+    double aEC[SC::KEC], aES[SC::KES], aOC[SC::KOC], aOS[SC::KOC];
+    {
+        const auto src = gmem(Lq.afrag + (long long)(dft_wave ? my_tile : 0) * qg.nks * 64 + lane);
+#pragma unroll
+        for (int ks = 0; ks < SC::KEC; ++ks)
+            aEC[ks] = (dft_wave && ks < qg.nk[0]) ? src[(long long)(qg.base[0] / 4 + ks) * 64] : 0.0;
+#pragma unroll
+        for (int ks = 0; ks < SC::KES; ++ks)
+            aES[ks] = (dft_wave && ks < qg.nk[1]) ? src[(long long)(qg.base[1] / 4 + ks) * 64] : 0.0;
+#pragma unroll
+        for (int ks = 0; ks < SC::KOC; ++ks) {
+            aOC[ks] = (dft_wave && ks < qg.nk[2]) ? src[(long long)(qg.base[2] / 4 + ks) * 64] : 0.0;
+            aOS[ks] = (dft_wave && ks < qg.nk[3]) ? src[(long long)(qg.base[3] / 4 + ks) * 64] : 0.0;
+        }
+    }
+
     // 1. rotation, into LDS (column-major: column m holds n = m..p
     //    contiguously).
     //    a. z_nm = c_nm e^{i m phi_t} of every field, in the slots the rotated
@@ -750,28 +773,6 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
         }
     }
     __syncthreads();   // LDS free: Fourier blocks and per-wave node buffers from here on
-
-    // register-resident A operand of the longitude sums of this wave's row
-    // tile (rows l = 16 tile .. 16 tile + 15): cos/sin(m phi_l) of the four
-    // term groups.  Waves w, w + nTp, .. share tile w % nTp and split the
-    // latitudes of a block.
-    const int my_tile = wv % qg.nTp;
-    const bool dft_wave = my_tile < qg.nT;
-    double aEC[SC::KEC], aES[SC::KES], aOC[SC::KOC], aOS[SC::KOC];
-    {
-        const auto src = gmem(Lq.afrag + (long long)(dft_wave ? my_tile : 0) * qg.nks * 64 + lane);
-#pragma unroll
-        for (int ks = 0; ks < SC::KEC; ++ks)
-            aEC[ks] = (dft_wave && ks < qg.nk[0]) ? src[(long long)(qg.base[0] / 4 + ks) * 64] : 0.0;
-#pragma unroll
-        for (int ks = 0; ks < SC::KES; ++ks)
-            aES[ks] = (dft_wave && ks < qg.nk[1]) ? src[(long long)(qg.base[1] / 4 + ks) * 64] : 0.0;
-#pragma unroll
-        for (int ks = 0; ks < SC::KOC; ++ks) {
-            aOC[ks] = (dft_wave && ks < qg.nk[2]) ? src[(long long)(qg.base[2] / 4 + ks) * 64] : 0.0;
-            aOS[ks] = (dft_wave && ks < qg.nk[3]) ? src[(long long)(qg.base[3] / 4 + ks) * 64] : 0.0;
-        }
-    }
 
     const int gsz = qg.nks * 64;                      // one latitude's Fourier block
     constexpr int NVP = NV | 1;                       // node record stride (odd: fewer bank conflicts)
