@@ -77,16 +77,16 @@ def self_exec_flops_per_drop(p: int, q: int, grid_mode: int) -> float:
 # rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs summarised in profiles/
 # (counters scaled by what they read for a plain device copy of known size),
 # valid only for the kernel source they were taken with.
-TRAFFIC_SOURCE_SHA256 = "def99c4dfd0b7dbc7d253684ce8ef98cf33829d8e13223e6158e5a31967e9df4"
+TRAFFIC_SOURCE_SHA256 = "6685be38d03a63cc51dfdfb60f31b07a6f140777652c00a999ffe929462daf7b"
 TRAFFIC_BYTES = {   # (workload, "fp64" | "fp32c", kernel name) -> bytes per launch of all its items
-    ("large_256_p32", "fp64", "k_far64"): 1.191e10,
+    ("large_256_p32", "fp64", "k_far64"): 1.178e10,
     ("large_256_p32", "fp64", "k_self<32>"): 1.815e9,
-    ("large_256_p32", "fp32c", "k_far32"): 1.161e10,
+    ("large_256_p32", "fp32c", "k_far32"): 1.167e10,
     ("large_256_p32", "fp32c", "k_self<32>"): 1.815e9,
-    ("batched_64_mixed_p", "fp64", "k_far64"): 1.771e9,
-    ("batched_64_mixed_p", "fp32c", "k_far32"): 4.689e8,
+    ("batched_64_mixed_p", "fp64", "k_far64"): 1.799e9,
+    ("batched_64_mixed_p", "fp32c", "k_far32"): 4.722e8,
 }
-for _pmax, _b in ((48, 6.407e8), (32, 1.202e8), (24, 2.543e7), (16, 7.392e6)):
+for _pmax, _b in ((48, 6.265e8), (32, 1.202e8), (24, 2.543e7), (16, 7.391e6)):
     for _prec in ("fp64", "fp32c"):
         TRAFFIC_BYTES[("batched_64_mixed_p", _prec, f"k_self<{_pmax}>")] = _b
 
