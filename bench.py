@@ -769,7 +769,8 @@ def main(argv=None):
                          "field E_u = 1, Ca_E = 0.3, clean drops, dt = 0.01")
     ap.add_argument("--serial", action="store_true",
                     help="self-interaction, then far field, on one stream (every kernel alone); by default "
-                         "the far field runs, whole or in part, on a second stream beside the self-interaction")
+                         "(overlap mode) the far field may run, whole or in part, on a second stream beside the "
+                         "degree classes that leave room for it (the library's overlap plan, reported in the line)")
     ap.add_argument("--near", action="store_true",
                     help="time the evaluation of two p = 32 spheres --near-gap apart with and without the "
                          "nearly singular correction")
