@@ -1143,7 +1143,9 @@ __global__ __launch_bounds__(SelfClass<PMAX>::NT) void k_self(
 
 // ---------------------------------------------------------------------------
 // Far field: each thread TPT targets (rows t, t + 256, ...), sources streamed
-// through LDS in tiles of one drop each (drop-aligned padding), tiles split
+// through LDS in tiles of one drop each (drop-aligned padding; a tile's
+// entry in tile_info gives its drop and how many of its slots, rounded up to
+// four, hold sources, and only those are loaded and summed), tiles split
 // over blockIdx.y.  partial[chunk][comp][T] (unscaled).  TPT and the number
 // of chunks are the tile-shape parameters the autotuner picks.
 // ---------------------------------------------------------------------------
@@ -1159,7 +1161,7 @@ __device__ __forceinline__ void far64_block(const double* __restrict__ tx,
                                                     const double* __restrict__ tnrm,
                                                     const int* __restrict__ tdrop, long long T,
                                                     const double* __restrict__ src, long long Spad,
-                                                    const int* __restrict__ tile_drop, int ntiles,
+                                                    const int2* __restrict__ tile_info, int ntiles,
                                                     int tiles_per_chunk, double* __restrict__ partial, int bx, int by)
 {
     constexpr bool wS = KM & EHD_STOKES_SL, wD = KM & EHD_STOKES_DL;
@@ -1185,11 +1187,13 @@ __device__ __forceinline__ void far64_block(const double* __restrict__ tx,
     const int bdrop = tdrop[tb0] == tdrop[tb1] ? tdrop[tb0] : -1;
     const int t0 = by * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
     for (int tile = t0; tile < t1; ++tile) {
-        if (tile_drop[tile] == bdrop) continue;   // uniform over the block
+        const int2 ti = tile_info[tile];          // (drop, sources in the tile)
+        if (ti.x == bdrop) continue;              // uniform over the block
         const long long s = (long long)tile * kTile + threadIdx.x;
-        for (int r = 0; r < kRec64; ++r) smd[r * kTile + threadIdx.x] = src[r * Spad + s];
+        if ((int)threadIdx.x < ti.y)
+            for (int r = 0; r < kRec64; ++r) smd[r * kTile + threadIdx.x] = src[r * Spad + s];
         __syncthreads();
-        const int sd = tile_drop[tile];
+        const int sd = ti.x;
         bool other = false;   // some target of this thread is not on the tile's drop
         for (int k = 0; k < TPT; ++k) other = other || (sd != myd[k]);
         double a[TPT][9], b[TPT][3];
@@ -1197,7 +1201,7 @@ __device__ __forceinline__ void far64_block(const double* __restrict__ tx,
             for (int c = 0; c < 9; ++c) a[k][c] = 0.0;
             for (int c = 0; c < 3; ++c) b[k][c] = 0.0;
         }
-        for (int q2 = 0; q2 < (other ? kTile / 2 : 0); ++q2) {
+        for (int q2 = 0; q2 < (other ? ti.y / 2 : 0); ++q2) {
             const double2 X = sm[0][q2], Y = sm[1][q2], Z = sm[2][q2];
             double2 NX, NY, NZ, F0, F1, F2, U0, U1, U2, SG;
             if constexpr (needN) { NX = sm[3][q2]; NY = sm[4][q2]; NZ = sm[5][q2]; }
@@ -1268,12 +1272,12 @@ template <int TPT, unsigned KM>
 __global__ __launch_bounds__(kThreads) void k_far64(const double* __restrict__ tx, const double* __restrict__ tnrm,
                                                     const int* __restrict__ tdrop, long long T,
                                                     const double* __restrict__ src, long long Spad,
-                                                    const int* __restrict__ tile_drop, int ntiles,
+                                                    const int2* __restrict__ tile_info, int ntiles,
                                                     int tiles_per_chunk, double* __restrict__ partial, int nbx,
                                                     int vb0, int vb1)
 {
     for (int vb = vb0 + (int)blockIdx.x; vb < vb1; vb += (int)gridDim.x)
-        far64_block<TPT, KM>(tx, tnrm, tdrop, T, src, Spad, tile_drop, ntiles, tiles_per_chunk, partial, vb % nbx,
+        far64_block<TPT, KM>(tx, tnrm, tdrop, T, src, Spad, tile_info, ntiles, tiles_per_chunk, partial, vb % nbx,
                              vb / nbx);
 }
 
@@ -1289,7 +1293,7 @@ __device__ __forceinline__ void far32_block(const double* __restrict__ tx,
                                                     const double* __restrict__ tnrm,
                                                     const int* __restrict__ tdrop, long long T,
                                                     const float* __restrict__ src, long long Spad,
-                                                    const int* __restrict__ tile_drop,
+                                                    const int2* __restrict__ tile_info,
                                                     const double* __restrict__ dcentre, int ntiles,
                                                     int tiles_per_chunk, double* __restrict__ partial, int bx, int by)
 {
@@ -1317,11 +1321,13 @@ __device__ __forceinline__ void far32_block(const double* __restrict__ tx,
     const int bdrop = tdrop[tb0] == tdrop[tb1] ? tdrop[tb0] : -1;
     const int t0 = by * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
     for (int tile = t0; tile < t1; ++tile) {
-        if (tile_drop[tile] == bdrop) continue;   // uniform over the block
+        const int2 ti = tile_info[tile];          // (drop, sources in the tile)
+        if (ti.x == bdrop) continue;              // uniform over the block
         const long long s = (long long)tile * kTile + threadIdx.x;
-        for (int r = 0; r < kRec32; ++r) smf[r * kTile + threadIdx.x] = src[r * Spad + s];
+        if ((int)threadIdx.x < ti.y)
+            for (int r = 0; r < kRec32; ++r) smf[r * kTile + threadIdx.x] = src[r * Spad + s];
         __syncthreads();
-        const int sd = tile_drop[tile];
+        const int sd = ti.x;
         bool other = false;   // some target of this thread is not on the tile's drop
         for (int k = 0; k < TPT; ++k) other = other || (sd != myd[k]);
         float ax[TPT], ay[TPT], az[TPT], bx[TPT], by[TPT], bz[TPT], a[TPT][9];
@@ -1341,7 +1347,7 @@ __device__ __forceinline__ void far32_block(const double* __restrict__ tx,
         const bool tail = !__all(far_all);
         auto pairs = [&](auto with_tail) {
         constexpr bool TAIL = decltype(with_tail)::value;
-        for (int q4 = 0; q4 < (other ? kTile / 4 : 0); ++q4) {
+        for (int q4 = 0; q4 < (other ? ti.y / 4 : 0); ++q4) {
             const float4 X = sm[0][q4], Y = sm[1][q4], Z = sm[2][q4];
             float4 NX, NY, NZ, F0, F1, F2, U0, U1, U2, SG;
             if constexpr (needN) { NX = sm[3][q4]; NY = sm[4][q4]; NZ = sm[5][q4]; }
@@ -1404,13 +1410,13 @@ template <int TPT, unsigned KM>
 __global__ __launch_bounds__(kThreads) void k_far32(const double* __restrict__ tx, const double* __restrict__ tnrm,
                                                     const int* __restrict__ tdrop, long long T,
                                                     const float* __restrict__ src, long long Spad,
-                                                    const int* __restrict__ tile_drop,
+                                                    const int2* __restrict__ tile_info,
                                                     const double* __restrict__ dcentre, int ntiles,
                                                     int tiles_per_chunk, double* __restrict__ partial, int nbx,
                                                     int vb0, int vb1)
 {
     for (int vb = vb0 + (int)blockIdx.x; vb < vb1; vb += (int)gridDim.x)
-        far32_block<TPT, KM>(tx, tnrm, tdrop, T, src, Spad, tile_drop, dcentre, ntiles, tiles_per_chunk, partial,
+        far32_block<TPT, KM>(tx, tnrm, tdrop, T, src, Spad, tile_info, dcentre, ntiles, tiles_per_chunk, partial,
                              vb % nbx, vb / nbx);
 }
 
@@ -1811,7 +1817,7 @@ struct ehd_ctx {
     int* d_tdrop = nullptr;          // [T]
     int* d_order = nullptr;          // [T] self work order
     int* d_slot_drop = nullptr;      // [Spad]
-    int* d_tile_drop = nullptr;      // [ntiles]
+    int2* d_tile_info = nullptr;     // [ntiles] (drop, sources in the tile rounded up to 4)
     double* d_centre = nullptr;      // [4*nd]: centre, (2 radius)^2
     double* d_src64 = nullptr;       // [kRec64][Spad]
     float* d_src32 = nullptr;        // [kRec32][Spad]
@@ -2106,13 +2112,13 @@ static const void* self_kernel_of_class(int cls, bool HF, bool HU, bool HS, int 
 
 // FP64 far-field launchers, one per (targets per thread, kinds mask).
 using Far64Launch = void (*)(dim3, hipStream_t, const double*, const double*, const int*, long long, const double*,
-                             long long, const int*, int, int, double*, int, int, int);
+                             long long, const int2*, int, int, double*, int, int, int);
 template <int TPT, unsigned KM>
 static void launch_far64_km(dim3 grid, hipStream_t st, const double* tx, const double* tn, const int* tdrop,
-                            long long T, const double* src, long long S, const int* tile_drop, int ntiles, int tpc,
+                            long long T, const double* src, long long S, const int2* tile_info, int ntiles, int tpc,
                             double* partial, int nbx, int vb0, int vb1)
 {
-    hipLaunchKernelGGL((k_far64<TPT, KM>), grid, dim3(kThreads), 0, st, tx, tn, tdrop, T, src, S, tile_drop, ntiles,
+    hipLaunchKernelGGL((k_far64<TPT, KM>), grid, dim3(kThreads), 0, st, tx, tn, tdrop, T, src, S, tile_info, ntiles,
                        tpc, partial, nbx, vb0, vb1);
 }
 template <int TPT, std::size_t... I>
@@ -2129,13 +2135,13 @@ static const std::array<Far64Launch, 32>& far64_table()
 
 // FP32 far-field launchers, one per (targets per thread, kinds mask).
 using Far32Launch = void (*)(dim3, hipStream_t, const double*, const double*, const int*, long long, const float*,
-                             long long, const int*, const double*, int, int, double*, int, int, int);
+                             long long, const int2*, const double*, int, int, double*, int, int, int);
 template <int TPT, unsigned KM>
 static void launch_far32_km(dim3 grid, hipStream_t st, const double* tx, const double* tn, const int* tdrop,
-                            long long T, const float* src, long long S, const int* tile_drop, const double* centre,
+                            long long T, const float* src, long long S, const int2* tile_info, const double* centre,
                             int ntiles, int tpc, double* partial, int nbx, int vb0, int vb1)
 {
-    hipLaunchKernelGGL((k_far32<TPT, KM>), grid, dim3(kThreads), 0, st, tx, tn, tdrop, T, src, S, tile_drop, centre,
+    hipLaunchKernelGGL((k_far32<TPT, KM>), grid, dim3(kThreads), 0, st, tx, tn, tdrop, T, src, S, tile_info, centre,
                        ntiles, tpc, partial, nbx, vb0, vb1);
 }
 template <int TPT, std::size_t... I>
@@ -2873,14 +2879,19 @@ int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
     if ((rc = upload(ctx, &ctx->d_info, ctx->info))) return rc;
 
     // index tables
-    std::vector<int> tdrop(ctx->T), slot_drop(ctx->Spad), tile_drop(ctx->ntiles);
+    std::vector<int> tdrop(ctx->T), slot_drop(ctx->Spad);
+    std::vector<int2> tile_info(ctx->ntiles);
     std::vector<int2> rows_p, rows_f, an_items;
     for (int d = 0; d < ndrops; ++d) {
         const DropInfo& D = ctx->info[d];
         for (long long t = 0; t < (long long)(D.p + 1) * D.nlon_p; ++t) tdrop[D.toff + t] = d;
         const long long padded = (D.ns + kTile - 1) / kTile * kTile;
         for (long long s = 0; s < padded; ++s) slot_drop[D.soff + s] = d;
-        for (long long tl = 0; tl < padded / kTile; ++tl) tile_drop[D.soff / kTile + tl] = d;
+        // the far-field kernels sum a tile's sources in fours; the padding
+        // slots past a drop's last source are skipped
+        for (long long tl = 0; tl < padded / kTile; ++tl)
+            tile_info[D.soff / kTile + tl] =
+                make_int2(d, (int)((std::min<long long>(kTile, D.ns - tl * kTile) + 3) / 4 * 4));
         for (int i = 0; i <= D.p; ++i) rows_p.push_back(make_int2(d, i));
         for (int i = 0; i <= D.qf; ++i) rows_f.push_back(make_int2(d, i));
         for (int k = 0; k < ncoef(D.p); ++k) an_items.push_back(make_int2(d, k));
@@ -2909,7 +2920,7 @@ int ehd_set_drops(ehd_ctx* ctx, int ndrops, const int* p_h, const int* q_self_h,
     ctx->cls_off[4] = (int)ctx->self_order_h.size();
     if ((rc = upload(ctx, &ctx->d_tdrop, tdrop))) return rc;
     if ((rc = upload(ctx, &ctx->d_slot_drop, slot_drop))) return rc;
-    if ((rc = upload(ctx, &ctx->d_tile_drop, tile_drop))) return rc;
+    if ((rc = upload(ctx, &ctx->d_tile_info, tile_info))) return rc;
     if ((rc = upload(ctx, &ctx->d_rows_p, rows_p))) return rc;
     if ((rc = upload(ctx, &ctx->d_rows_f, rows_f))) return rc;
     if ((rc = upload(ctx, &ctx->d_an_items, an_items))) return rc;
@@ -3034,11 +3045,11 @@ static int launch_far(ehd_ctx* ctx, int far_prec, unsigned kinds, int tpt, int n
     const dim3 grid((unsigned)(blocks > 0 ? std::min(blocks, vb1 - vb0) : vb1 - vb0));
     if (far_prec == EHD_FAR_FP64) {
         const Far64Launch fn = (tpt == 2 ? far64_table<2>() : far64_table<1>())[kinds & EHD_ALL_KINDS];
-        fn(grid, ctx->ls, ctx->d_tx, ctx->d_tn, ctx->d_tdrop, T, ctx->d_src64, S, ctx->d_tile_drop, ctx->ntiles, tpc,
+        fn(grid, ctx->ls, ctx->d_tx, ctx->d_tn, ctx->d_tdrop, T, ctx->d_src64, S, ctx->d_tile_info, ctx->ntiles, tpc,
            ctx->d_partial, (int)tblocks, (int)vb0, (int)vb1);
     } else {
         const Far32Launch fn = (tpt == 2 ? far32_table<2>() : far32_table<1>())[kinds & EHD_ALL_KINDS];
-        fn(grid, ctx->ls, ctx->d_tx, ctx->d_tn, ctx->d_tdrop, T, ctx->d_src32, S, ctx->d_tile_drop, ctx->d_centre,
+        fn(grid, ctx->ls, ctx->d_tx, ctx->d_tn, ctx->d_tdrop, T, ctx->d_src32, S, ctx->d_tile_info, ctx->d_centre,
            ctx->ntiles, tpc, ctx->d_partial, (int)tblocks, (int)vb0, (int)vb1);
     }
     EHD_HIP(ctx, hipGetLastError());
