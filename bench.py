@@ -77,16 +77,19 @@ def self_exec_flops_per_drop(p: int, q: int, grid_mode: int) -> float:
 # rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs summarised in profiles/
 # (counters scaled by what they read for a plain device copy of known size),
 # valid only for the kernel source they were taken with.
-TRAFFIC_SOURCE_SHA256 = "6685be38d03a63cc51dfdfb60f31b07a6f140777652c00a999ffe929462daf7b"
-TRAFFIC_BYTES = {   # (workload, "fp64" | "fp32c", kernel name) -> bytes per launch of all its items
-    ("large_256_p32", "fp64", "k_far64"): 1.178e10,
+TRAFFIC_SOURCE_SHA256 = "60810dad5ec8cec55a8307727e9bb7747487add5813133afb8f5c1052345e121"
+# (workload, "fp64" | "fp32c", kernel name[, far-field tile shape]) -> bytes per
+# launch of all its items; a far-field kernel's traffic depends on its tile
+# shape (per-chunk partial sums, source re-reads per block of targets)
+TRAFFIC_BYTES = {
+    ("large_256_p32", "fp64", "k_far64", "2x15"): 1.913e10,
     ("large_256_p32", "fp64", "k_self<32>"): 1.815e9,
-    ("large_256_p32", "fp32c", "k_far32"): 1.167e10,
+    ("large_256_p32", "fp32c", "k_far32", "2x15"): 5.569e9,
     ("large_256_p32", "fp32c", "k_self<32>"): 1.815e9,
-    ("batched_64_mixed_p", "fp64", "k_far64"): 1.799e9,
-    ("batched_64_mixed_p", "fp32c", "k_far32"): 4.722e8,
+    ("batched_64_mixed_p", "fp64", "k_far64", "2x12"): 2.078e9,
+    ("batched_64_mixed_p", "fp32c", "k_far32", "1x16"): 4.661e8,
 }
-for _pmax, _b in ((48, 6.265e8), (32, 1.202e8), (24, 2.543e7), (16, 7.391e6)):
+for _pmax, _b in ((48, 5.947e8), (32, 1.202e8), (24, 2.543e7), (16, 7.392e6)):
     for _prec in ("fp64", "fp32c"):
         TRAFFIC_BYTES[("batched_64_mixed_p", _prec, f"k_self<{_pmax}>")] = _b
 
@@ -102,10 +105,13 @@ def kernel_source_sha256() -> str:
     return hashlib.sha256(text[:cut] if cut > 0 else text).hexdigest()
 
 
-def measured_traffic(kernel: str, workload: str, far_prec: int):
+def measured_traffic(kernel: str, workload: str, far_prec: int, far_tile: str):
     if kernel_source_sha256() != TRAFFIC_SOURCE_SHA256:
         return None
-    return TRAFFIC_BYTES.get((workload, "fp64" if far_prec == 0 else "fp32c", kernel.split(" ")[0]))
+    key = (workload, "fp64" if far_prec == 0 else "fp32c", kernel.split(" ")[0])
+    if key[2].startswith("k_far"):
+        key += (far_tile,)
+    return TRAFFIC_BYTES.get(key)
 
 
 def far_interactions(s) -> float:
@@ -326,7 +332,8 @@ def time_evaluation(args, torch, E, ctx, s, far_prec, kinds, f, sig, out, u=None
     for k in kernels:
         k["unit"] = "TFLOP/s"
         k["frac"] = k["achieved"] / k["peak"]
-        k["traffic"] = measured_traffic(k["kernel"], args.workload, far_prec) if not k["shared"] else None
+        k["traffic"] = (measured_traffic(k["kernel"], args.workload, far_prec, f"{tpt_}x{nch_}")
+                        if not k["shared"] else None)
     roof = None
     alone = [k for k in kernels if not k["shared"]]
     if alone:

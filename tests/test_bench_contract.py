@@ -71,12 +71,19 @@ def test_self_exec_flops_by_hand():
         assert 0.3 < r < 0.45, (p, r)
 
 
-def test_traffic_lookup_is_tied_to_source_and_workload():
-    assert bench.measured_traffic("k_far64 (x)", "no_such_workload", 0) is None
+def test_traffic_lookup_is_tied_to_source_workload_and_tile():
+    assert bench.measured_traffic("k_far64 (x)", "no_such_workload", 0, "2x15") is None
     same = bench.kernel_source_sha256() == bench.TRAFFIC_SOURCE_SHA256
-    for (wl, prec, kern), v in bench.TRAFFIC_BYTES.items():
-        got = bench.measured_traffic(kern + " (x)", wl, 0 if prec == "fp64" else 1)
+    for key, v in bench.TRAFFIC_BYTES.items():
+        wl, prec, kern = key[:3]
+        tile = key[3] if len(key) > 3 else "1x1"
+        got = bench.measured_traffic(kern + " (x)", wl, 0 if prec == "fp64" else 1, tile)
         assert (got == v) if same else got is None
+        if kern.startswith("k_far"):
+            # another tile shape has no counted bytes
+            assert bench.measured_traffic(kern + " (x)", wl, 0 if prec == "fp64" else 1, "1x1") is None
+        else:
+            assert len(key) == 3
 
 
 @pytest.mark.gpu
