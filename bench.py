@@ -82,14 +82,42 @@ TRAFFIC_SOURCE_SHA256 = "60810dad5ec8cec55a8307727e9bb7747487add5813133afb8f5c10
 # launch of all its items; a far-field kernel's traffic depends on its tile
 # shape (per-chunk partial sums, source re-reads per block of targets)
 TRAFFIC_BYTES = {
-    ("large_256_p32", "fp64", "k_far64", "2x15"): 1.913e10,
+    ("large_256_p32", "fp32c", "k_far32", "1x12"): 9.241e+09,
+    ("large_256_p32", "fp32c", "k_far32", "1x14"): 9.513e+09,
+    ("large_256_p32", "fp32c", "k_far32", "1x15"): 9.478e+09,
+    ("large_256_p32", "fp32c", "k_far32", "1x16"): 1.091e+10,
+    ("large_256_p32", "fp32c", "k_far32", "2x12"): 5.428e+09,
+    ("large_256_p32", "fp32c", "k_far32", "2x14"): 5.514e+09,
+    ("large_256_p32", "fp32c", "k_far32", "2x15"): 5.564e+09,
+    ("large_256_p32", "fp32c", "k_far32", "2x16"): 5.648e+09,
+    ("large_256_p32", "fp64", "k_far64", "1x12"): 6.26e+10,
+    ("large_256_p32", "fp64", "k_far64", "1x14"): 8.783e+10,
+    ("large_256_p32", "fp64", "k_far64", "1x15"): 7.441e+10,
+    ("large_256_p32", "fp64", "k_far64", "1x16"): 9.977e+10,
+    ("large_256_p32", "fp64", "k_far64", "2x12"): 1.695e+10,
+    ("large_256_p32", "fp64", "k_far64", "2x14"): 1.902e+10,
+    ("large_256_p32", "fp64", "k_far64", "2x15"): 1.94e+10,
+    ("large_256_p32", "fp64", "k_far64", "2x16"): 2.234e+10,
+    ("batched_64_mixed_p", "fp32c", "k_far32", "1x12"): 4.735e+08,
+    ("batched_64_mixed_p", "fp32c", "k_far32", "1x14"): 4.518e+08,
+    ("batched_64_mixed_p", "fp32c", "k_far32", "1x15"): 4.571e+08,
+    ("batched_64_mixed_p", "fp32c", "k_far32", "1x16"): 4.661e+08,
+    ("batched_64_mixed_p", "fp32c", "k_far32", "2x12"): 5.844e+08,
+    ("batched_64_mixed_p", "fp32c", "k_far32", "2x14"): 5.558e+08,
+    ("batched_64_mixed_p", "fp32c", "k_far32", "2x15"): 5.453e+08,
+    ("batched_64_mixed_p", "fp32c", "k_far32", "2x16"): 5.381e+08,
+    ("batched_64_mixed_p", "fp64", "k_far64", "1x12"): 5.991e+09,
+    ("batched_64_mixed_p", "fp64", "k_far64", "1x14"): 4.871e+09,
+    ("batched_64_mixed_p", "fp64", "k_far64", "1x15"): 3.977e+09,
+    ("batched_64_mixed_p", "fp64", "k_far64", "1x16"): 3.348e+09,
+    ("batched_64_mixed_p", "fp64", "k_far64", "2x12"): 2.147e+09,
+    ("batched_64_mixed_p", "fp64", "k_far64", "2x14"): 2.085e+09,
+    ("batched_64_mixed_p", "fp64", "k_far64", "2x15"): 1.887e+09,
+    ("batched_64_mixed_p", "fp64", "k_far64", "2x16"): 1.746e+09,
     ("large_256_p32", "fp64", "k_self<32>"): 1.815e9,
-    ("large_256_p32", "fp32c", "k_far32", "2x15"): 5.569e9,
     ("large_256_p32", "fp32c", "k_self<32>"): 1.815e9,
-    ("batched_64_mixed_p", "fp64", "k_far64", "2x12"): 2.078e9,
-    ("batched_64_mixed_p", "fp32c", "k_far32", "1x16"): 4.661e8,
 }
-for _pmax, _b in ((48, 5.947e8), (32, 1.202e8), (24, 2.543e7), (16, 7.392e6)):
+for _pmax, _b in ((48, 6.773e8), (32, 1.202e8), (24, 2.543e7), (16, 7.398e6)):
     for _prec in ("fp64", "fp32c"):
         TRAFFIC_BYTES[("batched_64_mixed_p", _prec, f"k_self<{_pmax}>")] = _b
 
@@ -389,6 +417,11 @@ def bench_eval(args, torch, E, W, dev):
                      "timings_ms": {str(k): v for k, v in timings.items()}}
     log("self prefetch", self_tile)
     runs = {prec: time_evaluation(args, torch, E, ctx, s, prec, kinds, f, sig, out, u) for prec in precs}
+    # one lone far-field launch per listed tile shape, after the timed steps
+    # (for counter runs: each shape's dispatch has a grid size of its own)
+    for prec in precs:
+        for tpt, nch in args.count_shapes:
+            ctx.time_far(prec, tpt, nch, 1, kinds=kinds)
     ctx.close()
 
     golden = None
@@ -453,6 +486,8 @@ def bench_eval(args, torch, E, W, dev):
                            "roofline": r32["roofline"], "kernels": r32["kernels"],
                            "far_error": errors(r32),
                            "error_bound_stated": 1e-6}
+    if args.count_shapes:
+        res["counted_far_shapes"] = [f"{t}x{c}" for t, c in args.count_shapes]
     if args.copy_probe > 0:
         n = args.copy_probe * (1 << 20) // 8
         a = torch.ones(n, dtype=torch.float64, device=dev)
@@ -794,7 +829,16 @@ def main(argv=None):
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy a MIB-mebibyte device buffer once (a plain "
                          "copy kernel of known size, to scale hardware byte counters)")
+    ap.add_argument("--count-shapes", default="", metavar="TPTxCHUNKS[,...]",
+                    help="after the timed steps, launch the far-field kernel once alone in each of these "
+                         "tile shapes, per far-field precision (for hardware-counter runs)")
     args = ap.parse_args(argv)
+    try:
+        args.count_shapes = [tuple(int(v) for v in t.lower().split("x")) for t in args.count_shapes.split(",") if t]
+        if any(len(t) != 2 for t in args.count_shapes):
+            raise ValueError
+    except ValueError:
+        ap.error("--count-shapes takes TPTxCHUNKS[,TPTxCHUNKS...]")
 
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU implementation: --gpus must be 1 "
