@@ -24,6 +24,13 @@ def test_more_than_one_gpu_is_refused():
     assert "single-GPU" in msg["error"]
 
 
+def test_count_shapes_argument_is_checked():
+    for bad in ("2x", "2x15x1", "two"):
+        with pytest.raises(SystemExit) as e:
+            bench.main(["--count-shapes", bad])
+        assert e.value.code == 2
+
+
 @pytest.mark.parametrize("p, total", [(16, 1.35e9), (24, 9.27e9), (32, 3.72e10), (48, 2.68e11)])
 def test_self_flops_match_the_per_degree_table(p, total):
     # q = 2p on the paper's grid: rotation + Legendre + longitude sums + kernel
