@@ -12,8 +12,8 @@ rebuilt library never reuses a stale choice.
 
 The self-interaction autotuner does the same for the Legendre prefetch
 batch of each degree class present (ehd_time_self over the batches the
-library builds for the class), keyed by device, library build, class and the
-(p, q_self) mix of the class's drops.
+library builds for the class), keyed by device, library build, class, the
+(p, q_self) mix of the class's drops and their number.
 """
 from __future__ import annotations
 
@@ -108,8 +108,10 @@ def autotune_far(ctx, p, q_far, grid_mode: int, far_prec: int, kinds: int = 31, 
 def self_signature(ctx, cls: int, pq, grid_mode: int) -> str:
     prop = torch.cuda.get_device_properties(ctx.device)
     arch = getattr(prop, "gcnArchName", prop.name)
+    # the number of drops in the class too: its timings are reported, and a
+    # class of a few drops runs in a handful of waves per CU
     return (f"{arch}|{prop.multi_processor_count}|lib{library_hash()}|self{cls}|"
-            f"{sorted(set(pq))}|grid{int(grid_mode)}")
+            f"{sorted(set(pq))}|n{len(pq)}|grid{int(grid_mode)}")
 
 
 def autotune_self(ctx, p, q_self, grid_mode: int, fcoef, sigcoef, reps: int = 3,
